@@ -1,0 +1,183 @@
+"""ctypes front end of the FP64 CPU oracle (test infrastructure only).
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
+``bench.py`` may import this module.  The GPU library never does.
+
+The shared object is built from ``oracle/cgks_oracle.c`` with gcc and OpenMP,
+in plain IEEE double precision (no fast-math, no FMA contraction).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "cgks_oracle.c")
+LIB = os.path.join(HERE, "liboracle.so")
+
+OK, EINVAL, ENONPHYS = 0, -1, -4
+
+
+class Params(C.Structure):
+    """Mirror of ``or_params`` in cgks_oracle.c."""
+
+    _fields_ = [
+        ("gamma", C.c_double),
+        ("cfl", C.c_double),
+        ("tau_eps", C.c_double),
+        ("tau_C", C.c_double),
+        ("mu0", C.c_double),
+        ("T_ref", C.c_double),
+        ("S_suth", C.c_double),
+        ("Pr", C.c_double),
+        ("geno_C", C.c_double),
+        ("geno_eps", C.c_double),
+        ("geno_r", C.c_double),
+        ("viscous", C.c_int),
+        ("visc_law", C.c_int),
+        ("tau_zero", C.c_int),
+        ("linear", C.c_int),
+        ("prandtl_fix", C.c_int),
+    ]
+
+
+def params(**kw) -> Params:
+    """Oracle parameters; defaults are the paper's constants (Sec. 3.3, Sec. 5)."""
+    d = dict(gamma=1.4, cfl=0.5, tau_eps=0.05, tau_C=5.0, mu0=0.0, T_ref=1.0, S_suth=0.0,
+             Pr=1.0, geno_C=150.0, geno_eps=1e-15, geno_r=2.0, viscous=0, visc_law=0,
+             tau_zero=0, linear=0, prandtl_fix=0)
+    d.update(kw)
+    return Params(**d)
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle shared object (gcc -O2 -fopenmp, IEEE double)."""
+    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        tmp = LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=gnu99", "-fopenmp", "-ffp-contract=off",
+                               "-fPIC", "-shared", "-o", tmp, SRC, "-lm"])
+        os.replace(tmp, LIB)
+    return LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+            build(force=True)
+        L = C.CDLL(LIB)
+        dp, ip, lp = C.POINTER(C.c_double), C.POINTER(C.c_int), C.POINTER(C.c_long)
+        pp = C.POINTER(Params)
+        L.oracle_constants.argtypes = [dp, dp, dp, dp, dp, dp, ip]
+        L.oracle_metrics.argtypes = [ip, dp, dp, dp, dp, dp, dp]
+        L.oracle_recon.argtypes = [ip, dp, pp, dp, dp, dp, lp, C.c_long, dp]
+        L.oracle_flux.argtypes = [pp, C.c_long, dp, dp, dp, dp, dp, C.c_double, dp, dp, dp]
+        L.oracle_dt.argtypes = [ip, dp, pp, dp, dp]
+        L.oracle_stage.argtypes = [ip, dp, pp, C.c_int, C.c_double, dp, dp, dp, dp, C.c_int]
+        L.oracle_run.argtypes = [ip, dp, pp, dp, dp, dp, C.c_int, dp, dp, C.c_int]
+        L.oracle_s2o4.argtypes = [C.c_long, C.c_double, dp, dp, dp, dp, dp, dp]
+        L.oracle_num_threads.restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _d(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _arr(a):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a
+
+
+def _dims(dims):
+    return (C.c_int * 3)(*[int(x) for x in dims])
+
+
+def num_threads() -> int:
+    return int(lib().oracle_num_threads())
+
+
+def constants():
+    """R (34x72), EV (24x34), EG (24x3x34), GH, GL, GT (34x34), multi-indices (34x3)."""
+    R = np.zeros((34, 72)); ev = np.zeros((24, 34)); eg = np.zeros((24, 3, 34))
+    gh = np.zeros((34, 34)); gl = np.zeros((34, 34)); gt = np.zeros((34, 34))
+    mi = np.zeros((34, 3), dtype=np.int32)
+    lib().oracle_constants(_d(R), _d(ev), _d(eg), _d(gh), _d(gl), _d(gt),
+                           mi.ctypes.data_as(C.POINTER(C.c_int)))
+    return dict(R=R, EV=ev, EG=eg, GH=gh, GL=gl, GT=gt, MI=mi)
+
+
+def metrics(dims, nodes):
+    n = int(np.prod(dims))
+    nodes = _arr(nodes)
+    vol = np.zeros(n); J0 = np.zeros((n, 3, 3)); JiT = np.zeros((n, 3, 3))
+    fn = np.zeros((n, 3, 4, 3)); fw = np.zeros((n, 3, 4))
+    st = lib().oracle_metrics(_dims(dims), _d(nodes), _d(vol), _d(J0), _d(JiT), _d(fn), _d(fw))
+    if st:
+        raise ValueError(f"oracle_metrics status {st}")
+    return dict(vol=vol, J0=J0, JinvT=JiT, fn=fn, fw=fw)
+
+
+def recon(dims, nodes, prm, Q, G, L, cells):
+    """Gauss-point values and physical gradients: [ncells, 24, 5, 4]."""
+    nodes, Q, G, L = _arr(nodes), _arr(Q), _arr(G), _arr(L)
+    cells = np.ascontiguousarray(cells, dtype=np.int64)
+    out = np.zeros((len(cells), 24, 5, 4))
+    st = lib().oracle_recon(_dims(dims), _d(nodes), C.byref(prm), _d(Q), _d(G), _d(L),
+                            cells.ctypes.data_as(C.POINTER(C.c_long)), len(cells), _d(out))
+    if st:
+        raise ValueError(f"oracle_recon status {st}")
+    return out
+
+
+def flux(prm, ql, gl, qr, gr, nrm, dt):
+    """GKS flux at independent points.  ql[n,5], gl[n,5,3], nrm[n,3] -> F, Ft [n,5], sides [n,4,5]."""
+    ql, gl, qr, gr, nrm = map(_arr, (ql, gl, qr, gr, nrm))
+    n = ql.shape[0]
+    F = np.zeros((n, 5)); Ft = np.zeros((n, 5)); S = np.zeros((n, 4, 5))
+    st = lib().oracle_flux(C.byref(prm), n, _d(ql), _d(gl), _d(qr), _d(gr), _d(nrm), float(dt),
+                           _d(F), _d(Ft), _d(S))
+    return st, F, Ft, S
+
+
+def cfl_dt(dims, nodes, prm, Q):
+    nodes, Q = _arr(nodes), _arr(Q)
+    out = C.c_double(0)
+    st = lib().oracle_dt(_dims(dims), _d(nodes), C.byref(prm), _d(Q), C.byref(out))
+    if st:
+        raise ValueError(f"oracle_dt status {st}")
+    return out.value
+
+
+def stage(dims, nodes, prm, s, dt, Q, G, L, stash, nthreads=0):
+    """One stage in place on caller arrays (float64, C-contiguous)."""
+    nodes = _arr(nodes)
+    for a in (Q, G, L, stash):
+        assert a.dtype == np.float64 and a.flags.c_contiguous
+    return lib().oracle_stage(_dims(dims), _d(nodes), C.byref(prm), int(s), float(dt), _d(Q), _d(G),
+                              _d(L), _d(stash), int(nthreads))
+
+
+def run(dims, nodes, prm, Q, G, L, nsteps, dt=0.0, nthreads=0):
+    """nsteps S2O4 steps on copies; returns (status, Q, G, L, last dt, elapsed t)."""
+    nodes = _arr(nodes)
+    Q, G, L = _arr(Q).copy(), _arr(G).copy(), _arr(L).copy()
+    d = C.c_double(float(dt))
+    t = C.c_double(0)
+    st = lib().oracle_run(_dims(dims), _d(nodes), C.byref(prm), _d(Q), _d(G), _d(L), int(nsteps),
+                          C.byref(d), C.byref(t), int(nthreads))
+    return st, Q, G, L, d.value, t.value
+
+
+def s2o4(dt, q, Ln, Ltn, Lts):
+    q, Ln, Ltn, Lts = map(_arr, (q, Ln, Ltn, Lts))
+    qs = np.zeros_like(q); qn = np.zeros_like(q)
+    lib().oracle_s2o4(q.size, float(dt), _d(q), _d(Ln), _d(Ltn), _d(Lts), _d(qs), _d(qn))
+    return qs, qn
