@@ -1,0 +1,160 @@
+/*
+ * cgks.h — C ABI of the MI355X (gfx950) implementation of the per-stage path of the
+ * fifth-order compact gas-kinetic scheme (CGKS-5) of Yang, Zhao & Xu, "An effective
+ * implementation of high-order compact gas-kinetic scheme on structured meshes for
+ * compressible flows".
+ *
+ * One context holds the mesh of one or more periodic structured blocks, their metrics
+ * (Sec. 4: affine map to the standard cell, J0 and (J0^T)^-1; Sec. 2: 2x2 Gauss points
+ * per quadrilateral face; Appendix: trilinear cell volume), the constant reconstruction
+ * matrices of the standard cell (Sec. 3.3 eq. compact-big-5, Sec. 4 eq. compact-big-ref),
+ * and the work buffers of a stage.  The caller owns the flow state.
+ *
+ * State layout (all blocks concatenated; per block SoA, x fastest, cell c = i + nx(j + ny k)):
+ *   Q[5][N]      cell averages (rho, rho U, rho V, rho W, rho E)          (Sec. 2, eq. semi)
+ *   G[5][3][N]   cell-averaged physical gradient d Q_v / d x_j            (Sec. 3.1, eq. derivative)
+ *   L[5][12][N]  line derivatives in the reference frame: Q(G(s,+)) - Q(G(s,-)) along the
+ *                12 lines joining paired face Gauss points                 (Sec. 3.1, eq. derivative-l)
+ *                line s = 4q + k joins Gauss point k of the minus-q face to Gauss point k of
+ *                the plus-q face; Gauss point k on a face of axis q has coordinates
+ *                ((2(k&1)-1) g, (2(k>>1)-1) g) along the two other axes in ascending order,
+ *                g = 1/(2 sqrt 3), on the face parametrised over [-1/2, 1/2]^2.
+ * with N the total cell count.  Nodes of a block: (nx+1)(ny+1)(nz+1) x 3 doubles, x fastest;
+ * the block is periodic and node index n along an axis is node 0 shifted by the period.
+ *
+ * Pointers: "device" pointers are HIP device allocations owned by the caller; "host"
+ * pointers are ordinary host memory.  No call allocates on a stage or step; stage and step
+ * never synchronise the stream, so a sequence of them can be captured into a HIP graph.
+ * A context is bound to the device that was current at creation and is not thread-safe.
+ *
+ * Errors: every call returns a cgks_status.  Argument errors are detected on the host
+ * before any device work.  Non-physical states met by the kernels (rho <= 0, p <= 0 or a
+ * non-finite value at a Gauss point) set a device flag that cgks_check reports.  Nothing
+ * aborts and nothing prints; cgks_last_error() gives a message for the last failure of the
+ * calling thread.
+ */
+#ifndef CGKS_H
+#define CGKS_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct cgks_ctx cgks_ctx;
+
+typedef enum {
+    CGKS_OK = 0,
+    CGKS_EINVAL = -1,        /* bad argument (detected on the host)                         */
+    CGKS_EHIP = -2,          /* a HIP runtime call failed                                   */
+    CGKS_ENOMEM = -3,        /* device allocation failed (context creation only)            */
+    CGKS_ENONPHYS = -4,      /* non-physical state seen by a kernel (see cgks_check)        */
+    CGKS_EUNSUPPORTED = -5   /* option not available in this build                          */
+} cgks_status;
+
+/* Scheme parameters.  Defaults (cgks_default_params) are the paper's constants:
+ * gamma 1.4, CFL 0.5, inviscid collision time tau = tau_eps dt + tau_C |dp/sum p| dt with
+ * tau_eps 0.05, tau_C 5 (Sec. 5); GENO eps 1e-15, r = 2 (Sec. 3.3). */
+typedef struct {
+    double gamma;
+    double cfl;
+    double tau_eps, tau_C;
+    double mu0;          /* dynamic viscosity at T_ref (viscous mode)                       */
+    double T_ref;        /* Sutherland reference temperature, in units of p/rho             */
+    double S_suth;       /* Sutherland constant, same units                                 */
+    double Pr;           /* Prandtl number (heat-flux correction when prandtl_fix = 1)      */
+    double geno_C;       /* path-function constant of chi = tanh(C alpha)/tanh(C)           */
+    double geno_eps;     /* epsilon of the smoothness ratios and linear weights             */
+    double geno_r;       /* exponent r of the path function                                 */
+    int viscous;         /* 0: inviscid collision time; 1: tau = mu/p + tau_C |dp/sum p| dt */
+    int visc_law;        /* 0: constant mu0; 1: Sutherland                                  */
+    int tau_zero;        /* 1: tau = 0, f = g0 (1 + A t) (accuracy test of Sec. 5.1)        */
+    int linear;          /* 1: chi = 1 (linear CGKS-5)                                      */
+    int prandtl_fix;     /* 1: heat-flux correction to Pr (viscous mode only)               */
+    int recon_prec;      /* reconstruction arithmetic: 0 FP64                               */
+    int flux_prec;       /* flux arithmetic: 0 FP64                                         */
+    int recon_impl;      /* reconstruction kernel: 0 matrix cores (MFMA, default),
+                            1 vector-ALU kernel (one thread per cell and variable)          */
+} cgks_params;
+
+/* Fill *p with the defaults listed above (inviscid, nonlinear, FP64). */
+void cgks_default_params(cgks_params *p);
+
+/* Create a context on the current device.
+ *   nblocks      number of periodic blocks (>= 1)
+ *   dims         host, nblocks*3 ints: nx, ny, nz of each block (each >= 1)
+ *   nodes        host, nblocks pointers, each to (nx+1)(ny+1)(nz+1)*3 doubles (x fastest)
+ *   p            host, scheme parameters (copied)
+ *   stream       hipStream_t used for the set-up work (may be NULL: the null stream)
+ * Metrics are computed on the device.  Cells must have positive volume and positive
+ * det J0.  On failure *out is NULL. */
+int cgks_ctx_create(cgks_ctx **out, int nblocks, const int *dims, const double *const *nodes,
+                    const cgks_params *p, void *stream);
+
+/* Release every device buffer of the context (synchronises the device).  NULL is a no-op. */
+void cgks_ctx_destroy(cgks_ctx *ctx);
+
+/* Total number of cells N of the context. */
+long cgks_num_cells(const cgks_ctx *ctx);
+
+/* Global time step by the CFL condition of Sec. 5: dt = CFL / max over cells of
+ * sum_d (|U.n_d| + c)/h_d (h_d = volume / mean area of the two d-faces, n_d their mean
+ * normal), and in viscous mode also CFL h_min^2 / (3 nu).  Q: device [5][N];
+ * dt_dev: device, one double, written on the stream. */
+int cgks_dt(cgks_ctx *ctx, const double *Q, double *dt_dev, void *stream);
+
+/* One S2O4 stage in place (temporal-discretisation section of the paper).
+ *   stage 1: Q* = Q + dt/2 L(Q) + dt^2/8 dL/dt;  G*, L* from the interface values evolved to
+ *            t + dt/2; saves what stage 2 needs in the context.
+ *   stage 2: Q = Q^n + dt L(Q^n) + dt^2/6 (dL/dt(Q^n) + 2 dL/dt(Q*));  G, L from the
+ *            interface values at t^n evolved over dt with the stage-2 time derivative.
+ * dt_dev: device double (the same value for both stages).  Q, G, L: device state.
+ * Stage 2 must follow a stage 1 on the same context with the same dt. */
+int cgks_stage(cgks_ctx *ctx, int stage, const double *dt_dev, double *Q, double *G, double *L,
+               void *stream);
+
+/* One full S2O4 step: if use_cfl, dt is computed into *dt_dev first (cgks_dt); otherwise
+ * *dt_dev is used as given.  Then stage 1 and stage 2. */
+int cgks_step(cgks_ctx *ctx, double *Q, double *G, double *L, double *dt_dev, int use_cfl,
+              void *stream);
+
+/* Synchronise the context's last stream and report the device error flag:
+ * *flags_host = 0 if clean, else a bit mask (1: rho <= 0, 2: p <= 0, 4: non-finite).
+ * Returns CGKS_ENONPHYS if a flag is set (and clears it), CGKS_OK otherwise. */
+int cgks_check(cgks_ctx *ctx, int *flags_host);
+
+/* Gauss-point reconstruction of the whole state (test and diagnostics entry point):
+ * gp: device [N][24][5][4], per cell the value and physical gradient of every conserved
+ * variable at its 24 face Gauss points (face m = 2q+s, point k, index 4m+k). */
+int cgks_recon(cgks_ctx *ctx, const double *Q, const double *G, const double *L, double *gp,
+               void *stream);
+
+/* Gas-kinetic flux (Sec. 2, eq. flux and its time linearisation) at n independent points.
+ * Device arrays: ql, qr [n][5]; gl, gr [n][5][3] (physical gradients); nrm [n][3] unit
+ * normals pointing from left to right; dt_dev one double.  Outputs (device): F, Ft [n][5]
+ * (flux and its time derivative per unit area); sides [n][4][5] = (Q^l, dQ^l/dt, Q^r,
+ * dQ^r/dt) one-sided interface values.  Non-physical input sets the device flag of ctx. */
+int cgks_flux(cgks_ctx *ctx, long n, const double *ql, const double *gl, const double *qr,
+              const double *gr, const double *nrm, const double *dt_dev, double *F, double *Ft,
+              double *sides, void *stream);
+
+/* Per-cell metrics computed at creation (test entry point).  Device outputs, any may be
+ * NULL: vol [N]; J0 [N][9] row-major dx_i/dxi_j; fn [N][3][4][3] unit normals of the three
+ * plus faces; fw [N][3][4] Gauss weight times area element. */
+int cgks_metrics(cgks_ctx *ctx, double *vol, double *J0, double *fn, double *fw, void *stream);
+
+/* Kernel timing (tracing aid).  When enabled, every kernel launch of cgks_dt / cgks_stage is
+ * bracketed by HIP events recorded on the caller's stream; cgks_profile_read synchronises and
+ * returns, per kernel kind, the summed elapsed milliseconds and the launch count since the
+ * last read, then resets them.  Kinds: 0 dt, 1 reconstruction, 2 flux, 3 update.
+ * Not for use under HIP graph capture.  ms and launches: host arrays of CGKS_NKINDS. */
+#define CGKS_NKINDS 4
+int cgks_profile(cgks_ctx *ctx, int enable);
+int cgks_profile_read(cgks_ctx *ctx, double *ms, long *launches);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char *cgks_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CGKS_H */

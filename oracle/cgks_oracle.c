@@ -372,8 +372,41 @@ static void face_gp_geom(const or_mesh *M, int i, int j, int k, int q, int gp, d
     *wds = 0.25 * nn;
 }
 
+/* volume (3x3x3 Gauss, Appendix), J0 and (J0^T)^-1 of cell (i,j,k); returns 1 if degenerate */
+static int cell_geom(const or_mesh *M, int i, int j, int k, double *volp, double J0[9], double JiT[9]) {
+    static const double gl3[3] = {-0.38729833462074168852, 0.0, 0.38729833462074168852}; /* sqrt(3/5)/2 */
+    static const double wl3[3] = {5.0 / 18.0, 8.0 / 18.0, 5.0 / 18.0};
+    double vol = 0, X[3], Jm[3][3];
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b)
+            for (int d = 0; d < 3; ++d) {
+                double xi[3] = {gl3[a], gl3[b], gl3[d]};
+                trilinear(M, i, j, k, xi, X, Jm);
+                vol += wl3[a] * wl3[b] * wl3[d] * det3(Jm);
+            }
+    *volp = vol;
+    const double *n0 = node_at(M, i, j, k);
+    const double *nq[3] = {node_at(M, i + 1, j, k), node_at(M, i, j + 1, k), node_at(M, i, j, k + 1)};
+    double J[3][3];
+    for (int r = 0; r < 3; ++r)
+        for (int q = 0; q < 3; ++q) J[r][q] = nq[q][r] - n0[r];
+    for (int r = 0; r < 9; ++r) J0[r] = J[r / 3][r % 3];
+    /* (J^T)^{-1} = (J^{-1})^T = cofactor(J) / det */
+    double dt = det3(J);
+    double cof[3][3];
+    for (int r = 0; r < 3; ++r)
+        for (int q = 0; q < 3; ++q) {
+            int r1 = (r + 1) % 3, r2 = (r + 2) % 3, q1 = (q + 1) % 3, q2 = (q + 2) % 3;
+            cof[r][q] = J[r1][q1] * J[r2][q2] - J[r1][q2] * J[r2][q1];
+        }
+    for (int r = 0; r < 3; ++r)
+        for (int q = 0; q < 3; ++q) JiT[3 * r + q] = cof[r][q] / dt;
+    return !(vol > 0) || !(dt > 0);
+}
+
 static int mesh_build(or_mesh *M, const int dims[3], const double *nodes) {
     M->nx = dims[0]; M->ny = dims[1]; M->nz = dims[2];
+    M->n = 0;
     if (M->nx < 1 || M->ny < 1 || M->nz < 1 || !nodes) return OR_EINVAL;
     M->n = (long)M->nx * M->ny * M->nz;
     M->nodes = nodes;
@@ -382,39 +415,11 @@ static int mesh_build(or_mesh *M, const int dims[3], const double *nodes) {
     M->JinvT = malloc(sizeof(double) * 9 * M->n);
     M->fn = malloc(sizeof(double) * 3 * M->n * 4 * 3);
     M->fw = malloc(sizeof(double) * 3 * M->n * 4);
-    static const double gl3[3] = {-0.38729833462074168852, 0.0, 0.38729833462074168852}; /* sqrt(3/5)/2 */
-    static const double wl3[3] = {5.0 / 18.0, 8.0 / 18.0, 5.0 / 18.0};
     int bad = 0;
 #pragma omp parallel for schedule(static) reduction(| : bad)
     for (long c = 0; c < M->n; ++c) {
         int i = c % M->nx, j = (c / M->nx) % M->ny, k = c / ((long)M->nx * M->ny);
-        double vol = 0, X[3], Jm[3][3];
-        for (int a = 0; a < 3; ++a)
-            for (int b = 0; b < 3; ++b)
-                for (int d = 0; d < 3; ++d) {
-                    double xi[3] = {gl3[a], gl3[b], gl3[d]};
-                    trilinear(M, i, j, k, xi, X, Jm);
-                    vol += wl3[a] * wl3[b] * wl3[d] * det3(Jm);
-                }
-        M->vol[c] = vol;
-        if (!(vol > 0)) bad = 1;
-        const double *n0 = node_at(M, i, j, k);
-        const double *nq[3] = {node_at(M, i + 1, j, k), node_at(M, i, j + 1, k), node_at(M, i, j, k + 1)};
-        double J[3][3];
-        for (int r = 0; r < 3; ++r)
-            for (int q = 0; q < 3; ++q) J[r][q] = nq[q][r] - n0[r];
-        for (int r = 0; r < 9; ++r) M->J0[9 * c + r] = J[r / 3][r % 3];
-        /* (J^T)^{-1} = (J^{-1})^T = cofactor(J) / det */
-        double dt = det3(J);
-        if (!(dt > 0)) bad = 1;
-        double cof[3][3];
-        for (int r = 0; r < 3; ++r)
-            for (int q = 0; q < 3; ++q) {
-                int r1 = (r + 1) % 3, r2 = (r + 2) % 3, q1 = (q + 1) % 3, q2 = (q + 2) % 3;
-                cof[r][q] = J[r1][q1] * J[r2][q2] - J[r1][q2] * J[r2][q1];
-            }
-        for (int r = 0; r < 3; ++r)
-            for (int q = 0; q < 3; ++q) M->JinvT[9 * c + 3 * r + q] = cof[r][q] / dt;
+        bad |= cell_geom(M, i, j, k, &M->vol[c], &M->J0[9 * c], &M->JinvT[9 * c]);
         for (int q = 0; q < 3; ++q)
             for (int g = 0; g < 4; ++g)
                 face_gp_geom(M, i, j, k, q, g, &M->fn[((3 * c + q) * 4 + g) * 3], &M->fw[(3 * c + q) * 4 + g]);
@@ -442,7 +447,7 @@ static long face_of(const or_mesh *M, long c, int m) {
 
 /* out[g][v][0..3]: value and physical gradient at Gauss point g (=4m+k) of cell c */
 static void recon_cell(const or_mesh *M, const or_params *P, const double *Q, const double *G,
-                       const double *L, long c, double out[NGP][NV][4]) {
+                       const double *L, long c, const double *J, const double *JiT, double out[NGP][NV][4]) {
     const long N = M->n;
     int i = c % M->nx, j = (c / M->nx) % M->ny, k = c / ((long)M->nx * M->ny);
     long fnb[6], enb[12];
@@ -455,8 +460,6 @@ static void recon_cell(const or_mesh *M, const or_params *P, const double *Q, co
         double o[3]; edge_geom(n, o, t1[n], t2[n]);
         enb[n] = cell_id(M, i + (int)o[0], j + (int)o[1], k + (int)o[2]);
     }
-    const double *J = &M->J0[9 * c], *JiT = &M->JinvT[9 * c];
-
     for (int v = 0; v < NV; ++v) {
         double q0 = Q[v * N + c], b[NR], a[NB];
         for (int m = 0; m < 6; ++m) b[m] = Q[v * N + fnb[m]] - q0;
@@ -841,6 +844,73 @@ typedef struct {
     double F[4][5], Ft[4][5], side[4][4][5]; /* per Gauss point */
 } face_rec;
 
+/* Accumulation of the six faces of cell c (eq. semi, eqs. derivative, derivative-l) and the
+   S2O4 stage update.  fs[m], fnp[m], fwp[m]: flux record and geometry of face m (m = 2q+s).
+   Reads Q/G/L/stash at index c (stride N); writes Qo/Go/Lo at index co (stride N, or 1 per
+   cell block of the sampled entry point when No == 1). */
+static void cell_update(int stage, double dt, double vol, const face_rec *const fs[6], const double *const fnp[6],
+                        const double *const fwp[6], long N, long c, const double *Q, const double *G,
+                        const double *L, double *stash, double *Qo, double *Go, double *Lo, long co) {
+    double Lf[5] = {0}, Lt[5] = {0}, Gq[5][3] = {{0}}, Gt[5][3] = {{0}};
+    double ownq[6][4][5], ownt[6][4][5];
+    (void)G; (void)L;
+    for (int m = 0; m < 6; ++m) {
+        double sg = (m % 2) ? 1.0 : -1.0;
+        int sq = (m % 2) ? 0 : 2; /* own side: left of its plus face, right of its minus face */
+        for (int g = 0; g < 4; ++g) {
+            double w = fwp[m][g];
+            const double *nn = &fnp[m][3 * g];
+            for (int v = 0; v < 5; ++v) {
+                Lf[v] -= sg * w * fs[m]->F[g][v];
+                Lt[v] -= sg * w * fs[m]->Ft[g][v];
+                double qs = fs[m]->side[g][sq][v], qt = fs[m]->side[g][sq + 1][v];
+                ownq[m][g][v] = qs; ownt[m][g][v] = qt;
+                for (int r = 0; r < 3; ++r) { Gq[v][r] += sg * w * nn[r] * qs; Gt[v][r] += sg * w * nn[r] * qt; }
+            }
+        }
+    }
+    double iv = 1.0 / vol;
+    for (int v = 0; v < 5; ++v) {
+        Lf[v] *= iv; Lt[v] *= iv;
+        for (int r = 0; r < 3; ++r) { Gq[v][r] *= iv; Gt[v][r] *= iv; }
+    }
+    const long No = (Qo == Q) ? N : 1;
+    if (stage == 1) {
+        for (int v = 0; v < 5; ++v) {
+            double qn = Q[v * N + c];
+            if (stash) {
+                stash[v * N + c] = qn;
+                stash[(5 + v) * N + c] = Lf[v];
+                stash[(10 + v) * N + c] = Lt[v];
+            }
+            Qo[v * No + co] = qn + 0.5 * dt * Lf[v] + 0.125 * dt * dt * Lt[v];
+            for (int r = 0; r < 3; ++r) {
+                if (stash) stash[(15 + 3 * v + r) * N + c] = Gq[v][r];
+                Go[(v * 3 + r) * No + co] = Gq[v][r] + 0.5 * dt * Gt[v][r];
+            }
+            for (int s = 0; s < 12; ++s) {
+                int q = s / 4, g = s % 4;
+                double lb = ownq[2 * q + 1][g][v] - ownq[2 * q][g][v];
+                double lt = ownt[2 * q + 1][g][v] - ownt[2 * q][g][v];
+                if (stash) stash[(30 + 12 * v + s) * N + c] = lb;
+                Lo[(v * 12 + s) * No + co] = lb + 0.5 * dt * lt;
+            }
+        }
+    } else {
+        for (int v = 0; v < 5; ++v) {
+            double qn = stash[v * N + c], ln = stash[(5 + v) * N + c], ltn = stash[(10 + v) * N + c];
+            Qo[v * No + co] = qn + dt * ln + dt * dt / 6.0 * (ltn + 2.0 * Lt[v]);
+            for (int r = 0; r < 3; ++r)
+                Go[(v * 3 + r) * No + co] = stash[(15 + 3 * v + r) * N + c] + dt * Gt[v][r];
+            for (int s = 0; s < 12; ++s) {
+                int q = s / 4, g = s % 4;
+                double lt = ownt[2 * q + 1][g][v] - ownt[2 * q][g][v];
+                Lo[(v * 12 + s) * No + co] = stash[(30 + 12 * v + s) * N + c] + dt * lt;
+            }
+        }
+    }
+}
+
 static int run_stage(const or_mesh *M, const or_params *P, int stage, double dt, double *Q, double *G,
                      double *L, double *stash) {
     const long N = M->n;
@@ -848,7 +918,7 @@ static int run_stage(const or_mesh *M, const or_params *P, int stage, double dt,
     face_rec *fr = malloc(sizeof(face_rec) * 3 * N);
     int bad = 0;
 #pragma omp parallel for schedule(dynamic, 16)
-    for (long c = 0; c < N; ++c) recon_cell(M, P, Q, G, L, c, rec[c]);
+    for (long c = 0; c < N; ++c) recon_cell(M, P, Q, G, L, c, &M->J0[9 * c], &M->JinvT[9 * c], rec[c]);
 #pragma omp parallel for schedule(dynamic, 16) reduction(| : bad)
     for (long f = 0; f < 3 * N; ++f) {
         long c = f / 3;
@@ -871,60 +941,15 @@ static int run_stage(const or_mesh *M, const or_params *P, int stage, double dt,
     if (!bad) {
 #pragma omp parallel for schedule(static)
         for (long c = 0; c < N; ++c) {
-            double Lf[5] = {0}, Lt[5] = {0}, Gq[5][3] = {{0}}, Gt[5][3] = {{0}};
-            double ownq[6][4][5], ownt[6][4][5];
+            const face_rec *fs[6];
+            const double *fnp[6], *fwp[6];
             for (int m = 0; m < 6; ++m) {
                 long f = face_of(M, c, m);
-                double sg = (m % 2) ? 1.0 : -1.0;
-                int sq = (m % 2) ? 0 : 2; /* own side: left of its plus face, right of its minus face */
-                for (int g = 0; g < 4; ++g) {
-                    double w = M->fw[4 * f + g];
-                    const double *nn = &M->fn[(4 * f + g) * 3];
-                    for (int v = 0; v < 5; ++v) {
-                        Lf[v] -= sg * w * fr[f].F[g][v];
-                        Lt[v] -= sg * w * fr[f].Ft[g][v];
-                        double qs = fr[f].side[g][sq][v], qt = fr[f].side[g][sq + 1][v];
-                        ownq[m][g][v] = qs; ownt[m][g][v] = qt;
-                        for (int r = 0; r < 3; ++r) { Gq[v][r] += sg * w * nn[r] * qs; Gt[v][r] += sg * w * nn[r] * qt; }
-                    }
-                }
+                fs[m] = &fr[f];
+                fnp[m] = &M->fn[(4 * f) * 3];
+                fwp[m] = &M->fw[4 * f];
             }
-            double iv = 1.0 / M->vol[c];
-            for (int v = 0; v < 5; ++v) {
-                Lf[v] *= iv; Lt[v] *= iv;
-                for (int r = 0; r < 3; ++r) { Gq[v][r] *= iv; Gt[v][r] *= iv; }
-            }
-            if (stage == 1) {
-                for (int v = 0; v < 5; ++v) {
-                    stash[v * N + c] = Q[v * N + c];
-                    stash[(5 + v) * N + c] = Lf[v];
-                    stash[(10 + v) * N + c] = Lt[v];
-                    Q[v * N + c] = Q[v * N + c] + 0.5 * dt * Lf[v] + 0.125 * dt * dt * Lt[v];
-                    for (int r = 0; r < 3; ++r) {
-                        stash[(15 + 3 * v + r) * N + c] = Gq[v][r];
-                        G[(v * 3 + r) * N + c] = Gq[v][r] + 0.5 * dt * Gt[v][r];
-                    }
-                    for (int s = 0; s < 12; ++s) {
-                        int q = s / 4, g = s % 4;
-                        double lb = ownq[2 * q + 1][g][v] - ownq[2 * q][g][v];
-                        double lt = ownt[2 * q + 1][g][v] - ownt[2 * q][g][v];
-                        stash[(30 + 12 * v + s) * N + c] = lb;
-                        L[(v * 12 + s) * N + c] = lb + 0.5 * dt * lt;
-                    }
-                }
-            } else {
-                for (int v = 0; v < 5; ++v) {
-                    double qn = stash[v * N + c], ln = stash[(5 + v) * N + c], ltn = stash[(10 + v) * N + c];
-                    Q[v * N + c] = qn + dt * ln + dt * dt / 6.0 * (ltn + 2.0 * Lt[v]);
-                    for (int r = 0; r < 3; ++r)
-                        G[(v * 3 + r) * N + c] = stash[(15 + 3 * v + r) * N + c] + dt * Gt[v][r];
-                    for (int s = 0; s < 12; ++s) {
-                        int q = s / 4, g = s % 4;
-                        double lt = ownt[2 * q + 1][g][v] - ownt[2 * q][g][v];
-                        L[(v * 12 + s) * N + c] = stash[(30 + 12 * v + s) * N + c] + dt * lt;
-                    }
-                }
-            }
+            cell_update(stage, dt, M->vol[c], fs, fnp, fwp, N, c, Q, G, L, stash, Q, G, L, c);
         }
     }
     free(rec);
@@ -990,7 +1015,8 @@ int oracle_recon(const int dims[3], const double *nodes, const or_params *P, con
     if (st) { if (M.n > 0) mesh_free(&M); return st; }
 #pragma omp parallel for schedule(dynamic, 4)
     for (long t = 0; t < ncells; ++t)
-        recon_cell(&M, P, Q, G, L, cells[t], (double (*)[NV][4])(out + (size_t)t * NGP * NV * 4));
+        recon_cell(&M, P, Q, G, L, cells[t], &M.J0[9 * cells[t]], &M.JinvT[9 * cells[t]],
+                   (double (*)[NV][4])(out + (size_t)t * NGP * NV * 4));
     mesh_free(&M);
     return OR_OK;
 }
@@ -1086,4 +1112,71 @@ int oracle_s2o4(long n, double dt, const double *q, const double *Ln, const doub
         if (qnext) qnext[i] = q[i] + dt * Ln[i] + dt * dt / 6.0 * (Ltn[i] + 2.0 * Lts[i]);
     }
     return OR_OK;
+}
+
+/* Stage 1 (from the given state at t^n with step dt) for the listed cells only, without
+   metrics of the whole mesh: each cell reconstructs itself and its six face neighbours,
+   evaluates the fluxes of its 24 face Gauss points and applies the stage-1 update.
+   outQ [n][5], outG [n][5][3], outL [n][5][12]. */
+int oracle_stage1_cells(const int dims[3], const double *nodes, const or_params *P, double dt, const double *Q,
+                        const double *G, const double *L, const long *cells, long ncells, double *outQ,
+                        double *outG, double *outL) {
+    if (!(dt > 0) || !Q || !G || !L || !cells || ncells < 0) return OR_EINVAL;
+    init_consts();
+    or_mesh M;
+    memset(&M, 0, sizeof M);
+    M.nx = dims[0]; M.ny = dims[1]; M.nz = dims[2];
+    if (M.nx < 1 || M.ny < 1 || M.nz < 1 || !nodes) return OR_EINVAL;
+    M.n = (long)M.nx * M.ny * M.nz;
+    M.nodes = nodes;
+    const long N = M.n;
+    int bad = 0;
+#pragma omp parallel for schedule(dynamic, 1) reduction(| : bad)
+    for (long t = 0; t < ncells; ++t) {
+        long c = cells[t];
+        int i = c % M.nx, j = (c / M.nx) % M.ny, k = c / ((long)M.nx * M.ny);
+        double rec[7][NGP][NV][4];
+        long who[7];
+        who[0] = c;
+        for (int m = 0; m < 6; ++m) {
+            int idx[3] = {i, j, k};
+            idx[m / 2] += (m % 2) ? 1 : -1;
+            who[1 + m] = cell_id(&M, idx[0], idx[1], idx[2]);
+        }
+        double vol0 = 0;
+        for (int w = 0; w < 7; ++w) {
+            long cw = who[w];
+            int iw = cw % M.nx, jw = (cw / M.nx) % M.ny, kw = cw / ((long)M.nx * M.ny);
+            double vol, J[9], JiT[9];
+            bad |= cell_geom(&M, iw, jw, kw, &vol, J, JiT);
+            if (w == 0) vol0 = vol;
+            recon_cell(&M, P, Q, G, L, cw, J, JiT, rec[w]);
+        }
+        face_rec fr[6];
+        double fn[6][12], fw[6][4];
+        for (int m = 0; m < 6; ++m) {
+            int q = m / 2;
+            /* face owner (minus-side cell) and the cells left/right of the face */
+            long owner = (m % 2) ? c : who[1 + m];
+            const double (*lrec)[NV][4] = (m % 2) ? rec[0] : rec[1 + m];
+            const double (*rrec)[NV][4] = (m % 2) ? rec[1 + m] : rec[0];
+            int io = owner % M.nx, jo = (owner / M.nx) % M.ny, ko = owner / ((long)M.nx * M.ny);
+            for (int g = 0; g < 4; ++g) {
+                face_gp_geom(&M, io, jo, ko, q, g, &fn[m][3 * g], &fw[m][g]);
+                double ql[5], qr[5], gl[5][3], gr[5][3];
+                int gpl = 4 * (2 * q + 1) + g, gpr = 4 * (2 * q) + g;
+                for (int v = 0; v < 5; ++v) {
+                    ql[v] = lrec[gpl][v][0]; qr[v] = rrec[gpr][v][0];
+                    for (int r = 0; r < 3; ++r) { gl[v][r] = lrec[gpl][v][1 + r]; gr[v][r] = rrec[gpr][v][1 + r]; }
+                }
+                if (gks_flux(P, ql, gl, qr, gr, &fn[m][3 * g], dt, fr[m].F[g], fr[m].Ft[g], fr[m].side[g]))
+                    bad |= 2;
+            }
+        }
+        const face_rec *fs[6];
+        const double *fnp[6], *fwp[6];
+        for (int m = 0; m < 6; ++m) { fs[m] = &fr[m]; fnp[m] = fn[m]; fwp[m] = fw[m]; }
+        cell_update(1, dt, vol0, fs, fnp, fwp, N, c, Q, G, L, NULL, outQ + 5 * t, outG + 15 * t, outL + 60 * t, 0);
+    }
+    return bad ? ((bad & 2) ? OR_ENONPHYS : OR_EINVAL) : OR_OK;
 }

@@ -82,6 +82,7 @@ def lib():
         L.oracle_stage.argtypes = [ip, dp, pp, C.c_int, C.c_double, dp, dp, dp, dp, C.c_int]
         L.oracle_run.argtypes = [ip, dp, pp, dp, dp, dp, C.c_int, dp, dp, C.c_int]
         L.oracle_s2o4.argtypes = [C.c_long, C.c_double, dp, dp, dp, dp, dp, dp]
+        L.oracle_stage1_cells.argtypes = [ip, dp, pp, C.c_double, dp, dp, dp, lp, C.c_long, dp, dp, dp]
         L.oracle_num_threads.restype = C.c_int
         _lib = L
     return _lib
@@ -181,3 +182,14 @@ def s2o4(dt, q, Ln, Ltn, Lts):
     qs = np.zeros_like(q); qn = np.zeros_like(q)
     lib().oracle_s2o4(q.size, float(dt), _d(q), _d(Ln), _d(Ltn), _d(Lts), _d(qs), _d(qn))
     return qs, qn
+
+
+def stage1_cells(dims, nodes, prm, dt, Q, G, L, cells):
+    """Stage-1 outputs (Q*, G*, L*) of the listed cells only: [n,5], [n,5,3], [n,5,12]."""
+    nodes, Q, G, L = _arr(nodes), _arr(Q), _arr(G), _arr(L)
+    cells = np.ascontiguousarray(cells, dtype=np.int64)
+    n = len(cells)
+    oq = np.zeros((n, 5)); og = np.zeros((n, 5, 3)); ol = np.zeros((n, 5, 12))
+    st = lib().oracle_stage1_cells(_dims(dims), _d(nodes), C.byref(prm), float(dt), _d(Q), _d(G), _d(L),
+                                   cells.ctypes.data_as(C.POINTER(C.c_long)), n, _d(oq), _d(og), _d(ol))
+    return st, oq, og, ol

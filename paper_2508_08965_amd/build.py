@@ -1,0 +1,34 @@
+"""Build step of the HIP library (hipcc, gfx950) into paper_2508_08965_amd/lib/libcgks.so."""
+from __future__ import annotations
+
+import os
+import subprocess
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+CSRC = os.path.join(HERE, "csrc")
+OUT = os.path.join(HERE, "lib", "libcgks.so")
+
+SOURCES = ["cgks_capi.hip", "cgks_kernels.hip", "cgks_recon_mfma.hip", "cgks_consts.cpp"]
+
+FLAGS = ["-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC", "-shared",
+         # packed FP32 instructions are disabled for every HIP translation unit
+         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+
+
+def build(verbose: bool = False) -> str:
+    os.makedirs(os.path.dirname(OUT), exist_ok=True)
+    tmp = OUT + ".tmp"
+    cmd = (["hipcc"] + FLAGS + ["-I", os.path.join(ROOT, "include"), "-I", CSRC, "-o", tmp]
+           + [os.path.join(CSRC, s) for s in SOURCES])
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("hipcc failed:\n" + r.stderr)
+    if verbose:
+        print(r.stderr)
+    os.replace(tmp, OUT)
+    return OUT
+
+
+if __name__ == "__main__":
+    print(build())

@@ -1,0 +1,174 @@
+"""Python binding of the CGKS-5 C ABI (include/cgks.h).
+
+Argument marshalling only: every step of the path runs in the HIP library
+``paper_2508_08965_amd/lib/libcgks.so``.  Device arrays are torch tensors (float64,
+contiguous, on the context's device); streams are torch.cuda streams.  There is no CPU
+fallback: if the library is missing or a call fails, a RuntimeError is raised.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "lib", "libcgks.so")
+
+OK, EINVAL, EHIP, ENOMEM, ENONPHYS, EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+
+
+class Params(C.Structure):
+    """Mirror of cgks_params."""
+
+    _fields_ = [
+        ("gamma", C.c_double), ("cfl", C.c_double), ("tau_eps", C.c_double), ("tau_C", C.c_double),
+        ("mu0", C.c_double), ("T_ref", C.c_double), ("S_suth", C.c_double), ("Pr", C.c_double),
+        ("geno_C", C.c_double), ("geno_eps", C.c_double), ("geno_r", C.c_double),
+        ("viscous", C.c_int), ("visc_law", C.c_int), ("tau_zero", C.c_int), ("linear", C.c_int),
+        ("prandtl_fix", C.c_int), ("recon_prec", C.c_int), ("flux_prec", C.c_int), ("recon_impl", C.c_int),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    """Load libcgks.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"HIP library not built: {LIB_PATH} (run __graft_entry__.build())")
+        L = C.CDLL(LIB_PATH)
+        vp, dp, ip = C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int)
+        L.cgks_default_params.argtypes = [C.POINTER(Params)]
+        L.cgks_ctx_create.argtypes = [C.POINTER(vp), C.c_int, ip, C.POINTER(dp), C.POINTER(Params), vp]
+        L.cgks_ctx_destroy.argtypes = [vp]
+        L.cgks_num_cells.argtypes = [vp]
+        L.cgks_num_cells.restype = C.c_long
+        L.cgks_dt.argtypes = [vp, vp, vp, vp]
+        L.cgks_stage.argtypes = [vp, C.c_int, vp, vp, vp, vp, vp]
+        L.cgks_step.argtypes = [vp, vp, vp, vp, vp, C.c_int, vp]
+        L.cgks_check.argtypes = [vp, ip]
+        L.cgks_recon.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.cgks_flux.argtypes = [vp, C.c_long, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.cgks_metrics.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.cgks_profile.argtypes = [vp, C.c_int]
+        L.cgks_profile_read.argtypes = [vp, dp, C.POINTER(C.c_long)]
+        L.cgks_last_error.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+def last_error() -> str:
+    return lib().cgks_last_error().decode()
+
+
+def _check(st, what):
+    if st != OK:
+        raise RuntimeError(f"{what} failed with status {st}: {last_error()}")
+
+
+def default_params(**kw) -> Params:
+    p = Params()
+    lib().cgks_default_params(C.byref(p))
+    for k, v in kw.items():
+        if not hasattr(p, k):
+            raise KeyError(k)
+        setattr(p, k, v)
+    return p
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    import torch
+    if t.dtype != torch.float64 or not t.is_contiguous() or t.device.type != "cuda":
+        raise ValueError("device arrays must be contiguous float64 CUDA tensors")
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+class Context:
+    """A cgks_ctx: mesh, metrics, constant matrices and work buffers of one or more blocks."""
+
+    def __init__(self, dims, nodes, params: Params, stream=None):
+        import numpy as np
+        dims = [tuple(int(x) for x in d) for d in dims]
+        self._nodes = [np.ascontiguousarray(n.cpu().numpy() if hasattr(n, "cpu") else n, dtype=np.float64)
+                       for n in nodes]
+        flat = (C.c_int * (3 * len(dims)))(*[x for d in dims for x in d])
+        ptrs = (C.POINTER(C.c_double) * len(dims))(*[a.ctypes.data_as(C.POINTER(C.c_double))
+                                                     for a in self._nodes])
+        h = C.c_void_p()
+        _check(lib().cgks_ctx_create(C.byref(h), len(dims), flat, ptrs, C.byref(params), _stream(stream)),
+               "cgks_ctx_create")
+        self.h = h
+        self.params = params
+        self.dims = dims
+        self.ncells = int(lib().cgks_num_cells(h))
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().cgks_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def cgks_dt(ctx: Context, Q, dt_dev, stream=None):
+    _check(lib().cgks_dt(ctx.h, _ptr(Q), _ptr(dt_dev), _stream(stream)), "cgks_dt")
+
+
+def cgks_stage(ctx: Context, stage: int, dt_dev, Q, G, L, stream=None):
+    _check(lib().cgks_stage(ctx.h, int(stage), _ptr(dt_dev), _ptr(Q), _ptr(G), _ptr(L), _stream(stream)),
+           "cgks_stage")
+
+
+def cgks_step(ctx: Context, Q, G, L, dt_dev, use_cfl=True, stream=None):
+    _check(lib().cgks_step(ctx.h, _ptr(Q), _ptr(G), _ptr(L), _ptr(dt_dev), int(bool(use_cfl)), _stream(stream)),
+           "cgks_step")
+
+
+def cgks_check(ctx: Context):
+    """Returns (status, flags) without raising."""
+    f = C.c_int(0)
+    st = lib().cgks_check(ctx.h, C.byref(f))
+    return st, f.value
+
+
+def cgks_recon(ctx: Context, Q, G, L, gp, stream=None):
+    _check(lib().cgks_recon(ctx.h, _ptr(Q), _ptr(G), _ptr(L), _ptr(gp), _stream(stream)), "cgks_recon")
+
+
+def cgks_flux(ctx: Context, ql, gl, qr, gr, nrm, dt_dev, F, Ft, sides, stream=None):
+    n = ql.shape[0]
+    _check(lib().cgks_flux(ctx.h, n, _ptr(ql), _ptr(gl), _ptr(qr), _ptr(gr), _ptr(nrm), _ptr(dt_dev), _ptr(F),
+                           _ptr(Ft), _ptr(sides), _stream(stream)), "cgks_flux")
+
+
+def cgks_metrics(ctx: Context, vol=None, J0=None, fn=None, fw=None, stream=None):
+    _check(lib().cgks_metrics(ctx.h, _ptr(vol), _ptr(J0), _ptr(fn), _ptr(fw), _stream(stream)), "cgks_metrics")
+
+
+KERNEL_KINDS = ("dt", "reconstruction", "flux", "update")
+
+
+def cgks_profile(ctx: Context, enable: bool):
+    _check(lib().cgks_profile(ctx.h, int(bool(enable))), "cgks_profile")
+
+
+def cgks_profile_read(ctx: Context):
+    """{kind: (total ms, launches)} since the last read (synchronises)."""
+    ms = (C.c_double * 4)()
+    n = (C.c_long * 4)()
+    _check(lib().cgks_profile_read(ctx.h, ms, n), "cgks_profile_read")
+    return {k: (ms[i], n[i]) for i, k in enumerate(KERNEL_KINDS)}

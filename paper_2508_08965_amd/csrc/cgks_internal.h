@@ -1,0 +1,68 @@
+// Internal definitions shared by the host set-up and the HIP kernels of the library.
+#pragma once
+
+#include <cmath>
+
+namespace cgks {
+
+constexpr int kNV = 5;    // conserved variables
+constexpr int kNB = 34;   // basis of the quartic, 1 <= |d| <= 4
+constexpr int kNR = 72;   // stencil data per variable (rows of the standard-cell system)
+constexpr int kNGP = 24;  // face Gauss points of one cell
+
+// Row blocks of the standard-cell system (order of eq. compact-big-5 / compact-big-ref):
+// face averages (exact) | edge averages | face gradients (3 per face) | edge directional
+// derivatives (tau1, tau2 per edge) | line differences.
+constexpr int kRowEdgeAvg = 6;
+constexpr int kRowFaceGrad = 18;
+constexpr int kRowEdgeDir = 36;
+constexpr int kRowLine = 60;
+
+struct EdgeDef {
+    double off[3];  // offset of the edge neighbour
+    double t1[3];   // unit vector along the shared edge
+    double t2[3];   // unit vector from the target centroid to the neighbour centroid
+};
+
+// Edge n = 4p + (sa > 0) + 2 (sb > 0), axis pairs p: (0,1), (0,2), (1,2).
+inline EdgeDef edge_def(int n) {
+    static const int pa[3] = {0, 0, 1}, pb[3] = {1, 2, 2}, pc[3] = {2, 1, 0};
+    EdgeDef e;
+    int p = n / 4;
+    for (int q = 0; q < 3; ++q) e.off[q] = e.t1[q] = e.t2[q] = 0.0;
+    e.off[pa[p]] = (n & 1) ? 1.0 : -1.0;
+    e.off[pb[p]] = (n & 2) ? 1.0 : -1.0;
+    e.t1[pc[p]] = 1.0;
+    const double r = 1.0 / std::sqrt(2.0);
+    for (int q = 0; q < 3; ++q) e.t2[q] = e.off[q] * r;
+    return e;
+}
+
+// Constant matrices of the standard cell (host copy; uploaded once per context).
+struct HostConsts {
+    double R[kNB][kNR];         // a = R b
+    double E[kNGP][4][kNB];     // per Gauss point: value row, then d/dxi, d/deta, d/dzeta rows
+    double GH[kNB][kNB];        // Gram matrix of all derivatives 1..4  (IS^H)
+    double GL[kNB][kNB];        // first derivatives                    (IS^L)
+    double GT[kNB][kNB];        // derivatives 2..4                     (IS^tau)
+    double xg[kNGP][3];         // reference Gauss points (centred standard cell)
+};
+
+void build_constants(HostConsts &K);
+
+// Constant blocks of the matrix-core reconstruction (f64 16x16x4), 64 doubles per block in
+// the per-lane order the instruction reads: R (3 tiles x 18 k-steps), L_L^T (3 x 10),
+// L_T^T (2 x 10), E (6 x 10).
+constexpr int kMfmaOffA1 = 0, kMfmaOffAL = 54, kMfmaOffAT = 84, kMfmaOffA2 = 104, kMfmaBlocks = 164;
+bool pack_mfma_f64(const HostConsts &K, double *blocks);
+
+// Scheme parameters in the form the kernels read them.
+struct DevParams {
+    double gamma, K;             // ratio of specific heats, internal degrees of freedom
+    double cfl, tau_eps, tau_C;
+    double mu0, T_ref, S_suth, Pr;
+    double geno_C, geno_eps, geno_r, inv_tanhC;
+    int viscous, visc_law, tau_zero, linear, prandtl_fix;
+};
+
+}  // namespace cgks

@@ -1,0 +1,606 @@
+// HIP kernels of the CGKS-5 stage path for gfx950 (FP64 path).
+//
+//   k_metrics   : per-cell geometry (Sec. 4 J0 and (J0^T)^-1; Appendix trilinear volume;
+//                 2x2 Gauss points of the bilinear faces, Sec. 2)
+//   k_dt_*      : CFL time step, min over cells (Sec. 5)
+//   k_recon     : compact reconstruction on the standard cell + GENO blend (Sec. 3.3, 4)
+//   k_flux      : gas-kinetic flux at face Gauss points (Sec. 2, eq. flux, linearisation)
+//   k_update    : face -> cell accumulation and S2O4 stage update (Sec. 3.1, temporal section)
+//
+// Data layout (SoA, stride Ntot = cells of all blocks, x fastest inside a block):
+//   gp  [q][side][k][v*4 + c][Ntot]   reconstructed value (c = 0) and physical gradient
+//                                     (c = 1..3) at Gauss point k of face q of the face
+//                                     record owned by the minus-side cell; side 0 = values
+//                                     of the minus-side (left) cell, side 1 = plus-side cell.
+//   fo  [q][k][30][Ntot]              F^n (5), F_t^n (5), Q^l, dQ^l/dt, Q^r, dQ^r/dt (20)
+#include <hip/hip_runtime.h>
+
+#include "cgks_device.h"
+
+namespace cgks {
+
+// ------------------------------------------------------------------------------------------
+// small device helpers
+// ------------------------------------------------------------------------------------------
+struct Idx3 {
+    int i, j, k;
+};
+
+__device__ inline Idx3 unflatten(const BlockView &b, long cl) {
+    Idx3 r;
+    r.i = (int)(cl % b.nx);
+    long t = cl / b.nx;
+    r.j = (int)(t % b.ny);
+    r.k = (int)(t / b.ny);
+    return r;
+}
+
+__device__ inline long cell_at(const BlockView &b, int i, int j, int k) {
+    i = (i < 0) ? i + b.nx : (i >= b.nx ? i - b.nx : i);
+    j = (j < 0) ? j + b.ny : (j >= b.ny ? j - b.ny : j);
+    k = (k < 0) ? k + b.nz : (k >= b.nz ? k - b.nz : k);
+    return b.off + (long)i + (long)b.nx * ((long)j + (long)b.ny * k);
+}
+
+__device__ inline const double *node_ptr(const double *nodes, const BlockView &b, int i, int j, int k) {
+    return nodes + 3 * ((long)i + (long)(b.nx + 1) * ((long)j + (long)(b.ny + 1) * k));
+}
+
+// ------------------------------------------------------------------------------------------
+// metrics
+// ------------------------------------------------------------------------------------------
+// Bilinear face with corners P00, P10, P01, P11 over (s,t) in [-1/2,1/2]^2: area vector
+// dX/ds x dX/dt at (s,t).
+__device__ inline void face_area_vec(const double *P00, const double *P10, const double *P01,
+                                     const double *P11, double s, double t, double out[3]) {
+    double ds[3], dt[3];
+    for (int r = 0; r < 3; ++r) {
+        ds[r] = (0.5 - t) * (P10[r] - P00[r]) + (0.5 + t) * (P11[r] - P01[r]);
+        dt[r] = (0.5 - s) * (P01[r] - P00[r]) + (0.5 + s) * (P11[r] - P10[r]);
+    }
+    out[0] = ds[1] * dt[2] - ds[2] * dt[1];
+    out[1] = ds[2] * dt[0] - ds[0] * dt[2];
+    out[2] = ds[0] * dt[1] - ds[1] * dt[0];
+}
+
+__global__ void __launch_bounds__(256) k_metrics(BlockView b, const double *__restrict__ nodes, Metrics M,
+                                                 long Ntot, int *__restrict__ bad) {
+    long cl = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (cl >= b.N) return;
+    Idx3 id = unflatten(b, cl);
+    long c = b.off + cl;
+    const double *P[8];
+    for (int t = 0; t < 8; ++t) P[t] = node_ptr(nodes, b, id.i + (t & 1), id.j + ((t >> 1) & 1), id.k + (t >> 2));
+    // volume: 2x2x2 Gauss of det dX/dxi (exact for a trilinear map)
+    const double gq = 0.28867513459481288225;
+    double vol = 0.0;
+    for (int a = 0; a < 8; ++a) {
+        double xi[3] = {(a & 1) ? gq : -gq, ((a >> 1) & 1) ? gq : -gq, (a >> 2) ? gq : -gq};
+        double J[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+        for (int t = 0; t < 8; ++t) {
+            double s0 = (t & 1) ? 1.0 : -1.0, s1 = ((t >> 1) & 1) ? 1.0 : -1.0, s2 = (t >> 2) ? 1.0 : -1.0;
+            double f0 = 0.5 + s0 * xi[0], f1 = 0.5 + s1 * xi[1], f2 = 0.5 + s2 * xi[2];
+            for (int r = 0; r < 3; ++r) {
+                J[r][0] += P[t][r] * s0 * f1 * f2;
+                J[r][1] += P[t][r] * f0 * s1 * f2;
+                J[r][2] += P[t][r] * f0 * f1 * s2;
+            }
+        }
+        double det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) - J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+                     J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+        vol += 0.125 * det;
+    }
+    M.vol[c] = vol;
+    // J0 = [N2 - N1, N3 - N1, N4 - N1] with N1 = node (i,j,k)
+    double J0[3][3];
+    for (int r = 0; r < 3; ++r) {
+        J0[r][0] = P[1][r] - P[0][r];
+        J0[r][1] = P[2][r] - P[0][r];
+        J0[r][2] = P[4][r] - P[0][r];
+    }
+    double det = J0[0][0] * (J0[1][1] * J0[2][2] - J0[1][2] * J0[2][1]) - J0[0][1] * (J0[1][0] * J0[2][2] - J0[1][2] * J0[2][0]) +
+                 J0[0][2] * (J0[1][0] * J0[2][1] - J0[1][1] * J0[2][0]);
+    if (!(vol > 0.0) || !(det > 0.0)) atomicOr(bad, 1);
+    double inv = 1.0 / det;
+    for (int r = 0; r < 3; ++r)
+        for (int q = 0; q < 3; ++q) {
+            M.J0[(3 * r + q) * Ntot + c] = J0[r][q];
+            // ((J0^T)^-1)[r][q] = cofactor(J0)[r][q] / det
+            int r1 = (r + 1) % 3, r2 = (r + 2) % 3, q1 = (q + 1) % 3, q2 = (q + 2) % 3;
+            M.JiT[(3 * r + q) * Ntot + c] = (J0[r1][q1] * J0[r2][q2] - J0[r1][q2] * J0[r2][q1]) * inv;
+        }
+    // faces: for each axis the plus face (owned) and the minus face (for the time step)
+    const double gpt = 0.28867513459481288225;
+    double hsum[3];
+    for (int q = 0; q < 3; ++q) {
+        int a = (q == 0) ? 1 : 0, bb = (q == 2) ? 1 : 2;  // ascending tangential axes
+        double S[2][3] = {{0, 0, 0}, {0, 0, 0}};
+        double area[2] = {0, 0};
+        for (int side = 0; side < 2; ++side) {
+            // corners of the face: index along q fixed, (a, b) in {0,1}^2
+            const double *C[4];
+            for (int t = 0; t < 4; ++t) {
+                int o[3] = {0, 0, 0};
+                o[q] = side;
+                o[a] = t & 1;
+                o[bb] = t >> 1;
+                C[t] = node_ptr(nodes, b, id.i + o[0], id.j + o[1], id.k + o[2]);
+            }
+            for (int kk = 0; kk < 4; ++kk) {
+                double s = (kk & 1) ? gpt : -gpt, t = (kk >> 1) ? gpt : -gpt;
+                double av[3];
+                face_area_vec(C[0], C[1], C[2], C[3], s, t, av);
+                if (q == 1) { av[0] = -av[0]; av[1] = -av[1]; av[2] = -av[2]; }  // cyclic (zeta, xi)
+                double nrm = sqrt(av[0] * av[0] + av[1] * av[1] + av[2] * av[2]);
+                double wds = 0.25 * nrm;
+                if (side == 1) {
+                    for (int r = 0; r < 3; ++r) M.fn[((q * 4 + kk) * 3 + r) * Ntot + c] = av[r] / nrm;
+                    M.fw[(q * 4 + kk) * Ntot + c] = wds;
+                }
+                for (int r = 0; r < 3; ++r) S[side][r] += 0.25 * av[r];
+            }
+            area[side] = sqrt(S[side][0] * S[side][0] + S[side][1] * S[side][1] + S[side][2] * S[side][2]);
+        }
+        double nb[3] = {S[0][0] + S[1][0], S[0][1] + S[1][1], S[0][2] + S[1][2]};
+        double nl = sqrt(nb[0] * nb[0] + nb[1] * nb[1] + nb[2] * nb[2]);
+        for (int r = 0; r < 3; ++r) M.dtm[(q * 4 + r) * Ntot + c] = nb[r] / nl;
+        hsum[q] = vol / (0.5 * (area[0] + area[1]));
+        M.dtm[(q * 4 + 3) * Ntot + c] = 1.0 / hsum[q];
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// time step
+// ------------------------------------------------------------------------------------------
+__device__ inline double viscosity(const DevParams &P, double T) {
+    if (!P.visc_law) return P.mu0;
+    double r = T / P.T_ref;
+    return P.mu0 * r * sqrt(r) * (P.T_ref + P.S_suth) / (T + P.S_suth);
+}
+
+__device__ inline double block_min(double v) {
+    __shared__ double red[16];
+    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+    int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) red[w] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m = red[0];
+        for (int i = 1; i < (int)(blockDim.x >> 6); ++i) m = fmin(m, red[i]);
+        red[0] = m;
+    }
+    __syncthreads();
+    return red[0];
+}
+
+__global__ void __launch_bounds__(256) k_dt_partial(long off, long N, long Ntot, const double *__restrict__ Q,
+                                                    const double *__restrict__ dtm, DevParams P,
+                                                    double *__restrict__ part, int *__restrict__ flag) {
+    double best = INFINITY;
+    for (long cl = (long)blockIdx.x * blockDim.x + threadIdx.x; cl < N; cl += (long)gridDim.x * blockDim.x) {
+        long c = off + cl;
+        double rho = Q[c], ru = Q[Ntot + c], rv = Q[2 * Ntot + c], rw = Q[3 * Ntot + c], re = Q[4 * Ntot + c];
+        double u = ru / rho, v = rv / rho, w = rw / rho;
+        double p = (P.gamma - 1.0) * (re - 0.5 * rho * (u * u + v * v + w * w));
+        if (!(rho > 0.0) || !(p > 0.0)) {
+            atomicOr(flag, !(rho > 0.0) ? 1 : 2);
+            continue;
+        }
+        double cs = sqrt(P.gamma * p / rho);
+        double rate = 0.0, ihmax = 0.0;
+        for (int q = 0; q < 3; ++q) {
+            double nx = dtm[(q * 4) * Ntot + c], ny = dtm[(q * 4 + 1) * Ntot + c], nz = dtm[(q * 4 + 2) * Ntot + c];
+            double ih = dtm[(q * 4 + 3) * Ntot + c];
+            rate += (fabs(u * nx + v * ny + w * nz) + cs) * ih;
+            ihmax = fmax(ihmax, ih);
+        }
+        double d = P.cfl / rate;
+        if (P.viscous) {
+            double nu = viscosity(P, p / rho) / rho;
+            d = fmin(d, P.cfl / (ihmax * ihmax * 3.0 * nu));
+        }
+        best = fmin(best, d);
+    }
+    best = block_min(best);
+    if (threadIdx.x == 0) part[blockIdx.x] = best;
+}
+
+__global__ void __launch_bounds__(256) k_dt_final(const double *__restrict__ part, int n, double *__restrict__ dt) {
+    double best = INFINITY;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) best = fmin(best, part[i]);
+    best = block_min(best);
+    if (threadIdx.x == 0) *dt = best;
+}
+
+// ------------------------------------------------------------------------------------------
+// reconstruction + GENO blend: one thread per (cell, conserved variable)
+// ------------------------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_recon(BlockView b, long Ntot, const double *__restrict__ Q,
+                                               const double *__restrict__ G, const double *__restrict__ L,
+                                               Metrics M, const DevConsts *__restrict__ K, DevParams P,
+                                               double *__restrict__ gp) {
+    long cl = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (cl >= b.N) return;
+    const int v = blockIdx.y;
+    Idx3 id = unflatten(b, cl);
+    const long c = b.off + cl;
+    const double *Qv = Q + v * Ntot;
+    const double *Gv = G + 3 * v * Ntot;
+    const double *Lv = L + 12 * v * Ntot;
+
+    double J0[3][3];
+    for (int r = 0; r < 3; ++r)
+        for (int q = 0; q < 3; ++q) J0[r][q] = M.J0[(3 * r + q) * Ntot + c];
+
+    const double q0 = Qv[c];
+    double bvec[kNR];
+    long fnb[6];
+#pragma unroll
+    for (int m = 0; m < 6; ++m) {
+        int o[3] = {0, 0, 0};
+        o[m >> 1] = (m & 1) ? 1 : -1;
+        fnb[m] = cell_at(b, id.i + o[0], id.j + o[1], id.k + o[2]);
+        bvec[m] = Qv[fnb[m]] - q0;
+        double g0 = Gv[fnb[m]], g1 = Gv[Ntot + fnb[m]], g2 = Gv[2 * Ntot + fnb[m]];
+#pragma unroll
+        for (int j = 0; j < 3; ++j) bvec[kRowFaceGrad + 3 * m + j] = J0[0][j] * g0 + J0[1][j] * g1 + J0[2][j] * g2;
+    }
+#pragma unroll
+    for (int n = 0; n < 12; ++n) {
+        const int pa = (n < 8) ? 0 : 1, pb = (n < 4) ? 1 : 2, pc = 3 - pa - pb;
+        const int sa = (n & 1) ? 1 : -1, sb = (n & 2) ? 1 : -1;
+        int o[3] = {0, 0, 0};
+        o[pa] = sa;
+        o[pb] = sb;
+        long e = cell_at(b, id.i + o[0], id.j + o[1], id.k + o[2]);
+        bvec[kRowEdgeAvg + n] = Qv[e] - q0;
+        double g0 = Gv[e], g1 = Gv[Ntot + e], g2 = Gv[2 * Ntot + e];
+        double gr[3];
+#pragma unroll
+        for (int j = 0; j < 3; ++j) gr[j] = J0[0][j] * g0 + J0[1][j] * g1 + J0[2][j] * g2;
+        bvec[kRowEdgeDir + 2 * n] = gr[pc];
+        bvec[kRowEdgeDir + 2 * n + 1] = (sa * gr[pa] + sb * gr[pb]) * 0.70710678118654752440;
+    }
+    double lines[12];
+#pragma unroll
+    for (int s = 0; s < 12; ++s) {
+        lines[s] = Lv[s * Ntot + c];
+        bvec[kRowLine + s] = lines[s];
+    }
+
+    // low-order blend: linear polynomials of the six sub-stencils and their weights
+    double bbar[3] = {0.0, 0.0, 0.0};
+    if (!P.linear) {
+        double lm[3];
+#pragma unroll
+        for (int t = 0; t < 3; ++t) lm[t] = 0.25 * (lines[4 * t] + lines[4 * t + 1] + lines[4 * t + 2] + lines[4 * t + 3]);
+        double wsum = 0.0, wv[6], bm[6][3];
+#pragma unroll
+        for (int m = 0; m < 6; ++m) {
+            const int q = m >> 1;
+#pragma unroll
+            for (int t = 0; t < 3; ++t) bm[m][t] = (t == q) ? ((m & 1) ? bvec[m] : -bvec[m]) : lm[t];
+            double is = bm[m][0] * bm[m][0] + bm[m][1] * bm[m][1] + bm[m][2] * bm[m][2] + P.geno_eps;
+            double is2 = is * is;
+            wv[m] = (1.0 / 6.0) / (is2 * is2 * is);
+            wsum += wv[m];
+        }
+        double iw = 1.0 / wsum;
+#pragma unroll
+        for (int m = 0; m < 6; ++m)
+#pragma unroll
+            for (int t = 0; t < 3; ++t) bbar[t] += (wv[m] * iw) * bm[m][t];
+    }
+
+    // a = R b
+    double a[kNB];
+#pragma unroll
+    for (int r = 0; r < kNB; ++r) {
+        double s = 0.0;
+#pragma unroll
+        for (int col = 0; col < kNR; ++col) s = fma(K->R[r][col], bvec[col], s);
+        a[r] = s;
+    }
+
+    double chi = 1.0;
+    if (!P.linear) {
+        double isl = 0.0, ist = 0.0;
+#pragma unroll
+        for (int r = 0; r < kNB; ++r) {
+            double tl = 0.0, tt = 0.0;
+#pragma unroll
+            for (int s = 0; s < kNB; ++s) {
+                tl = fma(K->GL[r][s], a[s], tl);
+                tt = fma(K->GT[r][s], a[s], tt);
+            }
+            isl = fma(a[r], tl, isl);
+            ist = fma(a[r], tt, ist);
+        }
+        double ish = isl + ist;
+        double rh = ist / (ish + P.geno_eps), rl = ist / (isl + P.geno_eps);
+        double ah, al;
+        if (P.geno_r == 2.0) {
+            ah = 1.0 + rh * rh;
+            al = 1.0 + rl * rl;
+        } else {
+            ah = 1.0 + pow(rh, P.geno_r);
+            al = 1.0 + pow(rl, P.geno_r);
+        }
+        double alpha = 2.0 * ah / (ah + al);
+        chi = tanh(P.geno_C * alpha) * P.inv_tanhC;
+    }
+
+    double JiT[3][3];
+    for (int r = 0; r < 3; ++r)
+        for (int q = 0; q < 3; ++q) JiT[r][q] = M.JiT[(3 * r + q) * Ntot + c];
+
+    const double om = 1.0 - chi;
+#pragma unroll 1
+    for (int g = 0; g < kNGP; ++g) {
+        double pv = 0.0, p1 = 0.0, p2 = 0.0, p3 = 0.0;
+#pragma unroll
+        for (int r = 0; r < kNB; ++r) {
+            pv = fma(K->E[g][0][r], a[r], pv);
+            p1 = fma(K->E[g][1][r], a[r], p1);
+            p2 = fma(K->E[g][2][r], a[r], p2);
+            p3 = fma(K->E[g][3][r], a[r], p3);
+        }
+        const double *xg = K->xg[g];
+        double low = bbar[0] * xg[0] + bbar[1] * xg[1] + bbar[2] * xg[2];
+        double val = q0 + chi * pv + om * low;
+        double r0 = chi * p1 + om * bbar[0], r1 = chi * p2 + om * bbar[1], r2 = chi * p3 + om * bbar[2];
+        double out[4];
+        out[0] = val;
+#pragma unroll
+        for (int r = 0; r < 3; ++r) out[1 + r] = JiT[r][0] * r0 + JiT[r][1] * r1 + JiT[r][2] * r2;
+        const int m = g >> 2, kk = g & 3, q = m >> 1;
+        long f;
+        int side;
+        if (m & 1) {
+            f = c;
+            side = 0;
+        } else {
+            int o[3] = {0, 0, 0};
+            o[q] = -1;
+            f = cell_at(b, id.i + o[0], id.j + o[1], id.k + o[2]);
+            side = 1;
+        }
+        double *dst = gp + ((long)(((q * 2 + side) * 4 + kk) * 20 + v * 4)) * Ntot + f;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) dst[r * Ntot] = out[r];
+    }
+}
+
+// copy of the Gauss-point buffer into the per-cell export layout [c][24][5][4]
+__global__ void __launch_bounds__(256) k_gp_export(BlockView b, long Ntot, const double *__restrict__ gp,
+                                                   double *__restrict__ out) {
+    long cl = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (cl >= b.N) return;
+    Idx3 id = unflatten(b, cl);
+    long c = b.off + cl;
+    for (int g = 0; g < kNGP; ++g) {
+        int m = g >> 2, kk = g & 3, q = m >> 1;
+        long f;
+        int side;
+        if (m & 1) {
+            f = c;
+            side = 0;
+        } else {
+            int o[3] = {0, 0, 0};
+            o[q] = -1;
+            f = cell_at(b, id.i + o[0], id.j + o[1], id.k + o[2]);
+            side = 1;
+        }
+        for (int v = 0; v < 5; ++v)
+            for (int r = 0; r < 4; ++r)
+                out[((c * kNGP + g) * 5 + v) * 4 + r] = gp[((long)(((q * 2 + side) * 4 + kk) * 20 + v * 4 + r)) * Ntot + f];
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// gas-kinetic flux kernels
+// ------------------------------------------------------------------------------------------
+// Two lanes per Gauss point: thread t -> face record f = t / 2 of the block, side t & 1.
+__global__ void __launch_bounds__(256, 2) k_flux(BlockView b, long Ntot, const double *__restrict__ gp, Metrics M,
+                                              const double *__restrict__ dtp, DevParams P,
+                                              double *__restrict__ fo, int *__restrict__ flag) {
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long cl = t >> 1;
+    if (cl >= b.N) return;  // both lanes of a pair leave together
+    const int sd = (int)(t & 1);
+    const int q = blockIdx.y >> 2, kk = blockIdx.y & 3;
+    const long f = b.off + cl;
+    double qv[5], gv[5][3], n[3];
+    const double *src = gp + (long)(((q * 2 + sd) * 4 + kk) * 20) * Ntot + f;
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+        qv[v] = src[(4 * v) * Ntot];
+#pragma unroll
+        for (int j = 0; j < 3; ++j) gv[v][j] = src[(4 * v + 1 + j) * Ntot];
+    }
+#pragma unroll
+    for (int r = 0; r < 3; ++r) n[r] = M.fn[((q * 4 + kk) * 3 + r) * Ntot + f];
+    double F[5], Ft[5], Qs[5], dQs[5];
+    const int bad = gks_flux_pair(P, sd, qv, gv, n, *dtp, F, Ft, Qs, dQs);
+    if (bad && sd == 0) atomicOr(flag, bad);
+    double *dst = fo + (long)((q * 4 + kk) * 30) * Ntot + f;
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+        dst[(10 + 10 * sd + v) * Ntot] = Qs[v];
+        dst[(15 + 10 * sd + v) * Ntot] = dQs[v];
+        if (sd) {
+            dst[v * Ntot] = F[v];
+            dst[(5 + v) * Ntot] = Ft[v];
+        }
+    }
+}
+
+__global__ void __launch_bounds__(256) k_flux_points(long n, const double *__restrict__ ql_, const double *__restrict__ gl_,
+                                                     const double *__restrict__ qr_, const double *__restrict__ gr_,
+                                                     const double *__restrict__ nrm, const double *__restrict__ dtp,
+                                                     DevParams P, double *__restrict__ F_, double *__restrict__ Ft_,
+                                                     double *__restrict__ S_, int *__restrict__ flag) {
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long i = t >> 1;
+    if (i >= n) return;
+    const int sd = (int)(t & 1);
+    const double *q_ = sd ? qr_ : ql_;
+    const double *g_ = sd ? gr_ : gl_;
+    double qv[5], gv[5][3], nn[3];
+    for (int v = 0; v < 5; ++v) {
+        qv[v] = q_[5 * i + v];
+        for (int j = 0; j < 3; ++j) gv[v][j] = g_[15 * i + 3 * v + j];
+    }
+    for (int r = 0; r < 3; ++r) nn[r] = nrm[3 * i + r];
+    double F[5], Ft[5], Qs[5], dQs[5];
+    const int bad = gks_flux_pair(P, sd, qv, gv, nn, *dtp, F, Ft, Qs, dQs);
+    if (bad && sd == 0) atomicOr(flag, bad);
+    for (int v = 0; v < 5; ++v) {
+        S_[20 * i + 10 * sd + v] = Qs[v];
+        S_[20 * i + 10 * sd + 5 + v] = dQs[v];
+        if (sd) {
+            F_[5 * i + v] = F[v];
+            Ft_[5 * i + v] = Ft[v];
+        }
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// accumulation + S2O4 stage update: one thread per cell
+// stash [80][Ntot]: Qpre (5) = Q^n + dt L^n + dt^2/6 L_t^n, Gb (15), Lb (60)
+// ------------------------------------------------------------------------------------------
+template <int STAGE>
+__global__ void __launch_bounds__(256) k_update(BlockView b, long Ntot, const double *__restrict__ fo, Metrics M,
+                                                const double *__restrict__ dtp, double *__restrict__ Q,
+                                                double *__restrict__ G, double *__restrict__ L,
+                                                double *__restrict__ stash) {
+    long cl = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (cl >= b.N) return;
+    Idx3 id = unflatten(b, cl);
+    const long c = b.off + cl;
+    const double dt = *dtp;
+    double Lf[5] = {0, 0, 0, 0, 0}, Lt[5] = {0, 0, 0, 0, 0};
+    double Gq[5][3], Gt[5][3];
+#pragma unroll
+    for (int v = 0; v < 5; ++v)
+#pragma unroll
+        for (int r = 0; r < 3; ++r) Gq[v][r] = Gt[v][r] = 0.0;
+    const double iv = 1.0 / M.vol[c];
+#pragma unroll 1
+    for (int q = 0; q < 3; ++q) {
+        int o[3] = {0, 0, 0};
+        o[q] = -1;
+        const long fm = cell_at(b, id.i + o[0], id.j + o[1], id.k + o[2]);
+#pragma unroll 1
+        for (int kk = 0; kk < 4; ++kk) {
+            const double *Dp = fo + (long)((q * 4 + kk) * 30) * Ntot + c;   // plus face: this cell is left
+            const double *Dm = fo + (long)((q * 4 + kk) * 30) * Ntot + fm;  // minus face: this cell is right
+            const double wp = M.fw[(q * 4 + kk) * Ntot + c], wm = M.fw[(q * 4 + kk) * Ntot + fm];
+            double np_[3], nm_[3];
+#pragma unroll
+            for (int r = 0; r < 3; ++r) {
+                np_[r] = M.fn[((q * 4 + kk) * 3 + r) * Ntot + c];
+                nm_[r] = M.fn[((q * 4 + kk) * 3 + r) * Ntot + fm];
+            }
+            const int s = 4 * q + kk;
+#pragma unroll
+            for (int v = 0; v < 5; ++v) {
+                if (STAGE == 1) {
+                    Lf[v] += wm * Dm[v * Ntot] - wp * Dp[v * Ntot];
+                }
+                Lt[v] += wm * Dm[(5 + v) * Ntot] - wp * Dp[(5 + v) * Ntot];
+                const double dqp = Dp[(15 + v) * Ntot], dqm = Dm[(25 + v) * Ntot];
+#pragma unroll
+                for (int r = 0; r < 3; ++r) Gt[v][r] += wp * np_[r] * dqp - wm * nm_[r] * dqm;
+                const double lt = dqp - dqm;
+                if (STAGE == 1) {
+                    const double qp = Dp[(10 + v) * Ntot], qm = Dm[(20 + v) * Ntot];
+#pragma unroll
+                    for (int r = 0; r < 3; ++r) Gq[v][r] += wp * np_[r] * qp - wm * nm_[r] * qm;
+                    const double lb = qp - qm;
+                    stash[(20 + 12 * v + s) * Ntot + c] = lb;
+                    L[(12 * v + s) * Ntot + c] = lb + 0.5 * dt * lt;
+                } else {
+                    L[(12 * v + s) * Ntot + c] = stash[(20 + 12 * v + s) * Ntot + c] + dt * lt;
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+        if (STAGE == 1) {
+            const double l1 = Lf[v] * iv, l2 = Lt[v] * iv, qn = Q[v * Ntot + c];
+            stash[v * Ntot + c] = qn + dt * l1 + (dt * dt / 6.0) * l2;
+            Q[v * Ntot + c] = qn + 0.5 * dt * l1 + 0.125 * dt * dt * l2;
+#pragma unroll
+            for (int r = 0; r < 3; ++r) {
+                const double gb = Gq[v][r] * iv;
+                stash[(5 + 3 * v + r) * Ntot + c] = gb;
+                G[(3 * v + r) * Ntot + c] = gb + 0.5 * dt * (Gt[v][r] * iv);
+            }
+        } else {
+            Q[v * Ntot + c] = stash[v * Ntot + c] + (dt * dt / 3.0) * (Lt[v] * iv);
+#pragma unroll
+            for (int r = 0; r < 3; ++r)
+                G[(3 * v + r) * Ntot + c] = stash[(5 + 3 * v + r) * Ntot + c] + dt * (Gt[v][r] * iv);
+        }
+    }
+}
+
+// explicit instantiations through launch wrappers --------------------------------------------
+hipError_t launch_metrics(const BlockView &b, const double *nodes, const Metrics &M, long Ntot, int *bad, hipStream_t s) {
+    dim3 grid((unsigned)((b.N + 255) / 256));
+    hipLaunchKernelGGL(k_metrics, grid, dim3(256), 0, s, b, nodes, M, Ntot, bad);
+    return hipGetLastError();
+}
+
+hipError_t launch_dt(long off, long N, long Ntot, const double *Q, const double *dtm, const DevParams &P,
+                     double *part, int nparts, int *flag, hipStream_t s) {
+    hipLaunchKernelGGL(k_dt_partial, dim3(nparts), dim3(256), 0, s, off, N, Ntot, Q, dtm, P, part, flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_dt_final(const double *part, int n, double *dt, hipStream_t s) {
+    hipLaunchKernelGGL(k_dt_final, dim3(1), dim3(256), 0, s, part, n, dt);
+    return hipGetLastError();
+}
+
+hipError_t launch_recon(const BlockView &b, long Ntot, const double *Q, const double *G, const double *L,
+                        const Metrics &M, const DevConsts *K, const DevParams &P, double *gp, hipStream_t s) {
+    dim3 grid((unsigned)((b.N + 255) / 256), 5);
+    hipLaunchKernelGGL(k_recon, grid, dim3(256), 0, s, b, Ntot, Q, G, L, M, K, P, gp);
+    return hipGetLastError();
+}
+
+hipError_t launch_gp_export(const BlockView &b, long Ntot, const double *gp, double *out, hipStream_t s) {
+    dim3 grid((unsigned)((b.N + 255) / 256));
+    hipLaunchKernelGGL(k_gp_export, grid, dim3(256), 0, s, b, Ntot, gp, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_flux(const BlockView &b, long Ntot, const double *gp, const Metrics &M, const double *dt,
+                       const DevParams &P, double *fo, int *flag, hipStream_t s) {
+    dim3 grid((unsigned)((2 * b.N + 255) / 256), 12);
+    hipLaunchKernelGGL(k_flux, grid, dim3(256), 0, s, b, Ntot, gp, M, dt, P, fo, flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_flux_points(long n, const double *ql, const double *gl, const double *qr, const double *gr,
+                              const double *nrm, const double *dt, const DevParams &P, double *F, double *Ft,
+                              double *S, int *flag, hipStream_t s) {
+    dim3 grid((unsigned)((2 * n + 255) / 256));
+    hipLaunchKernelGGL(k_flux_points, grid, dim3(256), 0, s, n, ql, gl, qr, gr, nrm, dt, P, F, Ft, S, flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_update(int stage, const BlockView &b, long Ntot, const double *fo, const Metrics &M,
+                         const double *dt, double *Q, double *G, double *L, double *stash, hipStream_t s) {
+    dim3 grid((unsigned)((b.N + 255) / 256));
+    if (stage == 1)
+        hipLaunchKernelGGL(k_update<1>, grid, dim3(256), 0, s, b, Ntot, fo, M, dt, Q, G, L, stash);
+    else
+        hipLaunchKernelGGL(k_update<2>, grid, dim3(256), 0, s, b, Ntot, fo, M, dt, Q, G, L, stash);
+    return hipGetLastError();
+}
+
+}  // namespace cgks

@@ -1,0 +1,249 @@
+// Compact reconstruction + GENO blend on the matrix cores (v_mfma_f64_16x16x4f64).
+//
+// On the shared standard cell the reconstruction of every cell and conserved variable is the
+// same constant matrix applied to that cell's stacked stencil data (Sec. 4, last paragraph),
+// so the work is a dense contraction over all (cell, variable) columns:
+//   GEMM1  a  = R b            R: 34 x 72 (eq. compact-big-ref, constrained least squares)
+//   GEMMs  zL = L_L^T a,  zT = L_T^T a     IS^L = |zL|^2, IS^tau = |zT|^2 (Cholesky factors
+//          of the Gram matrices of the first / second-to-fourth derivatives, Sec. 3.3)
+//   GEMM2  y  = E a            E: 96 x 34, point value and reference gradient at the 24 face
+//                              Gauss points
+// One wavefront owns 16 columns (16 cells of one conserved variable).  Operand layouts of the
+// f64 16x16x4 instruction: lane l supplies A[l%16][l/16] and B[l/16][l%16] and receives
+// D[4(l/16)+v][l%16], v = 0..3.  Consequences used below:
+//   * the stencil item of k-step s and lane group g = l/16 is item perm(4s+g); the k-steps are
+//     ordered so that the four lane groups of a step do the same kind of work (no divergence):
+//     steps 0..5 face neighbour m (g=0 average difference, g=1..3 reference gradient
+//     components), 6..8 edge-neighbour differences (edge 4p+g), 9..14 edge directional
+//     derivatives (tau1, tau2 of edge 4p+g), 15..17 line differences (line 4t+g);
+//   * GEMM1 leaves a[16t+4g+v] in register v of tile t, which is fed back unchanged as the
+//     B operand of the next contractions (their k order is permuted to match on the host);
+//   * GEMM2 rows are ordered Gauss-point-major (value, d/dxi, d/deta, d/dzeta), so each lane
+//     receives one Gauss point's value and reference gradient: blend and back-transform with
+//     (J0^T)^-1 stay in the lane.
+// The constant blocks are packed on the host in exactly the per-lane order the instruction
+// reads and staged once per workgroup in LDS.
+#include <hip/hip_runtime.h>
+
+#include "cgks_device.h"
+
+namespace cgks {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+namespace {
+
+__device__ inline long wrap_cell(const BlockView &b, int i, int j, int k) {
+    i = (i < 0) ? i + b.nx : (i >= b.nx ? i - b.nx : i);
+    j = (j < 0) ? j + b.ny : (j >= b.ny ? j - b.ny : j);
+    k = (k < 0) ? k + b.nz : (k >= b.nz ? k - b.nz : k);
+    return b.off + (long)i + (long)b.nx * ((long)j + (long)b.ny * k);
+}
+
+__device__ inline v4d mfma(double a, double b, v4d c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+
+}  // namespace
+
+__global__ void __launch_bounds__(512) k_recon_mfma(BlockView b, long Ntot, const double *__restrict__ Q,
+                                                    const double *__restrict__ G, const double *__restrict__ L,
+                                                    Metrics M, const double *__restrict__ Kblk, DevParams P,
+                                                    double *__restrict__ gp) {
+    __shared__ double lds[kMfmaBlocks * 64];
+    for (int i = threadIdx.x; i < kMfmaBlocks * 64; i += blockDim.x) lds[i] = Kblk[i];
+    __syncthreads();
+
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+    const int g = lane >> 4, col = lane & 15;
+    const double *A1 = lds + kMfmaOffA1 * 64 + lane;
+    const double *AL = lds + kMfmaOffAL * 64 + lane;
+    const double *AT = lds + kMfmaOffAT * 64 + lane;
+    const double *A2 = lds + kMfmaOffA2 * 64 + lane;
+    const long nchunks = (b.N + 15) / 16;
+    const long nitems = nchunks * kNV;
+    // tangential coordinates of this lane's Gauss point (index g on every face)
+    const double gq = 0.28867513459481288225;
+    const double ta = (g & 1) ? gq : -gq, tb = (g & 2) ? gq : -gq;
+    // signs of this lane's edge in the edge steps
+    const int sa = (g & 1) ? 1 : -1, sb = (g & 2) ? 1 : -1;
+
+    for (long it = (long)blockIdx.x * nwaves + wave; it < nitems; it += (long)gridDim.x * nwaves) {
+        const int v = (int)(it % kNV);
+        const long cl0 = (it / kNV) * 16 + col;
+        const bool valid = cl0 < b.N;
+        const long cl = valid ? cl0 : b.N - 1;  // tail lanes compute a copy, store nothing
+        const int ci = (int)(cl % b.nx);
+        const long tt = cl / b.nx;
+        const int cj = (int)(tt % b.ny), ck = (int)(tt / b.ny);
+        const long c = b.off + cl;
+        const double *Qv = Q + v * Ntot;
+        const double *Gv = G + 3 * v * Ntot;
+        const double *Lv = L + 12 * v * Ntot;
+        double J0[3][3];
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+            for (int s = 0; s < 3; ++s) J0[r][s] = M.J0[(3 * r + s) * Ntot + c];
+        const double q0 = Qv[c];
+
+        v4d acc[3] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
+        // ---- steps 0..5: face neighbours (difference and reference gradient) -------------
+#pragma unroll 1
+        for (int m = 0; m < 6; ++m) {
+            int o[3] = {0, 0, 0};
+            o[m >> 1] = (m & 1) ? 1 : -1;
+            const long nb = wrap_cell(b, ci + o[0], cj + o[1], ck + o[2]);
+            const double g0 = Gv[nb], g1 = Gv[Ntot + nb], g2 = Gv[2 * Ntot + nb];
+            const double fd = Qv[nb] - q0;
+            const double r0 = J0[0][0] * g0 + J0[1][0] * g1 + J0[2][0] * g2;
+            const double r1 = J0[0][1] * g0 + J0[1][1] * g1 + J0[2][1] * g2;
+            const double r2 = J0[0][2] * g0 + J0[1][2] * g1 + J0[2][2] * g2;
+            const double item = (g == 0) ? fd : (g == 1) ? r0 : (g == 2) ? r1 : r2;
+#pragma unroll
+            for (int t = 0; t < 3; ++t) acc[t] = mfma(A1[(t * 18 + m) * 64], item, acc[t]);
+        }
+        // ---- steps 6..14: edge neighbours 4p+g ---------------------------------------------
+#pragma unroll 1
+        for (int p = 0; p < 3; ++p) {
+            const int pa = (p < 2) ? 0 : 1, pb = (p == 0) ? 1 : 2, pc = 3 - pa - pb;
+            int o[3] = {0, 0, 0};
+            o[pa] = sa;
+            o[pb] = sb;
+            const long nb = wrap_cell(b, ci + o[0], cj + o[1], ck + o[2]);
+            const double d = Qv[nb] - q0;
+#pragma unroll
+            for (int t = 0; t < 3; ++t) acc[t] = mfma(A1[(t * 18 + 6 + p) * 64], d, acc[t]);
+            const double g0 = Gv[nb], g1 = Gv[Ntot + nb], g2 = Gv[2 * Ntot + nb];
+            double rg[3];
+#pragma unroll
+            for (int s = 0; s < 3; ++s) rg[s] = J0[0][s] * g0 + J0[1][s] * g1 + J0[2][s] * g2;
+            const double e1 = (pc == 0) ? rg[0] : (pc == 1) ? rg[1] : rg[2];
+            const double ra = (pa == 0) ? rg[0] : rg[1], rb = (pb == 1) ? rg[1] : rg[2];
+            const double e2 = (sa * ra + sb * rb) * 0.70710678118654752440;
+#pragma unroll
+            for (int t = 0; t < 3; ++t) acc[t] = mfma(A1[(t * 18 + 9 + 2 * p) * 64], e1, acc[t]);
+#pragma unroll
+            for (int t = 0; t < 3; ++t) acc[t] = mfma(A1[(t * 18 + 10 + 2 * p) * 64], e2, acc[t]);
+        }
+        // ---- steps 15..17: line differences 4t+g ---------------------------------------------
+        double lsum[3];
+#pragma unroll
+        for (int s = 0; s < 3; ++s) {
+            const double ln = Lv[(4 * s + g) * Ntot + c];
+#pragma unroll
+            for (int t = 0; t < 3; ++t) acc[t] = mfma(A1[(t * 18 + 15 + s) * 64], ln, acc[t]);
+            double x = ln + __shfl_xor(ln, 16, 64);
+            lsum[s] = x + __shfl_xor(x, 32, 64);
+        }
+
+        // ---- path function chi: IS^L and IS^tau from the Cholesky-factor contractions ---------
+        double chi = 1.0, bbar[3] = {0.0, 0.0, 0.0};
+        if (!P.linear) {
+            double isl = 0.0, ist = 0.0;
+#pragma unroll 1
+            for (int u = 0; u < 5; ++u) {  // tiles 0..2: L_L^T rows, tiles 3..4: L_T^T rows
+                const double *Au = (u < 3) ? AL + (u * 10) * 64 : AT + ((u - 3) * 10) * 64;
+                v4d z = {0, 0, 0, 0};
+#pragma unroll
+                for (int s = 0; s < 10; ++s) z = mfma(Au[s * 64], acc[s >> 2][s & 3], z);
+                const double zz = z[0] * z[0] + z[1] * z[1] + z[2] * z[2] + z[3] * z[3];
+                if (u < 3) isl += zz;
+                else ist += zz;
+            }
+            isl += __shfl_xor(isl, 16, 64);
+            isl += __shfl_xor(isl, 32, 64);
+            ist += __shfl_xor(ist, 16, 64);
+            ist += __shfl_xor(ist, 32, 64);
+            const double ish = isl + ist;
+            const double rh = ist / (ish + P.geno_eps), rl = ist / (isl + P.geno_eps);
+            double ah, al;
+            if (P.geno_r == 2.0) {
+                ah = 1.0 + rh * rh;
+                al = 1.0 + rl * rl;
+            } else {
+                ah = 1.0 + pow(rh, P.geno_r);
+                al = 1.0 + pow(rl, P.geno_r);
+            }
+            chi = tanh(P.geno_C * (2.0 * ah / (ah + al))) * P.inv_tanhC;
+            // linear sub-polynomials of the six face sub-stencils (eq. compact-sub-2) and weights
+            const double lm[3] = {0.25 * lsum[0], 0.25 * lsum[1], 0.25 * lsum[2]};
+            double wsum = 0.0, wv[6], fdiff[6];
+#pragma unroll
+            for (int m = 0; m < 6; ++m) {
+                int o[3] = {0, 0, 0};
+                o[m >> 1] = (m & 1) ? 1 : -1;
+                fdiff[m] = Qv[wrap_cell(b, ci + o[0], cj + o[1], ck + o[2])] - q0;
+            }
+#pragma unroll
+            for (int m = 0; m < 6; ++m) {
+                const int q = m >> 1;
+                const double bn = (m & 1) ? fdiff[m] : -fdiff[m];
+                double is = P.geno_eps + bn * bn;
+#pragma unroll
+                for (int t = 0; t < 3; ++t)
+                    if (t != q) is += lm[t] * lm[t];
+                const double is2 = is * is;
+                wv[m] = (1.0 / 6.0) / (is2 * is2 * is);
+                wsum += wv[m];
+            }
+            const double iw = 1.0 / wsum;
+#pragma unroll
+            for (int m = 0; m < 6; ++m) {
+                const int q = m >> 1;
+                const double w = wv[m] * iw;
+                const double bn = (m & 1) ? fdiff[m] : -fdiff[m];
+#pragma unroll
+                for (int t = 0; t < 3; ++t) bbar[t] += w * ((t == q) ? bn : lm[t]);
+            }
+        }
+        double JiT[3][3];
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+            for (int s = 0; s < 3; ++s) JiT[r][s] = M.JiT[(3 * r + s) * Ntot + c];
+        const double om = 1.0 - chi;
+
+        // ---- Gauss-point values: face m = tile u, Gauss point k = g ----------------------------
+#pragma unroll 1
+        for (int u = 0; u < 6; ++u) {
+            v4d y = {0, 0, 0, 0};
+            const double *Au = A2 + (u * 10) * 64;
+#pragma unroll
+            for (int s = 0; s < 10; ++s) y = mfma(Au[s * 64], acc[s >> 2][s & 3], y);
+            const int q = u >> 1;
+            const double xq = (u & 1) ? 0.5 : -0.5;
+            const double x0 = (q == 0) ? xq : ta;
+            const double x1 = (q == 1) ? xq : ((q == 0) ? ta : tb);
+            const double x2 = (q == 2) ? xq : tb;
+            const double val = q0 + chi * y[0] + om * (bbar[0] * x0 + bbar[1] * x1 + bbar[2] * x2);
+            const double r0 = chi * y[1] + om * bbar[0], r1 = chi * y[2] + om * bbar[1], r2 = chi * y[3] + om * bbar[2];
+            long f;
+            int side;
+            if (u & 1) {
+                f = c;
+                side = 0;
+            } else {
+                f = wrap_cell(b, ci - (q == 0), cj - (q == 1), ck - (q == 2));
+                side = 1;
+            }
+            if (valid) {
+                double *dst = gp + ((long)(((q * 2 + side) * 4 + g) * 20 + v * 4)) * Ntot + f;
+                dst[0] = val;
+                dst[Ntot] = JiT[0][0] * r0 + JiT[0][1] * r1 + JiT[0][2] * r2;
+                dst[2 * Ntot] = JiT[1][0] * r0 + JiT[1][1] * r1 + JiT[1][2] * r2;
+                dst[3 * Ntot] = JiT[2][0] * r0 + JiT[2][1] * r1 + JiT[2][2] * r2;
+            }
+        }
+    }
+}
+
+hipError_t launch_recon_mfma(const BlockView &b, long Ntot, const double *Q, const double *G, const double *L,
+                             const Metrics &M, const double *Kblk, const DevParams &P, double *gp, int ngroups,
+                             hipStream_t s) {
+    const long items = ((b.N + 15) / 16) * kNV;
+    long grid = (items + 7) / 8;
+    if (grid > ngroups) grid = ngroups;
+    hipLaunchKernelGGL(k_recon_mfma, dim3((unsigned)grid), dim3(512), 0, s, b, Ntot, Q, G, L, M, Kblk, P, gp);
+    return hipGetLastError();
+}
+
+}  // namespace cgks

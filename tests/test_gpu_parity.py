@@ -1,0 +1,235 @@
+"""GPU parity of the HIP path against the FP64 CPU oracle, through the C ABI.
+
+Bar (FP64 path): relative L2 <= 1e-12 per array after the stated steps; per-point unit
+parity of the flux and the reconstruction at the same tolerance relative to the array scale.
+Inputs are the shared seeded generators; no oracle input comes from the GPU.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_2508_08965_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+GAM = 1.4
+TOL = 1e-12
+
+
+def K():
+    from paper_2508_08965_amd import cgks
+    return cgks
+
+
+def dev():
+    return torch.device("cuda:0")
+
+
+def rel_l2(a, b):
+    a = a.detach().cpu().numpy() if torch.is_tensor(a) else a
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def tgv_both(Ma=0.1, Re=1600.0, Pr=0.72):
+    p0 = 1.0 / (GAM * Ma * Ma)
+    kw = dict(viscous=1, visc_law=1, mu0=1.0 / Re, T_ref=p0, S_suth=p0 * 110.4 / 288.15, Pr=Pr, prandtl_fix=1)
+    return K().default_params(**kw), O.params(**kw)
+
+
+def cons(rho, u, p):
+    return np.array([rho, rho * u[0], rho * u[1], rho * u[2], p / (GAM - 1) + 0.5 * rho * np.dot(u, u)])
+
+
+@pytest.mark.parametrize("mode", ["inviscid", "viscous", "tau_zero"])
+def test_flux_points_parity(mode):
+    rng = np.random.default_rng(31)
+    npts = 777  # several workgroups and a ragged tail
+    ql = np.array([cons(rng.uniform(0.5, 2), rng.uniform(-1, 1, 3), rng.uniform(0.5, 2)) for _ in range(npts)])
+    qr = ql.copy()
+    jump = rng.random(npts) < 0.5  # half continuous, half discontinuous
+    qr[jump] = np.array([cons(rng.uniform(0.5, 2), rng.uniform(-1, 1, 3), rng.uniform(0.5, 2))
+                         for _ in range(int(jump.sum()))])
+    gl = rng.normal(scale=0.5, size=(npts, 5, 3))
+    gr = np.where(jump[:, None, None], rng.normal(scale=0.5, size=(npts, 5, 3)), gl)
+    nrm = rng.normal(size=(npts, 3))
+    nrm /= np.linalg.norm(nrm, axis=1)[:, None]
+    kw = {"inviscid": {}, "tau_zero": dict(tau_zero=1),
+          "viscous": dict(viscous=1, visc_law=1, mu0=0.01, T_ref=1.0, S_suth=0.38, Pr=0.72, prandtl_fix=1)}[mode]
+    dt = 0.013
+    st, F, Ft, S = O.flux(O.params(**kw), ql, gl, qr, gr, nrm, dt)
+    assert st == 0
+    ctx = K().Context([(2, 2, 2)], [W.cartesian_nodes((2, 2, 2))], K().default_params(**kw))
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev())
+    Fd = torch.zeros(npts, 5, dtype=torch.float64, device=dev())
+    Ftd = torch.zeros_like(Fd)
+    Sd = torch.zeros(npts, 4, 5, dtype=torch.float64, device=dev())
+    K().cgks_flux(ctx, t(ql), t(gl), t(qr), t(gr), t(nrm), t(np.array([dt])), Fd, Ftd, Sd)
+    torch.cuda.synchronize()
+    assert K().cgks_check(ctx) == (0, 0)
+    for a, b in ((Fd, F), (Ftd, Ft), (Sd, S)):
+        a = a.cpu().numpy()
+        assert np.abs(a - b).max() <= TOL * np.abs(b).max(), np.abs(a - b).max() / np.abs(b).max()
+    ctx.close()
+
+
+def test_metrics_parity():
+    n = (13, 11, 9)
+    nodes = W.perturbed_nodes(n, amp=0.05)
+    om = O.metrics(n, nodes.numpy())
+    ctx = K().Context([n], [nodes], K().default_params())
+    N = ctx.ncells
+    vol = torch.zeros(N, dtype=torch.float64, device=dev())
+    J0 = torch.zeros(9, N, dtype=torch.float64, device=dev())
+    fn = torch.zeros(3, 4, 3, N, dtype=torch.float64, device=dev())
+    fw = torch.zeros(3, 4, N, dtype=torch.float64, device=dev())
+    K().cgks_metrics(ctx, vol, J0, fn, fw)
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(vol.cpu().numpy(), om["vol"], rtol=1e-13)
+    np.testing.assert_allclose(J0.cpu().numpy().T.reshape(N, 3, 3), om["J0"], rtol=1e-13, atol=1e-15)
+    np.testing.assert_allclose(fn.cpu().numpy().transpose(3, 0, 1, 2), om["fn"], rtol=1e-13, atol=1e-14)
+    np.testing.assert_allclose(fw.cpu().numpy().transpose(2, 0, 1), om["fw"], rtol=1e-13)
+    ctx.close()
+
+
+@pytest.mark.parametrize("impl", [0, 1], ids=["mfma", "valu"])
+@pytest.mark.parametrize("linear", [0, 1])
+def test_reconstruction_parity_curvilinear(linear, impl):
+    n = (17, 12, 10)  # 2040 cells: several workgroups and a ragged tail
+    nodes = W.perturbed_nodes(n, amp=0.05)
+    Q, G, L = W.initial_state(nodes, W.taylor_green(Ma=0.3), GAM)
+    prm_g = K().default_params(linear=linear, recon_impl=impl)
+    prm_o = O.params(linear=linear)
+    cells = np.arange(Q.shape[1])
+    ref = O.recon(n, nodes.numpy(), prm_o, Q.numpy(), G.numpy(), L.numpy(), cells)
+    ctx = K().Context([n], [nodes], prm_g)
+    gp = torch.zeros(Q.shape[1], 24, 5, 4, dtype=torch.float64, device=dev())
+    K().cgks_recon(ctx, Q.to(dev()), G.to(dev()), L.to(dev()), gp)
+    torch.cuda.synchronize()
+    out = gp.cpu().numpy()
+    for v in range(5):
+        for c in range(4):
+            scale = max(np.abs(ref[:, :, v, c]).max(), 1e-300)
+            assert np.abs(out[:, :, v, c] - ref[:, :, v, c]).max() <= TOL * scale, (v, c)
+    ctx.close()
+
+
+def _run_gpu(n, nodes, prm, Q, G, L, nsteps, dt=None):
+    ctx = K().Context([n], [nodes], prm)
+    Qd, Gd, Ld = Q.clone().to(dev()), G.clone().to(dev()), L.clone().to(dev())
+    dtd = torch.zeros(1, dtype=torch.float64, device=dev())
+    if dt is not None:
+        dtd.fill_(dt)
+    dts = []
+    for _ in range(nsteps):
+        K().cgks_step(ctx, Qd, Gd, Ld, dtd, use_cfl=dt is None)
+        dts.append(dtd.item())
+    torch.cuda.synchronize()
+    st = K().cgks_check(ctx)
+    ctx.close()
+    return st, Qd, Gd, Ld, dts
+
+
+def test_density_wave_2d_ten_steps():
+    """2D Euler density wave, 40x40, tau = 0, nonlinear CGKS-5, CFL 0.5, 10 S2O4 steps."""
+    N = 40
+    h = 2.0 / N
+    n = (N, N, 1)
+    nodes = W.cartesian_nodes(n, (0, 0, 0), (2, 2, h))
+    Q, G, L = W.initial_state(nodes, W.density_wave(dim=2), GAM)
+    st, Qd, Gd, Ld, dts = _run_gpu(n, nodes, K().default_params(tau_zero=1), Q, G, L, 10)
+    assert st == (0, 0)
+    sto, Qo, Go, Lo, dto, t = O.run(n, nodes.numpy(), O.params(tau_zero=1), Q.numpy(), G.numpy(), L.numpy(), 10)
+    assert sto == 0
+    assert dts[-1] == pytest.approx(dto, rel=1e-13)
+    assert rel_l2(Qd, Qo) <= TOL and rel_l2(Gd, Go) <= TOL and rel_l2(Ld, Lo) <= TOL
+
+
+def test_tgv_curvilinear_parity():
+    """Navier-Stokes TGV (Re 1600, Ma 0.1, Pr 0.72, Sutherland) on the perturbed curvilinear mesh."""
+    n = (20, 18, 16)  # 5760 cells
+    nodes = W.perturbed_nodes(n, amp=0.05)
+    Q, G, L = W.initial_state(nodes, W.taylor_green(Ma=0.1), GAM)
+    pg, po = tgv_both()
+    st, Qd, Gd, Ld, dts = _run_gpu(n, nodes, pg, Q, G, L, 6)
+    assert st == (0, 0)
+    sto, Qo, Go, Lo, dto, t = O.run(n, nodes.numpy(), po, Q.numpy(), G.numpy(), L.numpy(), 6)
+    assert sto == 0
+    for a, b in ((Qd, Qo), (Gd, Go), (Ld, Lo)):
+        assert rel_l2(a, b) <= TOL, rel_l2(a, b)
+
+
+def test_double_sod_inviscid_parity():
+    """Discontinuous data: inviscid collision time, nonlinear blend active."""
+    N = 64
+    h = 1.0 / N
+    n = (N, 1, 1)
+    nodes = W.cartesian_nodes(n, (0, 0, 0), (1.0, h, h))
+    Q, G, L = W.initial_state(nodes, W.double_sod(), GAM)
+    st, Qd, Gd, Ld, dts = _run_gpu(n, nodes, K().default_params(), Q, G, L, 8)
+    assert st == (0, 0)
+    sto, Qo, Go, Lo, dto, t = O.run(n, nodes.numpy(), O.params(), Q.numpy(), G.numpy(), L.numpy(), 8)
+    assert sto == 0
+    for a, b in ((Qd, Qo), (Gd, Go), (Ld, Lo)):
+        assert rel_l2(a, b) <= TOL, rel_l2(a, b)
+
+
+def test_free_stream_and_conservation_128():
+    """Properties at the 128^3 curvilinear TGV size: free stream stays uniform; mass is conserved."""
+    n = (128, 128, 128)
+    nodes = W.perturbed_nodes(n, amp=0.05, device=dev())
+    pg, _ = tgv_both()
+    Q, G, L = W.initial_state(nodes, W.uniform(1.0, 0.5, 0.3, 0.2, 71.43), GAM)
+    st, Qd, Gd, Ld, dts = _run_gpu(n, nodes.cpu(), pg, Q, G, L, 2)
+    assert st == (0, 0)
+    for v in range(5):
+        assert (Qd[v] - Q[v].to(dev())).abs().max().item() <= 1e-12 * Q[v].abs().max().item()
+    del Qd, Gd, Ld
+    Q, G, L = W.initial_state(nodes, W.taylor_green(Ma=0.1), GAM)
+    ctx = K().Context([n], [nodes.cpu()], pg)
+    vol = torch.zeros(ctx.ncells, dtype=torch.float64, device=dev())
+    K().cgks_metrics(ctx, vol=vol)
+    m0 = (vol[None] * Q).sum(dim=1)
+    dtd = torch.zeros(1, dtype=torch.float64, device=dev())
+    for _ in range(2):
+        K().cgks_step(ctx, Q, G, L, dtd, use_cfl=True)
+    m1 = (vol[None] * Q).sum(dim=1)
+    scale = (vol[None] * Q.abs()).sum(dim=1).clamp(min=(vol * Q[0]).sum().item())
+    assert ((m1 - m0).abs() / scale).max().item() <= 1e-13
+    assert K().cgks_check(ctx) == (0, 0)
+    ctx.close()
+
+
+def test_bitwise_determinism():
+    n = (24, 20, 18)
+    nodes = W.perturbed_nodes(n, amp=0.05)
+    Q, G, L = W.initial_state(nodes, W.taylor_green(Ma=0.3), GAM)
+    pg, _ = tgv_both(Ma=0.3)
+    a = _run_gpu(n, nodes, pg, Q, G, L, 3)
+    b = _run_gpu(n, nodes, pg, Q, G, L, 3)
+    for x, y in zip(a[1:4], b[1:4]):
+        assert torch.equal(x, y)
+
+
+def test_nonphysical_state_flagged():
+    n = (8, 8, 8)
+    nodes = W.cartesian_nodes(n)
+    Q, G, L = W.initial_state(nodes, W.uniform(1.0, 0.1, 0.0, 0.0, 1.0), GAM)
+    Q[4, 100] = 0.0  # zero internal energy: non-physical
+    st, *_ = _run_gpu(n, nodes, K().default_params(), Q, G, L, 1, dt=1e-3)
+    assert st[0] == K().ENONPHYS and st[1] != 0
+
+
+def test_invalid_arguments_rejected():
+    with pytest.raises(RuntimeError):
+        K().Context([(0, 4, 4)], [W.cartesian_nodes((1, 4, 4))], K().default_params())
+    ctx = K().Context([(4, 4, 4)], [W.cartesian_nodes((4, 4, 4))], K().default_params())
+    z = torch.zeros(5, 64, dtype=torch.float64, device=dev())
+    with pytest.raises(RuntimeError):
+        K().cgks_stage(ctx, 2, torch.zeros(1, dtype=torch.float64, device=dev()), z, z, z)  # stage 2 first
+    with pytest.raises(RuntimeError):
+        K().cgks_stage(ctx, 3, torch.zeros(1, dtype=torch.float64, device=dev()), z, z, z)
+    ctx.close()

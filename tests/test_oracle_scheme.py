@@ -243,3 +243,21 @@ def test_taylor_green_initial_dissipation_rate():
     assert es[0] == pytest.approx(0.125 * sinc ** 6, rel=1e-3)
     # relative decay rate (dE_k/dt)/E_k = -nu <|omega|^2> / (<|U|^2>/2) = -6/Re
     assert slope / es[0] == pytest.approx(-6.0 / 1600.0, rel=0.03)
+
+
+def test_sampled_stage1_equals_full_stage():
+    """The per-cell stage-1 entry (used for parity at full size) reproduces the full stage bitwise."""
+    n = (9, 7, 6)
+    nodes = W.perturbed_nodes(n, amp=0.05)
+    Q, G, L = W.initial_state(nodes, W.taylor_green(Ma=0.3), GAM)
+    prm = tgv_params(Ma=0.3)
+    dt = 0.7 * O.cfl_dt(n, nodes.numpy(), prm, Q.numpy())
+    Qa, Ga, La = Q.numpy().copy(), G.numpy().copy(), L.numpy().copy()
+    stash = np.zeros((90, Qa.shape[1]))
+    assert O.stage(n, nodes.numpy(), prm, 1, dt, Qa, Ga, La, stash) == 0
+    cells = np.array([0, 5, 62, 63, 200, Qa.shape[1] - 1])
+    st, oq, og, ol = O.stage1_cells(n, nodes.numpy(), prm, dt, Q.numpy(), G.numpy(), L.numpy(), cells)
+    assert st == 0
+    assert np.array_equal(oq, Qa[:, cells].T)
+    assert np.array_equal(og, Ga[:, :, cells].transpose(2, 0, 1))
+    assert np.array_equal(ol, La[:, :, cells].transpose(2, 0, 1))
