@@ -70,8 +70,11 @@ typedef struct {
     int tau_zero;        /* 1: tau = 0, f = g0 (1 + A t) (accuracy test of Sec. 5.1)        */
     int linear;          /* 1: chi = 1 (linear CGKS-5)                                      */
     int prandtl_fix;     /* 1: heat-flux correction to Pr (viscous mode only)               */
-    int recon_prec;      /* reconstruction arithmetic: 0 FP64                               */
-    int flux_prec;       /* flux arithmetic: 0 FP64                                         */
+    int recon_prec;      /* reconstruction contractions: 0 FP64 matrix cores; 1 FP32x3 split
+                            precision on the FP32 matrix cores (FP32 accumulation)          */
+    int flux_prec;       /* gas-kinetic flux arithmetic: 0 FP64, 1 FP32.  Either reduced
+                            option stores Gauss-point data in FP32; metrics, the time step
+                            and the S2O4 accumulation of Q, G, L stay FP64                  */
     int recon_impl;      /* reconstruction kernel: 0 matrix cores (MFMA, default),
                             1 vector-ALU kernel (one thread per cell and variable)          */
 } cgks_params;

@@ -854,6 +854,10 @@ static void cell_update(int stage, double dt, double vol, const face_rec *const 
     double Lf[5] = {0}, Lt[5] = {0}, Gq[5][3] = {{0}}, Gt[5][3] = {{0}};
     double ownq[6][4][5], ownt[6][4][5];
     (void)G; (void)L;
+    /* Gauss's theorem on the closed cell surface: the integral of (Q - Qbar) n equals that of
+       Q n; subtracting the cell average avoids cancelling O(Q) surface terms */
+    double qbar[5];
+    for (int v = 0; v < 5; ++v) qbar[v] = Q[v * N + c];
     for (int m = 0; m < 6; ++m) {
         double sg = (m % 2) ? 1.0 : -1.0;
         int sq = (m % 2) ? 0 : 2; /* own side: left of its plus face, right of its minus face */
@@ -865,7 +869,7 @@ static void cell_update(int stage, double dt, double vol, const face_rec *const 
                 Lt[v] -= sg * w * fs[m]->Ft[g][v];
                 double qs = fs[m]->side[g][sq][v], qt = fs[m]->side[g][sq + 1][v];
                 ownq[m][g][v] = qs; ownt[m][g][v] = qt;
-                for (int r = 0; r < 3; ++r) { Gq[v][r] += sg * w * nn[r] * qs; Gt[v][r] += sg * w * nn[r] * qt; }
+                for (int r = 0; r < 3; ++r) { Gq[v][r] += sg * w * nn[r] * (qs - qbar[v]); Gt[v][r] += sg * w * nn[r] * qt; }
             }
         }
     }

@@ -124,15 +124,24 @@ static int check_params(const cgks_params *p) {
     if (p->viscous && !(p->mu0 > 0.0)) return fail(CGKS_EINVAL, "viscous mode needs mu0 > 0");
     if (p->visc_law && (!(p->T_ref > 0.0) || !(p->S_suth >= 0.0))) return fail(CGKS_EINVAL, "Sutherland needs T_ref > 0, S >= 0");
     if (p->prandtl_fix && !(p->Pr > 0.0)) return fail(CGKS_EINVAL, "Pr must be positive");
-    if (p->recon_prec != 0 || p->flux_prec != 0) return fail(CGKS_EUNSUPPORTED, "only FP64 arithmetic is available");
+    if (p->recon_prec < 0 || p->recon_prec > 1) return fail(CGKS_EUNSUPPORTED, "recon_prec must be 0 (FP64) or 1 (FP32x3)");
+    if (p->flux_prec < 0 || p->flux_prec > 1) return fail(CGKS_EUNSUPPORTED, "flux_prec must be 0 (FP64) or 1 (FP32)");
     if (p->recon_impl != 0 && p->recon_impl != 1) return fail(CGKS_EINVAL, "recon_impl must be 0 or 1");
+    if (p->recon_impl == 1 && (p->recon_prec != 0 || p->flux_prec != 0))
+        return fail(CGKS_EUNSUPPORTED, "the vector-ALU reconstruction is FP64 only");
     return CGKS_OK;
 }
+
+// Gauss-point buffer in FP32 whenever the reconstruction or the flux runs in reduced precision;
+// face buffer in FP32 when the flux does.  The state and the S2O4 accumulation stay FP64.
+static bool gp32(const cgks_ctx *c) { return c->user.recon_prec != 0 || c->user.flux_prec != 0; }
+static bool fo32(const cgks_ctx *c) { return c->user.flux_prec != 0; }
 
 static hipError_t run_recon(cgks_ctx *ctx, const BlockView &b, const double *Q, const double *G, const double *L,
                             hipStream_t s) {
     if (ctx->user.recon_impl == 1) return launch_recon(b, ctx->Ntot, Q, G, L, ctx->M, ctx->K, ctx->P, ctx->gp, s);
-    return launch_recon_mfma(b, ctx->Ntot, Q, G, L, ctx->M, ctx->Kmf, ctx->P, ctx->gp, ctx->ngroups, s);
+    return launch_recon_mfma(ctx->user.recon_prec, gp32(ctx), b, ctx->Ntot, Q, G, L, ctx->M, ctx->Kmf, ctx->P, ctx->gp,
+                             ctx->ngroups, s);
 }
 
 extern "C" {
@@ -236,7 +245,7 @@ int cgks_ctx_create(cgks_ctx **out, int nblocks, const int *dims, const double *
     std::memcpy(dk.GT, hk->GT, sizeof dk.GT);
     std::memcpy(dk.xg, hk->xg, sizeof dk.xg);
     std::vector<double> kmf(kMfmaBlocks * 64);
-    const bool packed = pack_mfma_f64(*hk, kmf.data());
+    const bool packed = pack_mfma(*hk, kmf.data(), p->recon_prec == 0);
     delete hk;
     if (!packed) {
         cgks_ctx_destroy(c);
@@ -304,11 +313,14 @@ int cgks_stage(cgks_ctx *ctx, int stage, const double *dt_dev, double *Q, double
         }
         {
             Timed t(ctx, s, 2);
-            HIP_TRY(launch_flux(b, ctx->Ntot, ctx->gp, ctx->M, dt_dev, ctx->P, ctx->fo, ctx->flag, s), "flux");
+            HIP_TRY(launch_flux(ctx->user.flux_prec, gp32(ctx), b, ctx->Ntot, ctx->gp, ctx->M, dt_dev, ctx->P, ctx->fo,
+                                ctx->flag, s),
+                    "flux");
         }
         {
             Timed t(ctx, s, 3);
-            HIP_TRY(launch_update(stage, b, ctx->Ntot, ctx->fo, ctx->M, dt_dev, Q, G, L, ctx->stash, s), "update");
+            HIP_TRY(launch_update(stage, fo32(ctx), b, ctx->Ntot, ctx->fo, ctx->M, dt_dev, Q, G, L, ctx->stash, s),
+                    "update");
         }
     }
     ctx->stage1_done = (stage == 1);
@@ -342,7 +354,7 @@ int cgks_recon(cgks_ctx *ctx, const double *Q, const double *G, const double *L,
     ctx->last = s;
     for (const BlockView &b : ctx->blocks) {
         HIP_TRY(run_recon(ctx, b, Q, G, L, s), "recon");
-        HIP_TRY(launch_gp_export(b, ctx->Ntot, ctx->gp, gp, s), "export");
+        HIP_TRY(launch_gp_export(gp32(ctx), b, ctx->Ntot, ctx->gp, gp, s), "export");
     }
     return CGKS_OK;
 }
@@ -354,7 +366,8 @@ int cgks_flux(cgks_ctx *ctx, long n, const double *ql, const double *gl, const d
     if (n == 0) return CGKS_OK;
     hipStream_t s = (hipStream_t)stream;
     ctx->last = s;
-    HIP_TRY(launch_flux_points(n, ql, gl, qr, gr, nrm, dt_dev, ctx->P, F, Ft, sides, ctx->flag, s), "flux points");
+    HIP_TRY(launch_flux_points(ctx->user.flux_prec, n, ql, gl, qr, gr, nrm, dt_dev, ctx->P, F, Ft, sides, ctx->flag, s),
+            "flux points");
     return CGKS_OK;
 }
 

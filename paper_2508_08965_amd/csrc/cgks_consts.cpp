@@ -325,13 +325,18 @@ int mfma_item(int k) {
     return kRowLine + 4 * (s - 15) + g;
 }
 
-// row of the quartic coefficient vector held in register v of GEMM1 tile t by lane group g,
-// i.e. the contraction index 4s'+g of the follow-up products, s' = 4t+v
-int mfma_arow(int sp, int g) { return 16 * (sp / 4) + 4 * g + (sp % 4); }
+// Output layout of the 16x16x4 instructions: register v of lane l holds row
+//   f32: 4 (l/16) + v          f64: 4 v + l/16          (column l % 16 in both).
+// Row of the quartic coefficient vector held in register v of GEMM1 tile t by lane group g,
+// i.e. the contraction index 4s'+g of the follow-up products, s' = 4t+v.
+int mfma_arow(int sp, int g, bool f64) {
+    const int t = sp / 4, v = sp % 4;
+    return 16 * t + (f64 ? 4 * v + g : 4 * g + v);
+}
 
 }  // namespace
 
-bool pack_mfma_f64(const HostConsts &K, double *blk) {
+bool pack_mfma(const HostConsts &K, double *blk, bool f64) {
     // Cholesky factors of the Gram matrices: IS^L = |L_L^T a|^2 over all 34 coefficients,
     // IS^tau = |L_T^T a_s|^2 over the 31 coefficients of degree >= 2 (indices 3..33)
     std::vector<double> gl(kNB * kNB), ll(kNB * kNB), gt(31 * 31), lt(31 * 31);
@@ -349,7 +354,7 @@ bool pack_mfma_f64(const HostConsts &K, double *blk) {
                 blk[(kMfmaOffA1 + t * 18 + s) * 64 + l] = (i < kNB) ? K.R[i][mfma_item(4 * s + g)] : 0.0;
             }
         for (int s = 0; s < 10; ++s) {
-            const int ar = mfma_arow(s, g);
+            const int ar = mfma_arow(s, g, f64);
             for (int u = 0; u < 3; ++u) {
                 const int i = 16 * u + row;  // row of L_L^T
                 blk[(kMfmaOffAL + u * 10 + s) * 64 + l] = (i < kNB && ar < kNB) ? ll[ar * kNB + i] : 0.0;
@@ -359,7 +364,8 @@ bool pack_mfma_f64(const HostConsts &K, double *blk) {
                 blk[(kMfmaOffAT + u * 10 + s) * 64 + l] = (i < 31 && ar >= 3 && ar < kNB) ? lt[(ar - 3) * 31 + i] : 0.0;
             }
             for (int u = 0; u < 6; ++u) {
-                const int gpl = row / 4, comp = row % 4;  // output row = 4 * Gauss point + component
+                // output rows of a tile: lane group = Gauss point, register = component
+                const int gpl = f64 ? row % 4 : row / 4, comp = f64 ? row / 4 : row % 4;
                 blk[(kMfmaOffA2 + u * 10 + s) * 64 + l] = (ar < kNB) ? K.E[4 * u + gpl][comp][ar] : 0.0;
             }
         }

@@ -50,11 +50,12 @@ struct HostConsts {
 
 void build_constants(HostConsts &K);
 
-// Constant blocks of the matrix-core reconstruction (f64 16x16x4), 64 doubles per block in
-// the per-lane order the instruction reads: R (3 tiles x 18 k-steps), L_L^T (3 x 10),
-// L_T^T (2 x 10), E (6 x 10).
+// Constant blocks of the matrix-core reconstruction (16x16x4 instructions), 64 values per
+// block in the per-lane order the instruction reads: R (3 tiles x 18 k-steps), L_L^T (3 x 10),
+// L_T^T (2 x 10), E (6 x 10).  f64 selects the output layout of the FP64 instruction
+// (register v of lane l holds row 4v + l/16), otherwise that of the FP32 one (row 4(l/16) + v).
 constexpr int kMfmaOffA1 = 0, kMfmaOffAL = 54, kMfmaOffAT = 84, kMfmaOffA2 = 104, kMfmaBlocks = 164;
-bool pack_mfma_f64(const HostConsts &K, double *blocks);
+bool pack_mfma(const HostConsts &K, double *blocks, bool f64);
 
 // Scheme parameters in the form the kernels read them.
 struct DevParams {

@@ -152,7 +152,7 @@ __global__ void __launch_bounds__(256) k_metrics(BlockView b, const double *__re
 // ------------------------------------------------------------------------------------------
 // time step
 // ------------------------------------------------------------------------------------------
-__device__ inline double viscosity(const DevParams &P, double T) {
+__device__ inline double viscosity_dt(const DevParams &P, double T) {
     if (!P.visc_law) return P.mu0;
     double r = T / P.T_ref;
     return P.mu0 * r * sqrt(r) * (P.T_ref + P.S_suth) / (T + P.S_suth);
@@ -196,7 +196,7 @@ __global__ void __launch_bounds__(256) k_dt_partial(long off, long N, long Ntot,
         }
         double d = P.cfl / rate;
         if (P.viscous) {
-            double nu = viscosity(P, p / rho) / rho;
+            double nu = viscosity_dt(P, p / rho) / rho;
             d = fmin(d, P.cfl / (ihmax * ihmax * 3.0 * nu));
         }
         best = fmin(best, d);
@@ -372,7 +372,8 @@ __global__ void __launch_bounds__(256) k_recon(BlockView b, long Ntot, const dou
 }
 
 // copy of the Gauss-point buffer into the per-cell export layout [c][24][5][4]
-__global__ void __launch_bounds__(256) k_gp_export(BlockView b, long Ntot, const double *__restrict__ gp,
+template <class TG>
+__global__ void __launch_bounds__(256) k_gp_export(BlockView b, long Ntot, const TG *__restrict__ gp,
                                                    double *__restrict__ out) {
     long cl = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (cl >= b.N) return;
@@ -393,7 +394,7 @@ __global__ void __launch_bounds__(256) k_gp_export(BlockView b, long Ntot, const
         }
         for (int v = 0; v < 5; ++v)
             for (int r = 0; r < 4; ++r)
-                out[((c * kNGP + g) * 5 + v) * 4 + r] = gp[((long)(((q * 2 + side) * 4 + kk) * 20 + v * 4 + r)) * Ntot + f];
+                out[((c * kNGP + g) * 5 + v) * 4 + r] = (double)gp[((long)(((q * 2 + side) * 4 + kk) * 20 + v * 4 + r)) * Ntot + f];
     }
 }
 
@@ -401,40 +402,42 @@ __global__ void __launch_bounds__(256) k_gp_export(BlockView b, long Ntot, const
 // gas-kinetic flux kernels
 // ------------------------------------------------------------------------------------------
 // Two lanes per Gauss point: thread t -> face record f = t / 2 of the block, side t & 1.
-__global__ void __launch_bounds__(256, 2) k_flux(BlockView b, long Ntot, const double *__restrict__ gp, Metrics M,
+template <class TC, class TG, class TF>
+__global__ void __launch_bounds__(256, 2) k_flux(BlockView b, long Ntot, const TG *__restrict__ gp, Metrics M,
                                               const double *__restrict__ dtp, DevParams P,
-                                              double *__restrict__ fo, int *__restrict__ flag) {
+                                              TF *__restrict__ fo, int *__restrict__ flag) {
     const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
     const long cl = t >> 1;
     if (cl >= b.N) return;  // both lanes of a pair leave together
     const int sd = (int)(t & 1);
     const int q = blockIdx.y >> 2, kk = blockIdx.y & 3;
     const long f = b.off + cl;
-    double qv[5], gv[5][3], n[3];
-    const double *src = gp + (long)(((q * 2 + sd) * 4 + kk) * 20) * Ntot + f;
+    TC qv[5], gv[5][3], n[3];
+    const TG *src = gp + (long)(((q * 2 + sd) * 4 + kk) * 20) * Ntot + f;
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
-        qv[v] = src[(4 * v) * Ntot];
+        qv[v] = (TC)src[(4 * v) * Ntot];
 #pragma unroll
-        for (int j = 0; j < 3; ++j) gv[v][j] = src[(4 * v + 1 + j) * Ntot];
+        for (int j = 0; j < 3; ++j) gv[v][j] = (TC)src[(4 * v + 1 + j) * Ntot];
     }
 #pragma unroll
-    for (int r = 0; r < 3; ++r) n[r] = M.fn[((q * 4 + kk) * 3 + r) * Ntot + f];
-    double F[5], Ft[5], Qs[5], dQs[5];
-    const int bad = gks_flux_pair(P, sd, qv, gv, n, *dtp, F, Ft, Qs, dQs);
+    for (int r = 0; r < 3; ++r) n[r] = (TC)M.fn[((q * 4 + kk) * 3 + r) * Ntot + f];
+    TC F[5], Ft[5], Qs[5], dQs[5];
+    const int bad = gks_flux_pair<DevMath, TC>(P, sd, qv, gv, n, (TC)*dtp, F, Ft, Qs, dQs);
     if (bad && sd == 0) atomicOr(flag, bad);
-    double *dst = fo + (long)((q * 4 + kk) * 30) * Ntot + f;
+    TF *dst = fo + (long)((q * 4 + kk) * 30) * Ntot + f;
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
-        dst[(10 + 10 * sd + v) * Ntot] = Qs[v];
-        dst[(15 + 10 * sd + v) * Ntot] = dQs[v];
+        dst[(10 + 10 * sd + v) * Ntot] = (TF)Qs[v];
+        dst[(15 + 10 * sd + v) * Ntot] = (TF)dQs[v];
         if (sd) {
-            dst[v * Ntot] = F[v];
-            dst[(5 + v) * Ntot] = Ft[v];
+            dst[v * Ntot] = (TF)F[v];
+            dst[(5 + v) * Ntot] = (TF)Ft[v];
         }
     }
 }
 
+template <class TC>
 __global__ void __launch_bounds__(256) k_flux_points(long n, const double *__restrict__ ql_, const double *__restrict__ gl_,
                                                      const double *__restrict__ qr_, const double *__restrict__ gr_,
                                                      const double *__restrict__ nrm, const double *__restrict__ dtp,
@@ -446,14 +449,14 @@ __global__ void __launch_bounds__(256) k_flux_points(long n, const double *__res
     const int sd = (int)(t & 1);
     const double *q_ = sd ? qr_ : ql_;
     const double *g_ = sd ? gr_ : gl_;
-    double qv[5], gv[5][3], nn[3];
+    TC qv[5], gv[5][3], nn[3];
     for (int v = 0; v < 5; ++v) {
-        qv[v] = q_[5 * i + v];
-        for (int j = 0; j < 3; ++j) gv[v][j] = g_[15 * i + 3 * v + j];
+        qv[v] = (TC)q_[5 * i + v];
+        for (int j = 0; j < 3; ++j) gv[v][j] = (TC)g_[15 * i + 3 * v + j];
     }
-    for (int r = 0; r < 3; ++r) nn[r] = nrm[3 * i + r];
-    double F[5], Ft[5], Qs[5], dQs[5];
-    const int bad = gks_flux_pair(P, sd, qv, gv, nn, *dtp, F, Ft, Qs, dQs);
+    for (int r = 0; r < 3; ++r) nn[r] = (TC)nrm[3 * i + r];
+    TC F[5], Ft[5], Qs[5], dQs[5];
+    const int bad = gks_flux_pair<DevMath, TC>(P, sd, qv, gv, nn, (TC)*dtp, F, Ft, Qs, dQs);
     if (bad && sd == 0) atomicOr(flag, bad);
     for (int v = 0; v < 5; ++v) {
         S_[20 * i + 10 * sd + v] = Qs[v];
@@ -469,8 +472,8 @@ __global__ void __launch_bounds__(256) k_flux_points(long n, const double *__res
 // accumulation + S2O4 stage update: one thread per cell
 // stash [80][Ntot]: Qpre (5) = Q^n + dt L^n + dt^2/6 L_t^n, Gb (15), Lb (60)
 // ------------------------------------------------------------------------------------------
-template <int STAGE>
-__global__ void __launch_bounds__(256) k_update(BlockView b, long Ntot, const double *__restrict__ fo, Metrics M,
+template <int STAGE, class TF>
+__global__ void __launch_bounds__(256) k_update(BlockView b, long Ntot, const TF *__restrict__ fo, Metrics M,
                                                 const double *__restrict__ dtp, double *__restrict__ Q,
                                                 double *__restrict__ G, double *__restrict__ L,
                                                 double *__restrict__ stash) {
@@ -493,8 +496,8 @@ __global__ void __launch_bounds__(256) k_update(BlockView b, long Ntot, const do
         const long fm = cell_at(b, id.i + o[0], id.j + o[1], id.k + o[2]);
 #pragma unroll 1
         for (int kk = 0; kk < 4; ++kk) {
-            const double *Dp = fo + (long)((q * 4 + kk) * 30) * Ntot + c;   // plus face: this cell is left
-            const double *Dm = fo + (long)((q * 4 + kk) * 30) * Ntot + fm;  // minus face: this cell is right
+            const TF *Dp = fo + (long)((q * 4 + kk) * 30) * Ntot + c;   // plus face: this cell is left
+            const TF *Dm = fo + (long)((q * 4 + kk) * 30) * Ntot + fm;  // minus face: this cell is right
             const double wp = M.fw[(q * 4 + kk) * Ntot + c], wm = M.fw[(q * 4 + kk) * Ntot + fm];
             double np_[3], nm_[3];
 #pragma unroll
@@ -506,17 +509,19 @@ __global__ void __launch_bounds__(256) k_update(BlockView b, long Ntot, const do
 #pragma unroll
             for (int v = 0; v < 5; ++v) {
                 if (STAGE == 1) {
-                    Lf[v] += wm * Dm[v * Ntot] - wp * Dp[v * Ntot];
+                    Lf[v] += wm * (double)Dm[v * Ntot] - wp * (double)Dp[v * Ntot];
                 }
-                Lt[v] += wm * Dm[(5 + v) * Ntot] - wp * Dp[(5 + v) * Ntot];
-                const double dqp = Dp[(15 + v) * Ntot], dqm = Dm[(25 + v) * Ntot];
+                Lt[v] += wm * (double)Dm[(5 + v) * Ntot] - wp * (double)Dp[(5 + v) * Ntot];
+                const double dqp = (double)Dp[(15 + v) * Ntot], dqm = (double)Dm[(25 + v) * Ntot];
 #pragma unroll
                 for (int r = 0; r < 3; ++r) Gt[v][r] += wp * np_[r] * dqp - wm * nm_[r] * dqm;
                 const double lt = dqp - dqm;
                 if (STAGE == 1) {
-                    const double qp = Dp[(10 + v) * Ntot], qm = Dm[(20 + v) * Ntot];
+                    const double qp = (double)Dp[(10 + v) * Ntot], qm = (double)Dm[(20 + v) * Ntot];
+                    // Gauss's theorem on the closed cell surface with the cell average removed
+                    const double qb = Q[v * Ntot + c];
 #pragma unroll
-                    for (int r = 0; r < 3; ++r) Gq[v][r] += wp * np_[r] * qp - wm * nm_[r] * qm;
+                    for (int r = 0; r < 3; ++r) Gq[v][r] += wp * np_[r] * (qp - qb) - wm * nm_[r] * (qm - qb);
                     const double lb = qp - qm;
                     stash[(20 + 12 * v + s) * Ntot + c] = lb;
                     L[(12 * v + s) * Ntot + c] = lb + 0.5 * dt * lt;
@@ -572,34 +577,55 @@ hipError_t launch_recon(const BlockView &b, long Ntot, const double *Q, const do
     return hipGetLastError();
 }
 
-hipError_t launch_gp_export(const BlockView &b, long Ntot, const double *gp, double *out, hipStream_t s) {
+hipError_t launch_gp_export(bool gp32, const BlockView &b, long Ntot, const void *gp, double *out, hipStream_t s) {
     dim3 grid((unsigned)((b.N + 255) / 256));
-    hipLaunchKernelGGL(k_gp_export, grid, dim3(256), 0, s, b, Ntot, gp, out);
+    if (gp32)
+        hipLaunchKernelGGL(k_gp_export<float>, grid, dim3(256), 0, s, b, Ntot, (const float *)gp, out);
+    else
+        hipLaunchKernelGGL(k_gp_export<double>, grid, dim3(256), 0, s, b, Ntot, (const double *)gp, out);
     return hipGetLastError();
 }
 
-hipError_t launch_flux(const BlockView &b, long Ntot, const double *gp, const Metrics &M, const double *dt,
-                       const DevParams &P, double *fo, int *flag, hipStream_t s) {
+hipError_t launch_flux(int flux_prec, bool gp32, const BlockView &b, long Ntot, const void *gp, const Metrics &M,
+                       const double *dt, const DevParams &P, void *fo, int *flag, hipStream_t s) {
     dim3 grid((unsigned)((2 * b.N + 255) / 256), 12);
-    hipLaunchKernelGGL(k_flux, grid, dim3(256), 0, s, b, Ntot, gp, M, dt, P, fo, flag);
+    if (flux_prec == 0 && !gp32)
+        hipLaunchKernelGGL((k_flux<double, double, double>), grid, dim3(256), 0, s, b, Ntot, (const double *)gp, M, dt, P,
+                           (double *)fo, flag);
+    else if (flux_prec == 0)
+        hipLaunchKernelGGL((k_flux<double, float, double>), grid, dim3(256), 0, s, b, Ntot, (const float *)gp, M, dt, P,
+                           (double *)fo, flag);
+    else
+        hipLaunchKernelGGL((k_flux<float, float, float>), grid, dim3(256), 0, s, b, Ntot, (const float *)gp, M, dt, P,
+                           (float *)fo, flag);
     return hipGetLastError();
 }
 
-hipError_t launch_flux_points(long n, const double *ql, const double *gl, const double *qr, const double *gr,
-                              const double *nrm, const double *dt, const DevParams &P, double *F, double *Ft,
-                              double *S, int *flag, hipStream_t s) {
+hipError_t launch_flux_points(int flux_prec, long n, const double *ql, const double *gl, const double *qr,
+                              const double *gr, const double *nrm, const double *dt, const DevParams &P, double *F,
+                              double *Ft, double *S, int *flag, hipStream_t s) {
     dim3 grid((unsigned)((2 * n + 255) / 256));
-    hipLaunchKernelGGL(k_flux_points, grid, dim3(256), 0, s, n, ql, gl, qr, gr, nrm, dt, P, F, Ft, S, flag);
+    if (flux_prec == 0)
+        hipLaunchKernelGGL(k_flux_points<double>, grid, dim3(256), 0, s, n, ql, gl, qr, gr, nrm, dt, P, F, Ft, S, flag);
+    else
+        hipLaunchKernelGGL(k_flux_points<float>, grid, dim3(256), 0, s, n, ql, gl, qr, gr, nrm, dt, P, F, Ft, S, flag);
     return hipGetLastError();
 }
 
-hipError_t launch_update(int stage, const BlockView &b, long Ntot, const double *fo, const Metrics &M,
+hipError_t launch_update(int stage, bool fo32, const BlockView &b, long Ntot, const void *fo, const Metrics &M,
                          const double *dt, double *Q, double *G, double *L, double *stash, hipStream_t s) {
     dim3 grid((unsigned)((b.N + 255) / 256));
-    if (stage == 1)
-        hipLaunchKernelGGL(k_update<1>, grid, dim3(256), 0, s, b, Ntot, fo, M, dt, Q, G, L, stash);
-    else
-        hipLaunchKernelGGL(k_update<2>, grid, dim3(256), 0, s, b, Ntot, fo, M, dt, Q, G, L, stash);
+    if (fo32) {
+        if (stage == 1)
+            hipLaunchKernelGGL((k_update<1, float>), grid, dim3(256), 0, s, b, Ntot, (const float *)fo, M, dt, Q, G, L, stash);
+        else
+            hipLaunchKernelGGL((k_update<2, float>), grid, dim3(256), 0, s, b, Ntot, (const float *)fo, M, dt, Q, G, L, stash);
+    } else {
+        if (stage == 1)
+            hipLaunchKernelGGL((k_update<1, double>), grid, dim3(256), 0, s, b, Ntot, (const double *)fo, M, dt, Q, G, L, stash);
+        else
+            hipLaunchKernelGGL((k_update<2, double>), grid, dim3(256), 0, s, b, Ntot, (const double *)fo, M, dt, Q, G, L, stash);
+    }
     return hipGetLastError();
 }
 

@@ -9,17 +9,17 @@
 //   GEMM2  y  = E a            E: 96 x 34, point value and reference gradient at the 24 face
 //                              Gauss points
 // One wavefront owns 16 columns (16 cells of one conserved variable).  Operand layouts of the
-// f64 16x16x4 instruction: lane l supplies A[l%16][l/16] and B[l/16][l%16] and receives
-// D[4(l/16)+v][l%16], v = 0..3.  Consequences used below:
+// 16x16x4 instructions: lane l supplies A[l%16][l/16] and B[l/16][l%16]; register v of lane l
+// receives D[4v + l/16][l%16] (FP64) or D[4(l/16) + v][l%16] (FP32).  Consequences used below:
 //   * the stencil item of k-step s and lane group g = l/16 is item perm(4s+g); the k-steps are
 //     ordered so that the four lane groups of a step do the same kind of work (no divergence):
 //     steps 0..5 face neighbour m (g=0 average difference, g=1..3 reference gradient
 //     components), 6..8 edge-neighbour differences (edge 4p+g), 9..14 edge directional
 //     derivatives (tau1, tau2 of edge 4p+g), 15..17 line differences (line 4t+g);
-//   * GEMM1 leaves a[16t+4g+v] in register v of tile t, which is fed back unchanged as the
-//     B operand of the next contractions (their k order is permuted to match on the host);
-//   * GEMM2 rows are ordered Gauss-point-major (value, d/dxi, d/deta, d/dzeta), so each lane
-//     receives one Gauss point's value and reference gradient: blend and back-transform with
+//   * GEMM1 leaves one coefficient of a in register v of tile t, which is fed back unchanged as
+//     the B operand of the next contractions (their k order is permuted to match on the host);
+//   * GEMM2 rows are ordered so that lane group g receives Gauss point g of the tile's face and
+//     register v component v (value, d/dxi, d/deta, d/dzeta): blend and back-transform with
 //     (J0^T)^-1 stay in the lane.
 // The constant blocks are packed on the host in exactly the per-lane order the instruction
 // reads and staged once per workgroup in LDS.
@@ -30,6 +30,27 @@
 namespace cgks {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+// Arithmetic of the contractions.
+//   PrecF64   : FP64 operands, FP64 accumulation (v_mfma_f64_16x16x4f64)
+//   PrecF32x3 : split precision on the FP32 matrix cores (v_mfma_f32_16x16x4f32, same operand
+//               layout): stencil data b = b_hi + b_lo and constants K = K_hi + K_lo are split
+//               into FP32 pairs; K b ~ K_hi b_hi + K_hi b_lo + K_lo b_hi with FP32
+//               accumulation.  The follow-up products take the FP32 coefficients as they are:
+//               K a ~ K_hi a + K_lo a.
+struct PrecF64 {
+    using T = double;
+    using V = v4d;
+    static constexpr int kSplit = 1;
+    __device__ static V mma(T a, T b, V c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+};
+struct PrecF32x3 {
+    using T = float;
+    using V = v4f;
+    static constexpr int kSplit = 2;
+    __device__ static V mma(T a, T b, V c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+};
 
 namespace {
 
@@ -40,24 +61,53 @@ __device__ inline long wrap_cell(const BlockView &b, int i, int j, int k) {
     return b.off + (long)i + (long)b.nx * ((long)j + (long)b.ny * k);
 }
 
-__device__ inline v4d mfma(double a, double b, v4d c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+// acc += K * x for an FP64 stencil value x (GEMM1 operand)
+template <class PR>
+__device__ inline typename PR::V mac_data(const typename PR::T *Ablk, int blk, double x, typename PR::V acc) {
+    if constexpr (PR::kSplit == 1) {
+        return PR::mma(Ablk[blk * 64], x, acc);
+    } else {
+        const float xh = (float)x, xl = (float)(x - (double)xh);
+        const float kh = Ablk[blk * 64], kl = Ablk[(kMfmaBlocks + blk) * 64];
+        acc = PR::mma(kh, xh, acc);
+        acc = PR::mma(kh, xl, acc);
+        return PR::mma(kl, xh, acc);
+    }
+}
+// acc += K * a for a coefficient a already in the working precision
+template <class PR>
+__device__ inline typename PR::V mac_coef(const typename PR::T *Ablk, int blk, typename PR::T a, typename PR::V acc) {
+    if constexpr (PR::kSplit == 1) {
+        return PR::mma(Ablk[blk * 64], a, acc);
+    } else {
+        acc = PR::mma(Ablk[blk * 64], a, acc);
+        return PR::mma(Ablk[(kMfmaBlocks + blk) * 64], a, acc);
+    }
+}
 
 }  // namespace
 
+template <class PR, class TG>
 __global__ void __launch_bounds__(512) k_recon_mfma(BlockView b, long Ntot, const double *__restrict__ Q,
                                                     const double *__restrict__ G, const double *__restrict__ L,
                                                     Metrics M, const double *__restrict__ Kblk, DevParams P,
-                                                    double *__restrict__ gp) {
-    __shared__ double lds[kMfmaBlocks * 64];
-    for (int i = threadIdx.x; i < kMfmaBlocks * 64; i += blockDim.x) lds[i] = Kblk[i];
+                                                    TG *__restrict__ gp) {
+    using T = typename PR::T;
+    using V = typename PR::V;
+    __shared__ T lds[PR::kSplit * kMfmaBlocks * 64];
+    for (int i = threadIdx.x; i < kMfmaBlocks * 64; i += blockDim.x) {
+        const double k = Kblk[i];
+        lds[i] = (T)k;
+        if constexpr (PR::kSplit == 2) lds[kMfmaBlocks * 64 + i] = (T)(k - (double)(T)k);
+    }
     __syncthreads();
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
     const int g = lane >> 4, col = lane & 15;
-    const double *A1 = lds + kMfmaOffA1 * 64 + lane;
-    const double *AL = lds + kMfmaOffAL * 64 + lane;
-    const double *AT = lds + kMfmaOffAT * 64 + lane;
-    const double *A2 = lds + kMfmaOffA2 * 64 + lane;
+    const T *A1 = lds + kMfmaOffA1 * 64 + lane;
+    const T *AL = lds + kMfmaOffAL * 64 + lane;
+    const T *AT = lds + kMfmaOffAT * 64 + lane;
+    const T *A2 = lds + kMfmaOffA2 * 64 + lane;
     const long nchunks = (b.N + 15) / 16;
     const long nitems = nchunks * kNV;
     // tangential coordinates of this lane's Gauss point (index g on every face)
@@ -85,7 +135,7 @@ __global__ void __launch_bounds__(512) k_recon_mfma(BlockView b, long Ntot, cons
             for (int s = 0; s < 3; ++s) J0[r][s] = M.J0[(3 * r + s) * Ntot + c];
         const double q0 = Qv[c];
 
-        v4d acc[3] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
+        V acc[3] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
         // ---- steps 0..5: face neighbours (difference and reference gradient) -------------
 #pragma unroll 1
         for (int m = 0; m < 6; ++m) {
@@ -99,7 +149,7 @@ __global__ void __launch_bounds__(512) k_recon_mfma(BlockView b, long Ntot, cons
             const double r2 = J0[0][2] * g0 + J0[1][2] * g1 + J0[2][2] * g2;
             const double item = (g == 0) ? fd : (g == 1) ? r0 : (g == 2) ? r1 : r2;
 #pragma unroll
-            for (int t = 0; t < 3; ++t) acc[t] = mfma(A1[(t * 18 + m) * 64], item, acc[t]);
+            for (int t = 0; t < 3; ++t) acc[t] = mac_data<PR>(A1, t * 18 + m, item, acc[t]);
         }
         // ---- steps 6..14: edge neighbours 4p+g ---------------------------------------------
 #pragma unroll 1
@@ -111,7 +161,7 @@ __global__ void __launch_bounds__(512) k_recon_mfma(BlockView b, long Ntot, cons
             const long nb = wrap_cell(b, ci + o[0], cj + o[1], ck + o[2]);
             const double d = Qv[nb] - q0;
 #pragma unroll
-            for (int t = 0; t < 3; ++t) acc[t] = mfma(A1[(t * 18 + 6 + p) * 64], d, acc[t]);
+            for (int t = 0; t < 3; ++t) acc[t] = mac_data<PR>(A1, t * 18 + 6 + p, d, acc[t]);
             const double g0 = Gv[nb], g1 = Gv[Ntot + nb], g2 = Gv[2 * Ntot + nb];
             double rg[3];
 #pragma unroll
@@ -120,9 +170,9 @@ __global__ void __launch_bounds__(512) k_recon_mfma(BlockView b, long Ntot, cons
             const double ra = (pa == 0) ? rg[0] : rg[1], rb = (pb == 1) ? rg[1] : rg[2];
             const double e2 = (sa * ra + sb * rb) * 0.70710678118654752440;
 #pragma unroll
-            for (int t = 0; t < 3; ++t) acc[t] = mfma(A1[(t * 18 + 9 + 2 * p) * 64], e1, acc[t]);
+            for (int t = 0; t < 3; ++t) acc[t] = mac_data<PR>(A1, t * 18 + 9 + 2 * p, e1, acc[t]);
 #pragma unroll
-            for (int t = 0; t < 3; ++t) acc[t] = mfma(A1[(t * 18 + 10 + 2 * p) * 64], e2, acc[t]);
+            for (int t = 0; t < 3; ++t) acc[t] = mac_data<PR>(A1, t * 18 + 10 + 2 * p, e2, acc[t]);
         }
         // ---- steps 15..17: line differences 4t+g ---------------------------------------------
         double lsum[3];
@@ -130,7 +180,7 @@ __global__ void __launch_bounds__(512) k_recon_mfma(BlockView b, long Ntot, cons
         for (int s = 0; s < 3; ++s) {
             const double ln = Lv[(4 * s + g) * Ntot + c];
 #pragma unroll
-            for (int t = 0; t < 3; ++t) acc[t] = mfma(A1[(t * 18 + 15 + s) * 64], ln, acc[t]);
+            for (int t = 0; t < 3; ++t) acc[t] = mac_data<PR>(A1, t * 18 + 15 + s, ln, acc[t]);
             double x = ln + __shfl_xor(ln, 16, 64);
             lsum[s] = x + __shfl_xor(x, 32, 64);
         }
@@ -141,11 +191,11 @@ __global__ void __launch_bounds__(512) k_recon_mfma(BlockView b, long Ntot, cons
             double isl = 0.0, ist = 0.0;
 #pragma unroll 1
             for (int u = 0; u < 5; ++u) {  // tiles 0..2: L_L^T rows, tiles 3..4: L_T^T rows
-                const double *Au = (u < 3) ? AL + (u * 10) * 64 : AT + ((u - 3) * 10) * 64;
-                v4d z = {0, 0, 0, 0};
+                const int base = (u < 3) ? kMfmaOffAL + u * 10 : kMfmaOffAT + (u - 3) * 10;
+                V z = {0, 0, 0, 0};
 #pragma unroll
-                for (int s = 0; s < 10; ++s) z = mfma(Au[s * 64], acc[s >> 2][s & 3], z);
-                const double zz = z[0] * z[0] + z[1] * z[1] + z[2] * z[2] + z[3] * z[3];
+                for (int s = 0; s < 10; ++s) z = mac_coef<PR>(lds + lane, base + s, acc[s >> 2][s & 3], z);
+                const double zz = (double)z[0] * z[0] + (double)z[1] * z[1] + (double)z[2] * z[2] + (double)z[3] * z[3];
                 if (u < 3) isl += zz;
                 else ist += zz;
             }
@@ -205,17 +255,17 @@ __global__ void __launch_bounds__(512) k_recon_mfma(BlockView b, long Ntot, cons
         // ---- Gauss-point values: face m = tile u, Gauss point k = g ----------------------------
 #pragma unroll 1
         for (int u = 0; u < 6; ++u) {
-            v4d y = {0, 0, 0, 0};
-            const double *Au = A2 + (u * 10) * 64;
+            V y = {0, 0, 0, 0};
 #pragma unroll
-            for (int s = 0; s < 10; ++s) y = mfma(Au[s * 64], acc[s >> 2][s & 3], y);
+            for (int s = 0; s < 10; ++s) y = mac_coef<PR>(lds + lane, kMfmaOffA2 + u * 10 + s, acc[s >> 2][s & 3], y);
             const int q = u >> 1;
             const double xq = (u & 1) ? 0.5 : -0.5;
             const double x0 = (q == 0) ? xq : ta;
             const double x1 = (q == 1) ? xq : ((q == 0) ? ta : tb);
             const double x2 = (q == 2) ? xq : tb;
-            const double val = q0 + chi * y[0] + om * (bbar[0] * x0 + bbar[1] * x1 + bbar[2] * x2);
-            const double r0 = chi * y[1] + om * bbar[0], r1 = chi * y[2] + om * bbar[1], r2 = chi * y[3] + om * bbar[2];
+            const double val = q0 + chi * (double)y[0] + om * (bbar[0] * x0 + bbar[1] * x1 + bbar[2] * x2);
+            const double r0 = chi * (double)y[1] + om * bbar[0], r1 = chi * (double)y[2] + om * bbar[1],
+                         r2 = chi * (double)y[3] + om * bbar[2];
             long f;
             int side;
             if (u & 1) {
@@ -226,23 +276,29 @@ __global__ void __launch_bounds__(512) k_recon_mfma(BlockView b, long Ntot, cons
                 side = 1;
             }
             if (valid) {
-                double *dst = gp + ((long)(((q * 2 + side) * 4 + g) * 20 + v * 4)) * Ntot + f;
-                dst[0] = val;
-                dst[Ntot] = JiT[0][0] * r0 + JiT[0][1] * r1 + JiT[0][2] * r2;
-                dst[2 * Ntot] = JiT[1][0] * r0 + JiT[1][1] * r1 + JiT[1][2] * r2;
-                dst[3 * Ntot] = JiT[2][0] * r0 + JiT[2][1] * r1 + JiT[2][2] * r2;
+                TG *dst = gp + ((long)(((q * 2 + side) * 4 + g) * 20 + v * 4)) * Ntot + f;
+                dst[0] = (TG)val;
+                dst[Ntot] = (TG)(JiT[0][0] * r0 + JiT[0][1] * r1 + JiT[0][2] * r2);
+                dst[2 * Ntot] = (TG)(JiT[1][0] * r0 + JiT[1][1] * r1 + JiT[1][2] * r2);
+                dst[3 * Ntot] = (TG)(JiT[2][0] * r0 + JiT[2][1] * r1 + JiT[2][2] * r2);
             }
         }
     }
 }
 
-hipError_t launch_recon_mfma(const BlockView &b, long Ntot, const double *Q, const double *G, const double *L,
-                             const Metrics &M, const double *Kblk, const DevParams &P, double *gp, int ngroups,
-                             hipStream_t s) {
+hipError_t launch_recon_mfma(int prec, bool gp32, const BlockView &b, long Ntot, const double *Q, const double *G,
+                             const double *L, const Metrics &M, const double *Kblk, const DevParams &P, void *gp,
+                             int ngroups, hipStream_t s) {
     const long items = ((b.N + 15) / 16) * kNV;
     long grid = (items + 7) / 8;
     if (grid > ngroups) grid = ngroups;
-    hipLaunchKernelGGL(k_recon_mfma, dim3((unsigned)grid), dim3(512), 0, s, b, Ntot, Q, G, L, M, Kblk, P, gp);
+    const dim3 gr((unsigned)grid), bl(512);
+    if (prec == 0 && !gp32)
+        hipLaunchKernelGGL((k_recon_mfma<PrecF64, double>), gr, bl, 0, s, b, Ntot, Q, G, L, M, Kblk, P, (double *)gp);
+    else if (prec == 0)
+        hipLaunchKernelGGL((k_recon_mfma<PrecF64, float>), gr, bl, 0, s, b, Ntot, Q, G, L, M, Kblk, P, (float *)gp);
+    else
+        hipLaunchKernelGGL((k_recon_mfma<PrecF32x3, float>), gr, bl, 0, s, b, Ntot, Q, G, L, M, Kblk, P, (float *)gp);
     return hipGetLastError();
 }
 

@@ -1,0 +1,79 @@
+// Source-level operation count of the gas-kinetic flux (gks_flux_pair) per Gauss point.
+//
+// The flux is generic in its arithmetic type; instantiating it on the host with a counting
+// type gives the number of additions, multiplications, fused multiply-adds, divisions and
+// transcendental calls (sqrt, exp, erfc, pow) of one lane.  Both lanes of a pair execute the
+// same instruction stream (the code has no lane-dependent branches; the pair exchange is a
+// value swap), so a Gauss point costs twice the count of one lane.  Prints one line:
+//   <flops per Gauss point> <adds> <muls> <fmas> <divs> <transcendentals>   (per lane)
+// with flops = adds + muls + 2 fmas + divs + transcendentals, times two lanes.
+// Usage: flux_opcount [viscous] [prandtl_fix] [sutherland] [tau_zero]   (0/1 each)
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+
+#include "cgks_device.h"
+
+namespace {
+
+struct Tally {
+    long add = 0, mul = 0, fma = 0, div = 0, trans = 0;
+};
+Tally tally;
+
+struct Cnt {
+    double v;
+    Cnt() : v(0.0) {}
+    Cnt(double x) : v(x) {}
+};
+inline Cnt operator+(Cnt a, Cnt b) { ++tally.add; return Cnt(a.v + b.v); }
+inline Cnt operator-(Cnt a, Cnt b) { ++tally.add; return Cnt(a.v - b.v); }
+inline Cnt operator*(Cnt a, Cnt b) { ++tally.mul; return Cnt(a.v * b.v); }
+inline Cnt operator/(Cnt a, Cnt b) { ++tally.div; return Cnt(a.v / b.v); }
+inline Cnt operator-(Cnt a) { return Cnt(-a.v); }
+inline Cnt &operator+=(Cnt &a, Cnt b) { ++tally.add; a.v += b.v; return a; }
+inline bool operator>(Cnt a, Cnt b) { return a.v > b.v; }
+inline bool operator<(Cnt a, Cnt b) { return a.v < b.v; }
+
+struct HostCount {
+    static Cnt swap(Cnt v) { return v; }
+    static int swapi(int v) { return v; }
+    static Cnt sqrt(Cnt x) { ++tally.trans; return Cnt(std::sqrt(x.v)); }
+    static Cnt exp(Cnt x) { ++tally.trans; return Cnt(std::exp(x.v)); }
+    static Cnt erfc(Cnt x) { ++tally.trans; return Cnt(std::erfc(x.v)); }
+    static Cnt pow(Cnt a, Cnt b) { ++tally.trans; return Cnt(std::pow(a.v, b.v)); }
+    static Cnt fabs(Cnt x) { return Cnt(std::fabs(x.v)); }
+    static Cnt fma(Cnt a, Cnt b, Cnt c) { ++tally.fma; return Cnt(a.v * b.v + c.v); }
+    static bool finite(Cnt x) { return std::isfinite(x.v); }
+};
+
+}  // namespace
+
+int main(int argc, char **argv) {
+    cgks::DevParams P{};
+    P.gamma = 1.4;
+    P.K = 2.0;
+    P.tau_eps = 0.05;
+    P.tau_C = 5.0;
+    P.mu0 = 1.0 / 1600.0;
+    P.T_ref = 71.4285714;
+    P.S_suth = P.T_ref * 110.4 / 288.15;
+    P.Pr = 0.72;
+    P.viscous = argc > 1 ? std::atoi(argv[1]) : 1;
+    P.prandtl_fix = argc > 2 ? std::atoi(argv[2]) : 1;
+    P.visc_law = argc > 3 ? std::atoi(argv[3]) : 1;
+    P.tau_zero = argc > 4 ? std::atoi(argv[4]) : 0;
+    // a physical left state with non-zero gradients and a tilted normal
+    Cnt q[5] = {1.01, 0.31, -0.22, 0.05, 180.0};
+    Cnt g[5][3];
+    for (int v = 0; v < 5; ++v)
+        for (int j = 0; j < 3; ++j) g[v][j] = Cnt(0.01 * (1 + v) * (j - 1));
+    const double nn = std::sqrt(1.0 + 0.04 + 0.01);
+    Cnt n[3] = {1.0 / nn, 0.2 / nn, 0.1 / nn};
+    Cnt Fo[5], Fto[5], Qs[5], dQs[5];
+    const int err = cgks::gks_flux_pair<HostCount, Cnt>(P, 0, q, g, n, Cnt(4e-4), Fo, Fto, Qs, dQs);
+    const long flops_lane = tally.add + tally.mul + 2 * tally.fma + tally.div + tally.trans;
+    std::printf("%ld %ld %ld %ld %ld %ld %d\n", 2 * flops_lane, tally.add, tally.mul, tally.fma, tally.div, tally.trans,
+                err);
+    return err;
+}
