@@ -4,9 +4,9 @@ Workload: 3D Navier-Stokes Taylor-Green vortex (Re 1600, Ma 0.1, Pr 0.72, Suther
 cells on the periodic perturbed curvilinear mesh x = xi + 0.05 sin(xi) sin(eta) sin(zeta) per
 axis, nonlinear CGKS-5.  A step is the CFL time step plus both S2O4 stages (reconstruction,
 gas-kinetic flux, update) over every cell.  Inputs are synthetic and resident in HBM before
-the timed region.  `value` is the FP64 path; the reduced-precision variant (FP32x3
-reconstruction on the FP32 matrix cores + FP32 flux, FP64 metrics and accumulation) is timed
-beside it with its L2/Linf error against FP64 after 50 steps.
+the timed region.  `value` is the FP64 path; the reduced-precision variants (FP32x3 or BF16x3
+split-precision reconstruction on the FP32 or BF16 matrix cores + FP32 flux, FP64 metrics and
+accumulation) are timed beside it with their L2/Linf error against FP64 after 50 steps.
 
 Prints one JSON line.  --gpus N > 1 is not supported (single-GPU build).
 """
@@ -20,7 +20,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 GAM = 1.4
-PEAK = {"fp64": 78.6, "fp32": 157.3}  # TFLOP/s, MI355X (vector and matrix FP64: 78.6)
+PEAK = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}  # TFLOP/s, MI355X dense (FP64 vector and matrix: 78.6)
 
 # Algorithmic work per unit (see the measurement section of the design notes):
 #   flux: source-level operation count of the gas-kinetic flux per Gauss point (flux_opcount.cpp);
@@ -137,7 +137,7 @@ def main():
     roof = roofline(prof, N, "fp64")
     del Q, G, L
 
-    # ---- reduced-precision variant, and its error against FP64 after error_steps ---------
+    # ---- reduced-precision variants, and their error against FP64 after error_steps --------
     variants = None
     if not args.no_variants:
         ne = args.error_steps
@@ -148,20 +148,6 @@ def main():
         del Gr, Lr
         ctx.close()
         torch.cuda.empty_cache()
-        vctx = K.Context([n], [nodes_h], K.default_params(recon_prec=1, flux_prec=1, **kw))
-        Qv, Gv, Lv = Q0.clone(), G0.clone(), L0.clone()
-        for _ in range(args.warmup):
-            K.cgks_step(vctx, Qv, Gv, Lv, dt, use_cfl=True)
-        torch.cuda.synchronize()
-        K.cgks_profile_read(vctx)
-        v_elapsed, v_prof = timed_steps(K, vctx, Qv, Gv, Lv, dt, args.steps)
-        Qv.copy_(Q0)
-        Gv.copy_(G0)
-        Lv.copy_(L0)
-        for _ in range(ne):
-            K.cgks_step(vctx, Qv, Gv, Lv, dt, use_cfl=True)
-        torch.cuda.synchronize()
-        v_status = K.cgks_check(vctx)
 
         def errs(a, b):
             d = a - b
@@ -169,21 +155,39 @@ def main():
                     "rel_linf": float(d.abs().max() / b.abs().max())}
 
         speed = lambda q: torch.sqrt(q[1] ** 2 + q[2] ** 2 + q[3] ** 2) / q[0]
-        v_value = N * args.steps / v_elapsed
-        variants = [{
-            "variant": "recon FP32x3 (FP32 matrix cores, split precision) + flux FP32; metrics, dt and S2O4 "
-                       "accumulation FP64",
-            "value": v_value, "unit": "cell-updates/s",
-            "ms_per_step": 1e3 * v_elapsed / args.steps,
-            "speedup_vs_fp64": v_value / value,
-            "kernel_ms": {k: {"total_ms": v[0], "launches": v[1]} for k, v in v_prof.items()},
-            "roofline": roofline(v_prof, N, "fp32"),
-            "error_vs_fp64": {"steps": ne, "reference": "GPU FP64 path (matches the oracle, see parity)",
-                              "rho": errs(Qv[0], Qr[0]), "speed": errs(speed(Qv), speed(Qr)),
-                              "rhoE": errs(Qv[4], Qr[4])},
-            "device_flags": v_status[1],
-        }]
-        vctx.close()
+        variants = []
+        for name, rp in (("recon FP32x3 (FP32 matrix cores, split precision)", 1),
+                         ("recon BF16x3 (BF16 matrix cores, split precision)", 2)):
+            vctx = K.Context([n], [nodes_h], K.default_params(recon_prec=rp, flux_prec=1, **kw))
+            Qv, Gv, Lv = Q0.clone(), G0.clone(), L0.clone()
+            for _ in range(args.warmup):
+                K.cgks_step(vctx, Qv, Gv, Lv, dt, use_cfl=True)
+            torch.cuda.synchronize()
+            K.cgks_profile_read(vctx)
+            v_elapsed, v_prof = timed_steps(K, vctx, Qv, Gv, Lv, dt, args.steps)
+            Qv.copy_(Q0)
+            Gv.copy_(G0)
+            Lv.copy_(L0)
+            for _ in range(ne):
+                K.cgks_step(vctx, Qv, Gv, Lv, dt, use_cfl=True)
+            torch.cuda.synchronize()
+            v_status = K.cgks_check(vctx)
+            v_value = N * args.steps / v_elapsed
+            variants.append({
+                "variant": name + " + flux FP32; metrics, dt and S2O4 accumulation FP64",
+                "value": v_value, "unit": "cell-updates/s",
+                "ms_per_step": 1e3 * v_elapsed / args.steps,
+                "speedup_vs_fp64": v_value / value,
+                "kernel_ms": {k: {"total_ms": v[0], "launches": v[1]} for k, v in v_prof.items()},
+                "roofline": roofline(v_prof, N, "bf16" if rp == 2 else "fp32"),
+                "error_vs_fp64": {"steps": ne, "reference": "GPU FP64 path (matches the oracle, see parity)",
+                                  "rho": errs(Qv[0], Qr[0]), "speed": errs(speed(Qv), speed(Qr)),
+                                  "rhoE": errs(Qv[4], Qr[4])},
+                "device_flags": v_status[1],
+            })
+            vctx.close()
+            del Qv, Gv, Lv
+            torch.cuda.empty_cache()
     else:
         ctx.close()
 

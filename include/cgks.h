@@ -71,7 +71,8 @@ typedef struct {
     int linear;          /* 1: chi = 1 (linear CGKS-5)                                      */
     int prandtl_fix;     /* 1: heat-flux correction to Pr (viscous mode only)               */
     int recon_prec;      /* reconstruction contractions: 0 FP64 matrix cores; 1 FP32x3 split
-                            precision on the FP32 matrix cores (FP32 accumulation)          */
+                            precision on the FP32 matrix cores; 2 BF16x3 split precision on
+                            the BF16 matrix cores (both with FP32 accumulation)             */
     int flux_prec;       /* gas-kinetic flux arithmetic: 0 FP64, 1 FP32.  Either reduced
                             option stores Gauss-point data in FP32; metrics, the time step
                             and the S2O4 accumulation of Q, G, L stay FP64                  */

@@ -124,7 +124,8 @@ static int check_params(const cgks_params *p) {
     if (p->viscous && !(p->mu0 > 0.0)) return fail(CGKS_EINVAL, "viscous mode needs mu0 > 0");
     if (p->visc_law && (!(p->T_ref > 0.0) || !(p->S_suth >= 0.0))) return fail(CGKS_EINVAL, "Sutherland needs T_ref > 0, S >= 0");
     if (p->prandtl_fix && !(p->Pr > 0.0)) return fail(CGKS_EINVAL, "Pr must be positive");
-    if (p->recon_prec < 0 || p->recon_prec > 1) return fail(CGKS_EUNSUPPORTED, "recon_prec must be 0 (FP64) or 1 (FP32x3)");
+    if (p->recon_prec < 0 || p->recon_prec > 2)
+        return fail(CGKS_EUNSUPPORTED, "recon_prec must be 0 (FP64), 1 (FP32x3) or 2 (BF16x3)");
     if (p->flux_prec < 0 || p->flux_prec > 1) return fail(CGKS_EUNSUPPORTED, "flux_prec must be 0 (FP64) or 1 (FP32)");
     if (p->recon_impl != 0 && p->recon_impl != 1) return fail(CGKS_EINVAL, "recon_impl must be 0 or 1");
     if (p->recon_impl == 1 && (p->recon_prec != 0 || p->flux_prec != 0))
@@ -218,7 +219,7 @@ int cgks_ctx_create(cgks_ctx **out, int nblocks, const int *dims, const double *
     auto alloc = [&](void **ptr, size_t bytes) -> bool { return hipMalloc(ptr, bytes) == hipSuccess; };
     const size_t nmet = 1 + 9 + 9 + 36 + 12 + 12;
     bool ok = alloc((void **)&c->metric_mem, sizeof(double) * nmet * Ntot) && alloc((void **)&c->K, sizeof(DevConsts)) &&
-              alloc((void **)&c->Kmf, sizeof(double) * kMfmaBlocks * 64) &&
+              alloc((void **)&c->Kmf, sizeof(double) * std::max(kMfmaBlocks * 64, kBfBlocks * 512)) &&
               alloc((void **)&c->gp, sizeof(double) * 480 * Ntot) && alloc((void **)&c->fo, sizeof(double) * 360 * Ntot) &&
               alloc((void **)&c->stash, sizeof(double) * 80 * Ntot) &&
               alloc((void **)&c->dt_part, sizeof(double) * kMaxDtParts) && alloc((void **)&c->flag, sizeof(int));
@@ -244,8 +245,8 @@ int cgks_ctx_create(cgks_ctx **out, int nblocks, const int *dims, const double *
     std::memcpy(dk.GL, hk->GL, sizeof dk.GL);
     std::memcpy(dk.GT, hk->GT, sizeof dk.GT);
     std::memcpy(dk.xg, hk->xg, sizeof dk.xg);
-    std::vector<double> kmf(kMfmaBlocks * 64);
-    const bool packed = pack_mfma(*hk, kmf.data(), p->recon_prec == 0);
+    std::vector<double> kmf(std::max(kMfmaBlocks * 64, kBfBlocks * 512));
+    const bool packed = (p->recon_prec == 2) ? pack_mfma_bf16(*hk, kmf.data()) : pack_mfma(*hk, kmf.data(), p->recon_prec == 0);
     delete hk;
     if (!packed) {
         cgks_ctx_destroy(c);

@@ -374,3 +374,55 @@ bool pack_mfma(const HostConsts &K, double *blk, bool f64) {
 }
 
 }  // namespace cgks
+
+namespace cgks {
+
+bool pack_mfma_bf16(const HostConsts &K, double *blk) {
+    // Cholesky factors as in pack_mfma
+    std::vector<double> gl(kNB * kNB), ll(kNB * kNB), gt(31 * 31), lt(31 * 31);
+    for (int i = 0; i < kNB; ++i)
+        for (int j = 0; j < kNB; ++j) gl[i * kNB + j] = K.GL[i][j];
+    for (int i = 0; i < 31; ++i)
+        for (int j = 0; j < 31; ++j) gt[i * 31 + j] = K.GT[3 + i][3 + j];
+    if (!cholesky(kNB, gl.data(), ll.data()) || !cholesky(31, gt.data(), lt.data())) return false;
+    for (int i = 0; i < kBfBlocks * 512; ++i) blk[i] = 0.0;
+    // item slot sigma = 8 s + j of lane group g is the uniform slot of the 16x16x4 kernels,
+    // i.e. stencil item mfma_item(4 sigma + g); slots 18..23 are padding
+    // coefficient slot sigma' = 8 s' + j of lane group g holds a-row 16 t + 4 g + v, (t, v) =
+    // (sigma' / 4, sigma' % 4), for sigma' < 12
+    auto arow = [](int sp, int j, int g) -> int {
+        const int sig = 8 * sp + j;
+        if (sig >= 12) return -1;
+        return 16 * (sig / 4) + 4 * g + (sig % 4);
+    };
+    for (int l = 0; l < 64; ++l) {
+        const int row = l % 16, g = l / 16;
+        for (int j = 0; j < 8; ++j) {
+            for (int t = 0; t < 3; ++t)
+                for (int s = 0; s < 3; ++s) {
+                    const int sig = 8 * s + j, i = 16 * t + row;
+                    const double v = (sig < 18 && i < kNB) ? K.R[i][mfma_item(4 * sig + g)] : 0.0;
+                    blk[((kBfOffA1 + t * 3 + s) * 64 + l) * 8 + j] = v;
+                }
+            for (int s = 0; s < 2; ++s) {
+                const int ar = arow(s, j, g);
+                for (int u = 0; u < 3; ++u) {
+                    const int i = 16 * u + row;
+                    blk[((kBfOffAL + u * 2 + s) * 64 + l) * 8 + j] = (ar >= 0 && ar < kNB && i < kNB) ? ll[ar * kNB + i] : 0.0;
+                }
+                for (int u = 0; u < 2; ++u) {
+                    const int i = 16 * u + row;
+                    blk[((kBfOffAT + u * 2 + s) * 64 + l) * 8 + j] =
+                        (ar >= 3 && ar < kNB && i < 31) ? lt[(ar - 3) * 31 + i] : 0.0;
+                }
+                for (int u = 0; u < 6; ++u) {
+                    const int gpl = row / 4, comp = row % 4;  // FP32-layout output rows
+                    blk[((kBfOffA2 + u * 2 + s) * 64 + l) * 8 + j] = (ar >= 0 && ar < kNB) ? K.E[4 * u + gpl][comp][ar] : 0.0;
+                }
+            }
+        }
+    }
+    return true;
+}
+
+}  // namespace cgks

@@ -57,6 +57,12 @@ void build_constants(HostConsts &K);
 constexpr int kMfmaOffA1 = 0, kMfmaOffAL = 54, kMfmaOffAT = 84, kMfmaOffA2 = 104, kMfmaBlocks = 164;
 bool pack_mfma(const HostConsts &K, double *blocks, bool f64);
 
+// Constant blocks of the BF16x3 reconstruction (16x16x32 BF16 instruction): 8 values per lane
+// and block: R (3 tiles x 3 k-steps), L_L^T (3 x 2), L_T^T (2 x 2), E (6 x 2); split into
+// BF16 hi/lo pairs on the device.
+constexpr int kBfOffA1 = 0, kBfOffAL = 9, kBfOffAT = 15, kBfOffA2 = 19, kBfBlocks = 31;
+bool pack_mfma_bf16(const HostConsts &K, double *blocks);
+
 // Scheme parameters in the form the kernels read them.
 struct DevParams {
     double gamma, K;             // ratio of specific heats, internal degrees of freedom

@@ -286,9 +286,235 @@ __global__ void __launch_bounds__(512) k_recon_mfma(BlockView b, long Ntot, cons
     }
 }
 
+// ------------------------------------------------------------------------------------------
+// BF16x3 variant on the 16x16x32 BF16 matrix cores (gfx950).  Lane l supplies A[l%16][8(l/16)+j]
+// and B[8(l/16)+j][l%16], j = 0..7, and register v receives D[4(l/16)+v][l%16] (FP32).  The 18
+// stencil slots of the 16x16x4 kernels are packed as slot 8s + j of k-step s (slots 18..23
+// zero); the 12 coefficients a lane holds after GEMM1 are packed the same way for the
+// follow-up products.  Every product is split: x = x_hi + x_lo and K = K_hi + K_lo in BF16,
+// K x ~ K_hi x_hi + K_hi x_lo + K_lo x_hi, FP32 accumulation.
+// ------------------------------------------------------------------------------------------
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+
+namespace {
+// Store x as the BF16 pair (hi, lo) in slot sl of the k-step vectors h[sl/8], l[sl/8].
+__device__ inline void put_bf16(v8bf *h, v8bf *l, int sl, double x) {
+    const __bf16 hi = (__bf16)(float)x;
+    h[sl / 8][sl % 8] = hi;
+    l[sl / 8][sl % 8] = (__bf16)(float)(x - (double)(float)hi);
+}
+__device__ inline v4f mma3(const v8bf *Kb, int blk, const v8bf &xh, const v8bf &xl, v4f acc) {
+    const v8bf kh = Kb[blk * 64], kl = Kb[(kBfBlocks + blk) * 64];
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(kh, xh, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(kh, xl, acc, 0, 0, 0);
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(kl, xh, acc, 0, 0, 0);
+}
+}  // namespace
+
+template <class TG>
+__global__ void __launch_bounds__(512) k_recon_bf16(BlockView b, long Ntot, const double *__restrict__ Q,
+                                                    const double *__restrict__ G, const double *__restrict__ L,
+                                                    Metrics M, const double *__restrict__ Kbf, DevParams P,
+                                                    TG *__restrict__ gp) {
+    __shared__ v8bf lds[2 * kBfBlocks * 64];
+    for (int i = threadIdx.x; i < kBfBlocks * 64; i += blockDim.x) {
+        v8bf h, lo;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) put_bf16(&h, &lo, j, Kbf[i * 8 + j]);
+        lds[i] = h;
+        lds[kBfBlocks * 64 + i] = lo;
+    }
+    __syncthreads();
+
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+    const int g = lane >> 4, col = lane & 15;
+    const v8bf *Kb = lds + lane;
+    const long nchunks = (b.N + 15) / 16;
+    const long nitems = nchunks * kNV;
+    const double gq = 0.28867513459481288225;
+    const double ta = (g & 1) ? gq : -gq, tb = (g & 2) ? gq : -gq;
+    const int sa = (g & 1) ? 1 : -1, sb = (g & 2) ? 1 : -1;
+
+    for (long it = (long)blockIdx.x * nwaves + wave; it < nitems; it += (long)gridDim.x * nwaves) {
+        const int v = (int)(it % kNV);
+        const long cl0 = (it / kNV) * 16 + col;
+        const bool valid = cl0 < b.N;
+        const long cl = valid ? cl0 : b.N - 1;
+        const int ci = (int)(cl % b.nx);
+        const long tt = cl / b.nx;
+        const int cj = (int)(tt % b.ny), ck = (int)(tt / b.ny);
+        const long c = b.off + cl;
+        const double *Qv = Q + v * Ntot;
+        const double *Gv = G + 3 * v * Ntot;
+        const double *Lv = L + 12 * v * Ntot;
+        double J0[3][3];
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+            for (int s = 0; s < 3; ++s) J0[r][s] = M.J0[(3 * r + s) * Ntot + c];
+        const double q0 = Qv[c];
+
+        // ---- the 18 stencil slots of this lane, split into BF16 hi/lo, slot 8s + j ----------
+        v8bf bh[3], bl[3];
+#pragma unroll
+        for (int s = 0; s < 3; ++s)
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                bh[s][j] = (__bf16)0.0f;
+                bl[s][j] = (__bf16)0.0f;
+            }
+        double fdiff[6];
+#pragma unroll
+        for (int m = 0; m < 6; ++m) {
+            int o[3] = {0, 0, 0};
+            o[m >> 1] = (m & 1) ? 1 : -1;
+            const long nb = wrap_cell(b, ci + o[0], cj + o[1], ck + o[2]);
+            const double g0 = Gv[nb], g1 = Gv[Ntot + nb], g2 = Gv[2 * Ntot + nb];
+            fdiff[m] = Qv[nb] - q0;
+            const double r0 = J0[0][0] * g0 + J0[1][0] * g1 + J0[2][0] * g2;
+            const double r1 = J0[0][1] * g0 + J0[1][1] * g1 + J0[2][1] * g2;
+            const double r2 = J0[0][2] * g0 + J0[1][2] * g1 + J0[2][2] * g2;
+            put_bf16(bh, bl, m, (g == 0) ? fdiff[m] : (g == 1) ? r0 : (g == 2) ? r1 : r2);
+        }
+#pragma unroll
+        for (int p = 0; p < 3; ++p) {
+            const int pa = (p < 2) ? 0 : 1, pb = (p == 0) ? 1 : 2, pc = 3 - pa - pb;
+            int o[3] = {0, 0, 0};
+            o[pa] = sa;
+            o[pb] = sb;
+            const long nb = wrap_cell(b, ci + o[0], cj + o[1], ck + o[2]);
+            const int s0 = 6 + p, s1 = 9 + 2 * p, s2 = 10 + 2 * p;
+            put_bf16(bh, bl, s0, Qv[nb] - q0);
+            const double g0 = Gv[nb], g1 = Gv[Ntot + nb], g2 = Gv[2 * Ntot + nb];
+            double rg[3];
+#pragma unroll
+            for (int s = 0; s < 3; ++s) rg[s] = J0[0][s] * g0 + J0[1][s] * g1 + J0[2][s] * g2;
+            put_bf16(bh, bl, s1, rg[pc]);
+            put_bf16(bh, bl, s2, (sa * rg[pa] + sb * rg[pb]) * 0.70710678118654752440);
+        }
+        double lsum[3];
+#pragma unroll
+        for (int s = 0; s < 3; ++s) {
+            const double ln = Lv[(4 * s + g) * Ntot + c];
+            const int sl = 15 + s;
+            put_bf16(bh, bl, sl, ln);
+            double x = ln + __shfl_xor(ln, 16, 64);
+            lsum[s] = x + __shfl_xor(x, 32, 64);
+        }
+        // ---- GEMM1: a = R b ---------------------------------------------------------------------
+        v4f acc[3] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
+#pragma unroll
+        for (int t = 0; t < 3; ++t)
+#pragma unroll
+            for (int s = 0; s < 3; ++s) acc[t] = mma3(Kb, kBfOffA1 + t * 3 + s, bh[s], bl[s], acc[t]);
+        // coefficients of this lane as BF16 hi/lo, slot 8s' + j = 4t + v
+        v8bf ch[2], cl2[2];
+#pragma unroll
+        for (int s = 0; s < 2; ++s)
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int sig = 8 * s + j;
+                const float x = (sig < 12) ? acc[sig / 4][sig % 4] : 0.0f;
+                const __bf16 h = (__bf16)x;
+                ch[s][j] = h;
+                cl2[s][j] = (__bf16)(x - (float)h);
+            }
+
+        double chi = 1.0, bbar[3] = {0.0, 0.0, 0.0};
+        if (!P.linear) {
+            double isl = 0.0, ist = 0.0;
+#pragma unroll
+            for (int u = 0; u < 5; ++u) {
+                const int base = (u < 3) ? kBfOffAL + u * 2 : kBfOffAT + (u - 3) * 2;
+                v4f z = {0, 0, 0, 0};
+#pragma unroll
+                for (int s = 0; s < 2; ++s) z = mma3(Kb, base + s, ch[s], cl2[s], z);
+                const double zz = (double)z[0] * z[0] + (double)z[1] * z[1] + (double)z[2] * z[2] + (double)z[3] * z[3];
+                if (u < 3) isl += zz;
+                else ist += zz;
+            }
+            isl += __shfl_xor(isl, 16, 64);
+            isl += __shfl_xor(isl, 32, 64);
+            ist += __shfl_xor(ist, 16, 64);
+            ist += __shfl_xor(ist, 32, 64);
+            const double ish = isl + ist;
+            const double rh = ist / (ish + P.geno_eps), rl = ist / (isl + P.geno_eps);
+            double ah, al;
+            if (P.geno_r == 2.0) {
+                ah = 1.0 + rh * rh;
+                al = 1.0 + rl * rl;
+            } else {
+                ah = 1.0 + pow(rh, P.geno_r);
+                al = 1.0 + pow(rl, P.geno_r);
+            }
+            chi = tanh(P.geno_C * (2.0 * ah / (ah + al))) * P.inv_tanhC;
+            const double lm[3] = {0.25 * lsum[0], 0.25 * lsum[1], 0.25 * lsum[2]};
+            double wsum = 0.0, wv[6];
+#pragma unroll
+            for (int m = 0; m < 6; ++m) {
+                const int q = m >> 1;
+                const double bn = (m & 1) ? fdiff[m] : -fdiff[m];
+                double is = P.geno_eps + bn * bn;
+#pragma unroll
+                for (int t = 0; t < 3; ++t)
+                    if (t != q) is += lm[t] * lm[t];
+                const double is2 = is * is;
+                wv[m] = (1.0 / 6.0) / (is2 * is2 * is);
+                wsum += wv[m];
+            }
+            const double iw = 1.0 / wsum;
+#pragma unroll
+            for (int m = 0; m < 6; ++m) {
+                const int q = m >> 1;
+                const double w = wv[m] * iw;
+                const double bn = (m & 1) ? fdiff[m] : -fdiff[m];
+#pragma unroll
+                for (int t = 0; t < 3; ++t) bbar[t] += w * ((t == q) ? bn : lm[t]);
+            }
+        }
+        double JiT[3][3];
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+            for (int s = 0; s < 3; ++s) JiT[r][s] = M.JiT[(3 * r + s) * Ntot + c];
+        const double om = 1.0 - chi;
+#pragma unroll 1
+        for (int u = 0; u < 6; ++u) {
+            v4f y = {0, 0, 0, 0};
+#pragma unroll
+            for (int s = 0; s < 2; ++s) y = mma3(Kb, kBfOffA2 + u * 2 + s, ch[s], cl2[s], y);
+            const int q = u >> 1;
+            const double xq = (u & 1) ? 0.5 : -0.5;
+            const double x0 = (q == 0) ? xq : ta;
+            const double x1 = (q == 1) ? xq : ((q == 0) ? ta : tb);
+            const double x2 = (q == 2) ? xq : tb;
+            const double val = q0 + chi * (double)y[0] + om * (bbar[0] * x0 + bbar[1] * x1 + bbar[2] * x2);
+            const double r0 = chi * (double)y[1] + om * bbar[0], r1 = chi * (double)y[2] + om * bbar[1],
+                         r2 = chi * (double)y[3] + om * bbar[2];
+            long f;
+            int side;
+            if (u & 1) {
+                f = c;
+                side = 0;
+            } else {
+                f = wrap_cell(b, ci - (q == 0), cj - (q == 1), ck - (q == 2));
+                side = 1;
+            }
+            if (valid) {
+                TG *dst = gp + ((long)(((q * 2 + side) * 4 + g) * 20 + v * 4)) * Ntot + f;
+                dst[0] = (TG)val;
+                dst[Ntot] = (TG)(JiT[0][0] * r0 + JiT[0][1] * r1 + JiT[0][2] * r2);
+                dst[2 * Ntot] = (TG)(JiT[1][0] * r0 + JiT[1][1] * r1 + JiT[1][2] * r2);
+                dst[3 * Ntot] = (TG)(JiT[2][0] * r0 + JiT[2][1] * r1 + JiT[2][2] * r2);
+            }
+        }
+    }
+}
+
 hipError_t launch_recon_mfma(int prec, bool gp32, const BlockView &b, long Ntot, const double *Q, const double *G,
                              const double *L, const Metrics &M, const double *Kblk, const DevParams &P, void *gp,
                              int ngroups, hipStream_t s) {
+    // prec: 0 FP64, 1 FP32x3, 2 BF16x3 (Kblk holds the blocks packed for that instruction)
     const long items = ((b.N + 15) / 16) * kNV;
     long grid = (items + 7) / 8;
     if (grid > ngroups) grid = ngroups;
@@ -297,8 +523,10 @@ hipError_t launch_recon_mfma(int prec, bool gp32, const BlockView &b, long Ntot,
         hipLaunchKernelGGL((k_recon_mfma<PrecF64, double>), gr, bl, 0, s, b, Ntot, Q, G, L, M, Kblk, P, (double *)gp);
     else if (prec == 0)
         hipLaunchKernelGGL((k_recon_mfma<PrecF64, float>), gr, bl, 0, s, b, Ntot, Q, G, L, M, Kblk, P, (float *)gp);
-    else
+    else if (prec == 1)
         hipLaunchKernelGGL((k_recon_mfma<PrecF32x3, float>), gr, bl, 0, s, b, Ntot, Q, G, L, M, Kblk, P, (float *)gp);
+    else
+        hipLaunchKernelGGL((k_recon_bf16<float>), gr, bl, 0, s, b, Ntot, Q, G, L, M, Kblk, P, (float *)gp);
     return hipGetLastError();
 }
 

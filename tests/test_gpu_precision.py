@@ -1,6 +1,6 @@
-"""Reduced-precision variants of the HIP path (FP32x3 split-precision reconstruction on the
-FP32 matrix cores, FP32 gas-kinetic flux; metrics and S2O4 accumulation FP64) against the
-FP64 oracle.  These are accuracy reports with bounds derived from FP32 rounding, not parity
+"""Reduced-precision variants of the HIP path (FP32x3 or BF16x3 split-precision reconstruction
+on the FP32 or BF16 matrix cores, FP32 gas-kinetic flux; metrics and S2O4 accumulation FP64)
+against the FP64 oracle.  These are accuracy reports with bounds derived from FP32 rounding, not parity
 at 1e-12: the FP32 flux evaluates values of size ~p (71 at Ma 0.1) whose face-to-face
 differences are ~1e-2 of that, so single-precision rounding (6e-8) leaves ~1e-5 relative
 error in a flux divergence; after a few steps the state differs from FP64 by ~1e-6."""
@@ -54,7 +54,46 @@ def test_fp32_flux_points_accuracy():
     ctx.close()
 
 
-@pytest.mark.parametrize("recon_prec,flux_prec", [(1, 0), (0, 1), (1, 1)])
+# Unit roundoff of the split representation x = hi + lo: FP32 pairs carry 48 significand bits,
+# but the operands start from FP64 values rounded once to FP32 and the products are summed in
+# FP32, so FP32x3 is accurate to ~2^-24; a BF16 pair carries 16 bits (2^-17 after the dropped
+# lo*lo term), FP32 accumulation below that.
+U_SPLIT = {1: 2.0 ** -24, 2: 2.0 ** -17}
+
+
+@pytest.mark.parametrize("recon_prec", [1, 2], ids=["fp32x3", "bf16x3"])
+def test_split_reconstruction_accuracy(recon_prec):
+    """Gauss-point values and gradients of the split-precision reconstruction against the FP64
+    oracle.  The reconstruction is linear in the stencil data b (differences to the cell average
+    and gradients) apart from the weights, so its error is bounded by ||E R||_inf * u * ||b||:
+    measured relative to the size of the deviations from the cell average (values) and of the
+    gradients, with ||E R||_inf <= 64 on the standard cell."""
+    n = (17, 12, 10)
+    nodes = W.perturbed_nodes(n, amp=0.05)
+    Q, G, L = W.initial_state(nodes, W.taylor_green(Ma=0.3), GAM)
+    cells = np.arange(Q.shape[1])
+    ref = O.recon(n, nodes.numpy(), O.params(), Q.numpy(), G.numpy(), L.numpy(), cells)
+    ctx = K().Context([n], [nodes], K().default_params(recon_prec=recon_prec))
+    gp = torch.zeros(Q.shape[1], 24, 5, 4, dtype=torch.float64, device=dev())
+    K().cgks_recon(ctx, Q.to(dev()), G.to(dev()), L.to(dev()), gp)
+    torch.cuda.synchronize()
+    assert K().cgks_check(ctx) == (0, 0)
+    out = gp.cpu().numpy()
+    q0 = Q.numpy().T[:, None, :]
+    tol = 64 * U_SPLIT[recon_prec]
+    for v in range(5):
+        dv = ref[:, :, v, 0] - q0[:, :, v]
+        err = np.abs(out[:, :, v, 0] - ref[:, :, v, 0]).max() / max(np.abs(dv).max(), 1e-300)
+        print("value", v, err)
+        assert err <= tol, (v, err)
+        for c in range(1, 4):
+            err = np.abs(out[:, :, v, c] - ref[:, :, v, c]).max() / max(np.abs(ref[:, :, v, 1:]).max(), 1e-300)
+            print("grad", v, c, err)
+            assert err <= tol, (v, c, err)
+    ctx.close()
+
+
+@pytest.mark.parametrize("recon_prec,flux_prec", [(1, 0), (0, 1), (1, 1), (2, 0), (2, 1)])
 def test_mixed_precision_tgv_error_vs_fp64(recon_prec, flux_prec):
     n = (20, 18, 16)
     nodes = W.perturbed_nodes(n, amp=0.05)
