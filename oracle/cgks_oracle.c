@@ -26,6 +26,8 @@
  *     interface evolution for gradients / line derivatives, one-sided values
  *   - Sec. 5 (intro): CFL 0.5, viscous time-step limit, collision times
  *   - Appendix: trilinear cell map and 3x3x3 Gauss volume
+ *   - Extension of Sec. 3.3: learned blend weights (an MLP in place of chi and
+ *     omega_m), its FP64 gradient, Adam, and the features it reads
  *
  * Readings where the paper is silent are listed (D1..D22) in the design
  * notes of the repository; the ones that shape code here are named inline.
@@ -445,9 +447,12 @@ static long face_of(const or_mesh *M, long c, int m) {
 /*  Compact reconstruction with GENO blend: Sec. 3.2, 3.3, 4          */
 /* ================================================================== */
 
-/* out[g][v][0..3]: value and physical gradient at Gauss point g (=4m+k) of cell c */
+/* out[g][v][0..3]: value and physical gradient at Gauss point g (=4m+k) of cell c.
+   win: NULL, or per variable the blend weights (chi, omega_1..6) to use instead of GENO's;
+   wout: NULL, or per variable the weights (chi, omega_1..6) the blend used. */
 static void recon_cell(const or_mesh *M, const or_params *P, const double *Q, const double *G,
-                       const double *L, long c, const double *J, const double *JiT, double out[NGP][NV][4]) {
+                       const double *L, long c, const double *J, const double *JiT, const double *win,
+                       double *wout, double out[NGP][NV][4]) {
     const long N = M->n;
     int i = c % M->nx, j = (c / M->nx) % M->ny, k = c / ((long)M->nx * M->ny);
     long fnb[6], enb[12];
@@ -490,8 +495,9 @@ static void recon_cell(const or_mesh *M, const or_params *P, const double *Q, co
         }
 
         /* path function chi (GENO with IS^L from P^4), readings D1, D3 */
-        double chi = 1.0, bbar[3] = {0, 0, 0};
-        if (!P->linear) {
+        double chi = 1.0, bbar[3] = {0, 0, 0}, om[6];
+        for (int m = 0; m < 6; ++m) om[m] = 1.0 / 6.0;
+        if (!P->linear || win) {
             double ish = 0, isl = 0, ist = 0;
             for (int r = 0; r < NB; ++r)
                 for (int s = 0; s < NB; ++s) {
@@ -521,8 +527,17 @@ static void recon_cell(const or_mesh *M, const or_params *P, const double *Q, co
                 wb[m] = (1.0 / 6.0) / pow(is + eps, 5.0);
                 wsum += wb[m];
             }
+            for (int m = 0; m < 6; ++m) om[m] = wb[m] / wsum;
+            if (win) { /* learned weights given from outside (extension of Sec. 3.3) */
+                chi = win[7 * v];
+                for (int m = 0; m < 6; ++m) om[m] = win[7 * v + 1 + m];
+            }
             for (int m = 0; m < 6; ++m)
-                for (int t = 0; t < 3; ++t) bbar[t] += (wb[m] / wsum) * bm[m][t];
+                for (int t = 0; t < 3; ++t) bbar[t] += om[m] * bm[m][t];
+        }
+        if (wout) {
+            wout[7 * v] = chi;
+            for (int m = 0; m < 6; ++m) wout[7 * v + 1 + m] = om[m];
         }
 
         for (int g = 0; g < NGP; ++g) {
@@ -922,7 +937,7 @@ static int run_stage(const or_mesh *M, const or_params *P, int stage, double dt,
     face_rec *fr = malloc(sizeof(face_rec) * 3 * N);
     int bad = 0;
 #pragma omp parallel for schedule(dynamic, 16)
-    for (long c = 0; c < N; ++c) recon_cell(M, P, Q, G, L, c, &M->J0[9 * c], &M->JinvT[9 * c], rec[c]);
+    for (long c = 0; c < N; ++c) recon_cell(M, P, Q, G, L, c, &M->J0[9 * c], &M->JinvT[9 * c], NULL, NULL, rec[c]);
 #pragma omp parallel for schedule(dynamic, 16) reduction(| : bad)
     for (long f = 0; f < 3 * N; ++f) {
         long c = f / 3;
@@ -1019,7 +1034,7 @@ int oracle_recon(const int dims[3], const double *nodes, const or_params *P, con
     if (st) { if (M.n > 0) mesh_free(&M); return st; }
 #pragma omp parallel for schedule(dynamic, 4)
     for (long t = 0; t < ncells; ++t)
-        recon_cell(&M, P, Q, G, L, cells[t], &M.J0[9 * cells[t]], &M.JinvT[9 * cells[t]],
+        recon_cell(&M, P, Q, G, L, cells[t], &M.J0[9 * cells[t]], &M.JinvT[9 * cells[t]], NULL, NULL,
                    (double (*)[NV][4])(out + (size_t)t * NGP * NV * 4));
     mesh_free(&M);
     return OR_OK;
@@ -1154,7 +1169,7 @@ int oracle_stage1_cells(const int dims[3], const double *nodes, const or_params 
             double vol, J[9], JiT[9];
             bad |= cell_geom(&M, iw, jw, kw, &vol, J, JiT);
             if (w == 0) vol0 = vol;
-            recon_cell(&M, P, Q, G, L, cw, J, JiT, rec[w]);
+            recon_cell(&M, P, Q, G, L, cw, J, JiT, NULL, NULL, rec[w]);
         }
         face_rec fr[6];
         double fn[6][12], fw[6][4];
@@ -1183,4 +1198,181 @@ int oracle_stage1_cells(const int dims[3], const double *nodes, const or_params 
         cell_update(1, dt, vol0, fs, fnp, fwp, N, c, Q, G, L, NULL, outQ + 5 * t, outG + 15 * t, outL + 60 * t, 0);
     }
     return bad ? ((bad & 2) ? OR_ENONPHYS : OR_EINVAL) : OR_OK;
+}
+
+/* ================================================================== */
+/*  Learned blend weights (extension of Sec. 3.3): features, jump      */
+/*  indicator, an MLP 18 -> 32 -> 7 and its training                  */
+/* ================================================================== */
+/*
+ * The MLP stands in for the nonlinear weights of Sec. 3.3: output 0 gives chi of
+ * eq. (weno-new) through a logistic sigmoid, outputs 1..6 the normalised weights
+ * omega_m of the six linear sub-polynomials of eq. (compact-sub-2) through a softmax.
+ * Input (reading D19): per cell and conserved variable the 6 face-neighbour differences
+ * Q_{1,m} - Q_0 (face order m = 2q + s) and the 12 line derivatives L_s of the cell,
+ * divided by (max of their magnitudes + 1e-12).  Hidden layer: 32 ReLU units.
+ * Parameter vector: W1[32][18], b1[32], W2[7][32], b2[7] (839 values).
+ * The paper defines none of this; the network is judged by the solution it produces.
+ */
+#define MLP_IN 18
+#define MLP_H 32
+#define MLP_OUT 7
+#define MLP_NPAR (MLP_H * MLP_IN + MLP_H + MLP_OUT * MLP_H + MLP_OUT)
+
+static void mlp_fwd(const double *w, const double *x, double h[MLP_H], double z[MLP_OUT], double y[MLP_OUT]) {
+    const double *W1 = w, *b1 = w + MLP_H * MLP_IN, *W2 = b1 + MLP_H, *b2 = W2 + MLP_OUT * MLP_H;
+    for (int j = 0; j < MLP_H; ++j) {
+        double s = b1[j];
+        for (int i = 0; i < MLP_IN; ++i) s += W1[j * MLP_IN + i] * x[i];
+        h[j] = s > 0.0 ? s : 0.0;
+    }
+    for (int o = 0; o < MLP_OUT; ++o) {
+        double s = b2[o];
+        for (int j = 0; j < MLP_H; ++j) s += W2[o * MLP_H + j] * h[j];
+        z[o] = s;
+    }
+    y[0] = 1.0 / (1.0 + exp(-z[0]));
+    double zmax = z[1];
+    for (int o = 2; o < MLP_OUT; ++o) zmax = z[o] > zmax ? z[o] : zmax;
+    double den = 0.0;
+    for (int o = 1; o < MLP_OUT; ++o) den += exp(z[o] - zmax);
+    for (int o = 1; o < MLP_OUT; ++o) y[o] = exp(z[o] - zmax) / den;
+}
+
+/* Y[n][7] = MLP(X[n][18]); H[n][32] hidden activations (may be NULL). */
+int oracle_mlp_forward(const double *w, long n, const double *X, double *Y, double *H) {
+    for (long s = 0; s < n; ++s) {
+        double h[MLP_H], z[MLP_OUT];
+        mlp_fwd(w, X + s * MLP_IN, h, z, Y + s * MLP_OUT);
+        if (H) memcpy(H + s * MLP_H, h, sizeof h);
+    }
+    return OR_OK;
+}
+
+/* Loss (1/n) sum_s sum_o (y_so - T_so)^2 and its gradient with respect to the 839
+   parameters, by the chain rule through softmax, sigmoid, the second layer, ReLU and
+   the first layer. */
+int oracle_mlp_loss_grad(const double *w, long n, const double *X, const double *T, double *loss,
+                         double *grad) {
+    const double *W2 = w + MLP_H * MLP_IN + MLP_H;
+    double *gW1 = grad, *gb1 = grad + MLP_H * MLP_IN, *gW2 = gb1 + MLP_H, *gb2 = gW2 + MLP_OUT * MLP_H;
+    memset(grad, 0, sizeof(double) * MLP_NPAR);
+    double L = 0.0;
+    if (n <= 0) { *loss = 0.0; return OR_EINVAL; }
+    for (long s = 0; s < n; ++s) {
+        const double *x = X + s * MLP_IN, *t = T + s * MLP_OUT;
+        double h[MLP_H], z[MLP_OUT], y[MLP_OUT], dy[MLP_OUT], dz[MLP_OUT], dh[MLP_H];
+        mlp_fwd(w, x, h, z, y);
+        for (int o = 0; o < MLP_OUT; ++o) {
+            L += (y[o] - t[o]) * (y[o] - t[o]);
+            dy[o] = 2.0 * (y[o] - t[o]) / (double)n;
+        }
+        dz[0] = dy[0] * y[0] * (1.0 - y[0]);
+        double sdot = 0.0;
+        for (int o = 1; o < MLP_OUT; ++o) sdot += dy[o] * y[o];
+        for (int o = 1; o < MLP_OUT; ++o) dz[o] = y[o] * (dy[o] - sdot);
+        for (int o = 0; o < MLP_OUT; ++o) {
+            gb2[o] += dz[o];
+            for (int j = 0; j < MLP_H; ++j) gW2[o * MLP_H + j] += dz[o] * h[j];
+        }
+        for (int j = 0; j < MLP_H; ++j) {
+            double sacc = 0.0;
+            for (int o = 0; o < MLP_OUT; ++o) sacc += W2[o * MLP_H + j] * dz[o];
+            dh[j] = h[j] > 0.0 ? sacc : 0.0;
+            gb1[j] += dh[j];
+            for (int i = 0; i < MLP_IN; ++i) gW1[j * MLP_IN + i] += dh[j] * x[i];
+        }
+    }
+    *loss = L / (double)n;
+    return OR_OK;
+}
+
+/* One Adam step (Kingma & Ba 2015) at step number t >= 1, in place on w, m, v. */
+int oracle_adam(long n, double *w, double *m, double *v, const double *g, int t, double lr, double b1,
+                double b2, double eps) {
+    if (t < 1) return OR_EINVAL;
+    const double c1 = 1.0 - pow(b1, t), c2 = 1.0 - pow(b2, t);
+    for (long i = 0; i < n; ++i) {
+        m[i] = b1 * m[i] + (1.0 - b1) * g[i];
+        v[i] = b2 * v[i] + (1.0 - b2) * g[i] * g[i];
+        w[i] -= lr * (m[i] / c1) / (sqrt(v[i] / c2) + eps);
+    }
+    return OR_OK;
+}
+
+/* Round to the nearest BF16 value, ties to even, through binary32 (x -> float -> bf16). */
+int oracle_bf16(long n, const double *in, double *out) {
+    for (long i = 0; i < n; ++i) {
+        float f = (float)in[i];
+        unsigned int u;
+        memcpy(&u, &f, 4);
+        if ((u & 0x7f800000u) != 0x7f800000u) {
+            u += 0x7fffu + ((u >> 16) & 1u);
+            u &= 0xffff0000u;
+        }
+        memcpy(&f, &u, 4);
+        out[i] = (double)f;
+    }
+    return OR_OK;
+}
+
+static double pressure_of(const or_params *P, const double *Q, long N, long c) {
+    const double r = Q[c], mu = Q[N + c], mv = Q[2 * N + c], mw = Q[3 * N + c], E = Q[4 * N + c];
+    return (P->gamma - 1.0) * (E - 0.5 * (mu * mu + mv * mv + mw * mw) / r);
+}
+
+/* Features X[ncells][5][18] of the listed cells and the jump indicator
+   jump[ncells] = (max_m |p_{1,m} - p_0| / (p_{1,m} + p_0) > thresh). */
+int oracle_features(const int dims[3], const double *nodes, const or_params *P, const double *Q,
+                    const double *L, const long *cells, long ncells, double thresh, double *X, int *jump) {
+    or_mesh M;
+    int st = mesh_build(&M, dims, nodes);
+    if (st) { if (M.n > 0) mesh_free(&M); return st; }
+    const long N = M.n;
+    for (long t = 0; t < ncells; ++t) {
+        const long c = cells[t];
+        int i = c % M.nx, j = (c / M.nx) % M.ny, k = c / ((long)M.nx * M.ny);
+        long nb[6];
+        for (int m = 0; m < 6; ++m) {
+            double o[3]; face_offset(m, o);
+            nb[m] = cell_id(&M, i + (int)o[0], j + (int)o[1], k + (int)o[2]);
+        }
+        const double p0 = pressure_of(P, Q, N, c);
+        double ind = 0.0;
+        for (int m = 0; m < 6; ++m) {
+            const double pm = pressure_of(P, Q, N, nb[m]);
+            const double r = fabs(pm - p0) / (pm + p0);
+            ind = r > ind ? r : ind;
+        }
+        if (jump) jump[t] = ind > thresh;
+        if (X) {
+            for (int v = 0; v < NV; ++v) {
+                double f[MLP_IN], mx = 0.0;
+                for (int m = 0; m < 6; ++m) f[m] = Q[v * N + nb[m]] - Q[v * N + c];
+                for (int s = 0; s < 12; ++s) f[6 + s] = L[(v * 12 + s) * N + c];
+                for (int a = 0; a < MLP_IN; ++a) mx = fabs(f[a]) > mx ? fabs(f[a]) : mx;
+                for (int a = 0; a < MLP_IN; ++a) X[(t * NV + v) * MLP_IN + a] = f[a] / (mx + 1e-12);
+            }
+        }
+    }
+    mesh_free(&M);
+    return OR_OK;
+}
+
+/* Reconstruction of the listed cells with given blend weights win[ncells][5][7] (chi,
+   omega_1..6), or GENO's if win is NULL; the weights used go to wout (may be NULL). */
+int oracle_recon_weights(const int dims[3], const double *nodes, const or_params *P, const double *Q,
+                         const double *G, const double *L, const long *cells, long ncells, const double *win,
+                         double *out, double *wout) {
+    init_consts();
+    or_mesh M;
+    int st = mesh_build(&M, dims, nodes);
+    if (st) { if (M.n > 0) mesh_free(&M); return st; }
+#pragma omp parallel for schedule(dynamic, 4)
+    for (long t = 0; t < ncells; ++t)
+        recon_cell(&M, P, Q, G, L, cells[t], &M.J0[9 * cells[t]], &M.JinvT[9 * cells[t]],
+                   win ? win + (size_t)t * NV * 7 : NULL, wout ? wout + (size_t)t * NV * 7 : NULL,
+                   (double (*)[NV][4])(out + (size_t)t * NGP * NV * 4));
+    mesh_free(&M);
+    return OR_OK;
 }

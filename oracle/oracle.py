@@ -84,6 +84,13 @@ def lib():
         L.oracle_s2o4.argtypes = [C.c_long, C.c_double, dp, dp, dp, dp, dp, dp]
         L.oracle_stage1_cells.argtypes = [ip, dp, pp, C.c_double, dp, dp, dp, lp, C.c_long, dp, dp, dp]
         L.oracle_num_threads.restype = C.c_int
+        L.oracle_mlp_forward.argtypes = [dp, C.c_long, dp, dp, dp]
+        L.oracle_mlp_loss_grad.argtypes = [dp, C.c_long, dp, dp, dp, dp]
+        L.oracle_adam.argtypes = [C.c_long, dp, dp, dp, dp, C.c_int, C.c_double, C.c_double, C.c_double,
+                                  C.c_double]
+        L.oracle_bf16.argtypes = [C.c_long, dp, dp]
+        L.oracle_features.argtypes = [ip, dp, pp, dp, dp, lp, C.c_long, C.c_double, dp, ip]
+        L.oracle_recon_weights.argtypes = [ip, dp, pp, dp, dp, dp, lp, C.c_long, dp, dp, dp]
         _lib = L
     return _lib
 
@@ -193,3 +200,74 @@ def stage1_cells(dims, nodes, prm, dt, Q, G, L, cells):
     st = lib().oracle_stage1_cells(_dims(dims), _d(nodes), C.byref(prm), float(dt), _d(Q), _d(G), _d(L),
                                    cells.ctypes.data_as(C.POINTER(C.c_long)), n, _d(oq), _d(og), _d(ol))
     return st, oq, og, ol
+
+
+# ---- learned blend weights (MLP 18 -> 32 -> 7) --------------------------------------------
+MLP_IN, MLP_H, MLP_OUT = 18, 32, 7
+MLP_NPAR = MLP_H * MLP_IN + MLP_H + MLP_OUT * MLP_H + MLP_OUT
+
+
+def mlp_forward(w, X):
+    """Outputs [n, 7] (chi, omega_1..6) and hidden activations [n, 32] of the FP64 MLP."""
+    w, X = _arr(w), _arr(X)
+    n = X.shape[0]
+    Y = np.zeros((n, MLP_OUT)); H = np.zeros((n, MLP_H))
+    lib().oracle_mlp_forward(_d(w), n, _d(X), _d(Y), _d(H))
+    return Y, H
+
+
+def mlp_loss_grad(w, X, T):
+    """Mean-square loss over the batch and its gradient [839]."""
+    w, X, T = _arr(w), _arr(X), _arr(T)
+    g = np.zeros(MLP_NPAR)
+    loss = C.c_double(0)
+    st = lib().oracle_mlp_loss_grad(_d(w), X.shape[0], _d(X), _d(T), C.byref(loss), _d(g))
+    if st:
+        raise ValueError(f"oracle_mlp_loss_grad status {st}")
+    return loss.value, g
+
+
+def adam(w, m, v, g, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+    """One Adam step on copies; returns (w, m, v)."""
+    w, m, v, g = (_arr(a).copy() for a in (w, m, v, g))
+    st = lib().oracle_adam(w.size, _d(w), _d(m), _d(v), _d(g), int(t), float(lr), float(b1), float(b2), float(eps))
+    if st:
+        raise ValueError(f"oracle_adam status {st}")
+    return w, m, v
+
+
+def bf16(x):
+    """Round to BF16 (nearest, ties to even) through binary32."""
+    x = _arr(x)
+    out = np.zeros_like(x)
+    lib().oracle_bf16(x.size, _d(x), _d(out))
+    return out
+
+
+def features(dims, nodes, prm, Q, L, cells, thresh=0.05):
+    """MLP input features [ncells, 5, 18] and jump indicator [ncells] of the listed cells."""
+    nodes, Q, L = _arr(nodes), _arr(Q), _arr(L)
+    cells = np.ascontiguousarray(cells, dtype=np.int64)
+    X = np.zeros((len(cells), 5, MLP_IN))
+    jump = np.zeros(len(cells), dtype=np.int32)
+    st = lib().oracle_features(_dims(dims), _d(nodes), C.byref(prm), _d(Q), _d(L),
+                               cells.ctypes.data_as(C.POINTER(C.c_long)), len(cells), float(thresh), _d(X),
+                               jump.ctypes.data_as(C.POINTER(C.c_int)))
+    if st:
+        raise ValueError(f"oracle_features status {st}")
+    return X, jump.astype(bool)
+
+
+def recon_weights(dims, nodes, prm, Q, G, L, cells, win=None):
+    """Reconstruction of the listed cells with given blend weights win [ncells, 5, 7] (or GENO's
+    if None); returns (gp [ncells, 24, 5, 4], weights used [ncells, 5, 7])."""
+    nodes, Q, G, L = _arr(nodes), _arr(Q), _arr(G), _arr(L)
+    cells = np.ascontiguousarray(cells, dtype=np.int64)
+    out = np.zeros((len(cells), 24, 5, 4))
+    wout = np.zeros((len(cells), 5, 7))
+    wp = None if win is None else _d(_arr(win))
+    st = lib().oracle_recon_weights(_dims(dims), _d(nodes), C.byref(prm), _d(Q), _d(G), _d(L),
+                                    cells.ctypes.data_as(C.POINTER(C.c_long)), len(cells), wp, _d(out), _d(wout))
+    if st:
+        raise ValueError(f"oracle_recon_weights status {st}")
+    return out, wout
