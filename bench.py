@@ -12,6 +12,7 @@ Prints one JSON line.  --gpus N > 1 is not supported (single-GPU build).
 """
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -69,6 +70,174 @@ def roofline(prof, N, peak_key):
     return roof
 
 
+def hit_kw():
+    # isotropic turbulence: rho 1, p 1/gamma (T = 1/gamma), Re_lambda 72 at u' = 0.2887, lambda 0.5
+    T0 = 1.0 / GAM
+    return dict(viscous=1, visc_law=1, mu0=2.0e-3, T_ref=T0, S_suth=T0 * 110.4 / 288.15, Pr=0.72, prandtl_fix=1)
+
+
+def bench_batching(K, W, torch, steps, warmup):
+    """Multi-block workload: 24 uneven periodic curvilinear blocks (seeded sizes) of decaying
+    isotropic turbulence (Mt 0.5, k0 4), FP64.  Per-block launches against one launch per
+    kernel over all blocks, with default and autotuned tiles, eager and graph-replayed."""
+    dev = torch.device("cuda:0")
+    dims = W.multiblock_dims()
+    N = sum(a * b * c for a, b, c in dims)
+    nodes_h, Qs, Gs, Ls = [], [], [], []
+    for b, n in enumerate(dims):
+        nd = W.perturbed_nodes(n, amp=0.05, device=dev)
+        q, g, l = W.initial_state(nd, W.isotropic_turbulence(64, k0=4.0, Mt=0.5, seed=8965 + b), GAM)
+        Qs.append(q)
+        Gs.append(g)
+        Ls.append(l)
+        nodes_h.append(nd.cpu())
+        del nd
+    Q0 = torch.cat(Qs, dim=1).contiguous()
+    G0 = torch.cat(Gs, dim=2).contiguous()
+    L0 = torch.cat(Ls, dim=2).contiguous()
+    del Qs, Gs, Ls
+    dt = torch.zeros(1, dtype=torch.float64, device=dev)
+    out = {"workload": f"{len(dims)} periodic perturbed curvilinear blocks, sizes from seed 8965 in "
+                       "[32,160]x[32,96]x[32,64], decaying isotropic turbulence Mt 0.5 k0 4 Re_lambda 72, FP64",
+           "cells": N, "blocks": len(dims), "variants": []}
+
+    def run(ctx, label, graph=False):
+        Q, G, L = Q0.clone(), G0.clone(), L0.clone()
+        step = K.cgks_step_graph if graph else K.cgks_step
+        for _ in range(warmup):
+            step(ctx, Q, G, L, dt, use_cfl=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            step(ctx, Q, G, L, dt, use_cfl=True)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        st = K.cgks_check(ctx)
+        out["variants"].append({"variant": label, "value": N * steps / el, "unit": "cell-updates/s",
+                                "ms_per_step": 1e3 * el / steps, "device_flags": st[1]})
+        return Q
+
+    ctx = K.Context(dims, nodes_h, K.default_params(per_block=1, **hit_kw()))
+    Qa = run(ctx, "per-block launches (3 kernels x 24 blocks per stage)")
+    ctx.close()
+    torch.cuda.empty_cache()
+    ctx = K.Context(dims, nodes_h, K.default_params(**hit_kw()))
+    Qb = run(ctx, "one launch per kernel over all blocks, default tiles")
+    out["bitwise_equal_to_per_block"] = bool(torch.equal(Qa, Qb))
+    del Qa, Qb
+    K.cgks_dt(ctx, Q0, dt)
+    tune = K.cgks_autotune(ctx, Q0, G0, L0, dt, reps=2)
+    out["autotune"] = {"candidates": tune, "picked": {K.KIND_NAMES[k]: K.cgks_get_launch(ctx, k) for k in (1, 2, 3)}}
+    run(ctx, "one launch per kernel over all blocks, autotuned")
+    run(ctx, "one launch per kernel over all blocks, autotuned, HIP graph of dt + 2 stages", graph=True)
+    ctx.close()
+    torch.cuda.empty_cache()
+    return out
+
+
+def bench_learned(K, W, torch, n_eval=256, n_train=64, eval_steps=50, train_steps=1500):
+    """Learned blend weights on supersonic isotropic turbulence (Mt 1.0, k0 8, Re_lambda 100):
+    pairs (features, GENO weights) from the plain FP64 scheme at n_train^3 (seeds 8967-8970, run
+    to t ~ lambda/u'), balanced between chi < 0.99 and chi ~ 1; FP32 Adam training on the GPU;
+    then n_eval^3 (seed 8966) advanced eval_steps steps with learned and with GENO weights."""
+    import numpy as np
+    dev = torch.device("cuda:0")
+    T0 = 1.0 / GAM
+    kw = dict(viscous=1, visc_law=1, mu0=1.44e-3, T_ref=T0, S_suth=T0 * 110.4 / 288.15, Pr=0.72, prandtl_fix=1)
+    two_pi = 2.0 * math.pi
+    t_end = 0.25 / 0.5774
+    # ---- training pairs -------------------------------------------------------------------------
+    m = (n_train,) * 3
+    nodes_m = W.cartesian_nodes(m, hi=(two_pi,) * 3)
+    Xs, Ts = [], []
+    gen = K.Context([m], [nodes_m], K.default_params(**kw))
+    N = n_train ** 3
+    X = torch.zeros(N * 5, 18, dtype=torch.float32, device=dev)
+    Wt = torch.zeros(N * 5, 7, dtype=torch.float64, device=dev)
+    rng = torch.Generator(device="cpu").manual_seed(8965)
+    for seed in (8967, 8968, 8969, 8970):
+        Q, G, L = W.initial_state(nodes_m.to(dev), W.isotropic_turbulence(64, k0=8.0, Mt=1.0, seed=seed), GAM)
+        dt = torch.zeros(1, dtype=torch.float64, device=dev)
+        t, k = 0.0, 0
+        while t < t_end and k < 400:
+            K.cgks_step(gen, Q, G, L, dt, use_cfl=True)
+            t += dt.item()
+            k += 1
+            if k % 10 == 0 or t >= t_end:
+                K.cgks_weights(gen, Q, G, L, X, Wt)
+                low = (Wt[:, 0] < 0.99).nonzero().squeeze(1)
+                high = (Wt[:, 0] >= 0.99).nonzero().squeeze(1)
+                take = max(1, min(len(low), 20000))
+                pick_l = low[torch.randperm(len(low), generator=rng)[:take].to(dev)] if len(low) else low
+                pick_h = high[torch.randperm(len(high), generator=rng)[:take].to(dev)]
+                idx = torch.cat([pick_l, pick_h])
+                Xs.append(X[idx].clone())
+                Ts.append(Wt[idx].float())
+        K.cgks_check(gen)
+    gen.close()
+    Xtr = torch.cat(Xs)
+    Ttr = torch.cat(Ts)
+    perm = torch.randperm(Xtr.shape[0], generator=rng).to(dev)
+    Xtr, Ttr = Xtr[perm].contiguous(), Ttr[perm].contiguous()
+    frac_low = float((Ttr[:, 0] < 0.99).float().mean())
+    del Xs, Ts, X, Wt
+    # ---- evaluation mesh and training ---------------------------------------------------------
+    e = (n_eval,) * 3
+    nodes_e = W.cartesian_nodes(e, hi=(two_pi,) * 3)
+    ctx = K.Context([e], [nodes_e], K.default_params(weights=1, **kw))
+    K.cgks_mlp_init(ctx, 8965)
+    torch.cuda.synchronize()
+    tt = time.perf_counter()
+    hist = K.cgks_mlp_train(ctx, Xtr, Ttr, steps=train_steps, batch=4096, lr=1e-3)
+    t_train = time.perf_counter() - tt
+    Q0, G0, L0 = W.initial_state(nodes_e.to(dev), W.isotropic_turbulence(128, k0=8.0, Mt=1.0, seed=8966), GAM)
+    Ne = n_eval ** 3
+    dt = torch.zeros(1, dtype=torch.float64, device=dev)
+
+    def run(c):
+        Q, G, L = Q0.clone(), G0.clone(), L0.clone()
+        K.cgks_step(c, Q, G, L, dt, use_cfl=True)
+        torch.cuda.synchronize()
+        Q.copy_(Q0)
+        G.copy_(G0)
+        L.copy_(L0)
+        t0 = time.perf_counter()
+        for _ in range(eval_steps):
+            K.cgks_step(c, Q, G, L, dt, use_cfl=True)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        return Q, el, K.cgks_check(c)
+
+    K.cgks_mlp_fallback(ctx)
+    Qm, el_m, st_m = run(ctx)
+    flagged, examined = K.cgks_mlp_fallback(ctx)
+    ctx.close()
+    torch.cuda.empty_cache()
+    plain = K.Context([e], [nodes_e], K.default_params(**kw))
+    Qp, el_p, st_p = run(plain)
+    plain.close()
+
+    def errs(a, b):
+        d = a - b
+        return {"rel_l2": float(torch.linalg.vector_norm(d) / torch.linalg.vector_norm(b)),
+                "rel_linf": float(d.abs().max() / b.abs().max())}
+
+    speed = lambda q: torch.sqrt(q[1] ** 2 + q[2] ** 2 + q[3] ** 2) / q[0]
+    return {
+        "workload": f"isotropic turbulence Mt 1.0 k0 8 Re_lambda 100, {n_eval}^3 periodic Cartesian, FP64; MLP "
+                    f"18-32-7 trained on {Xtr.shape[0]} balanced pairs from {n_train}^3 runs (4 seeds, t <= {t_end:.3f})",
+        "train": {"steps": train_steps, "batch": 4096, "lr": 1e-3, "seconds": t_train,
+                  "loss_first10": float(np.mean(hist[:10])), "loss_last100": float(np.mean(hist[-100:])),
+                  "pairs": int(Xtr.shape[0]), "fraction_chi_below_0.99": frac_low},
+        "learned": {"value": Ne * eval_steps / el_m, "unit": "cell-updates/s", "ms_per_step": 1e3 * el_m / eval_steps,
+                    "fallback_fraction": flagged / max(examined, 1), "device_flags": st_m[1]},
+        "geno": {"value": Ne * eval_steps / el_p, "unit": "cell-updates/s", "ms_per_step": 1e3 * el_p / eval_steps,
+                 "device_flags": st_p[1]},
+        "learned_vs_geno_after_steps": {"steps": eval_steps, "rho": errs(Qm[0], Qp[0]),
+                                        "speed": errs(speed(Qm), speed(Qp)), "rhoE": errs(Qm[4], Qp[4])},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -78,6 +247,8 @@ def main():
     ap.add_argument("--no-oracle", action="store_true", help="skip the sampled parity check and the CPU baseline")
     ap.add_argument("--no-variants", action="store_true", help="skip the reduced-precision variant")
     ap.add_argument("--error-steps", type=int, default=50, help="steps for the variant error against FP64")
+    ap.add_argument("--no-batching", action="store_true", help="skip the multi-block batching measurement")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-weight measurement")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported", file=sys.stderr)
@@ -191,20 +362,30 @@ def main():
     else:
         ctx.close()
 
+    # ---- multi-block batching ------------------------------------------------------------------
+    batching = None
+    if not args.no_batching:
+        batching = bench_batching(K, W, torch, args.steps, args.warmup)
+
+    # ---- learned blend weights -----------------------------------------------------------------
+    learned = None
+    if not args.no_learned:
+        learned = bench_learned(K, W, torch)
+
     # ---- CPU baseline: the oracle on a bounded sample of the same workload ------------------
     cpu = None
     if not args.no_oracle:
         from oracle import oracle as O
-        m = 64
+        m, ksteps = 96, 3
         ns = (m, m, m)
         nd = W.perturbed_nodes(ns, amp=0.05)
         Qs, Gs, Ls = W.initial_state(nd, W.taylor_green(Ma=0.1), GAM)
         tc = time.perf_counter()
-        st, *_ = O.run(ns, nd.numpy(), O.params(**kw), Qs.numpy(), Gs.numpy(), Ls.numpy(), 2)
+        st, *_ = O.run(ns, nd.numpy(), O.params(**kw), Qs.numpy(), Gs.numpy(), Ls.numpy(), ksteps)
         tc = time.perf_counter() - tc
-        cpu = {"value": 2 * m ** 3 / tc, "unit": "cell-updates/s", "cores": O.num_threads(), "kind": "oracle",
-               "sample": f"two S2O4 steps (CFL dt + 2 stages each) of the same TGV workload on a {m}^3 perturbed "
-                         f"mesh, {tc:.1f} s", "status": st}
+        cpu = {"value": ksteps * m ** 3 / tc, "unit": "cell-updates/s", "cores": O.num_threads(), "kind": "oracle",
+               "sample": f"{ksteps} S2O4 steps (CFL dt + 2 stages each) of the same TGV workload on a {m}^3 "
+                         f"perturbed mesh, {tc:.1f} s", "status": st}
 
     out = {
         "metric": "cell-updates/sec per S2O4 step at 256^3 TGV + L2 error vs FP64 oracle",
@@ -225,6 +406,8 @@ def main():
         "roofline": roof,
         "parity_vs_oracle": parity,
         "variants": variants,
+        "batching": batching,
+        "learned_weights": learned,
         "cpu_baseline": cpu,
         "device_flags": flags,
     }

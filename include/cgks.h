@@ -78,6 +78,14 @@ typedef struct {
                             and the S2O4 accumulation of Q, G, L stay FP64                  */
     int recon_impl;      /* reconstruction kernel: 0 matrix cores (MFMA, default),
                             1 vector-ALU kernel (one thread per cell and variable)          */
+    int per_block;       /* multi-block launches: 0 one launch per kernel covering every
+                            block (work list of tiles over all blocks, default); 1 one
+                            launch per kernel and block (the comparison baseline)          */
+    int weights;         /* blend weights: 0 GENO (Sec. 3.3); 1 learned (MLP, see below)
+                            with GENO where the jump indicator fires.  1 needs the FP64
+                            matrix-core reconstruction and the nonlinear scheme            */
+    double jump_thresh;  /* jump indicator: max over face neighbours m of
+                            |p_m - p_0| / (p_m + p_0) above this (default 0.05)            */
 } cgks_params;
 
 /* Fill *p with the defaults listed above (inviscid, nonlinear, FP64). */
@@ -154,6 +162,99 @@ int cgks_metrics(cgks_ctx *ctx, double *vol, double *J0, double *fn, double *fw,
 #define CGKS_NKINDS 4
 int cgks_profile(cgks_ctx *ctx, int enable);
 int cgks_profile_read(cgks_ctx *ctx, double *ms, long *launches);
+
+/* ---- Multi-block launches, autotuning and graph replay ------------------------------------
+ * The reconstruction, flux and update kernels walk a work list of tiles (runs of consecutive
+ * cells of one block) that spans every block, so one launch per kernel advances the whole
+ * multi-block mesh.  Launch configuration per kernel kind (1 reconstruction, 2 flux, 3 update):
+ *   tile_cells  cells per tile.  Reconstruction: a multiple of 16 in [16, 4096] (one
+ *               workgroup of 8 waves takes a tile; a wave takes 16 cells of one variable);
+ *               flux 128 and update 256 are fixed by their workgroup size.
+ *   ngroups     0: one workgroup per unit (tile, or tile and Gauss point for the flux);
+ *               > 0: a persistent grid of that many workgroups striding over the units
+ *               (reconstruction and update; the flux takes 0 only).
+ *   xcd         1: the workgroups on XCD x (w mod 8 == x) walk the x-th contiguous eighth of
+ *               the units (a persistent grid must then be a multiple of 8); 0: plain order.
+ * The arithmetic of a cell does not depend on the configuration: results are bitwise equal
+ * for every choice. */
+typedef struct {
+    int tile_cells;
+    int ngroups;
+    int xcd;
+} cgks_launch;
+
+/* Read the launch configuration of a kernel kind (1, 2 or 3) into *out (host). */
+int cgks_get_launch(const cgks_ctx *ctx, int kind, cgks_launch *out);
+
+/* Set the launch configuration of a kernel kind (host, copied).  Rebuilds the work list on
+ * the device (synchronises the device); not for use under HIP graph capture. */
+int cgks_set_launch(cgks_ctx *ctx, int kind, const cgks_launch *cfg);
+
+/* Autotuner: times candidate configurations of the reconstruction (tile size per block-size
+ * class: blocks below 2^17 cells, below 2^19, and larger; then grid and XCD order) and of the
+ * flux (XCD order) on the given state with HIP events, and keeps the fastest.
+ * Q, G, L, dt_dev: device state and time step (read only; the stage buffers of the context
+ * are overwritten).  reps: timed launches per candidate (>= 1).  report: host array of at
+ * least 64 doubles or NULL; receives per candidate (kind, tile_cells, ngroups, xcd, ms),
+ * preceded by the number of candidates.  Synchronises the stream; not capturable. */
+int cgks_autotune(cgks_ctx *ctx, const double *Q, const double *G, const double *L, const double *dt_dev,
+                  int reps, double *report, int report_len, void *stream);
+
+/* One S2O4 step as cgks_step, replayed from a HIP graph of [dt,] stage 1 and stage 2 that the
+ * context captures on first use and captures again when Q, G, L, dt_dev or use_cfl change.
+ * Launches the graph on `stream`.  Capture allocates the graph (once); replays allocate
+ * nothing.  Profiling events are not recorded for graph replays. */
+int cgks_step_graph(cgks_ctx *ctx, double *Q, double *G, double *L, double *dt_dev, int use_cfl,
+                    void *stream);
+
+/* ---- Learned blend weights ---------------------------------------------------------------
+ * An MLP 18 -> 32 (ReLU) -> 7 stands in for the nonlinear weights of Sec. 3.3: output 0 gives
+ * chi through a sigmoid, outputs 1..6 the weights omega_m of the six linear sub-polynomials
+ * through a softmax.  Inputs per cell and conserved variable: the 6 face-neighbour differences
+ * Q_{1,m} - Q_0 (m = 2q + s) and the 12 line derivatives L_s, divided by (their largest
+ * magnitude + 1e-12).  Parameters: FP32, 839 values W1[32][18], b1[32], W2[7][32], b2[7].
+ * Inference inside the reconstruction runs in BF16 on the matrix cores (FP32 accumulation);
+ * training runs in FP32 (mean over the batch of the squared error of the 7 outputs, Adam
+ * with beta1 0.9, beta2 0.999, eps 1e-8).  Feature and target arrays are device FP32,
+ * row-major [n][18] and [n][7]. */
+#define CGKS_MLP_PARAMS 839
+
+/* Initialise the parameters from a seed (uniform He initialisation, zero biases) and reset
+ * the Adam moments.  Synchronous. */
+int cgks_mlp_init(cgks_ctx *ctx, unsigned long long seed);
+
+/* Set / read the FP32 parameters (host arrays of n = CGKS_MLP_PARAMS).  Setting resets the
+ * Adam moments.  Synchronous. */
+int cgks_mlp_set(cgks_ctx *ctx, const float *w, int n);
+int cgks_mlp_get(cgks_ctx *ctx, float *w, int n);
+
+/* Gradient of the mean squared error over the n samples (X [n][18], T [n][7], device FP32)
+ * into grad (device, CGKS_MLP_PARAMS floats) and loss (device, 1 float).  Allocates a
+ * scratch of 72 n floats on first use (grows as needed). */
+int cgks_mlp_grad(cgks_ctx *ctx, const float *X, const float *T, long n, float *grad, float *loss,
+                  void *stream);
+
+/* `steps` Adam steps with batches of `batch` samples taken in order, wrapping around the n
+ * samples (step k uses samples k*batch .. k*batch+batch-1 mod n).  loss_hist: host array of
+ * `steps` floats for the batch losses, or NULL.  Synchronises the stream when loss_hist is
+ * given. */
+int cgks_mlp_train(cgks_ctx *ctx, const float *X, const float *T, long n, int steps, int batch, float lr,
+                   float *loss_hist, void *stream);
+
+/* BF16 inference of the current parameters on given features: Y [n][7] device doubles
+ * (chi, omega_1..6), exactly as the reconstruction evaluates them. */
+int cgks_mlp_infer(cgks_ctx *ctx, const float *X, long n, double *Y, void *stream);
+
+/* Reconstruction of the state that also reports, per cell and variable (sample index
+ * 5 c + v), the learned-weight input features X [N*5][18] (device FP32), the blend weights
+ * used Wt [N*5][7] (device doubles: chi, omega_1..6) and the jump flags jump [N] (device
+ * bytes, may be NULL).  FP64 contexts with the nonlinear scheme only. */
+int cgks_weights(cgks_ctx *ctx, const double *Q, const double *G, const double *L, float *X, double *Wt,
+                 unsigned char *jump, void *stream);
+
+/* Cells flagged by the jump indicator and cells examined since the last call (host outputs;
+ * synchronises the stream). */
+int cgks_mlp_fallback(cgks_ctx *ctx, long long *flagged, long long *examined);
 
 /* Message of the last failing call on this thread ("" if none). */
 const char *cgks_last_error(void);

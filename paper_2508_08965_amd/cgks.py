@@ -25,7 +25,14 @@ class Params(C.Structure):
         ("geno_C", C.c_double), ("geno_eps", C.c_double), ("geno_r", C.c_double),
         ("viscous", C.c_int), ("visc_law", C.c_int), ("tau_zero", C.c_int), ("linear", C.c_int),
         ("prandtl_fix", C.c_int), ("recon_prec", C.c_int), ("flux_prec", C.c_int), ("recon_impl", C.c_int),
+        ("per_block", C.c_int), ("weights", C.c_int), ("jump_thresh", C.c_double),
     ]
+
+
+class Launch(C.Structure):
+    """Mirror of cgks_launch."""
+
+    _fields_ = [("tile_cells", C.c_int), ("ngroups", C.c_int), ("xcd", C.c_int)]
 
 
 _lib = None
@@ -53,6 +60,19 @@ def lib():
         L.cgks_metrics.argtypes = [vp, vp, vp, vp, vp, vp]
         L.cgks_profile.argtypes = [vp, C.c_int]
         L.cgks_profile_read.argtypes = [vp, dp, C.POINTER(C.c_long)]
+        L.cgks_get_launch.argtypes = [vp, C.c_int, C.POINTER(Launch)]
+        L.cgks_set_launch.argtypes = [vp, C.c_int, C.POINTER(Launch)]
+        L.cgks_autotune.argtypes = [vp, vp, vp, vp, vp, C.c_int, dp, C.c_int, vp]
+        L.cgks_step_graph.argtypes = [vp, vp, vp, vp, vp, C.c_int, vp]
+        fp = C.POINTER(C.c_float)
+        L.cgks_mlp_init.argtypes = [vp, C.c_ulonglong]
+        L.cgks_mlp_set.argtypes = [vp, fp, C.c_int]
+        L.cgks_mlp_get.argtypes = [vp, fp, C.c_int]
+        L.cgks_mlp_grad.argtypes = [vp, vp, vp, C.c_long, vp, vp, vp]
+        L.cgks_mlp_train.argtypes = [vp, vp, vp, C.c_long, C.c_int, C.c_int, C.c_float, fp, vp]
+        L.cgks_mlp_infer.argtypes = [vp, vp, C.c_long, vp, vp]
+        L.cgks_weights.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
+        L.cgks_mlp_fallback.argtypes = [vp, C.POINTER(C.c_longlong), C.POINTER(C.c_longlong)]
         L.cgks_last_error.restype = C.c_char_p
         _lib = L
     return _lib
@@ -172,3 +192,93 @@ def cgks_profile_read(ctx: Context):
     n = (C.c_long * 4)()
     _check(lib().cgks_profile_read(ctx.h, ms, n), "cgks_profile_read")
     return {k: (ms[i], n[i]) for i, k in enumerate(KERNEL_KINDS)}
+
+
+KIND_NAMES = {1: "reconstruction", 2: "flux", 3: "update"}
+
+
+def cgks_get_launch(ctx: Context, kind: int) -> dict:
+    c = Launch()
+    _check(lib().cgks_get_launch(ctx.h, kind, C.byref(c)), "cgks_get_launch")
+    return {"tile_cells": c.tile_cells, "ngroups": c.ngroups, "xcd": c.xcd}
+
+
+def cgks_set_launch(ctx: Context, kind: int, tile_cells: int, ngroups: int, xcd: int):
+    c = Launch(tile_cells, ngroups, xcd)
+    _check(lib().cgks_set_launch(ctx.h, kind, C.byref(c)), "cgks_set_launch")
+
+
+def cgks_autotune(ctx: Context, Q, G, L, dt_dev, reps=3, stream=None):
+    """Run the autotuner; returns the timed candidates as a list of dicts."""
+    n = 1 + 5 * 64
+    rep = (C.c_double * n)()
+    _check(lib().cgks_autotune(ctx.h, _ptr(Q), _ptr(G), _ptr(L), _ptr(dt_dev), reps, rep, n, _stream(stream)),
+           "cgks_autotune")
+    out = []
+    for i in range(int(rep[0])):
+        k, t, g, x, ms = rep[1 + 5 * i: 6 + 5 * i]
+        out.append({"kind": KIND_NAMES[int(k)], "tile_cells": int(t), "ngroups": int(g), "xcd": int(x), "ms": ms})
+    return out
+
+
+def cgks_step_graph(ctx: Context, Q, G, L, dt_dev, use_cfl=True, stream=None):
+    _check(lib().cgks_step_graph(ctx.h, _ptr(Q), _ptr(G), _ptr(L), _ptr(dt_dev), 1 if use_cfl else 0,
+                                 _stream(stream)), "cgks_step_graph")
+
+
+# ---- learned blend weights -------------------------------------------------------------------
+MLP_PARAMS = 839
+
+
+def _fptr(t):
+    import torch
+    if t.dtype != torch.float32 or not t.is_contiguous() or t.device.type != "cuda":
+        raise ValueError("feature/target arrays must be contiguous float32 CUDA tensors")
+    return C.c_void_p(t.data_ptr())
+
+
+def cgks_mlp_init(ctx: Context, seed: int):
+    _check(lib().cgks_mlp_init(ctx.h, seed), "cgks_mlp_init")
+
+
+def cgks_mlp_set(ctx: Context, w):
+    import numpy as np
+    a = np.ascontiguousarray(w, dtype=np.float32)
+    _check(lib().cgks_mlp_set(ctx.h, a.ctypes.data_as(C.POINTER(C.c_float)), a.size), "cgks_mlp_set")
+
+
+def cgks_mlp_get(ctx: Context):
+    import numpy as np
+    a = np.zeros(MLP_PARAMS, dtype=np.float32)
+    _check(lib().cgks_mlp_get(ctx.h, a.ctypes.data_as(C.POINTER(C.c_float)), a.size), "cgks_mlp_get")
+    return a
+
+
+def cgks_mlp_grad(ctx: Context, X, T, grad, loss, stream=None):
+    _check(lib().cgks_mlp_grad(ctx.h, _fptr(X), _fptr(T), X.shape[0], _fptr(grad), _fptr(loss), _stream(stream)),
+           "cgks_mlp_grad")
+
+
+def cgks_mlp_train(ctx: Context, X, T, steps, batch, lr, history=True, stream=None):
+    import numpy as np
+    hist = np.zeros(max(steps, 1), dtype=np.float32) if history else None
+    hp = hist.ctypes.data_as(C.POINTER(C.c_float)) if history else None
+    _check(lib().cgks_mlp_train(ctx.h, _fptr(X), _fptr(T), X.shape[0], steps, batch, lr, hp, _stream(stream)),
+           "cgks_mlp_train")
+    return hist[:steps] if history else None
+
+
+def cgks_mlp_infer(ctx: Context, X, Y, stream=None):
+    _check(lib().cgks_mlp_infer(ctx.h, _fptr(X), X.shape[0], _ptr(Y), _stream(stream)), "cgks_mlp_infer")
+
+
+def cgks_weights(ctx: Context, Q, G, L, X, Wt, jump=None, stream=None):
+    jp = None if jump is None else C.c_void_p(jump.data_ptr())
+    _check(lib().cgks_weights(ctx.h, _ptr(Q), _ptr(G), _ptr(L), _fptr(X), _ptr(Wt), jp, _stream(stream)),
+           "cgks_weights")
+
+
+def cgks_mlp_fallback(ctx: Context):
+    f, e = C.c_longlong(), C.c_longlong()
+    _check(lib().cgks_mlp_fallback(ctx.h, C.byref(f), C.byref(e)), "cgks_mlp_fallback")
+    return f.value, e.value

@@ -1,6 +1,7 @@
 // C ABI of the CGKS-5 library (declared in include/cgks.h).
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -8,6 +9,7 @@
 
 #include "cgks.h"
 #include "cgks_device.h"
+#include "cgks_mlp.h"
 
 using namespace cgks;
 
@@ -46,9 +48,34 @@ struct cgks_ctx {
     double *fo = nullptr;     // [3][4][30][Ntot]
     double *stash = nullptr;  // [80][Ntot]
     double *Kmf = nullptr;    // constant blocks of the matrix-core reconstruction
-    int ngroups = 256;        // workgroups of the matrix-core reconstruction
     double *dt_part = nullptr;
     int nparts = 1;
+    int ncu = 256;
+    // work lists of the reconstruction (1), flux (2) and update (3) kernels
+    BlockView *d_blocks = nullptr;
+    struct List {
+        cgks_launch cfg{};
+        std::vector<int> tile_cells;  // per block
+        std::vector<int> first;       // per block: index of its first tile; first[nblocks] = ntiles
+        Tile *d = nullptr;
+        int n = 0, cap = 0;
+    } wl[4];
+    // learned blend weights
+    unsigned char *jump = nullptr;        // [Ntot] jump flags
+    unsigned long long *jcount = nullptr; // flagged cells since the last read
+    long long jexamined = 0;              // cells examined since the last read (host count)
+    float *mlp_w = nullptr, *mlp_m = nullptr, *mlp_v = nullptr, *mlp_g = nullptr, *mlp_loss = nullptr;
+    unsigned char *mlp_packed = nullptr;
+    float *mlp_scratch = nullptr;
+    long mlp_scratch_n = 0;
+    int adam_t = 0;
+    bool mlp_ready = false;
+    // graph of one step
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    const void *gkey[4] = {nullptr, nullptr, nullptr, nullptr};
+    int gkey_cfl = -1;
     int *flag = nullptr;      // device error mask
     hipStream_t last = nullptr;
     bool stage1_done = false;
@@ -113,6 +140,8 @@ static DevParams make_dev_params(const cgks_params &p) {
     d.tau_zero = p.tau_zero;
     d.linear = p.linear;
     d.prandtl_fix = p.prandtl_fix;
+    d.weights = p.weights;
+    d.jump_thresh = p.jump_thresh;
     return d;
 }
 
@@ -128,6 +157,11 @@ static int check_params(const cgks_params *p) {
         return fail(CGKS_EUNSUPPORTED, "recon_prec must be 0 (FP64), 1 (FP32x3) or 2 (BF16x3)");
     if (p->flux_prec < 0 || p->flux_prec > 1) return fail(CGKS_EUNSUPPORTED, "flux_prec must be 0 (FP64) or 1 (FP32)");
     if (p->recon_impl != 0 && p->recon_impl != 1) return fail(CGKS_EINVAL, "recon_impl must be 0 or 1");
+    if (p->per_block != 0 && p->per_block != 1) return fail(CGKS_EINVAL, "per_block must be 0 or 1");
+    if (p->weights != 0 && p->weights != 1) return fail(CGKS_EINVAL, "weights must be 0 (GENO) or 1 (learned)");
+    if (!(p->jump_thresh >= 0.0)) return fail(CGKS_EINVAL, "jump_thresh must be >= 0");
+    if (p->weights == 1 && (p->recon_impl != 0 || p->recon_prec != 0 || p->linear))
+        return fail(CGKS_EUNSUPPORTED, "learned weights need the nonlinear FP64 matrix-core reconstruction");
     if (p->recon_impl == 1 && (p->recon_prec != 0 || p->flux_prec != 0))
         return fail(CGKS_EUNSUPPORTED, "the vector-ALU reconstruction is FP64 only");
     return CGKS_OK;
@@ -138,11 +172,81 @@ static int check_params(const cgks_params *p) {
 static bool gp32(const cgks_ctx *c) { return c->user.recon_prec != 0 || c->user.flux_prec != 0; }
 static bool fo32(const cgks_ctx *c) { return c->user.flux_prec != 0; }
 
-static hipError_t run_recon(cgks_ctx *ctx, const BlockView &b, const double *Q, const double *G, const double *L,
-                            hipStream_t s) {
-    if (ctx->user.recon_impl == 1) return launch_recon(b, ctx->Ntot, Q, G, L, ctx->M, ctx->K, ctx->P, ctx->gp, s);
-    return launch_recon_mfma(ctx->user.recon_prec, gp32(ctx), b, ctx->Ntot, Q, G, L, ctx->M, ctx->Kmf, ctx->P, ctx->gp,
-                             ctx->ngroups, s);
+// Work list of kernel kind k restricted to block b (b < 0: every block).
+static WorkList work_list(const cgks_ctx *c, int k, int b) {
+    const cgks_ctx::List &l = c->wl[k];
+    WorkList w{c->d_blocks, l.d, l.n, l.cfg.xcd};
+    if (b >= 0) {
+        w.tiles = l.d + l.first[b];
+        w.ntiles = l.first[b + 1] - l.first[b];
+    }
+    return w;
+}
+
+// Tiles of every block for kind k with the per-block tile sizes of the list, uploaded to the
+// device (synchronous).
+static hipError_t build_list(cgks_ctx *c, int k) {
+    cgks_ctx::List &l = c->wl[k];
+    std::vector<Tile> t;
+    const int nb = (int)c->blocks.size();
+    l.first.assign(nb + 1, 0);
+    for (int b = 0; b < nb; ++b) {
+        l.first[b] = (int)t.size();
+        const long N = c->blocks[b].N, T = l.tile_cells[b];
+        for (long st = 0; st < N; st += T) t.push_back(Tile{b, (int)std::min(T, N - st), st});
+    }
+    l.first[nb] = (int)t.size();
+    if ((int)t.size() > l.cap) {
+        hipError_t e = hipDeviceSynchronize();
+        if (e != hipSuccess) return e;
+        (void)hipFree(l.d);
+        l.d = nullptr;
+        l.cap = 0;
+        e = hipMalloc((void **)&l.d, sizeof(Tile) * t.size());
+        if (e != hipSuccess) return e;
+        l.cap = (int)t.size();
+    }
+    l.n = (int)t.size();
+    return hipMemcpy(l.d, t.data(), sizeof(Tile) * t.size(), hipMemcpyHostToDevice);
+}
+
+static void drop_graph(cgks_ctx *c) {
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    c->gexec = nullptr;
+    c->graph = nullptr;
+    c->gkey_cfl = -1;
+}
+
+static hipError_t run_recon(cgks_ctx *ctx, int b, const double *Q, const double *G, const double *L, hipStream_t s) {
+    if (ctx->user.recon_impl == 1) {
+        // vector-ALU reference kernel: one launch per block
+        for (int i = 0; i < (int)ctx->blocks.size(); ++i) {
+            if (b >= 0 && i != b) continue;
+            hipError_t e = launch_recon(ctx->blocks[i], ctx->Ntot, Q, G, L, ctx->M, ctx->K, ctx->P, ctx->gp, s);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    }
+    BlendIO io{ctx->jump, ctx->mlp_packed, nullptr, nullptr};
+    if (ctx->P.weights == 1) {
+        hipError_t e = launch_jump(work_list(ctx, 3, b), ctx->Ntot, Q, ctx->P, ctx->jump, ctx->jcount, s);
+        if (e != hipSuccess) return e;
+        ctx->jexamined += (b < 0) ? ctx->Ntot : ctx->blocks[b].N;
+    }
+    return launch_recon_mfma(ctx->user.recon_prec, gp32(ctx), work_list(ctx, 1, b), ctx->Ntot, Q, G, L, ctx->M,
+                             ctx->Kmf, ctx->P, ctx->gp, ctx->wl[1].cfg.ngroups, io, false, s);
+}
+
+static hipError_t run_flux(cgks_ctx *ctx, int b, const double *dt_dev, hipStream_t s) {
+    return launch_flux(ctx->user.flux_prec, gp32(ctx), work_list(ctx, 2, b), ctx->Ntot, ctx->gp, ctx->M, dt_dev,
+                       ctx->P, ctx->fo, ctx->flag, s);
+}
+
+static hipError_t run_update(cgks_ctx *ctx, int stage, int b, const double *dt_dev, double *Q, double *G, double *L,
+                             hipStream_t s) {
+    return launch_update(stage, fo32(ctx), work_list(ctx, 3, b), ctx->Ntot, ctx->fo, ctx->M, dt_dev, Q, G, L,
+                         ctx->stash, ctx->wl[3].cfg.ngroups, s);
 }
 
 extern "C" {
@@ -161,6 +265,7 @@ void cgks_default_params(cgks_params *p) {
     p->geno_C = 150.0;
     p->geno_eps = 1e-15;
     p->geno_r = 2.0;
+    p->jump_thresh = 0.05;
 }
 
 const char *cgks_last_error(void) { return g_err.c_str(); }
@@ -181,6 +286,19 @@ void cgks_ctx_destroy(cgks_ctx *ctx) {
     (void)hipFree(ctx->stash);
     (void)hipFree(ctx->dt_part);
     (void)hipFree(ctx->flag);
+    (void)hipFree(ctx->d_blocks);
+    (void)hipFree(ctx->jump);
+    (void)hipFree(ctx->jcount);
+    (void)hipFree(ctx->mlp_w);
+    (void)hipFree(ctx->mlp_m);
+    (void)hipFree(ctx->mlp_v);
+    (void)hipFree(ctx->mlp_g);
+    (void)hipFree(ctx->mlp_loss);
+    (void)hipFree(ctx->mlp_packed);
+    (void)hipFree(ctx->mlp_scratch);
+    for (auto &l : ctx->wl) (void)hipFree(l.d);
+    drop_graph(ctx);
+    if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     for (auto &p : ctx->pending) {
         (void)hipEventDestroy(p.a);
         (void)hipEventDestroy(p.b);
@@ -222,7 +340,13 @@ int cgks_ctx_create(cgks_ctx **out, int nblocks, const int *dims, const double *
               alloc((void **)&c->Kmf, sizeof(double) * std::max(kMfmaBlocks * 64, kBfBlocks * 512)) &&
               alloc((void **)&c->gp, sizeof(double) * 480 * Ntot) && alloc((void **)&c->fo, sizeof(double) * 360 * Ntot) &&
               alloc((void **)&c->stash, sizeof(double) * 80 * Ntot) &&
-              alloc((void **)&c->dt_part, sizeof(double) * kMaxDtParts) && alloc((void **)&c->flag, sizeof(int));
+              alloc((void **)&c->dt_part, sizeof(double) * kMaxDtParts) && alloc((void **)&c->flag, sizeof(int)) &&
+              alloc((void **)&c->jump, Ntot) && alloc((void **)&c->jcount, sizeof(unsigned long long)) &&
+              alloc((void **)&c->mlp_w, sizeof(float) * kMlpParams) &&
+              alloc((void **)&c->mlp_m, sizeof(float) * kMlpParams) &&
+              alloc((void **)&c->mlp_v, sizeof(float) * kMlpParams) &&
+              alloc((void **)&c->mlp_g, sizeof(float) * kMlpParams) && alloc((void **)&c->mlp_loss, sizeof(float)) &&
+              alloc((void **)&c->mlp_packed, kMlpPackBytes);
     if (!ok) {
         cgks_ctx_destroy(c);
         return fail(CGKS_ENOMEM, "device allocation failed");
@@ -254,8 +378,11 @@ int cgks_ctx_create(cgks_ctx **out, int nblocks, const int *dims, const double *
     }
     {
         hipDeviceProp_t prop;
-        if (hipGetDeviceProperties(&prop, c->device) == hipSuccess) c->ngroups = 2 * prop.multiProcessorCount;
+        if (hipGetDeviceProperties(&prop, c->device) == hipSuccess) c->ncu = prop.multiProcessorCount;
     }
+    c->wl[1].cfg = cgks_launch{128, 0, 0};
+    c->wl[2].cfg = cgks_launch{kFluxTile, 0, 0};
+    c->wl[3].cfg = cgks_launch{kUpdateTile, 0, 0};
     int rc = CGKS_OK;
     do {
         hipError_t e = hipMemcpyAsync(c->K, &dk, sizeof dk, hipMemcpyHostToDevice, s);
@@ -263,7 +390,9 @@ int cgks_ctx_create(cgks_ctx **out, int nblocks, const int *dims, const double *
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         if (e != hipSuccess) { rc = hip_fail(e, "upload constants"); break; }
         e = hipMemsetAsync(c->flag, 0, sizeof(int), s);
-        if (e != hipSuccess) { rc = hip_fail(e, "clear flag"); break; }
+        if (e == hipSuccess) e = hipMemsetAsync(c->jcount, 0, sizeof(unsigned long long), s);
+        if (e == hipSuccess) e = hipMemsetAsync(c->jump, 0, Ntot, s);
+        if (e != hipSuccess) { rc = hip_fail(e, "clear flags"); break; }
         for (int b = 0; b < nblocks && rc == CGKS_OK; ++b) {
             const BlockView &bv = c->blocks[b];
             size_t nn = (size_t)(bv.nx + 1) * (bv.ny + 1) * (bv.nz + 1) * 3;
@@ -281,6 +410,14 @@ int cgks_ctx_create(cgks_ctx **out, int nblocks, const int *dims, const double *
         e = hipMemcpy(&bad, c->flag, sizeof(int), hipMemcpyDeviceToHost);
         if (e != hipSuccess) { rc = hip_fail(e, "read flag"); break; }
         if (bad) { rc = fail(CGKS_EINVAL, "mesh has a cell with non-positive volume or det J0"); break; }
+        e = hipMalloc((void **)&c->d_blocks, sizeof(BlockView) * nblocks);
+        if (e == hipSuccess)
+            e = hipMemcpy(c->d_blocks, c->blocks.data(), sizeof(BlockView) * nblocks, hipMemcpyHostToDevice);
+        for (int k = 1; k <= 3 && e == hipSuccess; ++k) {
+            c->wl[k].tile_cells.assign(nblocks, c->wl[k].cfg.tile_cells);
+            e = build_list(c, k);
+        }
+        if (e != hipSuccess) { rc = hip_fail(e, "work lists"); break; }
     } while (0);
     if (rc) {
         cgks_ctx_destroy(c);
@@ -305,23 +442,23 @@ int cgks_stage(cgks_ctx *ctx, int stage, const double *dt_dev, double *Q, double
     if (!ctx || !dt_dev || !Q || !G || !L) return fail(CGKS_EINVAL, "cgks_stage: NULL argument");
     if (stage != 1 && stage != 2) return fail(CGKS_EINVAL, "cgks_stage: stage must be 1 or 2");
     if (stage == 2 && !ctx->stage1_done) return fail(CGKS_EINVAL, "cgks_stage: stage 2 without a preceding stage 1");
+    if (ctx->P.weights == 1 && !ctx->mlp_ready) return fail(CGKS_EINVAL, "learned weights: no MLP parameters set");
     hipStream_t s = (hipStream_t)stream;
     ctx->last = s;
-    for (const BlockView &b : ctx->blocks) {
+    const int nb = ctx->user.per_block ? (int)ctx->blocks.size() : 1;
+    for (int i = 0; i < nb; ++i) {
+        const int b = ctx->user.per_block ? i : -1;
         {
             Timed t(ctx, s, 1);
             HIP_TRY(run_recon(ctx, b, Q, G, L, s), "recon");
         }
         {
             Timed t(ctx, s, 2);
-            HIP_TRY(launch_flux(ctx->user.flux_prec, gp32(ctx), b, ctx->Ntot, ctx->gp, ctx->M, dt_dev, ctx->P, ctx->fo,
-                                ctx->flag, s),
-                    "flux");
+            HIP_TRY(run_flux(ctx, b, dt_dev, s), "flux");
         }
         {
             Timed t(ctx, s, 3);
-            HIP_TRY(launch_update(stage, fo32(ctx), b, ctx->Ntot, ctx->fo, ctx->M, dt_dev, Q, G, L, ctx->stash, s),
-                    "update");
+            HIP_TRY(run_update(ctx, stage, b, dt_dev, Q, G, L, s), "update");
         }
     }
     ctx->stage1_done = (stage == 1);
@@ -351,12 +488,11 @@ int cgks_check(cgks_ctx *ctx, int *flags_host) {
 
 int cgks_recon(cgks_ctx *ctx, const double *Q, const double *G, const double *L, double *gp, void *stream) {
     if (!ctx || !Q || !G || !L || !gp) return fail(CGKS_EINVAL, "cgks_recon: NULL argument");
+    if (ctx->P.weights == 1 && !ctx->mlp_ready) return fail(CGKS_EINVAL, "learned weights: no MLP parameters set");
     hipStream_t s = (hipStream_t)stream;
     ctx->last = s;
-    for (const BlockView &b : ctx->blocks) {
-        HIP_TRY(run_recon(ctx, b, Q, G, L, s), "recon");
-        HIP_TRY(launch_gp_export(gp32(ctx), b, ctx->Ntot, ctx->gp, gp, s), "export");
-    }
+    HIP_TRY(run_recon(ctx, -1, Q, G, L, s), "recon");
+    for (const BlockView &b : ctx->blocks) HIP_TRY(launch_gp_export(gp32(ctx), b, ctx->Ntot, ctx->gp, gp, s), "export");
     return CGKS_OK;
 }
 
@@ -406,6 +542,362 @@ int cgks_profile_read(cgks_ctx *ctx, double *ms, long *launches) {
         ctx->pool.push_back(p.b);
     }
     ctx->pending.clear();
+    return CGKS_OK;
+}
+
+int cgks_get_launch(const cgks_ctx *ctx, int kind, cgks_launch *out) {
+    if (!ctx || !out) return fail(CGKS_EINVAL, "cgks_get_launch: NULL argument");
+    if (kind < 1 || kind > 3) return fail(CGKS_EINVAL, "cgks_get_launch: kind must be 1, 2 or 3");
+    *out = ctx->wl[kind].cfg;
+    return CGKS_OK;
+}
+
+static int check_launch(const cgks_ctx *ctx, int kind, const cgks_launch &c) {
+    if (kind < 1 || kind > 3) return fail(CGKS_EINVAL, "launch kind must be 1, 2 or 3");
+    if (kind == 1 && (c.tile_cells < 16 || c.tile_cells > 4096 || c.tile_cells % 16))
+        return fail(CGKS_EINVAL, "reconstruction tiles must be a multiple of 16 cells in [16, 4096]");
+    if (kind == 2 && (c.tile_cells != kFluxTile || c.ngroups != 0))
+        return fail(CGKS_EINVAL, "flux: tiles of 128 cells, one workgroup per unit (ngroups 0)");
+    if (kind == 3 && c.tile_cells != kUpdateTile) return fail(CGKS_EINVAL, "update tiles are 256 cells");
+    if (c.ngroups < 0 || c.ngroups > 64 * ctx->ncu) return fail(CGKS_EINVAL, "ngroups must be in [0, 64 x CUs]");
+    if (c.xcd != 0 && c.xcd != 1) return fail(CGKS_EINVAL, "xcd must be 0 or 1");
+    if (c.xcd && kind != 2 && c.ngroups % 8) return fail(CGKS_EINVAL, "XCD order needs ngroups a multiple of 8");
+    return CGKS_OK;
+}
+
+int cgks_set_launch(cgks_ctx *ctx, int kind, const cgks_launch *cfg) {
+    if (!ctx || !cfg) return fail(CGKS_EINVAL, "cgks_set_launch: NULL argument");
+    int st = check_launch(ctx, kind, *cfg);
+    if (st) return st;
+    HIP_TRY(hipDeviceSynchronize(), "sync");
+    drop_graph(ctx);
+    ctx->wl[kind].cfg = *cfg;
+    ctx->wl[kind].tile_cells.assign(ctx->blocks.size(), cfg->tile_cells);
+    HIP_TRY(build_list(ctx, kind), "work list");
+    return CGKS_OK;
+}
+
+int cgks_autotune(cgks_ctx *ctx, const double *Q, const double *G, const double *L, const double *dt_dev, int reps,
+                  double *report, int report_len, void *stream) {
+    if (!ctx || !Q || !G || !L || !dt_dev) return fail(CGKS_EINVAL, "cgks_autotune: NULL argument");
+    if (reps < 1) return fail(CGKS_EINVAL, "cgks_autotune: reps must be >= 1");
+    if (report && report_len < 1) return fail(CGKS_EINVAL, "cgks_autotune: report_len must be >= 1");
+    hipStream_t s = (hipStream_t)stream;
+    ctx->last = s;
+    HIP_TRY(hipDeviceSynchronize(), "sync");
+    drop_graph(ctx);
+    hipEvent_t e0 = get_event(ctx), e1 = get_event(ctx);
+    int nrep = 0;
+    auto note = [&](int kind, int tile, int ng, int xcd, double ms) {
+        if (!report) return;
+        const int at = 1 + 5 * nrep;
+        if (at + 5 > report_len) return;
+        report[at] = kind;
+        report[at + 1] = tile;
+        report[at + 2] = ng;
+        report[at + 3] = xcd;
+        report[at + 4] = ms;
+        report[0] = ++nrep;
+    };
+    // mean milliseconds of `reps` launches after one untimed launch
+    auto timeit = [&](auto &&launch, double &ms) -> hipError_t {
+        hipError_t e = launch();
+        if (e == hipSuccess) e = hipEventRecord(e0, s);
+        for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch();
+        if (e == hipSuccess) e = hipEventRecord(e1, s);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float t = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+        ms = (double)t / reps;
+        return e;
+    };
+    const bool saved_prof = ctx->prof;
+    ctx->prof = false;
+    int rc = CGKS_OK;
+    const int nb = (int)ctx->blocks.size();
+    do {
+        hipError_t e = hipSuccess;
+        if (ctx->user.recon_impl == 0) {
+            // 1) reconstruction tile size per block-size class, on a list of that class's blocks
+            cgks_ctx::List &l = ctx->wl[1];
+            const long lim[2] = {1L << 17, 1L << 19};
+            auto cls = [&](long N) { return N < lim[0] ? 0 : (N < lim[1] ? 1 : 2); };
+            const int cand[5] = {64, 128, 256, 512, 1024};
+            const cgks_launch base = l.cfg;
+            std::vector<int> best_tile(3, base.tile_cells);
+            for (int k = 0; k < 3 && e == hipSuccess; ++k) {
+                bool any = false;
+                for (int b = 0; b < nb; ++b) any |= cls(ctx->blocks[b].N) == k;
+                if (!any) continue;
+                double best = 1e300;
+                for (int ci = 0; ci < 5 && e == hipSuccess; ++ci) {
+                    for (int b = 0; b < nb; ++b) l.tile_cells[b] = cand[ci];
+                    e = build_list(ctx, 1);
+                    if (e != hipSuccess) break;
+                    // tiles of the class's blocks only: blocks of a class are not contiguous, so
+                    // time each block's sub-list and sum
+                    double ms_sum = 0.0;
+                    for (int b = 0; b < nb && e == hipSuccess; ++b) {
+                        if (cls(ctx->blocks[b].N) != k) continue;
+                        const WorkList w = work_list(ctx, 1, b);
+                        double ms = 0.0;
+                        e = timeit([&] { return launch_recon_mfma(ctx->user.recon_prec, gp32(ctx), w, ctx->Ntot, Q, G, L,
+                                                                  ctx->M, ctx->Kmf, ctx->P, ctx->gp, base.ngroups,
+                                                                  BlendIO{ctx->jump, ctx->mlp_packed, nullptr, nullptr},
+                                                                  false, s); },
+                                   ms);
+                        ms_sum += ms;
+                    }
+                    if (e != hipSuccess) break;
+                    note(1, cand[ci], base.ngroups, base.xcd, ms_sum);
+                    if (ms_sum < best) {
+                        best = ms_sum;
+                        best_tile[k] = cand[ci];
+                    }
+                }
+            }
+            if (e != hipSuccess) break;
+            for (int b = 0; b < nb; ++b) l.tile_cells[b] = best_tile[cls(ctx->blocks[b].N)];
+            e = build_list(ctx, 1);
+            if (e != hipSuccess) break;
+            l.cfg.tile_cells = best_tile[cls(ctx->blocks[0].N)];
+            // 2) grid and XCD order over the whole list
+            const int grids[4] = {ctx->ncu, 2 * ctx->ncu, 4 * ctx->ncu, 0};
+            double best = 1e300;
+            cgks_launch pick = l.cfg;
+            for (int gi = 0; gi < 4 && e == hipSuccess; ++gi)
+                for (int x = 0; x < 2 && e == hipSuccess; ++x) {
+                    if (x && grids[gi] % 8) continue;
+                    l.cfg.ngroups = grids[gi];
+                    l.cfg.xcd = x;
+                    const WorkList w = work_list(ctx, 1, -1);
+                    double ms = 0.0;
+                    e = timeit([&] { return launch_recon_mfma(ctx->user.recon_prec, gp32(ctx), w, ctx->Ntot, Q, G, L,
+                                                              ctx->M, ctx->Kmf, ctx->P, ctx->gp, grids[gi],
+                                                              BlendIO{ctx->jump, ctx->mlp_packed, nullptr, nullptr},
+                                                              false, s); },
+                               ms);
+                    note(1, l.cfg.tile_cells, grids[gi], x, ms);
+                    if (ms < best) {
+                        best = ms;
+                        pick = l.cfg;
+                    }
+                }
+            l.cfg.ngroups = pick.ngroups;
+            l.cfg.xcd = pick.xcd;
+            if (e != hipSuccess) break;
+        }
+        // 3) flux: XCD order (its inputs are the Gauss-point values of the reconstruction run
+        //    just before)
+        {
+            cgks_ctx::List &l = ctx->wl[2];
+            double best = 1e300;
+            cgks_launch pick = l.cfg;
+            e = run_recon(ctx, -1, Q, G, L, s);
+            for (int x = 0; x < 2 && e == hipSuccess; ++x) {
+                l.cfg.ngroups = 0;
+                l.cfg.xcd = x;
+                double ms = 0.0;
+                e = timeit([&] { return run_flux(ctx, -1, dt_dev, s); }, ms);
+                note(2, kFluxTile, 0, x, ms);
+                if (ms < best) {
+                    best = ms;
+                    pick = l.cfg;
+                }
+            }
+            l.cfg = pick;
+        }
+        if (e != hipSuccess) rc = hip_fail(e, "autotune");
+    } while (0);
+    ctx->prof = saved_prof;
+    ctx->pool.push_back(e0);
+    ctx->pool.push_back(e1);
+    ctx->stage1_done = false;
+    return rc;
+}
+
+int cgks_step_graph(cgks_ctx *ctx, double *Q, double *G, double *L, double *dt_dev, int use_cfl, void *stream) {
+    if (!ctx || !dt_dev || !Q || !G || !L) return fail(CGKS_EINVAL, "cgks_step_graph: NULL argument");
+    const void *key[4] = {Q, G, L, dt_dev};
+    const int cfl = use_cfl ? 1 : 0;
+    bool same = ctx->gexec && ctx->gkey_cfl == cfl;
+    for (int i = 0; i < 4 && same; ++i) same = ctx->gkey[i] == key[i];
+    if (!same) {
+        drop_graph(ctx);
+        if (!ctx->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking), "capture stream");
+        const bool saved_prof = ctx->prof;
+        ctx->prof = false;
+        HIP_TRY(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal), "begin capture");
+        const int st = cgks_step(ctx, Q, G, L, dt_dev, use_cfl, ctx->cap_stream);
+        hipGraph_t g = nullptr;
+        const hipError_t e = hipStreamEndCapture(ctx->cap_stream, &g);
+        ctx->prof = saved_prof;
+        if (st != CGKS_OK || e != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return st != CGKS_OK ? st : hip_fail(e, "end capture");
+        }
+        ctx->graph = g;
+        HIP_TRY(hipGraphInstantiate(&ctx->gexec, g, nullptr, nullptr, 0), "instantiate graph");
+        for (int i = 0; i < 4; ++i) ctx->gkey[i] = key[i];
+        ctx->gkey_cfl = cfl;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    ctx->last = s;
+    HIP_TRY(hipGraphLaunch(ctx->gexec, s), "graph launch");
+    ctx->stage1_done = false;
+    return CGKS_OK;
+}
+
+// ---- learned blend weights ---------------------------------------------------------------
+static int mlp_upload(cgks_ctx *ctx, const float *w) {
+    std::vector<unsigned char> packed(kMlpPackBytes);
+    mlp_pack(w, packed.data());
+    HIP_TRY(hipDeviceSynchronize(), "sync");
+    HIP_TRY(hipMemcpy(ctx->mlp_w, w, sizeof(float) * kMlpParams, hipMemcpyHostToDevice), "upload MLP");
+    HIP_TRY(hipMemcpy(ctx->mlp_packed, packed.data(), kMlpPackBytes, hipMemcpyHostToDevice), "upload MLP blocks");
+    HIP_TRY(hipMemset(ctx->mlp_m, 0, sizeof(float) * kMlpParams), "clear Adam");
+    HIP_TRY(hipMemset(ctx->mlp_v, 0, sizeof(float) * kMlpParams), "clear Adam");
+    ctx->adam_t = 0;
+    ctx->mlp_ready = true;
+    drop_graph(ctx);
+    return CGKS_OK;
+}
+
+int cgks_mlp_init(cgks_ctx *ctx, unsigned long long seed) {
+    if (!ctx) return fail(CGKS_EINVAL, "cgks_mlp_init: NULL context");
+    // splitmix64 stream -> uniform in [-1, 1)
+    unsigned long long x = seed;
+    auto next = [&]() {
+        unsigned long long z = (x += 0x9E3779B97F4A7C15ull);
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        z ^= z >> 31;
+        return (double)(z >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+    };
+    std::vector<float> w(kMlpParams, 0.0f);
+    const double a1 = std::sqrt(6.0 / kMlpIn), a2 = std::sqrt(6.0 / kMlpHidden);
+    for (int i = 0; i < kMlpHidden * kMlpIn; ++i) w[i] = (float)(a1 * next());
+    for (int i = 0; i < kMlpOut * kMlpHidden; ++i) w[kMlpOffW2 + i] = (float)(a2 * next());
+    return mlp_upload(ctx, w.data());
+}
+
+int cgks_mlp_set(cgks_ctx *ctx, const float *w, int n) {
+    if (!ctx || !w) return fail(CGKS_EINVAL, "cgks_mlp_set: NULL argument");
+    if (n != kMlpParams) return fail(CGKS_EINVAL, "cgks_mlp_set: n must be 839");
+    return mlp_upload(ctx, w);
+}
+
+int cgks_mlp_get(cgks_ctx *ctx, float *w, int n) {
+    if (!ctx || !w) return fail(CGKS_EINVAL, "cgks_mlp_get: NULL argument");
+    if (n != kMlpParams) return fail(CGKS_EINVAL, "cgks_mlp_get: n must be 839");
+    HIP_TRY(hipDeviceSynchronize(), "sync");
+    HIP_TRY(hipMemcpy(w, ctx->mlp_w, sizeof(float) * kMlpParams, hipMemcpyDeviceToHost), "read MLP");
+    return CGKS_OK;
+}
+
+static int mlp_scratch(cgks_ctx *ctx, long B) {
+    if (B <= ctx->mlp_scratch_n) return CGKS_OK;
+    HIP_TRY(hipDeviceSynchronize(), "sync");
+    (void)hipFree(ctx->mlp_scratch);
+    ctx->mlp_scratch = nullptr;
+    ctx->mlp_scratch_n = 0;
+    HIP_TRY(hipMalloc((void **)&ctx->mlp_scratch, sizeof(float) * (size_t)mlp_scratch_floats((int)B)), "MLP scratch");
+    ctx->mlp_scratch_n = B;
+    return CGKS_OK;
+}
+
+int cgks_mlp_grad(cgks_ctx *ctx, const float *X, const float *T, long n, float *grad, float *loss, void *stream) {
+    if (!ctx || !X || !T || !grad || !loss) return fail(CGKS_EINVAL, "cgks_mlp_grad: NULL argument");
+    if (n < 1 || n > (1L << 26)) return fail(CGKS_EINVAL, "cgks_mlp_grad: n must be in [1, 2^26]");
+    if (!ctx->mlp_ready) return fail(CGKS_EINVAL, "cgks_mlp_grad: no MLP parameters set");
+    int st = mlp_scratch(ctx, n);
+    if (st) return st;
+    hipStream_t s = (hipStream_t)stream;
+    ctx->last = s;
+    HIP_TRY(launch_mlp_grad(ctx->mlp_w, X, T, n, 0, (int)n, ctx->mlp_scratch, grad, loss, s), "MLP gradient");
+    return CGKS_OK;
+}
+
+int cgks_mlp_train(cgks_ctx *ctx, const float *X, const float *T, long n, int steps, int batch, float lr,
+                   float *loss_hist, void *stream) {
+    if (!ctx || !X || !T) return fail(CGKS_EINVAL, "cgks_mlp_train: NULL argument");
+    if (n < 1 || steps < 0 || batch < 1 || batch > (1 << 24) || !(lr > 0.0f))
+        return fail(CGKS_EINVAL, "cgks_mlp_train: need n >= 1, steps >= 0, 1 <= batch <= 2^24, lr > 0");
+    if (!ctx->mlp_ready) return fail(CGKS_EINVAL, "cgks_mlp_train: no MLP parameters set");
+    int st = mlp_scratch(ctx, batch);
+    if (st) return st;
+    hipStream_t s = (hipStream_t)stream;
+    ctx->last = s;
+    float *hist = nullptr;
+    if (loss_hist && steps > 0) HIP_TRY(hipMalloc((void **)&hist, sizeof(float) * steps), "loss history");
+    int rc = CGKS_OK;
+    for (int k = 0; k < steps && rc == CGKS_OK; ++k) {
+        const long first = (long)((long long)k * batch % n);
+        hipError_t e = launch_mlp_grad(ctx->mlp_w, X, T, n, first, batch, ctx->mlp_scratch, ctx->mlp_g,
+                                       hist ? hist + k : ctx->mlp_loss, s);
+        if (e == hipSuccess)
+            e = launch_mlp_adam(ctx->mlp_w, ctx->mlp_m, ctx->mlp_v, ctx->mlp_g, lr, 0.9f, 0.999f, 1e-8f, ++ctx->adam_t, s);
+        if (e != hipSuccess) rc = hip_fail(e, "MLP training step");
+    }
+    if (hist) {
+        if (rc == CGKS_OK) {
+            hipError_t e = hipMemcpyAsync(loss_hist, hist, sizeof(float) * steps, hipMemcpyDeviceToHost, s);
+            if (e == hipSuccess) e = hipStreamSynchronize(s);
+            if (e != hipSuccess) rc = hip_fail(e, "loss history");
+        } else {
+            (void)hipStreamSynchronize(s);
+        }
+        (void)hipFree(hist);
+    }
+    if (rc) return rc;
+    // refresh the inference blocks from the trained FP32 parameters
+    std::vector<float> w(kMlpParams);
+    std::vector<unsigned char> packed(kMlpPackBytes);
+    HIP_TRY(hipStreamSynchronize(s), "sync");
+    HIP_TRY(hipMemcpy(w.data(), ctx->mlp_w, sizeof(float) * kMlpParams, hipMemcpyDeviceToHost), "read MLP");
+    mlp_pack(w.data(), packed.data());
+    HIP_TRY(hipMemcpy(ctx->mlp_packed, packed.data(), kMlpPackBytes, hipMemcpyHostToDevice), "upload MLP blocks");
+    drop_graph(ctx);
+    return CGKS_OK;
+}
+
+int cgks_mlp_infer(cgks_ctx *ctx, const float *X, long n, double *Y, void *stream) {
+    if (!ctx || !X || !Y) return fail(CGKS_EINVAL, "cgks_mlp_infer: NULL argument");
+    if (n < 0) return fail(CGKS_EINVAL, "cgks_mlp_infer: n must be >= 0");
+    if (!ctx->mlp_ready) return fail(CGKS_EINVAL, "cgks_mlp_infer: no MLP parameters set");
+    hipStream_t s = (hipStream_t)stream;
+    ctx->last = s;
+    HIP_TRY(launch_mlp_infer(X, n, ctx->mlp_packed, Y, s), "MLP inference");
+    return CGKS_OK;
+}
+
+int cgks_weights(cgks_ctx *ctx, const double *Q, const double *G, const double *L, float *X, double *Wt,
+                 unsigned char *jump, void *stream) {
+    if (!ctx || !Q || !G || !L || !X || !Wt) return fail(CGKS_EINVAL, "cgks_weights: NULL argument");
+    if (ctx->user.recon_impl != 0 || ctx->user.recon_prec != 0 || gp32(ctx) || ctx->user.linear)
+        return fail(CGKS_EUNSUPPORTED, "cgks_weights: FP64 nonlinear matrix-core contexts only");
+    if (ctx->P.weights == 1 && !ctx->mlp_ready) return fail(CGKS_EINVAL, "learned weights: no MLP parameters set");
+    hipStream_t s = (hipStream_t)stream;
+    ctx->last = s;
+    HIP_TRY(launch_jump(work_list(ctx, 3, -1), ctx->Ntot, Q, ctx->P, ctx->jump, ctx->jcount, s), "jump");
+    ctx->jexamined += ctx->Ntot;
+    BlendIO io{ctx->jump, ctx->mlp_packed, Wt, X};
+    HIP_TRY(launch_recon_mfma(0, false, work_list(ctx, 1, -1), ctx->Ntot, Q, G, L, ctx->M, ctx->Kmf, ctx->P, ctx->gp,
+                              ctx->wl[1].cfg.ngroups, io, true, s),
+            "recon export");
+    if (jump) HIP_TRY(hipMemcpyAsync(jump, ctx->jump, ctx->Ntot, hipMemcpyDeviceToDevice, s), "copy jump flags");
+    return CGKS_OK;
+}
+
+int cgks_mlp_fallback(cgks_ctx *ctx, long long *flagged, long long *examined) {
+    if (!ctx || !flagged || !examined) return fail(CGKS_EINVAL, "cgks_mlp_fallback: NULL argument");
+    HIP_TRY(hipStreamSynchronize(ctx->last), "sync");
+    unsigned long long f = 0;
+    HIP_TRY(hipMemcpy(&f, ctx->jcount, sizeof f, hipMemcpyDeviceToHost), "read count");
+    HIP_TRY(hipMemset(ctx->jcount, 0, sizeof f), "clear count");
+    *flagged = (long long)f;
+    *examined = ctx->jexamined;
+    ctx->jexamined = 0;
     return CGKS_OK;
 }
 

@@ -13,6 +13,48 @@ struct BlockView {
     long off;  // offset of the block's first cell in the concatenated state
 };
 
+// A run of consecutive cells of one block (block-local linear index, x fastest): the unit of
+// the work lists that let one launch cover every block of a multi-block mesh.
+struct Tile {
+    int blk;     // index into the block table
+    int count;   // cells in the run (>= 1)
+    long start;  // first cell of the run
+};
+
+struct WorkList {
+    const BlockView *blocks;  // device table, one entry per block
+    const Tile *tiles;        // device, ntiles entries
+    int ntiles;
+    int xcd;  // 1: the workgroups of XCD x (w mod 8 == x) share the x-th contiguous eighth of the units
+};
+
+// Units [u, end) with stride `step` of the calling workgroup.  Workgroups are dispatched to the
+// 8 XCDs round-robin, so with xcd set (and a grid that is a multiple of 8) each XCD walks a
+// contiguous eighth of the list and keeps the neighbours of its cells in its own L2.
+struct UnitRange {
+    long u, end, step;
+};
+
+#ifdef __HIPCC__
+__device__ inline UnitRange unit_range(long nunits, int xcd) {
+    const long G = gridDim.x, w = blockIdx.x;
+    if (xcd && G >= 8 && (G & 7) == 0) {
+        const long x = w & 7, G8 = G >> 3;
+        return {nunits * x / 8 + (w >> 3), nunits * (x + 1) / 8, G8};
+    }
+    return {w, nunits, G};
+}
+
+// The one unit of a workgroup in a grid of 8 ceil(nunits / 8) (xcd set) or nunits workgroups;
+// -1 for the padding workgroups of the XCD order.
+__device__ inline long unit_once(long nunits, int xcd) {
+    const long w = blockIdx.x;
+    if (!xcd) return w;
+    const long x = w & 7, u = nunits * x / 8 + (w >> 3);
+    return u < nunits * (x + 1) / 8 ? u : -1;
+}
+#endif
+
 // Per-cell metrics, SoA with stride Ntot.
 struct Metrics {
     double *vol;  // [Ntot]
@@ -395,16 +437,37 @@ hipError_t launch_dt(long off, long N, long Ntot, const double *Q, const double 
 hipError_t launch_dt_final(const double *part, int n, double *dt, hipStream_t s);
 hipError_t launch_recon(const BlockView &b, long Ntot, const double *Q, const double *G, const double *L,
                         const Metrics &M, const DevConsts *K, const DevParams &P, double *gp, hipStream_t s);
-hipError_t launch_recon_mfma(int prec, bool gp32, const BlockView &b, long Ntot, const double *Q, const double *G,
+// Inputs and outputs of the blend-weight modes of the matrix-core reconstruction.
+struct BlendIO {
+    const unsigned char *jump;  // [Ntot] pressure-jump flags (learned weights)
+    const unsigned char *mlp;   // packed inference blocks (learned weights)
+    double *wexp;               // export: weights used, [Ntot][5][7] (chi, omega_1..6)
+    float *xexp;                // export: learned-weight input features, [Ntot][5][18]
+};
+hipError_t launch_recon_mfma(int prec, bool gp32, const WorkList &W, long Ntot, const double *Q, const double *G,
                              const double *L, const Metrics &M, const double *Kblk, const DevParams &P, void *gp,
-                             int ngroups, hipStream_t s);
+                             int ngroups, const BlendIO &io, bool exp, hipStream_t s);
+hipError_t launch_jump(const WorkList &W, long Ntot, const double *Q, const DevParams &P, unsigned char *flag,
+                       unsigned long long *count, hipStream_t s);
+hipError_t launch_mlp_infer(const float *X, long n, const unsigned char *packed, double *Y, hipStream_t s);
+hipError_t launch_mlp_grad(const float *w, const float *X, const float *T, long n, long first, int B, float *S,
+                           float *grad, float *loss, hipStream_t s);
+hipError_t launch_mlp_adam(float *w, float *m, float *v, const float *g, float lr, float b1, float b2, float eps,
+                           int t, hipStream_t s);
+int mlp_scratch_floats(int B);
 hipError_t launch_gp_export(bool gp32, const BlockView &b, long Ntot, const void *gp, double *out, hipStream_t s);
-hipError_t launch_flux(int flux_prec, bool gp32, const BlockView &b, long Ntot, const void *gp, const Metrics &M,
+// Work-list kernels: tiles of at most kFluxTile (flux) or kUpdateTile (update) cells.  The flux
+// launches one workgroup per unit (a loop over units would raise its register pressure past
+// the 256 VGPRs of two waves per SIMD); the update takes ngroups <= 0 for one workgroup per
+// unit, otherwise a persistent grid of ngroups workgroups.
+constexpr int kFluxTile = 128, kUpdateTile = 256;
+hipError_t launch_flux(int flux_prec, bool gp32, const WorkList &W, long Ntot, const void *gp, const Metrics &M,
                        const double *dt, const DevParams &P, void *fo, int *flag, hipStream_t s);
 hipError_t launch_flux_points(int flux_prec, long n, const double *ql, const double *gl, const double *qr,
                               const double *gr, const double *nrm, const double *dt, const DevParams &P, double *F,
                               double *Ft, double *S, int *flag, hipStream_t s);
-hipError_t launch_update(int stage, bool fo32, const BlockView &b, long Ntot, const void *fo, const Metrics &M,
-                         const double *dt, double *Q, double *G, double *L, double *stash, hipStream_t s);
+hipError_t launch_update(int stage, bool fo32, const WorkList &W, long Ntot, const void *fo, const Metrics &M,
+                         const double *dt, double *Q, double *G, double *L, double *stash, int ngroups,
+                         hipStream_t s);
 
 }  // namespace cgks

@@ -69,7 +69,9 @@ struct DevParams {
     double cfl, tau_eps, tau_C;
     double mu0, T_ref, S_suth, Pr;
     double geno_C, geno_eps, geno_r, inv_tanhC;
+    double jump_thresh;          // pressure-jump indicator of the learned-weight fallback
     int viscous, visc_law, tau_zero, linear, prandtl_fix;
+    int weights;                 // 0 GENO weights, 1 learned weights with GENO fallback
 };
 
 }  // namespace cgks

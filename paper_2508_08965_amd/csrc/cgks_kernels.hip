@@ -401,17 +401,19 @@ __global__ void __launch_bounds__(256) k_gp_export(BlockView b, long Ntot, const
 // ------------------------------------------------------------------------------------------
 // gas-kinetic flux kernels
 // ------------------------------------------------------------------------------------------
-// Two lanes per Gauss point: thread t -> face record f = t / 2 of the block, side t & 1.
+// Two lanes per Gauss point.  A unit is (tile, owned-face Gauss point qk = 4q + kk); thread t of
+// the workgroup serves cell t / 2 of the tile (the face record of its plus face), side t & 1.
 template <class TC, class TG, class TF>
-__global__ void __launch_bounds__(256, 2) k_flux(BlockView b, long Ntot, const TG *__restrict__ gp, Metrics M,
+__global__ void __launch_bounds__(256, 2) k_flux(WorkList W, long Ntot, const TG *__restrict__ gp, Metrics M,
                                               const double *__restrict__ dtp, DevParams P,
                                               TF *__restrict__ fo, int *__restrict__ flag) {
-    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    const long cl = t >> 1;
-    if (cl >= b.N) return;  // both lanes of a pair leave together
-    const int sd = (int)(t & 1);
-    const int q = blockIdx.y >> 2, kk = blockIdx.y & 3;
-    const long f = b.off + cl;
+    const long u = unit_once((long)W.ntiles * 12, W.xcd);
+    if (u < 0) return;
+    const Tile tile = W.tiles[u / 12];
+    const int qk = (int)(u % 12), q = qk >> 2, kk = qk & 3;
+    const int i = (int)(threadIdx.x >> 1), sd = (int)(threadIdx.x & 1);
+    if (i >= tile.count) return;  // both lanes of a pair leave together
+    const long f = W.blocks[tile.blk].off + tile.start + i;
     TC qv[5], gv[5][3], n[3];
     const TG *src = gp + (long)(((q * 2 + sd) * 4 + kk) * 20) * Ntot + f;
 #pragma unroll
@@ -473,15 +475,11 @@ __global__ void __launch_bounds__(256) k_flux_points(long n, const double *__res
 // stash [80][Ntot]: Qpre (5) = Q^n + dt L^n + dt^2/6 L_t^n, Gb (15), Lb (60)
 // ------------------------------------------------------------------------------------------
 template <int STAGE, class TF>
-__global__ void __launch_bounds__(256) k_update(BlockView b, long Ntot, const TF *__restrict__ fo, Metrics M,
-                                                const double *__restrict__ dtp, double *__restrict__ Q,
-                                                double *__restrict__ G, double *__restrict__ L,
-                                                double *__restrict__ stash) {
-    long cl = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (cl >= b.N) return;
+__device__ inline void update_cell(const BlockView &b, long cl, long Ntot, const TF *__restrict__ fo, const Metrics &M,
+                                   const double dt, double *__restrict__ Q, double *__restrict__ G,
+                                   double *__restrict__ L, double *__restrict__ stash) {
     Idx3 id = unflatten(b, cl);
     const long c = b.off + cl;
-    const double dt = *dtp;
     double Lf[5] = {0, 0, 0, 0, 0}, Lt[5] = {0, 0, 0, 0, 0};
     double Gq[5][3], Gt[5][3];
 #pragma unroll
@@ -552,6 +550,20 @@ __global__ void __launch_bounds__(256) k_update(BlockView b, long Ntot, const TF
     }
 }
 
+// A unit is one tile; thread t updates cell t of the tile.
+template <int STAGE, class TF>
+__global__ void __launch_bounds__(256) k_update(WorkList W, long Ntot, const TF *__restrict__ fo, Metrics M,
+                                                const double *__restrict__ dtp, double *__restrict__ Q,
+                                                double *__restrict__ G, double *__restrict__ L,
+                                                double *__restrict__ stash) {
+    const double dt = *dtp;
+    for (UnitRange ur = unit_range(W.ntiles, W.xcd); ur.u < ur.end; ur.u += ur.step) {
+        const Tile tile = W.tiles[ur.u];
+        if ((int)threadIdx.x >= tile.count) continue;
+        update_cell<STAGE, TF>(W.blocks[tile.blk], tile.start + threadIdx.x, Ntot, fo, M, dt, Q, G, L, stash);
+    }
+}
+
 // explicit instantiations through launch wrappers --------------------------------------------
 hipError_t launch_metrics(const BlockView &b, const double *nodes, const Metrics &M, long Ntot, int *bad, hipStream_t s) {
     dim3 grid((unsigned)((b.N + 255) / 256));
@@ -586,18 +598,24 @@ hipError_t launch_gp_export(bool gp32, const BlockView &b, long Ntot, const void
     return hipGetLastError();
 }
 
-hipError_t launch_flux(int flux_prec, bool gp32, const BlockView &b, long Ntot, const void *gp, const Metrics &M,
+static dim3 work_grid(long units, int ngroups) {
+    return dim3((unsigned)((ngroups <= 0 || ngroups > units) ? units : ngroups));
+}
+
+hipError_t launch_flux(int flux_prec, bool gp32, const WorkList &W, long Ntot, const void *gp, const Metrics &M,
                        const double *dt, const DevParams &P, void *fo, int *flag, hipStream_t s) {
-    dim3 grid((unsigned)((2 * b.N + 255) / 256), 12);
+    if (W.ntiles <= 0) return hipSuccess;
+    const long units = (long)W.ntiles * 12;
+    const dim3 grid((unsigned)(W.xcd ? 8 * ((units + 7) / 8) : units));
     if (flux_prec == 0 && !gp32)
-        hipLaunchKernelGGL((k_flux<double, double, double>), grid, dim3(256), 0, s, b, Ntot, (const double *)gp, M, dt, P,
-                           (double *)fo, flag);
+        hipLaunchKernelGGL((k_flux<double, double, double>), grid, dim3(2 * kFluxTile), 0, s, W, Ntot,
+                           (const double *)gp, M, dt, P, (double *)fo, flag);
     else if (flux_prec == 0)
-        hipLaunchKernelGGL((k_flux<double, float, double>), grid, dim3(256), 0, s, b, Ntot, (const float *)gp, M, dt, P,
-                           (double *)fo, flag);
+        hipLaunchKernelGGL((k_flux<double, float, double>), grid, dim3(2 * kFluxTile), 0, s, W, Ntot,
+                           (const float *)gp, M, dt, P, (double *)fo, flag);
     else
-        hipLaunchKernelGGL((k_flux<float, float, float>), grid, dim3(256), 0, s, b, Ntot, (const float *)gp, M, dt, P,
-                           (float *)fo, flag);
+        hipLaunchKernelGGL((k_flux<float, float, float>), grid, dim3(2 * kFluxTile), 0, s, W, Ntot,
+                           (const float *)gp, M, dt, P, (float *)fo, flag);
     return hipGetLastError();
 }
 
@@ -612,19 +630,21 @@ hipError_t launch_flux_points(int flux_prec, long n, const double *ql, const dou
     return hipGetLastError();
 }
 
-hipError_t launch_update(int stage, bool fo32, const BlockView &b, long Ntot, const void *fo, const Metrics &M,
-                         const double *dt, double *Q, double *G, double *L, double *stash, hipStream_t s) {
-    dim3 grid((unsigned)((b.N + 255) / 256));
+hipError_t launch_update(int stage, bool fo32, const WorkList &W, long Ntot, const void *fo, const Metrics &M,
+                         const double *dt, double *Q, double *G, double *L, double *stash, int ngroups,
+                         hipStream_t s) {
+    if (W.ntiles <= 0) return hipSuccess;
+    const dim3 grid = work_grid(W.ntiles, ngroups), bl(kUpdateTile);
     if (fo32) {
         if (stage == 1)
-            hipLaunchKernelGGL((k_update<1, float>), grid, dim3(256), 0, s, b, Ntot, (const float *)fo, M, dt, Q, G, L, stash);
+            hipLaunchKernelGGL((k_update<1, float>), grid, bl, 0, s, W, Ntot, (const float *)fo, M, dt, Q, G, L, stash);
         else
-            hipLaunchKernelGGL((k_update<2, float>), grid, dim3(256), 0, s, b, Ntot, (const float *)fo, M, dt, Q, G, L, stash);
+            hipLaunchKernelGGL((k_update<2, float>), grid, bl, 0, s, W, Ntot, (const float *)fo, M, dt, Q, G, L, stash);
     } else {
         if (stage == 1)
-            hipLaunchKernelGGL((k_update<1, double>), grid, dim3(256), 0, s, b, Ntot, (const double *)fo, M, dt, Q, G, L, stash);
+            hipLaunchKernelGGL((k_update<1, double>), grid, bl, 0, s, W, Ntot, (const double *)fo, M, dt, Q, G, L, stash);
         else
-            hipLaunchKernelGGL((k_update<2, double>), grid, dim3(256), 0, s, b, Ntot, (const double *)fo, M, dt, Q, G, L, stash);
+            hipLaunchKernelGGL((k_update<2, double>), grid, bl, 0, s, W, Ntot, (const double *)fo, M, dt, Q, G, L, stash);
     }
     return hipGetLastError();
 }

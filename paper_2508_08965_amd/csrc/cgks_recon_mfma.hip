@@ -26,6 +26,7 @@
 #include <hip/hip_runtime.h>
 
 #include "cgks_device.h"
+#include "cgks_mlp.h"
 
 namespace cgks {
 
@@ -87,18 +88,29 @@ __device__ inline typename PR::V mac_coef(const typename PR::T *Ablk, int blk, t
 
 }  // namespace
 
-template <class PR, class TG>
-__global__ void __launch_bounds__(512) k_recon_mfma(BlockView b, long Ntot, const double *__restrict__ Q,
+// Blend-weight modes: WM = 0 GENO (Sec. 3.3); WM = 1 learned weights (cgks_mlp.h) with GENO
+// where the pressure-jump flag of the cell is set.  EXP: also write the weights used
+// (wexp [N][5][7]: chi, omega_1..6) and the MLP input features (xexp [N][5][18]).
+
+template <class PR, class TG, int WM, bool EXP>
+__global__ void __launch_bounds__(512) k_recon_mfma(WorkList W, long Ntot, const double *__restrict__ Q,
                                                     const double *__restrict__ G, const double *__restrict__ L,
                                                     Metrics M, const double *__restrict__ Kblk, DevParams P,
-                                                    TG *__restrict__ gp) {
+                                                    TG *__restrict__ gp, BlendIO io) {
     using T = typename PR::T;
     using V = typename PR::V;
     __shared__ T lds[PR::kSplit * kMfmaBlocks * 64];
+    __shared__ v8bf_t mlp_w[WM ? 3 * 64 : 1];
+    __shared__ float mlp_b[WM ? kMlpHidden + 8 : 1];
     for (int i = threadIdx.x; i < kMfmaBlocks * 64; i += blockDim.x) {
         const double k = Kblk[i];
         lds[i] = (T)k;
         if constexpr (PR::kSplit == 2) lds[kMfmaBlocks * 64 + i] = (T)(k - (double)(T)k);
+    }
+    if constexpr (WM == 1) {
+        for (int i = threadIdx.x; i < 3 * 64; i += blockDim.x) mlp_w[i] = ((const v8bf_t *)io.mlp)[i];
+        for (int i = threadIdx.x; i < kMlpHidden + 8; i += blockDim.x)
+            mlp_b[i] = ((const float *)(io.mlp + kMlpPackBf16 * 2))[i];
     }
     __syncthreads();
 
@@ -108,179 +120,235 @@ __global__ void __launch_bounds__(512) k_recon_mfma(BlockView b, long Ntot, cons
     const T *AL = lds + kMfmaOffAL * 64 + lane;
     const T *AT = lds + kMfmaOffAT * 64 + lane;
     const T *A2 = lds + kMfmaOffA2 * 64 + lane;
-    const long nchunks = (b.N + 15) / 16;
-    const long nitems = nchunks * kNV;
     // tangential coordinates of this lane's Gauss point (index g on every face)
     const double gq = 0.28867513459481288225;
     const double ta = (g & 1) ? gq : -gq, tb = (g & 2) ? gq : -gq;
     // signs of this lane's edge in the edge steps
     const int sa = (g & 1) ? 1 : -1, sb = (g & 2) ? 1 : -1;
 
-    for (long it = (long)blockIdx.x * nwaves + wave; it < nitems; it += (long)gridDim.x * nwaves) {
-        const int v = (int)(it % kNV);
-        const long cl0 = (it / kNV) * 16 + col;
-        const bool valid = cl0 < b.N;
-        const long cl = valid ? cl0 : b.N - 1;  // tail lanes compute a copy, store nothing
-        const int ci = (int)(cl % b.nx);
-        const long tt = cl / b.nx;
-        const int cj = (int)(tt % b.ny), ck = (int)(tt / b.ny);
-        const long c = b.off + cl;
-        const double *Qv = Q + v * Ntot;
-        const double *Gv = G + 3 * v * Ntot;
-        const double *Lv = L + 12 * v * Ntot;
-        double J0[3][3];
-#pragma unroll
-        for (int r = 0; r < 3; ++r)
-#pragma unroll
-            for (int s = 0; s < 3; ++s) J0[r][s] = M.J0[(3 * r + s) * Ntot + c];
-        const double q0 = Qv[c];
+    for (UnitRange ur = unit_range(W.ntiles, W.xcd); ur.u < ur.end; ur.u += ur.step) {
+        const Tile tile = W.tiles[ur.u];
+        const BlockView b = W.blocks[tile.blk];
+        const int nit = ((tile.count + 15) >> 4) * kNV;
+        for (int it = wave; it < nit; it += nwaves) {
+            const int v = it % kNV;
+            const long cl0 = tile.start + (it / kNV) * 16 + col;
+            const long cend = tile.start + tile.count;
+            const bool valid = cl0 < cend;
+            const long cl = valid ? cl0 : cend - 1;  // tail lanes compute a copy, store nothing
+            const int ci = (int)(cl % b.nx);
+            const long tt = cl / b.nx;
+            const int cj = (int)(tt % b.ny), ck = (int)(tt / b.ny);
+            const long c = b.off + cl;
+            const double *Qv = Q + v * Ntot;
+            const double *Gv = G + 3 * v * Ntot;
+            const double *Lv = L + 12 * v * Ntot;
+            double J0[3][3];
+    #pragma unroll
+            for (int r = 0; r < 3; ++r)
+    #pragma unroll
+                for (int s = 0; s < 3; ++s) J0[r][s] = M.J0[(3 * r + s) * Ntot + c];
+            const double q0 = Qv[c];
 
-        V acc[3] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
-        // ---- steps 0..5: face neighbours (difference and reference gradient) -------------
-#pragma unroll 1
-        for (int m = 0; m < 6; ++m) {
-            int o[3] = {0, 0, 0};
-            o[m >> 1] = (m & 1) ? 1 : -1;
-            const long nb = wrap_cell(b, ci + o[0], cj + o[1], ck + o[2]);
-            const double g0 = Gv[nb], g1 = Gv[Ntot + nb], g2 = Gv[2 * Ntot + nb];
-            const double fd = Qv[nb] - q0;
-            const double r0 = J0[0][0] * g0 + J0[1][0] * g1 + J0[2][0] * g2;
-            const double r1 = J0[0][1] * g0 + J0[1][1] * g1 + J0[2][1] * g2;
-            const double r2 = J0[0][2] * g0 + J0[1][2] * g1 + J0[2][2] * g2;
-            const double item = (g == 0) ? fd : (g == 1) ? r0 : (g == 2) ? r1 : r2;
-#pragma unroll
-            for (int t = 0; t < 3; ++t) acc[t] = mac_data<PR>(A1, t * 18 + m, item, acc[t]);
-        }
-        // ---- steps 6..14: edge neighbours 4p+g ---------------------------------------------
-#pragma unroll 1
-        for (int p = 0; p < 3; ++p) {
-            const int pa = (p < 2) ? 0 : 1, pb = (p == 0) ? 1 : 2, pc = 3 - pa - pb;
-            int o[3] = {0, 0, 0};
-            o[pa] = sa;
-            o[pb] = sb;
-            const long nb = wrap_cell(b, ci + o[0], cj + o[1], ck + o[2]);
-            const double d = Qv[nb] - q0;
-#pragma unroll
-            for (int t = 0; t < 3; ++t) acc[t] = mac_data<PR>(A1, t * 18 + 6 + p, d, acc[t]);
-            const double g0 = Gv[nb], g1 = Gv[Ntot + nb], g2 = Gv[2 * Ntot + nb];
-            double rg[3];
-#pragma unroll
-            for (int s = 0; s < 3; ++s) rg[s] = J0[0][s] * g0 + J0[1][s] * g1 + J0[2][s] * g2;
-            const double e1 = (pc == 0) ? rg[0] : (pc == 1) ? rg[1] : rg[2];
-            const double ra = (pa == 0) ? rg[0] : rg[1], rb = (pb == 1) ? rg[1] : rg[2];
-            const double e2 = (sa * ra + sb * rb) * 0.70710678118654752440;
-#pragma unroll
-            for (int t = 0; t < 3; ++t) acc[t] = mac_data<PR>(A1, t * 18 + 9 + 2 * p, e1, acc[t]);
-#pragma unroll
-            for (int t = 0; t < 3; ++t) acc[t] = mac_data<PR>(A1, t * 18 + 10 + 2 * p, e2, acc[t]);
-        }
-        // ---- steps 15..17: line differences 4t+g ---------------------------------------------
-        double lsum[3];
-#pragma unroll
-        for (int s = 0; s < 3; ++s) {
-            const double ln = Lv[(4 * s + g) * Ntot + c];
-#pragma unroll
-            for (int t = 0; t < 3; ++t) acc[t] = mac_data<PR>(A1, t * 18 + 15 + s, ln, acc[t]);
-            double x = ln + __shfl_xor(ln, 16, 64);
-            lsum[s] = x + __shfl_xor(x, 32, 64);
-        }
-
-        // ---- path function chi: IS^L and IS^tau from the Cholesky-factor contractions ---------
-        double chi = 1.0, bbar[3] = {0.0, 0.0, 0.0};
-        if (!P.linear) {
-            double isl = 0.0, ist = 0.0;
-#pragma unroll 1
-            for (int u = 0; u < 5; ++u) {  // tiles 0..2: L_L^T rows, tiles 3..4: L_T^T rows
-                const int base = (u < 3) ? kMfmaOffAL + u * 10 : kMfmaOffAT + (u - 3) * 10;
-                V z = {0, 0, 0, 0};
-#pragma unroll
-                for (int s = 0; s < 10; ++s) z = mac_coef<PR>(lds + lane, base + s, acc[s >> 2][s & 3], z);
-                const double zz = (double)z[0] * z[0] + (double)z[1] * z[1] + (double)z[2] * z[2] + (double)z[3] * z[3];
-                if (u < 3) isl += zz;
-                else ist += zz;
-            }
-            isl += __shfl_xor(isl, 16, 64);
-            isl += __shfl_xor(isl, 32, 64);
-            ist += __shfl_xor(ist, 16, 64);
-            ist += __shfl_xor(ist, 32, 64);
-            const double ish = isl + ist;
-            const double rh = ist / (ish + P.geno_eps), rl = ist / (isl + P.geno_eps);
-            double ah, al;
-            if (P.geno_r == 2.0) {
-                ah = 1.0 + rh * rh;
-                al = 1.0 + rl * rl;
-            } else {
-                ah = 1.0 + pow(rh, P.geno_r);
-                al = 1.0 + pow(rl, P.geno_r);
-            }
-            chi = tanh(P.geno_C * (2.0 * ah / (ah + al))) * P.inv_tanhC;
-            // linear sub-polynomials of the six face sub-stencils (eq. compact-sub-2) and weights
-            const double lm[3] = {0.25 * lsum[0], 0.25 * lsum[1], 0.25 * lsum[2]};
-            double wsum = 0.0, wv[6], fdiff[6];
-#pragma unroll
+            V acc[3] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
+            // ---- steps 0..5: face neighbours (difference and reference gradient) -------------
+    #pragma unroll 1
             for (int m = 0; m < 6; ++m) {
                 int o[3] = {0, 0, 0};
                 o[m >> 1] = (m & 1) ? 1 : -1;
-                fdiff[m] = Qv[wrap_cell(b, ci + o[0], cj + o[1], ck + o[2])] - q0;
+                const long nb = wrap_cell(b, ci + o[0], cj + o[1], ck + o[2]);
+                const double g0 = Gv[nb], g1 = Gv[Ntot + nb], g2 = Gv[2 * Ntot + nb];
+                const double fd = Qv[nb] - q0;
+                const double r0 = J0[0][0] * g0 + J0[1][0] * g1 + J0[2][0] * g2;
+                const double r1 = J0[0][1] * g0 + J0[1][1] * g1 + J0[2][1] * g2;
+                const double r2 = J0[0][2] * g0 + J0[1][2] * g1 + J0[2][2] * g2;
+                const double item = (g == 0) ? fd : (g == 1) ? r0 : (g == 2) ? r1 : r2;
+    #pragma unroll
+                for (int t = 0; t < 3; ++t) acc[t] = mac_data<PR>(A1, t * 18 + m, item, acc[t]);
             }
-#pragma unroll
-            for (int m = 0; m < 6; ++m) {
-                const int q = m >> 1;
-                const double bn = (m & 1) ? fdiff[m] : -fdiff[m];
-                double is = P.geno_eps + bn * bn;
-#pragma unroll
-                for (int t = 0; t < 3; ++t)
-                    if (t != q) is += lm[t] * lm[t];
-                const double is2 = is * is;
-                wv[m] = (1.0 / 6.0) / (is2 * is2 * is);
-                wsum += wv[m];
+            // ---- steps 6..14: edge neighbours 4p+g ---------------------------------------------
+    #pragma unroll 1
+            for (int p = 0; p < 3; ++p) {
+                const int pa = (p < 2) ? 0 : 1, pb = (p == 0) ? 1 : 2, pc = 3 - pa - pb;
+                int o[3] = {0, 0, 0};
+                o[pa] = sa;
+                o[pb] = sb;
+                const long nb = wrap_cell(b, ci + o[0], cj + o[1], ck + o[2]);
+                const double d = Qv[nb] - q0;
+    #pragma unroll
+                for (int t = 0; t < 3; ++t) acc[t] = mac_data<PR>(A1, t * 18 + 6 + p, d, acc[t]);
+                const double g0 = Gv[nb], g1 = Gv[Ntot + nb], g2 = Gv[2 * Ntot + nb];
+                double rg[3];
+    #pragma unroll
+                for (int s = 0; s < 3; ++s) rg[s] = J0[0][s] * g0 + J0[1][s] * g1 + J0[2][s] * g2;
+                const double e1 = (pc == 0) ? rg[0] : (pc == 1) ? rg[1] : rg[2];
+                const double ra = (pa == 0) ? rg[0] : rg[1], rb = (pb == 1) ? rg[1] : rg[2];
+                const double e2 = (sa * ra + sb * rb) * 0.70710678118654752440;
+    #pragma unroll
+                for (int t = 0; t < 3; ++t) acc[t] = mac_data<PR>(A1, t * 18 + 9 + 2 * p, e1, acc[t]);
+    #pragma unroll
+                for (int t = 0; t < 3; ++t) acc[t] = mac_data<PR>(A1, t * 18 + 10 + 2 * p, e2, acc[t]);
             }
-            const double iw = 1.0 / wsum;
-#pragma unroll
-            for (int m = 0; m < 6; ++m) {
-                const int q = m >> 1;
-                const double w = wv[m] * iw;
-                const double bn = (m & 1) ? fdiff[m] : -fdiff[m];
-#pragma unroll
-                for (int t = 0; t < 3; ++t) bbar[t] += w * ((t == q) ? bn : lm[t]);
+            // ---- steps 15..17: line differences 4t+g ---------------------------------------------
+            double lsum[3], lval[3];
+    #pragma unroll
+            for (int s = 0; s < 3; ++s) {
+                const double ln = Lv[(4 * s + g) * Ntot + c];
+                lval[s] = ln;
+    #pragma unroll
+                for (int t = 0; t < 3; ++t) acc[t] = mac_data<PR>(A1, t * 18 + 15 + s, ln, acc[t]);
+                double x = ln + __shfl_xor(ln, 16, 64);
+                lsum[s] = x + __shfl_xor(x, 32, 64);
             }
-        }
-        double JiT[3][3];
-#pragma unroll
-        for (int r = 0; r < 3; ++r)
-#pragma unroll
-            for (int s = 0; s < 3; ++s) JiT[r][s] = M.JiT[(3 * r + s) * Ntot + c];
-        const double om = 1.0 - chi;
 
-        // ---- Gauss-point values: face m = tile u, Gauss point k = g ----------------------------
-#pragma unroll 1
-        for (int u = 0; u < 6; ++u) {
-            V y = {0, 0, 0, 0};
-#pragma unroll
-            for (int s = 0; s < 10; ++s) y = mac_coef<PR>(lds + lane, kMfmaOffA2 + u * 10 + s, acc[s >> 2][s & 3], y);
-            const int q = u >> 1;
-            const double xq = (u & 1) ? 0.5 : -0.5;
-            const double x0 = (q == 0) ? xq : ta;
-            const double x1 = (q == 1) ? xq : ((q == 0) ? ta : tb);
-            const double x2 = (q == 2) ? xq : tb;
-            const double val = q0 + chi * (double)y[0] + om * (bbar[0] * x0 + bbar[1] * x1 + bbar[2] * x2);
-            const double r0 = chi * (double)y[1] + om * bbar[0], r1 = chi * (double)y[2] + om * bbar[1],
-                         r2 = chi * (double)y[3] + om * bbar[2];
-            long f;
-            int side;
-            if (u & 1) {
-                f = c;
-                side = 0;
-            } else {
-                f = wrap_cell(b, ci - (q == 0), cj - (q == 1), ck - (q == 2));
-                side = 1;
+            // ---- blend weights ------------------------------------------------------------------------
+            double chi = 1.0, bbar[3] = {0.0, 0.0, 0.0};
+            if (!P.linear) {
+                // linear sub-polynomials of the six face sub-stencils (eq. compact-sub-2)
+                const double lm[3] = {0.25 * lsum[0], 0.25 * lsum[1], 0.25 * lsum[2]};
+                double fdiff[6];
+    #pragma unroll
+                for (int m = 0; m < 6; ++m) {
+                    int o[3] = {0, 0, 0};
+                    o[m >> 1] = (m & 1) ? 1 : -1;
+                    fdiff[m] = Qv[wrap_cell(b, ci + o[0], cj + o[1], ck + o[2])] - q0;
+                }
+                // learned-weight inputs: differences and line derivatives over their largest magnitude
+                double fscale = 1.0;
+                if constexpr (WM == 1 || EXP) {
+                    double mx = fmax(fmax(fabs(lval[0]), fabs(lval[1])), fabs(lval[2]));
+                    mx = fmax(mx, __shfl_xor(mx, 16, 64));
+                    mx = fmax(mx, __shfl_xor(mx, 32, 64));
+    #pragma unroll
+                    for (int m = 0; m < 6; ++m) mx = fmax(mx, fabs(fdiff[m]));
+                    fscale = 1.0 / (mx + 1e-12);
+                }
+                double chi_l = 1.0, om_l[6] = {0, 0, 0, 0, 0, 0};
+                bool geno = true;
+                if constexpr (WM == 1) {
+                    geno = io.jump[c] != 0;
+                    v8bf_t xin;
+    #pragma unroll
+                    for (int jx = 0; jx < 8; ++jx) {
+                        const double f = (jx < 3) ? lval[jx]
+                                                  : ((jx < 5 && g < 3) ? fdiff[2 * g + jx - 3] : 0.0);
+                        xin[jx] = (__bf16)(float)(f * fscale);
+                    }
+                    float z[7];
+                    mlp_eval(mlp_w + lane, mlp_b, mlp_b + kMlpHidden, xin, g, col, z);
+                    mlp_weights(z, chi_l, om_l);
+                }
+                double chi_g = 1.0, om_g[6] = {0, 0, 0, 0, 0, 0};
+                if (WM == 0 || __any(geno)) {
+                    // path function chi: IS^L and IS^tau from the Cholesky-factor contractions
+                    double isl = 0.0, ist = 0.0;
+    #pragma unroll 1
+                    for (int u = 0; u < 5; ++u) {  // tiles 0..2: L_L^T rows, tiles 3..4: L_T^T rows
+                        const int base = (u < 3) ? kMfmaOffAL + u * 10 : kMfmaOffAT + (u - 3) * 10;
+                        V z = {0, 0, 0, 0};
+    #pragma unroll
+                        for (int s = 0; s < 10; ++s) z = mac_coef<PR>(lds + lane, base + s, acc[s >> 2][s & 3], z);
+                        const double zz = (double)z[0] * z[0] + (double)z[1] * z[1] + (double)z[2] * z[2] + (double)z[3] * z[3];
+                        if (u < 3) isl += zz;
+                        else ist += zz;
+                    }
+                    isl += __shfl_xor(isl, 16, 64);
+                    isl += __shfl_xor(isl, 32, 64);
+                    ist += __shfl_xor(ist, 16, 64);
+                    ist += __shfl_xor(ist, 32, 64);
+                    const double ish = isl + ist;
+                    const double rh = ist / (ish + P.geno_eps), rl = ist / (isl + P.geno_eps);
+                    double ah, al;
+                    if (P.geno_r == 2.0) {
+                        ah = 1.0 + rh * rh;
+                        al = 1.0 + rl * rl;
+                    } else {
+                        ah = 1.0 + pow(rh, P.geno_r);
+                        al = 1.0 + pow(rl, P.geno_r);
+                    }
+                    chi_g = tanh(P.geno_C * (2.0 * ah / (ah + al))) * P.inv_tanhC;
+                    double wsum = 0.0;
+    #pragma unroll
+                    for (int m = 0; m < 6; ++m) {
+                        const int q = m >> 1;
+                        const double bn = (m & 1) ? fdiff[m] : -fdiff[m];
+                        double is = P.geno_eps + bn * bn;
+    #pragma unroll
+                        for (int t = 0; t < 3; ++t)
+                            if (t != q) is += lm[t] * lm[t];
+                        const double is2 = is * is;
+                        om_g[m] = (1.0 / 6.0) / (is2 * is2 * is);
+                        wsum += om_g[m];
+                    }
+                    const double iw = 1.0 / wsum;
+    #pragma unroll
+                    for (int m = 0; m < 6; ++m) om_g[m] *= iw;
+                }
+                chi = geno ? chi_g : chi_l;
+    #pragma unroll
+                for (int m = 0; m < 6; ++m) {
+                    const int q = m >> 1;
+                    const double w = geno ? om_g[m] : om_l[m];
+                    const double bn = (m & 1) ? fdiff[m] : -fdiff[m];
+    #pragma unroll
+                    for (int t = 0; t < 3; ++t) bbar[t] += w * ((t == q) ? bn : lm[t]);
+                }
+                if constexpr (EXP) {
+                    if (valid) {
+                        const long sidx = c * kNV + v;
+                        if (g == 0) {
+                            io.wexp[sidx * 7] = chi;
+    #pragma unroll
+                            for (int m = 0; m < 6; ++m) io.wexp[sidx * 7 + 1 + m] = geno ? om_g[m] : om_l[m];
+                        }
+    #pragma unroll
+                        for (int jx = 0; jx < 5; ++jx) {
+                            const int f = mlp_slot_feature(g, jx);
+                            if (f >= 0) {
+                                const double val = (jx < 3) ? lval[jx] : fdiff[2 * g + jx - 3];
+                                io.xexp[sidx * kMlpIn + f] = (float)(val * fscale);
+                            }
+                        }
+                    }
+                }
             }
-            if (valid) {
-                TG *dst = gp + ((long)(((q * 2 + side) * 4 + g) * 20 + v * 4)) * Ntot + f;
-                dst[0] = (TG)val;
-                dst[Ntot] = (TG)(JiT[0][0] * r0 + JiT[0][1] * r1 + JiT[0][2] * r2);
-                dst[2 * Ntot] = (TG)(JiT[1][0] * r0 + JiT[1][1] * r1 + JiT[1][2] * r2);
-                dst[3 * Ntot] = (TG)(JiT[2][0] * r0 + JiT[2][1] * r1 + JiT[2][2] * r2);
+            double JiT[3][3];
+    #pragma unroll
+            for (int r = 0; r < 3; ++r)
+    #pragma unroll
+                for (int s = 0; s < 3; ++s) JiT[r][s] = M.JiT[(3 * r + s) * Ntot + c];
+            const double om = 1.0 - chi;
+
+            // ---- Gauss-point values: face m = tile u, Gauss point k = g ----------------------------
+    #pragma unroll 1
+            for (int u = 0; u < 6; ++u) {
+                V y = {0, 0, 0, 0};
+    #pragma unroll
+                for (int s = 0; s < 10; ++s) y = mac_coef<PR>(lds + lane, kMfmaOffA2 + u * 10 + s, acc[s >> 2][s & 3], y);
+                const int q = u >> 1;
+                const double xq = (u & 1) ? 0.5 : -0.5;
+                const double x0 = (q == 0) ? xq : ta;
+                const double x1 = (q == 1) ? xq : ((q == 0) ? ta : tb);
+                const double x2 = (q == 2) ? xq : tb;
+                const double val = q0 + chi * (double)y[0] + om * (bbar[0] * x0 + bbar[1] * x1 + bbar[2] * x2);
+                const double r0 = chi * (double)y[1] + om * bbar[0], r1 = chi * (double)y[2] + om * bbar[1],
+                             r2 = chi * (double)y[3] + om * bbar[2];
+                long f;
+                int side;
+                if (u & 1) {
+                    f = c;
+                    side = 0;
+                } else {
+                    f = wrap_cell(b, ci - (q == 0), cj - (q == 1), ck - (q == 2));
+                    side = 1;
+                }
+                if (valid) {
+                    TG *dst = gp + ((long)(((q * 2 + side) * 4 + g) * 20 + v * 4)) * Ntot + f;
+                    dst[0] = (TG)val;
+                    dst[Ntot] = (TG)(JiT[0][0] * r0 + JiT[0][1] * r1 + JiT[0][2] * r2);
+                    dst[2 * Ntot] = (TG)(JiT[1][0] * r0 + JiT[1][1] * r1 + JiT[1][2] * r2);
+                    dst[3 * Ntot] = (TG)(JiT[2][0] * r0 + JiT[2][1] * r1 + JiT[2][2] * r2);
+                }
             }
         }
     }
@@ -312,7 +380,7 @@ __device__ inline v4f mma3(const v8bf *Kb, int blk, const v8bf &xh, const v8bf &
 }  // namespace
 
 template <class TG>
-__global__ void __launch_bounds__(512) k_recon_bf16(BlockView b, long Ntot, const double *__restrict__ Q,
+__global__ void __launch_bounds__(512) k_recon_bf16(WorkList W, long Ntot, const double *__restrict__ Q,
                                                     const double *__restrict__ G, const double *__restrict__ L,
                                                     Metrics M, const double *__restrict__ Kbf, DevParams P,
                                                     TG *__restrict__ gp) {
@@ -329,204 +397,222 @@ __global__ void __launch_bounds__(512) k_recon_bf16(BlockView b, long Ntot, cons
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
     const int g = lane >> 4, col = lane & 15;
     const v8bf *Kb = lds + lane;
-    const long nchunks = (b.N + 15) / 16;
-    const long nitems = nchunks * kNV;
     const double gq = 0.28867513459481288225;
     const double ta = (g & 1) ? gq : -gq, tb = (g & 2) ? gq : -gq;
     const int sa = (g & 1) ? 1 : -1, sb = (g & 2) ? 1 : -1;
 
-    for (long it = (long)blockIdx.x * nwaves + wave; it < nitems; it += (long)gridDim.x * nwaves) {
-        const int v = (int)(it % kNV);
-        const long cl0 = (it / kNV) * 16 + col;
-        const bool valid = cl0 < b.N;
-        const long cl = valid ? cl0 : b.N - 1;
-        const int ci = (int)(cl % b.nx);
-        const long tt = cl / b.nx;
-        const int cj = (int)(tt % b.ny), ck = (int)(tt / b.ny);
-        const long c = b.off + cl;
-        const double *Qv = Q + v * Ntot;
-        const double *Gv = G + 3 * v * Ntot;
-        const double *Lv = L + 12 * v * Ntot;
-        double J0[3][3];
-#pragma unroll
-        for (int r = 0; r < 3; ++r)
-#pragma unroll
-            for (int s = 0; s < 3; ++s) J0[r][s] = M.J0[(3 * r + s) * Ntot + c];
-        const double q0 = Qv[c];
+    for (UnitRange ur = unit_range(W.ntiles, W.xcd); ur.u < ur.end; ur.u += ur.step) {
+        const Tile tile = W.tiles[ur.u];
+        const BlockView b = W.blocks[tile.blk];
+        const int nit = ((tile.count + 15) >> 4) * kNV;
+        for (int it = wave; it < nit; it += nwaves) {
+            const int v = it % kNV;
+            const long cl0 = tile.start + (it / kNV) * 16 + col;
+            const long cend = tile.start + tile.count;
+            const bool valid = cl0 < cend;
+            const long cl = valid ? cl0 : cend - 1;  // tail lanes compute a copy, store nothing
+            const int ci = (int)(cl % b.nx);
+            const long tt = cl / b.nx;
+            const int cj = (int)(tt % b.ny), ck = (int)(tt / b.ny);
+            const long c = b.off + cl;
+            const double *Qv = Q + v * Ntot;
+            const double *Gv = G + 3 * v * Ntot;
+            const double *Lv = L + 12 * v * Ntot;
+            double J0[3][3];
+    #pragma unroll
+            for (int r = 0; r < 3; ++r)
+    #pragma unroll
+                for (int s = 0; s < 3; ++s) J0[r][s] = M.J0[(3 * r + s) * Ntot + c];
+            const double q0 = Qv[c];
 
-        // ---- the 18 stencil slots of this lane, split into BF16 hi/lo, slot 8s + j ----------
-        v8bf bh[3], bl[3];
-#pragma unroll
-        for (int s = 0; s < 3; ++s)
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                bh[s][j] = (__bf16)0.0f;
-                bl[s][j] = (__bf16)0.0f;
+            // ---- the 18 stencil slots of this lane, split into BF16 hi/lo, slot 8s + j ----------
+            v8bf bh[3], bl[3];
+    #pragma unroll
+            for (int s = 0; s < 3; ++s)
+    #pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    bh[s][j] = (__bf16)0.0f;
+                    bl[s][j] = (__bf16)0.0f;
+                }
+            double fdiff[6];
+    #pragma unroll
+            for (int m = 0; m < 6; ++m) {
+                int o[3] = {0, 0, 0};
+                o[m >> 1] = (m & 1) ? 1 : -1;
+                const long nb = wrap_cell(b, ci + o[0], cj + o[1], ck + o[2]);
+                const double g0 = Gv[nb], g1 = Gv[Ntot + nb], g2 = Gv[2 * Ntot + nb];
+                fdiff[m] = Qv[nb] - q0;
+                const double r0 = J0[0][0] * g0 + J0[1][0] * g1 + J0[2][0] * g2;
+                const double r1 = J0[0][1] * g0 + J0[1][1] * g1 + J0[2][1] * g2;
+                const double r2 = J0[0][2] * g0 + J0[1][2] * g1 + J0[2][2] * g2;
+                put_bf16(bh, bl, m, (g == 0) ? fdiff[m] : (g == 1) ? r0 : (g == 2) ? r1 : r2);
             }
-        double fdiff[6];
-#pragma unroll
-        for (int m = 0; m < 6; ++m) {
-            int o[3] = {0, 0, 0};
-            o[m >> 1] = (m & 1) ? 1 : -1;
-            const long nb = wrap_cell(b, ci + o[0], cj + o[1], ck + o[2]);
-            const double g0 = Gv[nb], g1 = Gv[Ntot + nb], g2 = Gv[2 * Ntot + nb];
-            fdiff[m] = Qv[nb] - q0;
-            const double r0 = J0[0][0] * g0 + J0[1][0] * g1 + J0[2][0] * g2;
-            const double r1 = J0[0][1] * g0 + J0[1][1] * g1 + J0[2][1] * g2;
-            const double r2 = J0[0][2] * g0 + J0[1][2] * g1 + J0[2][2] * g2;
-            put_bf16(bh, bl, m, (g == 0) ? fdiff[m] : (g == 1) ? r0 : (g == 2) ? r1 : r2);
-        }
-#pragma unroll
-        for (int p = 0; p < 3; ++p) {
-            const int pa = (p < 2) ? 0 : 1, pb = (p == 0) ? 1 : 2, pc = 3 - pa - pb;
-            int o[3] = {0, 0, 0};
-            o[pa] = sa;
-            o[pb] = sb;
-            const long nb = wrap_cell(b, ci + o[0], cj + o[1], ck + o[2]);
-            const int s0 = 6 + p, s1 = 9 + 2 * p, s2 = 10 + 2 * p;
-            put_bf16(bh, bl, s0, Qv[nb] - q0);
-            const double g0 = Gv[nb], g1 = Gv[Ntot + nb], g2 = Gv[2 * Ntot + nb];
-            double rg[3];
-#pragma unroll
-            for (int s = 0; s < 3; ++s) rg[s] = J0[0][s] * g0 + J0[1][s] * g1 + J0[2][s] * g2;
-            put_bf16(bh, bl, s1, rg[pc]);
-            put_bf16(bh, bl, s2, (sa * rg[pa] + sb * rg[pb]) * 0.70710678118654752440);
-        }
-        double lsum[3];
-#pragma unroll
-        for (int s = 0; s < 3; ++s) {
-            const double ln = Lv[(4 * s + g) * Ntot + c];
-            const int sl = 15 + s;
-            put_bf16(bh, bl, sl, ln);
-            double x = ln + __shfl_xor(ln, 16, 64);
-            lsum[s] = x + __shfl_xor(x, 32, 64);
-        }
-        // ---- GEMM1: a = R b ---------------------------------------------------------------------
-        v4f acc[3] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
-#pragma unroll
-        for (int t = 0; t < 3; ++t)
-#pragma unroll
-            for (int s = 0; s < 3; ++s) acc[t] = mma3(Kb, kBfOffA1 + t * 3 + s, bh[s], bl[s], acc[t]);
-        // coefficients of this lane as BF16 hi/lo, slot 8s' + j = 4t + v
-        v8bf ch[2], cl2[2];
-#pragma unroll
-        for (int s = 0; s < 2; ++s)
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const int sig = 8 * s + j;
-                const float x = (sig < 12) ? acc[sig / 4][sig % 4] : 0.0f;
-                const __bf16 h = (__bf16)x;
-                ch[s][j] = h;
-                cl2[s][j] = (__bf16)(x - (float)h);
+    #pragma unroll
+            for (int p = 0; p < 3; ++p) {
+                const int pa = (p < 2) ? 0 : 1, pb = (p == 0) ? 1 : 2, pc = 3 - pa - pb;
+                int o[3] = {0, 0, 0};
+                o[pa] = sa;
+                o[pb] = sb;
+                const long nb = wrap_cell(b, ci + o[0], cj + o[1], ck + o[2]);
+                const int s0 = 6 + p, s1 = 9 + 2 * p, s2 = 10 + 2 * p;
+                put_bf16(bh, bl, s0, Qv[nb] - q0);
+                const double g0 = Gv[nb], g1 = Gv[Ntot + nb], g2 = Gv[2 * Ntot + nb];
+                double rg[3];
+    #pragma unroll
+                for (int s = 0; s < 3; ++s) rg[s] = J0[0][s] * g0 + J0[1][s] * g1 + J0[2][s] * g2;
+                put_bf16(bh, bl, s1, rg[pc]);
+                put_bf16(bh, bl, s2, (sa * rg[pa] + sb * rg[pb]) * 0.70710678118654752440);
             }
+            double lsum[3];
+    #pragma unroll
+            for (int s = 0; s < 3; ++s) {
+                const double ln = Lv[(4 * s + g) * Ntot + c];
+                const int sl = 15 + s;
+                put_bf16(bh, bl, sl, ln);
+                double x = ln + __shfl_xor(ln, 16, 64);
+                lsum[s] = x + __shfl_xor(x, 32, 64);
+            }
+            // ---- GEMM1: a = R b ---------------------------------------------------------------------
+            v4f acc[3] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
+    #pragma unroll
+            for (int t = 0; t < 3; ++t)
+    #pragma unroll
+                for (int s = 0; s < 3; ++s) acc[t] = mma3(Kb, kBfOffA1 + t * 3 + s, bh[s], bl[s], acc[t]);
+            // coefficients of this lane as BF16 hi/lo, slot 8s' + j = 4t + v
+            v8bf ch[2], cl2[2];
+    #pragma unroll
+            for (int s = 0; s < 2; ++s)
+    #pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    const int sig = 8 * s + j;
+                    const float x = (sig < 12) ? acc[sig / 4][sig % 4] : 0.0f;
+                    const __bf16 h = (__bf16)x;
+                    ch[s][j] = h;
+                    cl2[s][j] = (__bf16)(x - (float)h);
+                }
 
-        double chi = 1.0, bbar[3] = {0.0, 0.0, 0.0};
-        if (!P.linear) {
-            double isl = 0.0, ist = 0.0;
-#pragma unroll
-            for (int u = 0; u < 5; ++u) {
-                const int base = (u < 3) ? kBfOffAL + u * 2 : kBfOffAT + (u - 3) * 2;
-                v4f z = {0, 0, 0, 0};
-#pragma unroll
-                for (int s = 0; s < 2; ++s) z = mma3(Kb, base + s, ch[s], cl2[s], z);
-                const double zz = (double)z[0] * z[0] + (double)z[1] * z[1] + (double)z[2] * z[2] + (double)z[3] * z[3];
-                if (u < 3) isl += zz;
-                else ist += zz;
+            double chi = 1.0, bbar[3] = {0.0, 0.0, 0.0};
+            if (!P.linear) {
+                double isl = 0.0, ist = 0.0;
+    #pragma unroll
+                for (int u = 0; u < 5; ++u) {
+                    const int base = (u < 3) ? kBfOffAL + u * 2 : kBfOffAT + (u - 3) * 2;
+                    v4f z = {0, 0, 0, 0};
+    #pragma unroll
+                    for (int s = 0; s < 2; ++s) z = mma3(Kb, base + s, ch[s], cl2[s], z);
+                    const double zz = (double)z[0] * z[0] + (double)z[1] * z[1] + (double)z[2] * z[2] + (double)z[3] * z[3];
+                    if (u < 3) isl += zz;
+                    else ist += zz;
+                }
+                isl += __shfl_xor(isl, 16, 64);
+                isl += __shfl_xor(isl, 32, 64);
+                ist += __shfl_xor(ist, 16, 64);
+                ist += __shfl_xor(ist, 32, 64);
+                const double ish = isl + ist;
+                const double rh = ist / (ish + P.geno_eps), rl = ist / (isl + P.geno_eps);
+                double ah, al;
+                if (P.geno_r == 2.0) {
+                    ah = 1.0 + rh * rh;
+                    al = 1.0 + rl * rl;
+                } else {
+                    ah = 1.0 + pow(rh, P.geno_r);
+                    al = 1.0 + pow(rl, P.geno_r);
+                }
+                chi = tanh(P.geno_C * (2.0 * ah / (ah + al))) * P.inv_tanhC;
+                const double lm[3] = {0.25 * lsum[0], 0.25 * lsum[1], 0.25 * lsum[2]};
+                double wsum = 0.0, wv[6];
+    #pragma unroll
+                for (int m = 0; m < 6; ++m) {
+                    const int q = m >> 1;
+                    const double bn = (m & 1) ? fdiff[m] : -fdiff[m];
+                    double is = P.geno_eps + bn * bn;
+    #pragma unroll
+                    for (int t = 0; t < 3; ++t)
+                        if (t != q) is += lm[t] * lm[t];
+                    const double is2 = is * is;
+                    wv[m] = (1.0 / 6.0) / (is2 * is2 * is);
+                    wsum += wv[m];
+                }
+                const double iw = 1.0 / wsum;
+    #pragma unroll
+                for (int m = 0; m < 6; ++m) {
+                    const int q = m >> 1;
+                    const double w = wv[m] * iw;
+                    const double bn = (m & 1) ? fdiff[m] : -fdiff[m];
+    #pragma unroll
+                    for (int t = 0; t < 3; ++t) bbar[t] += w * ((t == q) ? bn : lm[t]);
+                }
             }
-            isl += __shfl_xor(isl, 16, 64);
-            isl += __shfl_xor(isl, 32, 64);
-            ist += __shfl_xor(ist, 16, 64);
-            ist += __shfl_xor(ist, 32, 64);
-            const double ish = isl + ist;
-            const double rh = ist / (ish + P.geno_eps), rl = ist / (isl + P.geno_eps);
-            double ah, al;
-            if (P.geno_r == 2.0) {
-                ah = 1.0 + rh * rh;
-                al = 1.0 + rl * rl;
-            } else {
-                ah = 1.0 + pow(rh, P.geno_r);
-                al = 1.0 + pow(rl, P.geno_r);
-            }
-            chi = tanh(P.geno_C * (2.0 * ah / (ah + al))) * P.inv_tanhC;
-            const double lm[3] = {0.25 * lsum[0], 0.25 * lsum[1], 0.25 * lsum[2]};
-            double wsum = 0.0, wv[6];
-#pragma unroll
-            for (int m = 0; m < 6; ++m) {
-                const int q = m >> 1;
-                const double bn = (m & 1) ? fdiff[m] : -fdiff[m];
-                double is = P.geno_eps + bn * bn;
-#pragma unroll
-                for (int t = 0; t < 3; ++t)
-                    if (t != q) is += lm[t] * lm[t];
-                const double is2 = is * is;
-                wv[m] = (1.0 / 6.0) / (is2 * is2 * is);
-                wsum += wv[m];
-            }
-            const double iw = 1.0 / wsum;
-#pragma unroll
-            for (int m = 0; m < 6; ++m) {
-                const int q = m >> 1;
-                const double w = wv[m] * iw;
-                const double bn = (m & 1) ? fdiff[m] : -fdiff[m];
-#pragma unroll
-                for (int t = 0; t < 3; ++t) bbar[t] += w * ((t == q) ? bn : lm[t]);
-            }
-        }
-        double JiT[3][3];
-#pragma unroll
-        for (int r = 0; r < 3; ++r)
-#pragma unroll
-            for (int s = 0; s < 3; ++s) JiT[r][s] = M.JiT[(3 * r + s) * Ntot + c];
-        const double om = 1.0 - chi;
-#pragma unroll 1
-        for (int u = 0; u < 6; ++u) {
-            v4f y = {0, 0, 0, 0};
-#pragma unroll
-            for (int s = 0; s < 2; ++s) y = mma3(Kb, kBfOffA2 + u * 2 + s, ch[s], cl2[s], y);
-            const int q = u >> 1;
-            const double xq = (u & 1) ? 0.5 : -0.5;
-            const double x0 = (q == 0) ? xq : ta;
-            const double x1 = (q == 1) ? xq : ((q == 0) ? ta : tb);
-            const double x2 = (q == 2) ? xq : tb;
-            const double val = q0 + chi * (double)y[0] + om * (bbar[0] * x0 + bbar[1] * x1 + bbar[2] * x2);
-            const double r0 = chi * (double)y[1] + om * bbar[0], r1 = chi * (double)y[2] + om * bbar[1],
-                         r2 = chi * (double)y[3] + om * bbar[2];
-            long f;
-            int side;
-            if (u & 1) {
-                f = c;
-                side = 0;
-            } else {
-                f = wrap_cell(b, ci - (q == 0), cj - (q == 1), ck - (q == 2));
-                side = 1;
-            }
-            if (valid) {
-                TG *dst = gp + ((long)(((q * 2 + side) * 4 + g) * 20 + v * 4)) * Ntot + f;
-                dst[0] = (TG)val;
-                dst[Ntot] = (TG)(JiT[0][0] * r0 + JiT[0][1] * r1 + JiT[0][2] * r2);
-                dst[2 * Ntot] = (TG)(JiT[1][0] * r0 + JiT[1][1] * r1 + JiT[1][2] * r2);
-                dst[3 * Ntot] = (TG)(JiT[2][0] * r0 + JiT[2][1] * r1 + JiT[2][2] * r2);
+            double JiT[3][3];
+    #pragma unroll
+            for (int r = 0; r < 3; ++r)
+    #pragma unroll
+                for (int s = 0; s < 3; ++s) JiT[r][s] = M.JiT[(3 * r + s) * Ntot + c];
+            const double om = 1.0 - chi;
+    #pragma unroll 1
+            for (int u = 0; u < 6; ++u) {
+                v4f y = {0, 0, 0, 0};
+    #pragma unroll
+                for (int s = 0; s < 2; ++s) y = mma3(Kb, kBfOffA2 + u * 2 + s, ch[s], cl2[s], y);
+                const int q = u >> 1;
+                const double xq = (u & 1) ? 0.5 : -0.5;
+                const double x0 = (q == 0) ? xq : ta;
+                const double x1 = (q == 1) ? xq : ((q == 0) ? ta : tb);
+                const double x2 = (q == 2) ? xq : tb;
+                const double val = q0 + chi * (double)y[0] + om * (bbar[0] * x0 + bbar[1] * x1 + bbar[2] * x2);
+                const double r0 = chi * (double)y[1] + om * bbar[0], r1 = chi * (double)y[2] + om * bbar[1],
+                             r2 = chi * (double)y[3] + om * bbar[2];
+                long f;
+                int side;
+                if (u & 1) {
+                    f = c;
+                    side = 0;
+                } else {
+                    f = wrap_cell(b, ci - (q == 0), cj - (q == 1), ck - (q == 2));
+                    side = 1;
+                }
+                if (valid) {
+                    TG *dst = gp + ((long)(((q * 2 + side) * 4 + g) * 20 + v * 4)) * Ntot + f;
+                    dst[0] = (TG)val;
+                    dst[Ntot] = (TG)(JiT[0][0] * r0 + JiT[0][1] * r1 + JiT[0][2] * r2);
+                    dst[2 * Ntot] = (TG)(JiT[1][0] * r0 + JiT[1][1] * r1 + JiT[1][2] * r2);
+                    dst[3 * Ntot] = (TG)(JiT[2][0] * r0 + JiT[2][1] * r1 + JiT[2][2] * r2);
+                }
             }
         }
     }
 }
 
-hipError_t launch_recon_mfma(int prec, bool gp32, const BlockView &b, long Ntot, const double *Q, const double *G,
+hipError_t launch_recon_mfma(int prec, bool gp32, const WorkList &W, long Ntot, const double *Q, const double *G,
                              const double *L, const Metrics &M, const double *Kblk, const DevParams &P, void *gp,
-                             int ngroups, hipStream_t s) {
-    // prec: 0 FP64, 1 FP32x3, 2 BF16x3 (Kblk holds the blocks packed for that instruction)
-    const long items = ((b.N + 15) / 16) * kNV;
-    long grid = (items + 7) / 8;
-    if (grid > ngroups) grid = ngroups;
+                             int ngroups, const BlendIO &io, bool exp, hipStream_t s) {
+    // prec: 0 FP64, 1 FP32x3, 2 BF16x3 (Kblk holds the blocks packed for that instruction).
+    // A workgroup takes whole tiles; ngroups <= 0 launches one workgroup per tile.  Learned
+    // weights (P.weights = 1) and the export exist for the FP64 reconstruction only.
+    if (W.ntiles <= 0) return hipSuccess;
+    if ((P.weights == 1 || exp) && prec != 0) return hipErrorInvalidValue;
+    if (exp && gp32) return hipErrorInvalidValue;
+    const int grid = (ngroups <= 0 || ngroups > W.ntiles) ? W.ntiles : ngroups;
     const dim3 gr((unsigned)grid), bl(512);
-    if (prec == 0 && !gp32)
-        hipLaunchKernelGGL((k_recon_mfma<PrecF64, double>), gr, bl, 0, s, b, Ntot, Q, G, L, M, Kblk, P, (double *)gp);
-    else if (prec == 0)
-        hipLaunchKernelGGL((k_recon_mfma<PrecF64, float>), gr, bl, 0, s, b, Ntot, Q, G, L, M, Kblk, P, (float *)gp);
-    else if (prec == 1)
-        hipLaunchKernelGGL((k_recon_mfma<PrecF32x3, float>), gr, bl, 0, s, b, Ntot, Q, G, L, M, Kblk, P, (float *)gp);
-    else
-        hipLaunchKernelGGL((k_recon_bf16<float>), gr, bl, 0, s, b, Ntot, Q, G, L, M, Kblk, P, (float *)gp);
+#define CGKS_RECON(PRC, TGT, WMV, EXV) \
+    hipLaunchKernelGGL((k_recon_mfma<PRC, TGT, WMV, EXV>), gr, bl, 0, s, W, Ntot, Q, G, L, M, Kblk, P, (TGT *)gp, io)
+    if (prec == 0 && !gp32) {
+        if (P.weights == 1) {
+            if (exp) CGKS_RECON(PrecF64, double, 1, true);
+            else CGKS_RECON(PrecF64, double, 1, false);
+        } else {
+            if (exp) CGKS_RECON(PrecF64, double, 0, true);
+            else CGKS_RECON(PrecF64, double, 0, false);
+        }
+    } else if (prec == 0) {
+        if (P.weights == 1) CGKS_RECON(PrecF64, float, 1, false);
+        else CGKS_RECON(PrecF64, float, 0, false);
+    } else if (prec == 1) {
+        CGKS_RECON(PrecF32x3, float, 0, false);
+    } else {
+        hipLaunchKernelGGL((k_recon_bf16<float>), gr, bl, 0, s, W, Ntot, Q, G, L, M, Kblk, P, (float *)gp);
+    }
+#undef CGKS_RECON
     return hipGetLastError();
 }
 

@@ -271,3 +271,16 @@ def isotropic_turbulence(n, k0=4.0, Mt=0.5, gamma=1.4, seed=8965, period=2.0 * m
         one = torch.ones_like(x)
         return one, out[0], out[1], out[2], p_amb * one
     return f
+
+
+def multiblock_dims(nblocks=24, seed=8965):
+    """Uneven block sizes of the multi-block batching workload: nx in [32, 160], ny in [32, 96],
+    nz in [32, 64], drawn per block from one seeded generator."""
+    g = np.random.default_rng(seed)
+    dims = []
+    for _ in range(nblocks):
+        nx = int(g.integers(32, 161))
+        ny = int(g.integers(32, 97))
+        nz = int(g.integers(32, 65))
+        dims.append((nx, ny, nz))
+    return dims

@@ -54,6 +54,13 @@ def test_host_side_argument_errors():
     f = C.c_int()
     assert L.cgks_check(None, C.byref(f)) == K.EINVAL
     assert L.cgks_num_cells(None) == 0
+    bad = K.default_params(per_block=2)
+    assert L.cgks_ctx_create(C.byref(h), 1, dims, nodes, C.byref(bad), None) == K.EINVAL
+    cfg = K.Launch(128, 0, 0)
+    assert L.cgks_get_launch(None, 1, C.byref(cfg)) == K.EINVAL
+    assert L.cgks_set_launch(None, 1, C.byref(cfg)) == K.EINVAL
+    assert L.cgks_autotune(None, None, None, None, None, 1, None, 0, None) == K.EINVAL
+    assert L.cgks_step_graph(None, None, None, None, None, 1, None) == K.EINVAL
 
 
 def test_default_params_are_the_papers_constants():

@@ -1,0 +1,221 @@
+"""Learned blend weights on the GPU against the FP64 oracle: the FP32 gradient of the training
+loss, Adam, the BF16 inference, the exported features / weights / jump flags, the fused blend
+with the weights the GPU used, and training on pairs the plain scheme generates."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_2508_08965_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+GAM = 1.4
+
+
+def K():
+    from paper_2508_08965_amd import cgks
+    return cgks
+
+
+def dev():
+    return torch.device("cuda:0")
+
+
+def tiny_ctx(**kw):
+    n = (4, 4, 4)
+    return K().Context([n], [W.cartesian_nodes(n)], K().default_params(**kw))
+
+
+def rand_batch(seed, n):
+    g = np.random.default_rng(seed)
+    X = g.uniform(-1, 1, size=(n, 18)).astype(np.float32)
+    z = g.normal(size=(n, 7))
+    T = np.zeros((n, 7))
+    T[:, 0] = 1 / (1 + np.exp(-z[:, 0]))
+    e = np.exp(z[:, 1:])
+    T[:, 1:] = e / e.sum(axis=1, keepdims=True)
+    return X, T.astype(np.float32)
+
+
+def f32(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(dev())
+
+
+def test_gradient_matches_fp64_oracle():
+    ctx = tiny_ctx()
+    K().cgks_mlp_init(ctx, 8965)
+    w = K().cgks_mlp_get(ctx).astype(np.float64)
+    X, T = rand_batch(1, 777)
+    grad = torch.zeros(K().MLP_PARAMS, dtype=torch.float32, device=dev())
+    loss = torch.zeros(1, dtype=torch.float32, device=dev())
+    K().cgks_mlp_grad(ctx, f32(X), f32(T), grad, loss)
+    torch.cuda.synchronize()
+    lo, go = O.mlp_loss_grad(w, X.astype(np.float64), T.astype(np.float64))
+    g = grad.cpu().numpy().astype(np.float64)
+    assert abs(loss.item() - lo) <= 1e-5 * lo
+    assert np.abs(g - go).max() <= 1e-4 * np.abs(go).max()
+    ctx.close()
+
+
+def test_adam_step_matches_oracle_on_the_same_gradient():
+    ctx = tiny_ctx()
+    K().cgks_mlp_init(ctx, 3)
+    w0 = K().cgks_mlp_get(ctx).astype(np.float64)
+    X, T = rand_batch(2, 300)
+    B = 128
+    grad = torch.zeros(K().MLP_PARAMS, dtype=torch.float32, device=dev())
+    loss = torch.zeros(1, dtype=torch.float32, device=dev())
+    K().cgks_mlp_grad(ctx, f32(X[:B]), f32(T[:B]), grad, loss)  # the first training batch
+    hist = K().cgks_mlp_train(ctx, f32(X), f32(T), steps=1, batch=B, lr=1e-2)
+    assert abs(hist[0] - loss.item()) <= 1e-6 * loss.item()
+    w1 = K().cgks_mlp_get(ctx).astype(np.float64)
+    g = grad.cpu().numpy().astype(np.float64)
+    wo, _, _ = O.adam(w0, np.zeros_like(w0), np.zeros_like(w0), g, 1, lr=1e-2)
+    np.testing.assert_allclose(w1, wo, rtol=0, atol=1e-6)
+    ctx.close()
+
+
+def test_bf16_inference_within_its_rounding_bound():
+    """Against the FP64 MLP evaluated on the BF16-rounded parameters and inputs: the GPU also
+    rounds the hidden activations to BF16 (relative 2^-8) and accumulates in FP32, so each
+    output moves by at most sum_j |W2_oj| (2^-8 |h_j| + 1e-6) + 1e-6 (sigmoid and softmax are
+    1-Lipschitz in the max norm)."""
+    ctx = tiny_ctx()
+    g = np.random.default_rng(4)
+    w = g.normal(scale=0.4, size=K().MLP_PARAMS).astype(np.float32)
+    K().cgks_mlp_set(ctx, w)
+    X, _ = rand_batch(5, 1000)  # 1000 = 62 waves of 16 + a ragged tail of 8
+    Y = torch.zeros(1000, 7, dtype=torch.float64, device=dev())
+    K().cgks_mlp_infer(ctx, f32(X), Y)
+    torch.cuda.synchronize()
+    wb = w.astype(np.float64)
+    nW1, nb1 = 32 * 18, 32
+    wb[:nW1] = O.bf16(wb[:nW1])
+    wb[nW1 + nb1:nW1 + nb1 + 7 * 32] = O.bf16(wb[nW1 + nb1:nW1 + nb1 + 7 * 32])
+    Yo, Ho = O.mlp_forward(wb, O.bf16(X.astype(np.float64)))
+    W2 = np.abs(wb[nW1 + nb1:nW1 + nb1 + 7 * 32].reshape(7, 32))
+    bound = (W2 @ (2.0 ** -8 * Ho.T + 1e-6)).max(axis=0) + 1e-6
+    err = np.abs(Y.cpu().numpy() - Yo).max(axis=1)
+    assert np.all(err <= bound), float((err / bound).max())
+    ctx.close()
+
+
+def _hit_state(n, Mt=1.0, k0=8.0, seed=8967):
+    nodes = W.perturbed_nodes(n, amp=0.05)
+    Q, G, L = W.initial_state(nodes, W.isotropic_turbulence(32, k0=k0, Mt=Mt, seed=seed), GAM)
+    return nodes, Q, G, L
+
+
+def _evolve(n, nodes, Q, G, L, steps, **kw):
+    ctx = K().Context([n], [nodes], K().default_params(**kw))
+    Qd, Gd, Ld = Q.to(dev()), G.to(dev()), L.to(dev())
+    dt = torch.zeros(1, dtype=torch.float64, device=dev())
+    for _ in range(steps):
+        K().cgks_step(ctx, Qd, Gd, Ld, dt, use_cfl=True)
+    torch.cuda.synchronize()
+    assert K().cgks_check(ctx) == (0, 0)
+    ctx.close()
+    return Qd, Gd, Ld
+
+
+HIT_KW = dict(viscous=1, visc_law=0, mu0=1.44e-3, Pr=0.72, prandtl_fix=1)
+
+
+def _export(ctx, Qd, Gd, Ld):
+    N = Qd.shape[1]
+    X = torch.zeros(N * 5, 18, dtype=torch.float32, device=dev())
+    Wt = torch.zeros(N * 5, 7, dtype=torch.float64, device=dev())
+    jump = torch.zeros(N, dtype=torch.uint8, device=dev())
+    K().cgks_weights(ctx, Qd, Gd, Ld, X, Wt, jump)
+    torch.cuda.synchronize()
+    return X, Wt, jump
+
+
+def test_export_matches_oracle_in_geno_mode():
+    n = (14, 11, 9)
+    nodes, Q, G, L = _hit_state(n)
+    Qd, Gd, Ld = _evolve(n, nodes, Q, G, L, 3, **HIT_KW)
+    ctx = K().Context([n], [nodes], K().default_params(**HIT_KW))
+    X, Wt, jump = _export(ctx, Qd, Gd, Ld)
+    Qh, Gh, Lh = (t.cpu().numpy() for t in (Qd, Gd, Ld))
+    cells = np.arange(Qh.shape[1])
+    Xo, jo = O.features(n, nodes.numpy(), O.params(**HIT_KW), Qh, Lh, cells, thresh=0.05)
+    _, wo = O.recon_weights(n, nodes.numpy(), O.params(**HIT_KW), Qh, Gh, Lh, cells)
+    np.testing.assert_array_equal(jump.cpu().numpy().astype(bool), jo)
+    assert np.abs(X.cpu().numpy() - Xo.reshape(-1, 18)).max() <= 2.0 ** -23
+    assert np.abs(Wt.cpu().numpy() - wo.reshape(-1, 7)).max() <= 1e-9
+    ctx.close()
+
+
+def test_learned_mode_blend_parity_and_fallback():
+    """Learned weights where the jump flag is clear (equal to the inference kernel on the
+    exported features), GENO weights where it is set, and a reconstruction that matches the
+    oracle's given the weights the GPU used."""
+    n = (14, 11, 9)
+    nodes, Q, G, L = _hit_state(n)
+    Qd, Gd, Ld = _evolve(n, nodes, Q, G, L, 3, **HIT_KW)
+    ctx = K().Context([n], [nodes], K().default_params(weights=1, **HIT_KW))
+    with pytest.raises(RuntimeError):  # no parameters yet
+        K().cgks_step(ctx, Qd.clone(), Gd.clone(), Ld.clone(), torch.zeros(1, dtype=torch.float64, device=dev()))
+    K().cgks_mlp_init(ctx, 11)
+    X, Wt, jump = _export(ctx, Qd, Gd, Ld)
+    Qh, Gh, Lh = (t.cpu().numpy() for t in (Qd, Gd, Ld))
+    cells = np.arange(Qh.shape[1])
+    j = jump.cpu().numpy().astype(bool)
+    assert j.any() and not j.all(), j.mean()
+    Y = torch.zeros_like(Wt)
+    K().cgks_mlp_infer(ctx, X, Y)
+    torch.cuda.synchronize()
+    Wg, Yg = Wt.cpu().numpy().reshape(-1, 5, 7), Y.cpu().numpy().reshape(-1, 5, 7)
+    np.testing.assert_array_equal(Wg[~j], Yg[~j])
+    _, wo = O.recon_weights(n, nodes.numpy(), O.params(**HIT_KW), Qh, Gh, Lh, cells)
+    assert np.abs(Wg[j] - wo[j]).max() <= 1e-9
+    gp = torch.zeros(Qh.shape[1], 24, 5, 4, dtype=torch.float64, device=dev())
+    K().cgks_recon(ctx, Qd, Gd, Ld, gp)
+    torch.cuda.synchronize()
+    ref, _ = O.recon_weights(n, nodes.numpy(), O.params(**HIT_KW), Qh, Gh, Lh, cells, win=Wg)
+    out = gp.cpu().numpy()
+    for v in range(5):
+        for c in range(4):
+            scale = max(np.abs(ref[:, :, v, c]).max(), 1e-300)
+            assert np.abs(out[:, :, v, c] - ref[:, :, v, c]).max() <= 1e-12 * scale, (v, c)
+    flagged, examined = K().cgks_mlp_fallback(ctx)
+    assert examined == 2 * Qh.shape[1] and flagged == 2 * int(j.sum())
+    ctx.close()
+
+
+def test_training_on_scheme_pairs_and_learned_run():
+    """Pairs (features, GENO weights) from the plain scheme on supersonic turbulence; the FP32
+    trainer lowers the loss; a run with the learned weights stays physical and close to the
+    plain scheme."""
+    n = (24, 24, 24)
+    nodes, Q, G, L = _hit_state(n)
+    Qd, Gd, Ld = _evolve(n, nodes, Q, G, L, 8, **HIT_KW)
+    ctx = K().Context([n], [nodes], K().default_params(weights=1, **HIT_KW))
+    gen = K().Context([n], [nodes], K().default_params(**HIT_KW))
+    X, Wt, jump = _export(gen, Qd, Gd, Ld)
+    gen.close()
+    T = Wt.float().contiguous()
+    perm = torch.from_numpy(np.random.default_rng(8969).permutation(X.shape[0])).to(dev())
+    X, T = X[perm].contiguous(), T[perm].contiguous()
+    K().cgks_mlp_init(ctx, 8970)
+    hist = K().cgks_mlp_train(ctx, X, T, steps=600, batch=1024, lr=3e-3)
+    assert np.all(np.isfinite(hist))
+    assert hist[-50:].mean() < 0.5 * hist[:10].mean(), (hist[:10].mean(), hist[-50:].mean())
+    dt = torch.zeros(1, dtype=torch.float64, device=dev())
+    Qm, Gm, Lm = Qd.clone(), Gd.clone(), Ld.clone()
+    Qp, Gp, Lp = Qd.clone(), Gd.clone(), Ld.clone()
+    plain = K().Context([n], [nodes], K().default_params(**HIT_KW))
+    for _ in range(5):
+        K().cgks_step(ctx, Qm, Gm, Lm, dt, use_cfl=True)
+        K().cgks_step(plain, Qp, Gp, Lp, dt, use_cfl=True)
+    torch.cuda.synchronize()
+    assert K().cgks_check(ctx) == (0, 0) and K().cgks_check(plain) == (0, 0)
+    rel = float(torch.linalg.vector_norm(Qm[0] - Qp[0]) / torch.linalg.vector_norm(Qp[0]))
+    assert rel < 1e-2, rel
+    flagged, examined = K().cgks_mlp_fallback(ctx)
+    assert examined == 10 * Qd.shape[1] and 0 <= flagged <= examined
+    ctx.close()
+    plain.close()
