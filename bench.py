@@ -249,6 +249,8 @@ def main():
     ap.add_argument("--error-steps", type=int, default=50, help="steps for the variant error against FP64")
     ap.add_argument("--no-batching", action="store_true", help="skip the multi-block batching measurement")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-weight measurement")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first copy 1 GiB device to device (reference for hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported", file=sys.stderr)
@@ -261,6 +263,12 @@ def main():
     from paper_2508_08965_amd import workloads as W
 
     dev = torch.device("cuda:0")
+    if args.copy_calibration:
+        a = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     n = (args.n,) * 3
     N = n[0] * n[1] * n[2]
     nodes = W.perturbed_nodes(n, amp=0.05, device=dev)
