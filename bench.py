@@ -249,6 +249,8 @@ def main():
     ap.add_argument("--error-steps", type=int, default=50, help="steps for the variant error against FP64")
     ap.add_argument("--no-batching", action="store_true", help="skip the multi-block batching measurement")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-weight measurement")
+    ap.add_argument("--dump-state", default=None,
+                    help="write the initial state and parameters of the FP64 workload for cgks_runner, then exit")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy 1 GiB device to device (reference for hardware byte counters)")
     args = ap.parse_args()
@@ -276,6 +278,18 @@ def main():
     nodes_h = nodes.cpu()
     del nodes
     kw = tgv_kw()
+    if args.dump_state:
+        import ctypes
+        prm = K.default_params(**kw)
+        with open(args.dump_state, "wb") as f:
+            f.write(b"CGKSST01")
+            f.write(np.array([n[0], n[1], n[2], ctypes.sizeof(prm)], dtype=np.int32).tobytes())
+            f.write(bytes(prm))
+            nodes_h.numpy().astype(np.float64).tofile(f)
+            for t in (Q0, G0, L0):
+                t.cpu().numpy().tofile(f)
+        print(json.dumps({"dumped": args.dump_state, "cells": N}))
+        return
     dt = torch.zeros(1, dtype=torch.float64, device=dev)
     ctx = K.Context([n], [nodes_h], K.default_params(**kw))
 

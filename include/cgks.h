@@ -181,6 +181,9 @@ typedef struct {
     int tile_cells;
     int ngroups;
     int xcd;
+    int brick_y, brick_z;  /* reconstruction only: 0, 0 for runs of tile_cells cells; both > 0 for
+                              bricks of tile_cells x brick_y x brick_z cells (clipped to the
+                              block) whose workgroup walks its planes in order of z */
 } cgks_launch;
 
 /* Read the launch configuration of a kernel kind (1, 2 or 3) into *out (host). */
@@ -190,13 +193,13 @@ int cgks_get_launch(const cgks_ctx *ctx, int kind, cgks_launch *out);
  * the device (synchronises the device); not for use under HIP graph capture. */
 int cgks_set_launch(cgks_ctx *ctx, int kind, const cgks_launch *cfg);
 
-/* Autotuner: times candidate configurations of the reconstruction (tile size per block-size
- * class: blocks below 2^17 cells, below 2^19, and larger; then grid and XCD order) and of the
+/* Autotuner: times candidate configurations of the reconstruction (runs or bricks per
+ * block-size class: blocks below 2^17 cells, below 2^19, and larger; then grid and XCD order) and of the
  * flux (XCD order) on the given state with HIP events, and keeps the fastest.
  * Q, G, L, dt_dev: device state and time step (read only; the stage buffers of the context
  * are overwritten).  reps: timed launches per candidate (>= 1).  report: host array of at
- * least 64 doubles or NULL; receives per candidate (kind, tile_cells, ngroups, xcd, ms),
- * preceded by the number of candidates.  Synchronises the stream; not capturable. */
+ * least report_len doubles or NULL; receives per candidate (kind, tile_cells, ngroups, xcd,
+ * brick_y, brick_z, ms), preceded by the number of candidates.  Synchronises the stream; not capturable. */
 int cgks_autotune(cgks_ctx *ctx, const double *Q, const double *G, const double *L, const double *dt_dev,
                   int reps, double *report, int report_len, void *stream);
 

@@ -8,6 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "lib", "libcgks.so")
+RUNNER = os.path.join(HERE, "lib", "cgks_runner")
 
 SOURCES = ["cgks_capi.hip", "cgks_kernels.hip", "cgks_recon_mfma.hip", "cgks_mlp.hip", "cgks_consts.cpp"]
 
@@ -27,6 +28,15 @@ def build(verbose: bool = False) -> str:
     if verbose:
         print(r.stderr)
     os.replace(tmp, OUT)
+    # native runner (no PyTorch) used for hardware-counter profiles
+    rflags = [f for f in FLAGS if f not in ("-shared", "-fPIC")]
+    cmd = (["hipcc"] + rflags + ["-I", os.path.join(ROOT, "include"), "-o", RUNNER + ".tmp",
+                                 os.path.join(CSRC, "cgks_runner.cpp"), "-L", os.path.dirname(OUT), "-lcgks",
+                                 "-Wl,-rpath,$ORIGIN"])
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("hipcc failed (runner):\n" + r.stderr)
+    os.replace(RUNNER + ".tmp", RUNNER)
     return OUT
 
 

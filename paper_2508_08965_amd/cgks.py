@@ -32,7 +32,8 @@ class Params(C.Structure):
 class Launch(C.Structure):
     """Mirror of cgks_launch."""
 
-    _fields_ = [("tile_cells", C.c_int), ("ngroups", C.c_int), ("xcd", C.c_int)]
+    _fields_ = [("tile_cells", C.c_int), ("ngroups", C.c_int), ("xcd", C.c_int), ("brick_y", C.c_int),
+                ("brick_z", C.c_int)]
 
 
 _lib = None
@@ -200,24 +201,26 @@ KIND_NAMES = {1: "reconstruction", 2: "flux", 3: "update"}
 def cgks_get_launch(ctx: Context, kind: int) -> dict:
     c = Launch()
     _check(lib().cgks_get_launch(ctx.h, kind, C.byref(c)), "cgks_get_launch")
-    return {"tile_cells": c.tile_cells, "ngroups": c.ngroups, "xcd": c.xcd}
+    return {"tile_cells": c.tile_cells, "ngroups": c.ngroups, "xcd": c.xcd, "brick_y": c.brick_y,
+            "brick_z": c.brick_z}
 
 
-def cgks_set_launch(ctx: Context, kind: int, tile_cells: int, ngroups: int, xcd: int):
-    c = Launch(tile_cells, ngroups, xcd)
+def cgks_set_launch(ctx: Context, kind: int, tile_cells: int, ngroups: int, xcd: int, brick_y=0, brick_z=0):
+    c = Launch(tile_cells, ngroups, xcd, brick_y, brick_z)
     _check(lib().cgks_set_launch(ctx.h, kind, C.byref(c)), "cgks_set_launch")
 
 
 def cgks_autotune(ctx: Context, Q, G, L, dt_dev, reps=3, stream=None):
     """Run the autotuner; returns the timed candidates as a list of dicts."""
-    n = 1 + 5 * 64
+    n = 1 + 7 * 128
     rep = (C.c_double * n)()
     _check(lib().cgks_autotune(ctx.h, _ptr(Q), _ptr(G), _ptr(L), _ptr(dt_dev), reps, rep, n, _stream(stream)),
            "cgks_autotune")
     out = []
     for i in range(int(rep[0])):
-        k, t, g, x, ms = rep[1 + 5 * i: 6 + 5 * i]
-        out.append({"kind": KIND_NAMES[int(k)], "tile_cells": int(t), "ngroups": int(g), "xcd": int(x), "ms": ms})
+        k, t, g, x, by, bz, ms = rep[1 + 7 * i: 8 + 7 * i]
+        out.append({"kind": KIND_NAMES[int(k)], "tile_cells": int(t), "ngroups": int(g), "xcd": int(x),
+                    "brick_y": int(by), "brick_z": int(bz), "ms": ms})
     return out
 
 

@@ -55,7 +55,8 @@ struct cgks_ctx {
     BlockView *d_blocks = nullptr;
     struct List {
         cgks_launch cfg{};
-        std::vector<int> tile_cells;  // per block
+        std::vector<int> tile_cells;  // per block: run length, or brick x extent
+        std::vector<int> by, bz;      // per block: brick extents in y and z (0: runs)
         std::vector<int> first;       // per block: index of its first tile; first[nblocks] = ntiles
         Tile *d = nullptr;
         int n = 0, cap = 0;
@@ -192,8 +193,19 @@ static hipError_t build_list(cgks_ctx *c, int k) {
     l.first.assign(nb + 1, 0);
     for (int b = 0; b < nb; ++b) {
         l.first[b] = (int)t.size();
-        const long N = c->blocks[b].N, T = l.tile_cells[b];
-        for (long st = 0; st < N; st += T) t.push_back(Tile{b, (int)std::min(T, N - st), st});
+        const BlockView &bv = c->blocks[b];
+        const long T = l.tile_cells[b];
+        const int by = l.by.empty() ? 0 : l.by[b], bz = l.bz.empty() ? 0 : l.bz[b];
+        if (by > 0) {
+            for (int z0 = 0; z0 < bv.nz; z0 += bz)
+                for (int y0 = 0; y0 < bv.ny; y0 += by)
+                    for (int x0 = 0; x0 < bv.nx; x0 += (int)T)
+                        t.push_back(Tile{b, (int)std::min<long>(T, bv.nx - x0),
+                                         x0 + (long)bv.nx * (y0 + (long)bv.ny * z0), std::min(by, bv.ny - y0),
+                                         std::min(bz, bv.nz - z0), 0, 0});
+        } else {
+            for (long st = 0; st < bv.N; st += T) t.push_back(Tile{b, (int)std::min(T, bv.N - st), st, 0, 0, 0, 0});
+        }
     }
     l.first[nb] = (int)t.size();
     if ((int)t.size() > l.cap) {
@@ -380,9 +392,9 @@ int cgks_ctx_create(cgks_ctx **out, int nblocks, const int *dims, const double *
         hipDeviceProp_t prop;
         if (hipGetDeviceProperties(&prop, c->device) == hipSuccess) c->ncu = prop.multiProcessorCount;
     }
-    c->wl[1].cfg = cgks_launch{128, 0, 0};
-    c->wl[2].cfg = cgks_launch{kFluxTile, 0, 0};
-    c->wl[3].cfg = cgks_launch{kUpdateTile, 0, 0};
+    c->wl[1].cfg = cgks_launch{512, 0, 0, 0, 0};
+    c->wl[2].cfg = cgks_launch{kFluxTile, 0, 0, 0, 0};
+    c->wl[3].cfg = cgks_launch{kUpdateTile, 0, 0, 0, 0};
     int rc = CGKS_OK;
     do {
         hipError_t e = hipMemcpyAsync(c->K, &dk, sizeof dk, hipMemcpyHostToDevice, s);
@@ -415,6 +427,8 @@ int cgks_ctx_create(cgks_ctx **out, int nblocks, const int *dims, const double *
             e = hipMemcpy(c->d_blocks, c->blocks.data(), sizeof(BlockView) * nblocks, hipMemcpyHostToDevice);
         for (int k = 1; k <= 3 && e == hipSuccess; ++k) {
             c->wl[k].tile_cells.assign(nblocks, c->wl[k].cfg.tile_cells);
+            c->wl[k].by.assign(nblocks, c->wl[k].cfg.brick_y);
+            c->wl[k].bz.assign(nblocks, c->wl[k].cfg.brick_z);
             e = build_list(c, k);
         }
         if (e != hipSuccess) { rc = hip_fail(e, "work lists"); break; }
@@ -556,6 +570,9 @@ static int check_launch(const cgks_ctx *ctx, int kind, const cgks_launch &c) {
     if (kind < 1 || kind > 3) return fail(CGKS_EINVAL, "launch kind must be 1, 2 or 3");
     if (kind == 1 && (c.tile_cells < 16 || c.tile_cells > 4096 || c.tile_cells % 16))
         return fail(CGKS_EINVAL, "reconstruction tiles must be a multiple of 16 cells in [16, 4096]");
+    if (c.brick_y < 0 || c.brick_z < 0 || (c.brick_y > 0) != (c.brick_z > 0) || c.brick_y > 4096 || c.brick_z > 4096)
+        return fail(CGKS_EINVAL, "brick_y and brick_z must both be 0 (runs) or both in [1, 4096]");
+    if (kind != 1 && c.brick_y != 0) return fail(CGKS_EINVAL, "bricks are for the reconstruction only");
     if (kind == 2 && (c.tile_cells != kFluxTile || c.ngroups != 0))
         return fail(CGKS_EINVAL, "flux: tiles of 128 cells, one workgroup per unit (ngroups 0)");
     if (kind == 3 && c.tile_cells != kUpdateTile) return fail(CGKS_EINVAL, "update tiles are 256 cells");
@@ -573,6 +590,8 @@ int cgks_set_launch(cgks_ctx *ctx, int kind, const cgks_launch *cfg) {
     drop_graph(ctx);
     ctx->wl[kind].cfg = *cfg;
     ctx->wl[kind].tile_cells.assign(ctx->blocks.size(), cfg->tile_cells);
+    ctx->wl[kind].by.assign(ctx->blocks.size(), cfg->brick_y);
+    ctx->wl[kind].bz.assign(ctx->blocks.size(), cfg->brick_z);
     HIP_TRY(build_list(ctx, kind), "work list");
     return CGKS_OK;
 }
@@ -588,15 +607,17 @@ int cgks_autotune(cgks_ctx *ctx, const double *Q, const double *G, const double 
     drop_graph(ctx);
     hipEvent_t e0 = get_event(ctx), e1 = get_event(ctx);
     int nrep = 0;
-    auto note = [&](int kind, int tile, int ng, int xcd, double ms) {
+    auto note = [&](int kind, const cgks_launch &c, double ms) {
         if (!report) return;
-        const int at = 1 + 5 * nrep;
-        if (at + 5 > report_len) return;
+        const int at = 1 + 7 * nrep;
+        if (at + 7 > report_len) return;
         report[at] = kind;
-        report[at + 1] = tile;
-        report[at + 2] = ng;
-        report[at + 3] = xcd;
-        report[at + 4] = ms;
+        report[at + 1] = c.tile_cells;
+        report[at + 2] = c.ngroups;
+        report[at + 3] = c.xcd;
+        report[at + 4] = c.brick_y;
+        report[at + 5] = c.brick_z;
+        report[at + 6] = ms;
         report[0] = ++nrep;
     };
     // mean milliseconds of `reps` launches after one untimed launch
@@ -622,20 +643,27 @@ int cgks_autotune(cgks_ctx *ctx, const double *Q, const double *G, const double 
             cgks_ctx::List &l = ctx->wl[1];
             const long lim[2] = {1L << 17, 1L << 19};
             auto cls = [&](long N) { return N < lim[0] ? 0 : (N < lim[1] ? 1 : 2); };
-            const int cand[5] = {64, 128, 256, 512, 1024};
+            // candidates: runs of 64..512 cells and bricks (x, y, z extents) that march along z
+            const int ncand = 11;
+            const int cand[ncand][3] = {{64, 0, 0},  {128, 0, 0}, {256, 0, 0},  {512, 0, 0},
+                                        {1024, 0, 0}, {2048, 0, 0}, {16, 8, 16}, {16, 8, 64},
+                                        {32, 4, 32}, {16, 16, 16}, {64, 2, 32}};
             const cgks_launch base = l.cfg;
-            std::vector<int> best_tile(3, base.tile_cells);
+            std::vector<int> best_c(3, -1);
             for (int k = 0; k < 3 && e == hipSuccess; ++k) {
                 bool any = false;
                 for (int b = 0; b < nb; ++b) any |= cls(ctx->blocks[b].N) == k;
                 if (!any) continue;
-                double best = 1e300;
-                for (int ci = 0; ci < 5 && e == hipSuccess; ++ci) {
-                    for (int b = 0; b < nb; ++b) l.tile_cells[b] = cand[ci];
+                double bestms = 1e300;
+                for (int ci = 0; ci < ncand && e == hipSuccess; ++ci) {
+                    for (int b = 0; b < nb; ++b) {
+                        l.tile_cells[b] = cand[ci][0];
+                        l.by[b] = cand[ci][1];
+                        l.bz[b] = cand[ci][2];
+                    }
                     e = build_list(ctx, 1);
                     if (e != hipSuccess) break;
-                    // tiles of the class's blocks only: blocks of a class are not contiguous, so
-                    // time each block's sub-list and sum
+                    // blocks of a class are not contiguous: time each block's sub-list and sum
                     double ms_sum = 0.0;
                     for (int b = 0; b < nb && e == hipSuccess; ++b) {
                         if (cls(ctx->blocks[b].N) != k) continue;
@@ -649,18 +677,25 @@ int cgks_autotune(cgks_ctx *ctx, const double *Q, const double *G, const double 
                         ms_sum += ms;
                     }
                     if (e != hipSuccess) break;
-                    note(1, cand[ci], base.ngroups, base.xcd, ms_sum);
-                    if (ms_sum < best) {
-                        best = ms_sum;
-                        best_tile[k] = cand[ci];
+                    note(1, cgks_launch{cand[ci][0], base.ngroups, base.xcd, cand[ci][1], cand[ci][2]}, ms_sum);
+                    if (ms_sum < bestms) {
+                        bestms = ms_sum;
+                        best_c[k] = ci;
                     }
                 }
             }
             if (e != hipSuccess) break;
-            for (int b = 0; b < nb; ++b) l.tile_cells[b] = best_tile[cls(ctx->blocks[b].N)];
+            for (int b = 0; b < nb; ++b) {
+                const int ci = best_c[cls(ctx->blocks[b].N)];
+                l.tile_cells[b] = ci >= 0 ? cand[ci][0] : base.tile_cells;
+                l.by[b] = ci >= 0 ? cand[ci][1] : base.brick_y;
+                l.bz[b] = ci >= 0 ? cand[ci][2] : base.brick_z;
+            }
             e = build_list(ctx, 1);
             if (e != hipSuccess) break;
-            l.cfg.tile_cells = best_tile[cls(ctx->blocks[0].N)];
+            l.cfg.tile_cells = l.tile_cells[0];
+            l.cfg.brick_y = l.by[0];
+            l.cfg.brick_z = l.bz[0];
             // 2) grid and XCD order over the whole list
             const int grids[4] = {ctx->ncu, 2 * ctx->ncu, 4 * ctx->ncu, 0};
             double best = 1e300;
@@ -677,7 +712,7 @@ int cgks_autotune(cgks_ctx *ctx, const double *Q, const double *G, const double 
                                                               BlendIO{ctx->jump, ctx->mlp_packed, nullptr, nullptr},
                                                               false, s); },
                                ms);
-                    note(1, l.cfg.tile_cells, grids[gi], x, ms);
+                    note(1, l.cfg, ms);
                     if (ms < best) {
                         best = ms;
                         pick = l.cfg;
@@ -699,7 +734,7 @@ int cgks_autotune(cgks_ctx *ctx, const double *Q, const double *G, const double 
                 l.cfg.xcd = x;
                 double ms = 0.0;
                 e = timeit([&] { return run_flux(ctx, -1, dt_dev, s); }, ms);
-                note(2, kFluxTile, 0, x, ms);
+                note(2, l.cfg, ms);
                 if (ms < best) {
                     best = ms;
                     pick = l.cfg;

@@ -15,10 +15,16 @@ struct BlockView {
 
 // A run of consecutive cells of one block (block-local linear index, x fastest): the unit of
 // the work lists that let one launch cover every block of a multi-block mesh.
+// A tile is either a run of consecutive cells (ty = 0; every kernel) or, for the
+// reconstruction, a brick of count x ty x tz cells whose corner cell is `start` (rows of the
+// brick are split into chunks of 16 cells along x, planes are visited in order of z so that a
+// workgroup re-reads the neighbour planes it has just touched).
 struct Tile {
     int blk;     // index into the block table
-    int count;   // cells in the run (>= 1)
-    long start;  // first cell of the run
+    int count;   // cells in the run (>= 1), or x extent of the brick
+    long start;  // first cell of the run, or corner cell of the brick (block-local)
+    int ty, tz;  // brick extents in y and z (0 for a run)
+    int pad0, pad1;
 };
 
 struct WorkList {

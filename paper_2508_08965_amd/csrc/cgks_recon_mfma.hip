@@ -129,16 +129,38 @@ __global__ void __launch_bounds__(512) k_recon_mfma(WorkList W, long Ntot, const
     for (UnitRange ur = unit_range(W.ntiles, W.xcd); ur.u < ur.end; ur.u += ur.step) {
         const Tile tile = W.tiles[ur.u];
         const BlockView b = W.blocks[tile.blk];
-        const int nit = ((tile.count + 15) >> 4) * kNV;
+        const int cpr = (tile.count + 15) >> 4;  // chunks per run / per brick row
+        int bx0 = 0, by0 = 0, bz0 = 0;
+        if (tile.ty > 0) {
+            bx0 = (int)(tile.start % b.nx);
+            const long t0 = tile.start / b.nx;
+            by0 = (int)(t0 % b.ny);
+            bz0 = (int)(t0 / b.ny);
+        }
+        const int nit = cpr * (tile.ty > 0 ? tile.ty * tile.tz : 1) * kNV;
         for (int it = wave; it < nit; it += nwaves) {
             const int v = it % kNV;
-            const long cl0 = tile.start + (it / kNV) * 16 + col;
-            const long cend = tile.start + tile.count;
-            const bool valid = cl0 < cend;
-            const long cl = valid ? cl0 : cend - 1;  // tail lanes compute a copy, store nothing
-            const int ci = (int)(cl % b.nx);
-            const long tt = cl / b.nx;
-            const int cj = (int)(tt % b.ny), ck = (int)(tt / b.ny);
+            const int chunk = it / kNV;
+            bool valid;
+            int ci, cj, ck;
+            long cl;
+            if (tile.ty > 0) {
+                const int xo = 16 * (chunk % cpr) + col, row = chunk / cpr;
+                valid = xo < tile.count;
+                ci = bx0 + (valid ? xo : 0);  // tail lanes compute a copy, store nothing
+                cj = by0 + row % tile.ty;
+                ck = bz0 + row / tile.ty;
+                cl = ci + (long)b.nx * (cj + (long)b.ny * ck);
+            } else {
+                const long cl0 = tile.start + chunk * 16 + col;
+                const long cend = tile.start + tile.count;
+                valid = cl0 < cend;
+                cl = valid ? cl0 : cend - 1;
+                ci = (int)(cl % b.nx);
+                const long tt = cl / b.nx;
+                cj = (int)(tt % b.ny);
+                ck = (int)(tt / b.ny);
+            }
             const long c = b.off + cl;
             const double *Qv = Q + v * Ntot;
             const double *Gv = G + 3 * v * Ntot;
@@ -151,50 +173,61 @@ __global__ void __launch_bounds__(512) k_recon_mfma(WorkList W, long Ntot, const
             const double q0 = Qv[c];
 
             V acc[3] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
-            // ---- steps 0..5: face neighbours (difference and reference gradient) -------------
-    #pragma unroll 1
-            for (int m = 0; m < 6; ++m) {
-                int o[3] = {0, 0, 0};
-                o[m >> 1] = (m & 1) ? 1 : -1;
-                const long nb = wrap_cell(b, ci + o[0], cj + o[1], ck + o[2]);
-                const double g0 = Gv[nb], g1 = Gv[Ntot + nb], g2 = Gv[2 * Ntot + nb];
-                const double fd = Qv[nb] - q0;
-                const double r0 = J0[0][0] * g0 + J0[1][0] * g1 + J0[2][0] * g2;
-                const double r1 = J0[0][1] * g0 + J0[1][1] * g1 + J0[2][1] * g2;
-                const double r2 = J0[0][2] * g0 + J0[1][2] * g1 + J0[2][2] * g2;
-                const double item = (g == 0) ? fd : (g == 1) ? r0 : (g == 2) ? r1 : r2;
+            // line derivatives of the cell (steps 15..17), loaded ahead of the neighbour gather
+            double lval[3];
     #pragma unroll
-                for (int t = 0; t < 3; ++t) acc[t] = mac_data<PR>(A1, t * 18 + m, item, acc[t]);
-            }
-            // ---- steps 6..14: edge neighbours 4p+g ---------------------------------------------
-    #pragma unroll 1
-            for (int p = 0; p < 3; ++p) {
-                const int pa = (p < 2) ? 0 : 1, pb = (p == 0) ? 1 : 2, pc = 3 - pa - pb;
+            for (int s = 0; s < 3; ++s) lval[s] = Lv[(4 * s + g) * Ntot + c];
+            // ---- steps 0..14: face neighbours m (steps m), then edge neighbours 4p+g (steps
+            // 6+p, 9+2p, 10+2p).  Gather step st+1 is loaded while step st is contracted.
+            auto nb_of = [&](int st) -> long {
                 int o[3] = {0, 0, 0};
-                o[pa] = sa;
-                o[pb] = sb;
-                const long nb = wrap_cell(b, ci + o[0], cj + o[1], ck + o[2]);
-                const double d = Qv[nb] - q0;
-    #pragma unroll
-                for (int t = 0; t < 3; ++t) acc[t] = mac_data<PR>(A1, t * 18 + 6 + p, d, acc[t]);
-                const double g0 = Gv[nb], g1 = Gv[Ntot + nb], g2 = Gv[2 * Ntot + nb];
+                if (st < 6) {
+                    o[st >> 1] = (st & 1) ? 1 : -1;
+                } else {
+                    const int p = st - 6, pa = (p < 2) ? 0 : 1, pb = (p == 0) ? 1 : 2;
+                    o[pa] = sa;
+                    o[pb] = sb;
+                }
+                return wrap_cell(b, ci + o[0], cj + o[1], ck + o[2]);
+            };
+            long nb = nb_of(0);
+            double nq = Qv[nb], n0 = Gv[nb], n1 = Gv[Ntot + nb], n2 = Gv[2 * Ntot + nb];
+    #pragma unroll 1
+            for (int st = 0; st < 9; ++st) {
+                const double d = nq - q0, g0 = n0, g1 = n1, g2 = n2;
+                if (st < 8) {
+                    nb = nb_of(st + 1);
+                    nq = Qv[nb];
+                    n0 = Gv[nb];
+                    n1 = Gv[Ntot + nb];
+                    n2 = Gv[2 * Ntot + nb];
+                }
                 double rg[3];
     #pragma unroll
-                for (int s = 0; s < 3; ++s) rg[s] = J0[0][s] * g0 + J0[1][s] * g1 + J0[2][s] * g2;
-                const double e1 = (pc == 0) ? rg[0] : (pc == 1) ? rg[1] : rg[2];
-                const double ra = (pa == 0) ? rg[0] : rg[1], rb = (pb == 1) ? rg[1] : rg[2];
-                const double e2 = (sa * ra + sb * rb) * 0.70710678118654752440;
+                for (int r = 0; r < 3; ++r) rg[r] = J0[0][r] * g0 + J0[1][r] * g1 + J0[2][r] * g2;
+                if (st < 6) {
+                    const double item = (g == 0) ? d : (g == 1) ? rg[0] : (g == 2) ? rg[1] : rg[2];
     #pragma unroll
-                for (int t = 0; t < 3; ++t) acc[t] = mac_data<PR>(A1, t * 18 + 9 + 2 * p, e1, acc[t]);
+                    for (int t = 0; t < 3; ++t) acc[t] = mac_data<PR>(A1, t * 18 + st, item, acc[t]);
+                } else {
+                    const int p = st - 6;
+                    const int pa = (p < 2) ? 0 : 1, pb = (p == 0) ? 1 : 2, pc = 3 - pa - pb;
+                    const double e1 = (pc == 0) ? rg[0] : (pc == 1) ? rg[1] : rg[2];
+                    const double ra = (pa == 0) ? rg[0] : rg[1], rb = (pb == 1) ? rg[1] : rg[2];
+                    const double e2 = (sa * ra + sb * rb) * 0.70710678118654752440;
     #pragma unroll
-                for (int t = 0; t < 3; ++t) acc[t] = mac_data<PR>(A1, t * 18 + 10 + 2 * p, e2, acc[t]);
+                    for (int t = 0; t < 3; ++t) acc[t] = mac_data<PR>(A1, t * 18 + 6 + p, d, acc[t]);
+    #pragma unroll
+                    for (int t = 0; t < 3; ++t) acc[t] = mac_data<PR>(A1, t * 18 + 9 + 2 * p, e1, acc[t]);
+    #pragma unroll
+                    for (int t = 0; t < 3; ++t) acc[t] = mac_data<PR>(A1, t * 18 + 10 + 2 * p, e2, acc[t]);
+                }
             }
             // ---- steps 15..17: line differences 4t+g ---------------------------------------------
-            double lsum[3], lval[3];
+            double lsum[3];
     #pragma unroll
             for (int s = 0; s < 3; ++s) {
-                const double ln = Lv[(4 * s + g) * Ntot + c];
-                lval[s] = ln;
+                const double ln = lval[s];
     #pragma unroll
                 for (int t = 0; t < 3; ++t) acc[t] = mac_data<PR>(A1, t * 18 + 15 + s, ln, acc[t]);
                 double x = ln + __shfl_xor(ln, 16, 64);
@@ -404,16 +437,38 @@ __global__ void __launch_bounds__(512) k_recon_bf16(WorkList W, long Ntot, const
     for (UnitRange ur = unit_range(W.ntiles, W.xcd); ur.u < ur.end; ur.u += ur.step) {
         const Tile tile = W.tiles[ur.u];
         const BlockView b = W.blocks[tile.blk];
-        const int nit = ((tile.count + 15) >> 4) * kNV;
+        const int cpr = (tile.count + 15) >> 4;  // chunks per run / per brick row
+        int bx0 = 0, by0 = 0, bz0 = 0;
+        if (tile.ty > 0) {
+            bx0 = (int)(tile.start % b.nx);
+            const long t0 = tile.start / b.nx;
+            by0 = (int)(t0 % b.ny);
+            bz0 = (int)(t0 / b.ny);
+        }
+        const int nit = cpr * (tile.ty > 0 ? tile.ty * tile.tz : 1) * kNV;
         for (int it = wave; it < nit; it += nwaves) {
             const int v = it % kNV;
-            const long cl0 = tile.start + (it / kNV) * 16 + col;
-            const long cend = tile.start + tile.count;
-            const bool valid = cl0 < cend;
-            const long cl = valid ? cl0 : cend - 1;  // tail lanes compute a copy, store nothing
-            const int ci = (int)(cl % b.nx);
-            const long tt = cl / b.nx;
-            const int cj = (int)(tt % b.ny), ck = (int)(tt / b.ny);
+            const int chunk = it / kNV;
+            bool valid;
+            int ci, cj, ck;
+            long cl;
+            if (tile.ty > 0) {
+                const int xo = 16 * (chunk % cpr) + col, row = chunk / cpr;
+                valid = xo < tile.count;
+                ci = bx0 + (valid ? xo : 0);  // tail lanes compute a copy, store nothing
+                cj = by0 + row % tile.ty;
+                ck = bz0 + row / tile.ty;
+                cl = ci + (long)b.nx * (cj + (long)b.ny * ck);
+            } else {
+                const long cl0 = tile.start + chunk * 16 + col;
+                const long cend = tile.start + tile.count;
+                valid = cl0 < cend;
+                cl = valid ? cl0 : cend - 1;
+                ci = (int)(cl % b.nx);
+                const long tt = cl / b.nx;
+                cj = (int)(tt % b.ny);
+                ck = (int)(tt / b.ny);
+            }
             const long c = b.off + cl;
             const double *Qv = Q + v * Ntot;
             const double *Gv = G + 3 * v * Ntot;

@@ -110,21 +110,25 @@ def test_batched_equals_per_block_launches_bitwise():
     assert a[4] == b[4]
 
 
-@pytest.mark.parametrize("rtile,rgroups,rxcd,fgroups,fxcd,ugroups", [
-    (16, 0, 0, 0, 0, 0),
-    (48, 8, 1, 0, 1, 8),
-    (4096, 3, 0, 0, 0, 1),
-    (128, 512, 1, 0, 1, 0),
+@pytest.mark.parametrize("rtile,rgroups,rxcd,fgroups,fxcd,ugroups,by,bz", [
+    (16, 0, 0, 0, 0, 0, 0, 0),
+    (48, 8, 1, 0, 1, 8, 0, 0),
+    (4096, 3, 0, 0, 0, 1, 0, 0),
+    (128, 512, 1, 0, 1, 0, 0, 0),
+    (16, 0, 0, 0, 0, 0, 8, 16),   # bricks with ragged edges in x, y and z
+    (32, 24, 1, 0, 1, 0, 3, 5),
+    (4096, 0, 1, 0, 0, 0, 4096, 4096),  # one brick per block
 ])
-def test_launch_configurations_bitwise(rtile, rgroups, rxcd, fgroups, fxcd, ugroups):
+def test_launch_configurations_bitwise(rtile, rgroups, rxcd, fgroups, fxcd, ugroups, by, bz):
     nodes, states = blocks_state()
     ref = run_gpu(K().default_params(**hit_kw()), nodes, states, 2)
 
     def configure(ctx):
-        K().cgks_set_launch(ctx, 1, rtile, rgroups, rxcd)
+        K().cgks_set_launch(ctx, 1, rtile, rgroups, rxcd, by, bz)
         K().cgks_set_launch(ctx, 2, 128, fgroups, fxcd)
         K().cgks_set_launch(ctx, 3, 256, ugroups, 0)
-        assert K().cgks_get_launch(ctx, 1) == {"tile_cells": rtile, "ngroups": rgroups, "xcd": rxcd}
+        assert K().cgks_get_launch(ctx, 1) == {"tile_cells": rtile, "ngroups": rgroups, "xcd": rxcd,
+                                              "brick_y": by, "brick_z": bz}
 
     got = run_gpu(K().default_params(**hit_kw()), nodes, states, 2, configure=configure)
     assert got[0] == (0, 0)
@@ -135,10 +139,12 @@ def test_launch_configurations_bitwise(rtile, rgroups, rxcd, fgroups, fxcd, ugro
 def test_invalid_launch_configurations_rejected():
     nodes, states = blocks_state()
     ctx = K().Context(DIMS, nodes, K().default_params(**hit_kw()))
-    for kind, t, g, x in [(1, 24, 0, 0), (1, 8192, 0, 0), (2, 64, 0, 0), (3, 128, 0, 0), (1, 128, 12, 1),
-                          (4, 128, 0, 0), (1, 128, -1, 0), (2, 128, 16, 0)]:
+    for kind, t, g, x, by, bz in [(1, 24, 0, 0, 0, 0), (1, 8192, 0, 0, 0, 0), (2, 64, 0, 0, 0, 0),
+                                  (3, 128, 0, 0, 0, 0), (1, 128, 12, 1, 0, 0), (4, 128, 0, 0, 0, 0),
+                                  (1, 128, -1, 0, 0, 0), (2, 128, 16, 0, 0, 0), (1, 16, 0, 0, 4, 0),
+                                  (1, 16, 0, 0, -1, 2), (3, 256, 0, 0, 2, 2)]:
         with pytest.raises(RuntimeError):
-            K().cgks_set_launch(ctx, kind, t, g, x)
+            K().cgks_set_launch(ctx, kind, t, g, x, by, bz)
     ctx.close()
 
 
