@@ -44,11 +44,15 @@ struct PrecF64 {
     using T = double;
     using V = v4d;
     static constexpr int kSplit = 1;
+    // k-steps of the coefficient contractions: in this layout k-step 9 holds rows 36..39 of
+    // the 34 coefficients only (all zero) and is skipped
+    static constexpr int kCoefSteps = 9;
     __device__ static V mma(T a, T b, V c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
 };
 struct PrecF32x3 {
     using T = float;
     using V = v4f;
+    static constexpr int kCoefSteps = 10;
     static constexpr int kSplit = 2;
     __device__ static V mma(T a, T b, V c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
 };
@@ -278,9 +282,13 @@ __global__ void __launch_bounds__(512) k_recon_mfma(WorkList W, long Ntot, const
     #pragma unroll 1
                     for (int u = 0; u < 5; ++u) {  // tiles 0..2: L_L^T rows, tiles 3..4: L_T^T rows
                         const int base = (u < 3) ? kMfmaOffAL + u * 10 : kMfmaOffAT + (u - 3) * 10;
+                        // the Cholesky factors are triangular: rows 16w.. of tile w = u (mod 3) vanish on
+                        // the coefficients of k-steps below 4w, which are skipped (their products are zero)
+                        const int s0 = 4 * ((u < 3) ? u : u - 3);
                         V z = {0, 0, 0, 0};
     #pragma unroll
-                        for (int s = 0; s < 10; ++s) z = mac_coef<PR>(lds + lane, base + s, acc[s >> 2][s & 3], z);
+                        for (int s = 0; s < PR::kCoefSteps; ++s)
+                            if (s >= s0) z = mac_coef<PR>(lds + lane, base + s, acc[s >> 2][s & 3], z);
                         const double zz = (double)z[0] * z[0] + (double)z[1] * z[1] + (double)z[2] * z[2] + (double)z[3] * z[3];
                         if (u < 3) isl += zz;
                         else ist += zz;
@@ -357,7 +365,8 @@ __global__ void __launch_bounds__(512) k_recon_mfma(WorkList W, long Ntot, const
             for (int u = 0; u < 6; ++u) {
                 V y = {0, 0, 0, 0};
     #pragma unroll
-                for (int s = 0; s < 10; ++s) y = mac_coef<PR>(lds + lane, kMfmaOffA2 + u * 10 + s, acc[s >> 2][s & 3], y);
+                for (int s = 0; s < PR::kCoefSteps; ++s)
+                    y = mac_coef<PR>(lds + lane, kMfmaOffA2 + u * 10 + s, acc[s >> 2][s & 3], y);
                 const int q = u >> 1;
                 const double xq = (u & 1) ? 0.5 : -0.5;
                 const double x0 = (q == 0) ? xq : ta;
