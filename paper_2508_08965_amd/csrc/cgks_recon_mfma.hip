@@ -47,12 +47,16 @@ struct PrecF64 {
     // k-steps of the coefficient contractions: in this layout k-step 9 holds rows 36..39 of
     // the 34 coefficients only (all zero) and is skipped
     static constexpr int kCoefSteps = 9;
+    // coefficients 32 and 33 (the only real rows of the third GEMM1 tile) are accumulated on the
+    // vector ALU instead of with 18 mostly-padding matrix instructions
+    static constexpr bool kTailOnValu = true;
     __device__ static V mma(T a, T b, V c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
 };
 struct PrecF32x3 {
     using T = float;
     using V = v4f;
     static constexpr int kCoefSteps = 10;
+    static constexpr bool kTailOnValu = false;
     static constexpr int kSplit = 2;
     __device__ static V mma(T a, T b, V c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
 };
@@ -177,6 +181,19 @@ __global__ void __launch_bounds__(512) k_recon_mfma(WorkList W, long Ntot, const
             const double q0 = Qv[c];
 
             V acc[3] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
+            double a32 = 0.0, a33 = 0.0;  // partial sums of coefficients 32, 33 (kTailOnValu)
+            // GEMM1 step: the stencil item of this lane times column sb of R
+            auto gemm1 = [&](int sb, double item) {
+                acc[0] = mac_data<PR>(A1, sb, item, acc[0]);
+                acc[1] = mac_data<PR>(A1, 18 + sb, item, acc[1]);
+                if constexpr (PR::kTailOnValu) {
+                    const T *r2 = lds + (kMfmaOffA1 + 36 + sb) * 64 + 16 * g;  // rows 32, 33 of tile 2
+                    a32 = fma((double)r2[0], item, a32);
+                    a33 = fma((double)r2[1], item, a33);
+                } else {
+                    acc[2] = mac_data<PR>(A1, 36 + sb, item, acc[2]);
+                }
+            };
             // line derivatives of the cell (steps 15..17), loaded ahead of the neighbour gather
             double lval[3];
     #pragma unroll
@@ -211,20 +228,16 @@ __global__ void __launch_bounds__(512) k_recon_mfma(WorkList W, long Ntot, const
                 for (int r = 0; r < 3; ++r) rg[r] = J0[0][r] * g0 + J0[1][r] * g1 + J0[2][r] * g2;
                 if (st < 6) {
                     const double item = (g == 0) ? d : (g == 1) ? rg[0] : (g == 2) ? rg[1] : rg[2];
-    #pragma unroll
-                    for (int t = 0; t < 3; ++t) acc[t] = mac_data<PR>(A1, t * 18 + st, item, acc[t]);
+                    gemm1(st, item);
                 } else {
                     const int p = st - 6;
                     const int pa = (p < 2) ? 0 : 1, pb = (p == 0) ? 1 : 2, pc = 3 - pa - pb;
                     const double e1 = (pc == 0) ? rg[0] : (pc == 1) ? rg[1] : rg[2];
                     const double ra = (pa == 0) ? rg[0] : rg[1], rb = (pb == 1) ? rg[1] : rg[2];
                     const double e2 = (sa * ra + sb * rb) * 0.70710678118654752440;
-    #pragma unroll
-                    for (int t = 0; t < 3; ++t) acc[t] = mac_data<PR>(A1, t * 18 + 6 + p, d, acc[t]);
-    #pragma unroll
-                    for (int t = 0; t < 3; ++t) acc[t] = mac_data<PR>(A1, t * 18 + 9 + 2 * p, e1, acc[t]);
-    #pragma unroll
-                    for (int t = 0; t < 3; ++t) acc[t] = mac_data<PR>(A1, t * 18 + 10 + 2 * p, e2, acc[t]);
+                    gemm1(6 + p, d);
+                    gemm1(9 + 2 * p, e1);
+                    gemm1(10 + 2 * p, e2);
                 }
             }
             // ---- steps 15..17: line differences 4t+g ---------------------------------------------
@@ -232,10 +245,17 @@ __global__ void __launch_bounds__(512) k_recon_mfma(WorkList W, long Ntot, const
     #pragma unroll
             for (int s = 0; s < 3; ++s) {
                 const double ln = lval[s];
-    #pragma unroll
-                for (int t = 0; t < 3; ++t) acc[t] = mac_data<PR>(A1, t * 18 + 15 + s, ln, acc[t]);
+                gemm1(15 + s, ln);
                 double x = ln + __shfl_xor(ln, 16, 64);
                 lsum[s] = x + __shfl_xor(x, 32, 64);
+            }
+            if constexpr (PR::kTailOnValu) {
+                // sum over the four lane groups; in register 0 of tile 2, lane group g holds row 32+g
+                a32 += __shfl_xor(a32, 16, 64);
+                a32 += __shfl_xor(a32, 32, 64);
+                a33 += __shfl_xor(a33, 16, 64);
+                a33 += __shfl_xor(a33, 32, 64);
+                acc[2] = V{(g == 0) ? a32 : ((g == 1) ? a33 : 0.0), 0.0, 0.0, 0.0};
             }
 
             // ---- blend weights ------------------------------------------------------------------------
