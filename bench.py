@@ -23,13 +23,44 @@ sys.path.insert(0, ROOT)
 GAM = 1.4
 PEAK = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}  # TFLOP/s, MI355X dense (FP64 vector and matrix: 78.6)
 
-# Algorithmic work per unit (see the measurement section of the design notes):
+# Algorithmic work per unit:
 #   flux: source-level operation count of the gas-kinetic flux per Gauss point (flux_opcount.cpp);
 #         one stage evaluates 12 Gauss points per cell (3 owned faces x 4 points)
-#   reconstruction: the formulated dense products per cell and stage, 5 variables x
-#         2 (34x72 + 34x34 + 31x34 + 96x34)  (a = R b, Cholesky factors, Gauss-point values)
+#   reconstruction: the products the method needs per cell and stage, 5 variables x 2 flops x
+#         (34 x 72 for a = R b, 96 x 34 for the Gauss-point values and gradients E a, and the two
+#         smoothness forms through their triangular factors, 34 x 35 / 2 + 31 x 32 / 2)
 FLUX_FLOP_PER_GP = 8454
-RECON_FLOP_PER_CELL = 2 * 5 * (34 * 72 + 34 * 34 + 31 * 34 + 96 * 34)
+RECON_FLOP_PER_CELL = 2 * 5 * (34 * 72 + 96 * 34 + 34 * 35 // 2 + 31 * 32 // 2)
+COUNTERS = os.path.join(ROOT, "profiles", "counters_tgv256_fp64.md")
+
+
+def source_digest():
+    """sha256 over the library sources (csrc/*.hip, *.h, *.cpp, sorted by name)."""
+    import hashlib
+    d = os.path.join(ROOT, "paper_2508_08965_amd", "csrc")
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(d)):
+        if name.endswith((".hip", ".h", ".cpp")):
+            h.update(name.encode())
+            with open(os.path.join(d, name), "rb") as f:
+                h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed hardware-counter summary (FETCH_SIZE and
+    WRITE_SIZE scaled by a copy kernel of known size), or None if the summary is missing, was taken
+    on another workload, or the library sources changed since it was taken."""
+    try:
+        text = open(COUNTERS).read()
+        blob = text.split("```json", 1)[1].split("```", 1)[0]
+        rec = json.loads(blob)
+    except (OSError, IndexError, ValueError):
+        return None
+    if rec.get("source_sha256") != source_digest():
+        return None
+    k = rec.get("kernels", {}).get(kernel)
+    return None if k is None else k["read_bytes"] + k["write_bytes"]
 
 
 def tgv_kw():
@@ -51,7 +82,7 @@ def timed_steps(K, ctx, Q, G, L, dt, steps):
     return t1 - t0, K.cgks_profile_read(ctx)
 
 
-def roofline(prof, N, peak_key):
+def roofline(prof, N, peak_key, counters=False):
     kinds = {k: v for k, v in prof.items() if v[1] > 0}
     dom = max(kinds, key=lambda k: kinds[k][0])
     avg_ms = kinds[dom][0] / kinds[dom][1]
@@ -64,7 +95,8 @@ def roofline(prof, N, peak_key):
     else:
         return {"kernel": dom, "avg_ms": avg_ms, "bound": None, "achieved": None, "peak": None, "unit": None,
                 "frac": None, "traffic": None}
-    roof.update({"achieved": work / (avg_ms * 1e-3) / 1e12, "unit": "TFLOP/s", "traffic": None})
+    roof.update({"achieved": work / (avg_ms * 1e-3) / 1e12, "unit": "TFLOP/s",
+                 "traffic": measured_traffic(dom) if counters else None})
     roof["frac"] = roof["achieved"] / roof["peak"]
     roof.update({"kernel": dom, "avg_ms": avg_ms, "work_per_launch": work})
     return roof
@@ -327,7 +359,7 @@ def main():
     status, flags = K.cgks_check(ctx)
     ms_per_step = 1e3 * elapsed / args.steps
     value = N * args.steps / elapsed
-    roof = roofline(prof, N, "fp64")
+    roof = roofline(prof, N, "fp64", counters=(args.n == 256))
     del Q, G, L
 
     # ---- reduced-precision variants, and their error against FP64 after error_steps --------

@@ -2,7 +2,7 @@
 // the time per step.  It makes no use of PyTorch, so hardware-counter profilers see only the
 // library's kernels (plus one plain copy kernel of known size, the reference for byte counters).
 //
-// usage: cgks_runner STATE_FILE STEPS [COPY_MIB]
+// usage: cgks_runner STATE_FILE STEPS [COPY_MIB [RECON_PREC FLUX_PREC]]
 //
 // State file (little endian): 8-byte magic "CGKSST01"; int32 nx, ny, nz, size of cgks_params;
 // the cgks_params struct; nodes (nx+1)(ny+1)(nz+1)*3 doubles; Q[5][N], G[5][3][N], L[5][12][N]
@@ -38,7 +38,7 @@ bool read_exact(FILE *f, void *p, size_t bytes) { return std::fread(p, 1, bytes,
 
 int main(int argc, char **argv) {
     if (argc < 3) {
-        std::fprintf(stderr, "usage: %s STATE_FILE STEPS [COPY_MIB]\n", argv[0]);
+        std::fprintf(stderr, "usage: %s STATE_FILE STEPS [COPY_MIB [RECON_PREC FLUX_PREC]]\n", argv[0]);
         return 2;
     }
     const int steps = std::atoi(argv[2]);
@@ -55,6 +55,10 @@ int main(int argc, char **argv) {
         hdr[3] != (int)sizeof(cgks_params) || !read_exact(f, &p, sizeof p)) {
         std::fprintf(stderr, "bad state file header\n");
         return 2;
+    }
+    if (argc > 5) {  // precision variant of the same workload
+        p.recon_prec = std::atoi(argv[4]);
+        p.flux_prec = std::atoi(argv[5]);
     }
     const int dims[3] = {hdr[0], hdr[1], hdr[2]};
     if (dims[0] < 1 || dims[1] < 1 || dims[2] < 1 || steps < 0) {
