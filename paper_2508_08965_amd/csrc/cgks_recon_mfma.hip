@@ -299,7 +299,7 @@ __global__ void __launch_bounds__(512) k_recon_mfma(WorkList W, long Ntot, const
                 if (WM == 0 || __any(geno)) {
                     // path function chi: IS^L and IS^tau from the Cholesky-factor contractions
                     double isl = 0.0, ist = 0.0;
-    #pragma unroll 1
+    #pragma unroll
                     for (int u = 0; u < 5; ++u) {  // tiles 0..2: L_L^T rows, tiles 3..4: L_T^T rows
                         const int base = (u < 3) ? kMfmaOffAL + u * 10 : kMfmaOffAT + (u - 3) * 10;
                         // the Cholesky factors are triangular: rows 16w.. of tile w = u (mod 3) vanish on
@@ -381,7 +381,7 @@ __global__ void __launch_bounds__(512) k_recon_mfma(WorkList W, long Ntot, const
             const double om = 1.0 - chi;
 
             // ---- Gauss-point values: face m = tile u, Gauss point k = g ----------------------------
-    #pragma unroll 1
+    #pragma unroll 2
             for (int u = 0; u < 6; ++u) {
                 V y = {0, 0, 0, 0};
     #pragma unroll
@@ -633,7 +633,7 @@ __global__ void __launch_bounds__(512) k_recon_bf16(WorkList W, long Ntot, const
     #pragma unroll
                 for (int s = 0; s < 3; ++s) JiT[r][s] = M.JiT[(3 * r + s) * Ntot + c];
             const double om = 1.0 - chi;
-    #pragma unroll 1
+    #pragma unroll 2
             for (int u = 0; u < 6; ++u) {
                 v4f y = {0, 0, 0, 0};
     #pragma unroll
