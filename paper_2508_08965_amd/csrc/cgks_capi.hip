@@ -250,9 +250,9 @@ static hipError_t run_recon(cgks_ctx *ctx, int b, const double *Q, const double 
                              ctx->Kmf, ctx->P, ctx->gp, ctx->wl[1].cfg.ngroups, io, false, s);
 }
 
-static hipError_t run_flux(cgks_ctx *ctx, int b, const double *dt_dev, hipStream_t s) {
+static hipError_t run_flux(cgks_ctx *ctx, int b, const double *dt_dev, hipStream_t s, bool full = true) {
     return launch_flux(ctx->user.flux_prec, gp32(ctx), work_list(ctx, 2, b), ctx->Ntot, ctx->gp, ctx->M, dt_dev,
-                       ctx->P, ctx->fo, ctx->flag, s);
+                       ctx->P, ctx->fo, ctx->flag, full, s);
 }
 
 static hipError_t run_update(cgks_ctx *ctx, int stage, int b, const double *dt_dev, double *Q, double *G, double *L,
@@ -468,7 +468,7 @@ int cgks_stage(cgks_ctx *ctx, int stage, const double *dt_dev, double *Q, double
         }
         {
             Timed t(ctx, s, 2);
-            HIP_TRY(run_flux(ctx, b, dt_dev, s), "flux");
+            HIP_TRY(run_flux(ctx, b, dt_dev, s, stage == 1), "flux");
         }
         {
             Timed t(ctx, s, 3);

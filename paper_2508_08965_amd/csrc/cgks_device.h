@@ -467,8 +467,10 @@ hipError_t launch_gp_export(bool gp32, const BlockView &b, long Ntot, const void
 // the 256 VGPRs of two waves per SIMD); the update takes ngroups <= 0 for one workgroup per
 // unit, otherwise a persistent grid of ngroups workgroups.
 constexpr int kFluxTile = 128, kUpdateTile = 256;
+// full = false (second stage) skips the flux and one-sided states, which the second update
+// does not read.
 hipError_t launch_flux(int flux_prec, bool gp32, const WorkList &W, long Ntot, const void *gp, const Metrics &M,
-                       const double *dt, const DevParams &P, void *fo, int *flag, hipStream_t s);
+                       const double *dt, const DevParams &P, void *fo, int *flag, bool full, hipStream_t s);
 hipError_t launch_flux_points(int flux_prec, long n, const double *ql, const double *gl, const double *qr,
                               const double *gr, const double *nrm, const double *dt, const DevParams &P, double *F,
                               double *Ft, double *S, int *flag, hipStream_t s);

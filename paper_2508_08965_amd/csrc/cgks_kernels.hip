@@ -406,7 +406,7 @@ __global__ void __launch_bounds__(256) k_gp_export(BlockView b, long Ntot, const
 template <class TC, class TG, class TF>
 __global__ void __launch_bounds__(256, 2) k_flux(WorkList W, long Ntot, const TG *__restrict__ gp, Metrics M,
                                               const double *__restrict__ dtp, DevParams P,
-                                              TF *__restrict__ fo, int *__restrict__ flag) {
+                                              TF *__restrict__ fo, int *__restrict__ flag, int full) {
     const long u = unit_once((long)W.ntiles * 12, W.xcd);
     if (u < 0) return;
     const Tile tile = W.tiles[u / 12];
@@ -430,10 +430,11 @@ __global__ void __launch_bounds__(256, 2) k_flux(WorkList W, long Ntot, const TG
     TF *dst = fo + (long)((q * 4 + kk) * 30) * Ntot + f;
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
-        dst[(10 + 10 * sd + v) * Ntot] = (TF)Qs[v];
+        // the second stage's update reads only the time derivatives F_t and dQ/dt
+        if (full) dst[(10 + 10 * sd + v) * Ntot] = (TF)Qs[v];
         dst[(15 + 10 * sd + v) * Ntot] = (TF)dQs[v];
         if (sd) {
-            dst[v * Ntot] = (TF)F[v];
+            if (full) dst[v * Ntot] = (TF)F[v];
             dst[(5 + v) * Ntot] = (TF)Ft[v];
         }
     }
@@ -603,19 +604,19 @@ static dim3 work_grid(long units, int ngroups) {
 }
 
 hipError_t launch_flux(int flux_prec, bool gp32, const WorkList &W, long Ntot, const void *gp, const Metrics &M,
-                       const double *dt, const DevParams &P, void *fo, int *flag, hipStream_t s) {
+                       const double *dt, const DevParams &P, void *fo, int *flag, bool full, hipStream_t s) {
     if (W.ntiles <= 0) return hipSuccess;
     const long units = (long)W.ntiles * 12;
     const dim3 grid((unsigned)(W.xcd ? 8 * ((units + 7) / 8) : units));
     if (flux_prec == 0 && !gp32)
         hipLaunchKernelGGL((k_flux<double, double, double>), grid, dim3(2 * kFluxTile), 0, s, W, Ntot,
-                           (const double *)gp, M, dt, P, (double *)fo, flag);
+                           (const double *)gp, M, dt, P, (double *)fo, flag, (int)full);
     else if (flux_prec == 0)
         hipLaunchKernelGGL((k_flux<double, float, double>), grid, dim3(2 * kFluxTile), 0, s, W, Ntot,
-                           (const float *)gp, M, dt, P, (double *)fo, flag);
+                           (const float *)gp, M, dt, P, (double *)fo, flag, (int)full);
     else
         hipLaunchKernelGGL((k_flux<float, float, float>), grid, dim3(2 * kFluxTile), 0, s, W, Ntot,
-                           (const float *)gp, M, dt, P, (float *)fo, flag);
+                           (const float *)gp, M, dt, P, (float *)fo, flag, (int)full);
     return hipGetLastError();
 }
 
