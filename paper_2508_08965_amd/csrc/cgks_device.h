@@ -195,9 +195,10 @@ __host__ __device__ inline T dev_viscosity(const DevParams &P, T Tm) {
     return T(P.mu0) * r * X::sqrt(r) * (T(P.T_ref) + T(P.S_suth)) / (Tm + T(P.S_suth));
 }
 
-// Time integrals over [0,T] of the six coefficients of the interface distribution.
+// Time integrals over [0,T] of the six coefficients of the interface distribution, given
+// e = exp(-T / tau) (unused when tau_zero).
 template <class X, class T>
-__host__ __device__ inline void time_integrals(T Tw, T tau, bool tau_zero, T C[6]) {
+__host__ __device__ inline void time_integrals(T Tw, T tau, T e, bool tau_zero, T C[6]) {
     if (tau_zero) {
         C[0] = Tw;
         C[1] = T(0.0);
@@ -205,7 +206,7 @@ __host__ __device__ inline void time_integrals(T Tw, T tau, bool tau_zero, T C[6
         C[3] = C[4] = C[5] = T(0.0);
         return;
     }
-    const T e = X::exp(-Tw / tau), ome = T(1.0) - e;
+    const T ome = T(1.0) - e;
     C[0] = Tw - tau * ome;
     C[1] = T(2.0) * tau * tau * ome - tau * Tw * (T(1.0) + e);
     C[2] = T(0.5) * Tw * Tw - tau * Tw + tau * tau * ome;
@@ -369,9 +370,12 @@ __host__ __device__ inline int gks_flux_pair(const DevParams &P, const int sd, c
         tau = P.viscous ? dev_viscosity<X, T>(P, p0 * ir0) / p0 + T(P.tau_C) * jump * dt
                         : (T(P.tau_eps) + T(P.tau_C) * jump) * dt;
     }
+    // exp(-dt / tau) = exp(-dt / (2 tau))^2: one exponential serves both windows and the
+    // one-sided values below
+    const T eh = P.tau_zero ? T(0.0) : X::exp(T(-0.5) * dt / tau), ef = eh * eh;
     T C1[6], C2[6];
-    time_integrals<X, T>(dt, tau, P.tau_zero != 0, C1);
-    time_integrals<X, T>(T(0.5) * dt, tau, P.tau_zero != 0, C2);
+    time_integrals<X, T>(dt, tau, ef, P.tau_zero != 0, C1);
+    time_integrals<X, T>(T(0.5) * dt, tau, eh, P.tau_zero != 0, C2);
     const T idt = T(1.0) / dt;
     T cn[6], ct[6];
 #pragma unroll
@@ -409,7 +413,7 @@ __host__ __device__ inline int gks_flux_pair(const DevParams &P, const int sd, c
         }
     }
     // one-sided interface values (tau0 = tau)
-    const T e0 = P.tau_zero ? T(0.0) : X::exp(-dt / tau), oe = T(1.0) - e0;
+    const T e0 = ef, oe = T(1.0) - e0;
     T Sq[5], St[5];
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
