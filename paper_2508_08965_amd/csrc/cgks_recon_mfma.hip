@@ -433,6 +433,12 @@ __device__ inline void put_bf16(v8bf *h, v8bf *l, int sl, double x) {
     h[sl / 8][sl % 8] = hi;
     l[sl / 8][sl % 8] = (__bf16)(float)(x - (double)(float)hi);
 }
+// Store x as the BF16 pair (hi, lo) in slot sl, from an FP32 value.
+__device__ inline void put_bf16f(v8bf *h, v8bf *l, int sl, float x) {
+    const __bf16 hi = (__bf16)x;
+    h[sl / 8][sl % 8] = hi;
+    l[sl / 8][sl % 8] = (__bf16)(x - (float)hi);
+}
 __device__ inline v4f mma3(const v8bf *Kb, int blk, const v8bf &xh, const v8bf &xl, v4f acc) {
     const v8bf kh = Kb[blk * 64], kl = Kb[(kBfBlocks + blk) * 64];
     acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(kh, xh, acc, 0, 0, 0);
@@ -502,11 +508,13 @@ __global__ void __launch_bounds__(512) k_recon_bf16(WorkList W, long Ntot, const
             const double *Qv = Q + v * Ntot;
             const double *Gv = G + 3 * v * Ntot;
             const double *Lv = L + 12 * v * Ntot;
-            double J0[3][3];
+            // The split products carry 2^-17 of their operands, so the vector work here runs in
+            // FP32 (2^-24); only the differences to the cell average are formed in FP64.
+            float J0[3][3];
     #pragma unroll
             for (int r = 0; r < 3; ++r)
     #pragma unroll
-                for (int s = 0; s < 3; ++s) J0[r][s] = M.J0[(3 * r + s) * Ntot + c];
+                for (int s = 0; s < 3; ++s) J0[r][s] = (float)M.J0[(3 * r + s) * Ntot + c];
             const double q0 = Qv[c];
 
             // ---- the 18 stencil slots of this lane, split into BF16 hi/lo, slot 8s + j ----------
@@ -518,18 +526,18 @@ __global__ void __launch_bounds__(512) k_recon_bf16(WorkList W, long Ntot, const
                     bh[s][j] = (__bf16)0.0f;
                     bl[s][j] = (__bf16)0.0f;
                 }
-            double fdiff[6];
+            float fdiff[6];
     #pragma unroll
             for (int m = 0; m < 6; ++m) {
                 int o[3] = {0, 0, 0};
                 o[m >> 1] = (m & 1) ? 1 : -1;
                 const long nb = wrap_cell(b, ci + o[0], cj + o[1], ck + o[2]);
-                const double g0 = Gv[nb], g1 = Gv[Ntot + nb], g2 = Gv[2 * Ntot + nb];
-                fdiff[m] = Qv[nb] - q0;
-                const double r0 = J0[0][0] * g0 + J0[1][0] * g1 + J0[2][0] * g2;
-                const double r1 = J0[0][1] * g0 + J0[1][1] * g1 + J0[2][1] * g2;
-                const double r2 = J0[0][2] * g0 + J0[1][2] * g1 + J0[2][2] * g2;
-                put_bf16(bh, bl, m, (g == 0) ? fdiff[m] : (g == 1) ? r0 : (g == 2) ? r1 : r2);
+                const float g0 = (float)Gv[nb], g1 = (float)Gv[Ntot + nb], g2 = (float)Gv[2 * Ntot + nb];
+                fdiff[m] = (float)(Qv[nb] - q0);
+                const float r0 = J0[0][0] * g0 + J0[1][0] * g1 + J0[2][0] * g2;
+                const float r1 = J0[0][1] * g0 + J0[1][1] * g1 + J0[2][1] * g2;
+                const float r2 = J0[0][2] * g0 + J0[1][2] * g1 + J0[2][2] * g2;
+                put_bf16f(bh, bl, m, (g == 0) ? fdiff[m] : (g == 1) ? r0 : (g == 2) ? r1 : r2);
             }
     #pragma unroll
             for (int p = 0; p < 3; ++p) {
@@ -539,21 +547,20 @@ __global__ void __launch_bounds__(512) k_recon_bf16(WorkList W, long Ntot, const
                 o[pb] = sb;
                 const long nb = wrap_cell(b, ci + o[0], cj + o[1], ck + o[2]);
                 const int s0 = 6 + p, s1 = 9 + 2 * p, s2 = 10 + 2 * p;
-                put_bf16(bh, bl, s0, Qv[nb] - q0);
-                const double g0 = Gv[nb], g1 = Gv[Ntot + nb], g2 = Gv[2 * Ntot + nb];
-                double rg[3];
+                put_bf16f(bh, bl, s0, (float)(Qv[nb] - q0));
+                const float g0 = (float)Gv[nb], g1 = (float)Gv[Ntot + nb], g2 = (float)Gv[2 * Ntot + nb];
+                float rg[3];
     #pragma unroll
                 for (int s = 0; s < 3; ++s) rg[s] = J0[0][s] * g0 + J0[1][s] * g1 + J0[2][s] * g2;
-                put_bf16(bh, bl, s1, rg[pc]);
-                put_bf16(bh, bl, s2, (sa * rg[pa] + sb * rg[pb]) * 0.70710678118654752440);
+                put_bf16f(bh, bl, s1, rg[pc]);
+                put_bf16f(bh, bl, s2, ((float)sa * rg[pa] + (float)sb * rg[pb]) * 0.70710678118654752440f);
             }
-            double lsum[3];
+            float lsum[3];
     #pragma unroll
             for (int s = 0; s < 3; ++s) {
-                const double ln = Lv[(4 * s + g) * Ntot + c];
-                const int sl = 15 + s;
-                put_bf16(bh, bl, sl, ln);
-                double x = ln + __shfl_xor(ln, 16, 64);
+                const float ln = (float)Lv[(4 * s + g) * Ntot + c];
+                put_bf16f(bh, bl, 15 + s, ln);
+                const float x = ln + __shfl_xor(ln, 16, 64);
                 lsum[s] = x + __shfl_xor(x, 32, 64);
             }
             // ---- GEMM1: a = R b ---------------------------------------------------------------------
@@ -575,16 +582,16 @@ __global__ void __launch_bounds__(512) k_recon_bf16(WorkList W, long Ntot, const
                     cl2[s][j] = (__bf16)(x - (float)h);
                 }
 
-            double chi = 1.0, bbar[3] = {0.0, 0.0, 0.0};
+            float chi = 1.0f, bbar[3] = {0.0f, 0.0f, 0.0f};
             if (!P.linear) {
-                double isl = 0.0, ist = 0.0;
+                float isl = 0.0f, ist = 0.0f;
     #pragma unroll
                 for (int u = 0; u < 5; ++u) {
                     const int base = (u < 3) ? kBfOffAL + u * 2 : kBfOffAT + (u - 3) * 2;
                     v4f z = {0, 0, 0, 0};
     #pragma unroll
                     for (int s = 0; s < 2; ++s) z = mma3(Kb, base + s, ch[s], cl2[s], z);
-                    const double zz = (double)z[0] * z[0] + (double)z[1] * z[1] + (double)z[2] * z[2] + (double)z[3] * z[3];
+                    const float zz = z[0] * z[0] + z[1] * z[1] + z[2] * z[2] + z[3] * z[3];
                     if (u < 3) isl += zz;
                     else ist += zz;
                 }
@@ -592,60 +599,71 @@ __global__ void __launch_bounds__(512) k_recon_bf16(WorkList W, long Ntot, const
                 isl += __shfl_xor(isl, 32, 64);
                 ist += __shfl_xor(ist, 16, 64);
                 ist += __shfl_xor(ist, 32, 64);
-                const double ish = isl + ist;
-                const double rh = ist / (ish + P.geno_eps), rl = ist / (isl + P.geno_eps);
-                double ah, al;
+                const float eps = (float)P.geno_eps;
+                const float ish = isl + ist;
+                const float rh = ist / (ish + eps), rl = ist / (isl + eps);
+                float ah, al;
                 if (P.geno_r == 2.0) {
-                    ah = 1.0 + rh * rh;
-                    al = 1.0 + rl * rl;
+                    ah = 1.0f + rh * rh;
+                    al = 1.0f + rl * rl;
                 } else {
-                    ah = 1.0 + pow(rh, P.geno_r);
-                    al = 1.0 + pow(rl, P.geno_r);
+                    ah = 1.0f + powf(rh, (float)P.geno_r);
+                    al = 1.0f + powf(rl, (float)P.geno_r);
                 }
-                chi = tanh(P.geno_C * (2.0 * ah / (ah + al))) * P.inv_tanhC;
-                const double lm[3] = {0.25 * lsum[0], 0.25 * lsum[1], 0.25 * lsum[2]};
-                double wsum = 0.0, wv[6];
+                chi = tanhf((float)P.geno_C * (2.0f * ah / (ah + al))) * (float)P.inv_tanhC;
+                // linear weights (1/6)/IS_m^5, normalised by the largest 1/IS_m so that the fifth
+                // powers stay inside the FP32 range
+                const float lm[3] = {0.25f * lsum[0], 0.25f * lsum[1], 0.25f * lsum[2]};
+                float ti[6], tmax = 0.0f;
     #pragma unroll
                 for (int m = 0; m < 6; ++m) {
                     const int q = m >> 1;
-                    const double bn = (m & 1) ? fdiff[m] : -fdiff[m];
-                    double is = P.geno_eps + bn * bn;
+                    const float bn = fdiff[m];
+                    float is = eps + bn * bn;
     #pragma unroll
                     for (int t = 0; t < 3; ++t)
                         if (t != q) is += lm[t] * lm[t];
-                    const double is2 = is * is;
-                    wv[m] = (1.0 / 6.0) / (is2 * is2 * is);
-                    wsum += wv[m];
+                    ti[m] = 1.0f / is;
+                    tmax = fmaxf(tmax, ti[m]);
                 }
-                const double iw = 1.0 / wsum;
+                float wsum = 0.0f;
+    #pragma unroll
+                for (int m = 0; m < 6; ++m) {
+                    const float r = ti[m] / tmax, r2 = r * r;
+                    ti[m] = r2 * r2 * r;
+                    wsum += ti[m];
+                }
+                const float iw = 1.0f / wsum;
     #pragma unroll
                 for (int m = 0; m < 6; ++m) {
                     const int q = m >> 1;
-                    const double w = wv[m] * iw;
-                    const double bn = (m & 1) ? fdiff[m] : -fdiff[m];
+                    const float w = ti[m] * iw;
+                    const float bn = (m & 1) ? fdiff[m] : -fdiff[m];
     #pragma unroll
                     for (int t = 0; t < 3; ++t) bbar[t] += w * ((t == q) ? bn : lm[t]);
                 }
             }
-            double JiT[3][3];
+            float JiT[3][3];
     #pragma unroll
             for (int r = 0; r < 3; ++r)
     #pragma unroll
-                for (int s = 0; s < 3; ++s) JiT[r][s] = M.JiT[(3 * r + s) * Ntot + c];
-            const double om = 1.0 - chi;
+                for (int s = 0; s < 3; ++s) JiT[r][s] = (float)M.JiT[(3 * r + s) * Ntot + c];
+            const float om = 1.0f - chi;
+            const float taf = (float)ta, tbf = (float)tb;
     #pragma unroll 2
             for (int u = 0; u < 6; ++u) {
                 v4f y = {0, 0, 0, 0};
     #pragma unroll
                 for (int s = 0; s < 2; ++s) y = mma3(Kb, kBfOffA2 + u * 2 + s, ch[s], cl2[s], y);
                 const int q = u >> 1;
-                const double xq = (u & 1) ? 0.5 : -0.5;
-                const double x0 = (q == 0) ? xq : ta;
-                const double x1 = (q == 1) ? xq : ((q == 0) ? ta : tb);
-                const double x2 = (q == 2) ? xq : tb;
-                const double val = q0 + chi * (double)y[0] + om * (bbar[0] * x0 + bbar[1] * x1 + bbar[2] * x2);
-                const double r0 = chi * (double)y[1] + om * bbar[0], r1 = chi * (double)y[2] + om * bbar[1],
-                             r2 = chi * (double)y[3] + om * bbar[2];
+                const float xq = (u & 1) ? 0.5f : -0.5f;
+                const float x0 = (q == 0) ? xq : taf;
+                const float x1 = (q == 1) ? xq : ((q == 0) ? taf : tbf);
+                const float x2 = (q == 2) ? xq : tbf;
+                // the deviation from the cell average in FP32, added to the FP64 average
+                const float dv = chi * y[0] + om * (bbar[0] * x0 + bbar[1] * x1 + bbar[2] * x2);
+                const float r0 = chi * y[1] + om * bbar[0], r1 = chi * y[2] + om * bbar[1],
+                            r2 = chi * y[3] + om * bbar[2];
                 long f;
                 int side;
                 if (u & 1) {
@@ -657,7 +675,7 @@ __global__ void __launch_bounds__(512) k_recon_bf16(WorkList W, long Ntot, const
                 }
                 if (valid) {
                     TG *dst = gp + ((long)(((q * 2 + side) * 4 + g) * 20 + v * 4)) * Ntot + f;
-                    dst[0] = (TG)val;
+                    dst[0] = (TG)(q0 + (double)dv);
                     dst[Ntot] = (TG)(JiT[0][0] * r0 + JiT[0][1] * r1 + JiT[0][2] * r2);
                     dst[2 * Ntot] = (TG)(JiT[1][0] * r0 + JiT[1][1] * r1 + JiT[1][2] * r2);
                     dst[3 * Ntot] = (TG)(JiT[2][0] * r0 + JiT[2][1] * r1 + JiT[2][2] * r2);

@@ -219,3 +219,31 @@ def test_training_on_scheme_pairs_and_learned_run():
     assert examined == 10 * Qd.shape[1] and 0 <= flagged <= examined
     ctx.close()
     plain.close()
+
+
+def test_learned_weights_with_fp32_flux_and_graph_replay():
+    """The learned-weight reconstruction also feeds the FP32 flux (FP32 Gauss-point buffer), and
+    a captured step (jump flags + fused inference) replays identically to eager steps."""
+    n = (12, 10, 8)
+    nodes, Q, G, L = _hit_state(n)
+    outs = []
+    for flux_prec in (0, 1):
+        ctx = K().Context([n], [nodes], K().default_params(weights=1, flux_prec=flux_prec, **HIT_KW))
+        K().cgks_mlp_init(ctx, 5)
+        Qd, Gd, Ld = Q.to(dev()), G.to(dev()), L.to(dev())
+        dt = torch.zeros(1, dtype=torch.float64, device=dev())
+        for _ in range(3):
+            K().cgks_step(ctx, Qd, Gd, Ld, dt, use_cfl=True)
+        torch.cuda.synchronize()
+        assert K().cgks_check(ctx) == (0, 0)
+        outs.append(Qd.cpu())
+        if flux_prec == 0:
+            Qg, Gg, Lg = Q.to(dev()), G.to(dev()), L.to(dev())
+            dtg = torch.zeros(1, dtype=torch.float64, device=dev())
+            for _ in range(3):
+                K().cgks_step_graph(ctx, Qg, Gg, Lg, dtg, use_cfl=True)
+                torch.cuda.synchronize()
+            assert torch.equal(Qg.cpu(), outs[0]) and torch.equal(Gg, Gd) and torch.equal(Lg, Ld)
+        ctx.close()
+    rel = float(torch.linalg.vector_norm(outs[1] - outs[0]) / torch.linalg.vector_norm(outs[0]))
+    assert rel <= 1e-5, rel
