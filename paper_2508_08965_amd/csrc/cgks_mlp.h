@@ -67,21 +67,21 @@ __device__ inline void mlp_eval(const v8bf_t *Wl, const float *b1, const float *
     for (int v = 0; v < 3; ++v) z[4 + v] = __shfl(zz[v], col + 16, 64) + b2[4 + v];
 }
 
-// chi (sigmoid) and omega_1..6 (softmax) from the outputs
+// chi (sigmoid) and omega_1..6 (softmax) from the outputs, in FP32 like the outputs themselves
 __device__ inline void mlp_weights(const float z[7], double &chi, double om[6]) {
-    chi = 1.0 / (1.0 + exp(-(double)z[0]));
-    double zmax = z[1];
+    chi = (double)(1.0f / (1.0f + __expf(-z[0])));
+    float zmax = z[1];
 #pragma unroll
-    for (int m = 2; m < 7; ++m) zmax = (double)z[m] > zmax ? (double)z[m] : zmax;
-    double den = 0.0;
+    for (int m = 2; m < 7; ++m) zmax = fmaxf(zmax, z[m]);
+    float e[6], den = 0.0f;
 #pragma unroll
     for (int m = 0; m < 6; ++m) {
-        om[m] = exp((double)z[1 + m] - zmax);
-        den += om[m];
+        e[m] = __expf(z[1 + m] - zmax);
+        den += e[m];
     }
-    const double id = 1.0 / den;
+    const float id = 1.0f / den;
 #pragma unroll
-    for (int m = 0; m < 6; ++m) om[m] *= id;
+    for (int m = 0; m < 6; ++m) om[m] = (double)(e[m] * id);
 }
 #endif
 
