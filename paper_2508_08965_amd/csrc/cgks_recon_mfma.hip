@@ -50,6 +50,7 @@ struct PrecF64 {
     // coefficients 32 and 33 (the only real rows of the third GEMM1 tile) are accumulated on the
     // vector ALU instead of with 18 mostly-padding matrix instructions
     static constexpr bool kTailOnValu = true;
+    using Blend = double;  // type of the blend and Gauss-point output arithmetic
     __device__ static V mma(T a, T b, V c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
 };
 struct PrecF32x3 {
@@ -57,6 +58,7 @@ struct PrecF32x3 {
     using V = v4f;
     static constexpr int kCoefSteps = 10;
     static constexpr bool kTailOnValu = false;
+    using Blend = float;
     static constexpr int kSplit = 2;
     __device__ static V mma(T a, T b, V c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
 };
@@ -259,16 +261,19 @@ __global__ void __launch_bounds__(512) k_recon_mfma(WorkList W, long Ntot, const
             }
 
             // ---- blend weights ------------------------------------------------------------------------
-            double chi = 1.0, bbar[3] = {0.0, 0.0, 0.0};
+            // FP64 reconstruction: all in FP64.  FP32x3: the blend and the Gauss-point outputs run in
+            // FP32 (the stored values are FP32 and the split products carry 2^-24 of the data).
+            using RW = typename PR::Blend;
+            RW chi = 1, bbar[3] = {0, 0, 0};
             if (!P.linear) {
                 // linear sub-polynomials of the six face sub-stencils (eq. compact-sub-2)
-                const double lm[3] = {0.25 * lsum[0], 0.25 * lsum[1], 0.25 * lsum[2]};
-                double fdiff[6];
+                const RW lm[3] = {RW(0.25 * lsum[0]), RW(0.25 * lsum[1]), RW(0.25 * lsum[2])};
+                RW fdiff[6];
     #pragma unroll
                 for (int m = 0; m < 6; ++m) {
                     int o[3] = {0, 0, 0};
                     o[m >> 1] = (m & 1) ? 1 : -1;
-                    fdiff[m] = Qv[wrap_cell(b, ci + o[0], cj + o[1], ck + o[2])] - q0;
+                    fdiff[m] = RW(Qv[wrap_cell(b, ci + o[0], cj + o[1], ck + o[2])] - q0);
                 }
                 // learned-weight inputs: differences and line derivatives over their largest magnitude
                 double fscale = 1.0;
@@ -295,10 +300,10 @@ __global__ void __launch_bounds__(512) k_recon_mfma(WorkList W, long Ntot, const
                     mlp_eval(mlp_w + lane, mlp_b, mlp_b + kMlpHidden, xin, g, col, z);
                     mlp_weights(z, chi_l, om_l);
                 }
-                double chi_g = 1.0, om_g[6] = {0, 0, 0, 0, 0, 0};
+                RW chi_g = 1, om_g[6] = {0, 0, 0, 0, 0, 0};
                 if (WM == 0 || __any(geno)) {
                     // path function chi: IS^L and IS^tau from the Cholesky-factor contractions
-                    double isl = 0.0, ist = 0.0;
+                    RW isl = 0, ist = 0;
     #pragma unroll
                     for (int u = 0; u < 5; ++u) {  // tiles 0..2: L_L^T rows, tiles 3..4: L_T^T rows
                         const int base = (u < 3) ? kMfmaOffAL + u * 10 : kMfmaOffAT + (u - 3) * 10;
@@ -309,7 +314,7 @@ __global__ void __launch_bounds__(512) k_recon_mfma(WorkList W, long Ntot, const
     #pragma unroll
                         for (int s = 0; s < PR::kCoefSteps; ++s)
                             if (s >= s0) z = mac_coef<PR>(lds + lane, base + s, acc[s >> 2][s & 3], z);
-                        const double zz = (double)z[0] * z[0] + (double)z[1] * z[1] + (double)z[2] * z[2] + (double)z[3] * z[3];
+                        const RW zz = (RW)z[0] * z[0] + (RW)z[1] * z[1] + (RW)z[2] * z[2] + (RW)z[3] * z[3];
                         if (u < 3) isl += zz;
                         else ist += zz;
                     }
@@ -317,40 +322,66 @@ __global__ void __launch_bounds__(512) k_recon_mfma(WorkList W, long Ntot, const
                     isl += __shfl_xor(isl, 32, 64);
                     ist += __shfl_xor(ist, 16, 64);
                     ist += __shfl_xor(ist, 32, 64);
-                    const double ish = isl + ist;
-                    const double rh = ist / (ish + P.geno_eps), rl = ist / (isl + P.geno_eps);
-                    double ah, al;
+                    const RW eps = RW(P.geno_eps);
+                    const RW ish = isl + ist;
+                    const RW rh = ist / (ish + eps), rl = ist / (isl + eps);
+                    RW ah, al;
                     if (P.geno_r == 2.0) {
-                        ah = 1.0 + rh * rh;
-                        al = 1.0 + rl * rl;
+                        ah = RW(1) + rh * rh;
+                        al = RW(1) + rl * rl;
                     } else {
-                        ah = 1.0 + pow(rh, P.geno_r);
-                        al = 1.0 + pow(rl, P.geno_r);
+                        ah = RW(1) + pow(rh, RW(P.geno_r));
+                        al = RW(1) + pow(rl, RW(P.geno_r));
                     }
-                    chi_g = tanh(P.geno_C * (2.0 * ah / (ah + al))) * P.inv_tanhC;
-                    double wsum = 0.0;
+                    chi_g = tanh(RW(P.geno_C) * (RW(2) * ah / (ah + al))) * RW(P.inv_tanhC);
+                    if constexpr (sizeof(RW) == 8) {
+                        double wsum = 0.0;
+        #pragma unroll
+                        for (int m = 0; m < 6; ++m) {
+                            const int q = m >> 1;
+                            const double bn = (m & 1) ? fdiff[m] : -fdiff[m];
+                            double is = eps + bn * bn;
+        #pragma unroll
+                            for (int t = 0; t < 3; ++t)
+                                if (t != q) is += lm[t] * lm[t];
+                            const double is2 = is * is;
+                            om_g[m] = (1.0 / 6.0) / (is2 * is2 * is);
+                            wsum += om_g[m];
+                        }
+                        const double iw = 1.0 / wsum;
+        #pragma unroll
+                        for (int m = 0; m < 6; ++m) om_g[m] *= iw;
+                    } else {
+                        // (1/6)/IS_m^5 normalised by the largest 1/IS_m (FP32 range)
+                        RW tmax = 0;
     #pragma unroll
-                    for (int m = 0; m < 6; ++m) {
-                        const int q = m >> 1;
-                        const double bn = (m & 1) ? fdiff[m] : -fdiff[m];
-                        double is = P.geno_eps + bn * bn;
+                        for (int m = 0; m < 6; ++m) {
+                            const int q = m >> 1;
+                            RW is = eps + fdiff[m] * fdiff[m];
     #pragma unroll
-                        for (int t = 0; t < 3; ++t)
-                            if (t != q) is += lm[t] * lm[t];
-                        const double is2 = is * is;
-                        om_g[m] = (1.0 / 6.0) / (is2 * is2 * is);
-                        wsum += om_g[m];
+                            for (int t = 0; t < 3; ++t)
+                                if (t != q) is += lm[t] * lm[t];
+                            om_g[m] = RW(1) / is;
+                            tmax = fmax(tmax, om_g[m]);
+                        }
+                        RW wsum = 0;
+    #pragma unroll
+                        for (int m = 0; m < 6; ++m) {
+                            const RW r = om_g[m] / tmax, r2 = r * r;
+                            om_g[m] = r2 * r2 * r;
+                            wsum += om_g[m];
+                        }
+                        const RW iw = RW(1) / wsum;
+    #pragma unroll
+                        for (int m = 0; m < 6; ++m) om_g[m] *= iw;
                     }
-                    const double iw = 1.0 / wsum;
-    #pragma unroll
-                    for (int m = 0; m < 6; ++m) om_g[m] *= iw;
                 }
-                chi = geno ? chi_g : chi_l;
+                chi = geno ? chi_g : RW(chi_l);
     #pragma unroll
                 for (int m = 0; m < 6; ++m) {
                     const int q = m >> 1;
-                    const double w = geno ? om_g[m] : om_l[m];
-                    const double bn = (m & 1) ? fdiff[m] : -fdiff[m];
+                    const RW w = geno ? om_g[m] : RW(om_l[m]);
+                    const RW bn = (m & 1) ? fdiff[m] : -fdiff[m];
     #pragma unroll
                     for (int t = 0; t < 3; ++t) bbar[t] += w * ((t == q) ? bn : lm[t]);
                 }
@@ -373,12 +404,12 @@ __global__ void __launch_bounds__(512) k_recon_mfma(WorkList W, long Ntot, const
                     }
                 }
             }
-            double JiT[3][3];
+            RW JiT[3][3];
     #pragma unroll
             for (int r = 0; r < 3; ++r)
     #pragma unroll
                 for (int s = 0; s < 3; ++s) JiT[r][s] = M.JiT[(3 * r + s) * Ntot + c];
-            const double om = 1.0 - chi;
+            const RW om = RW(1) - chi;
 
             // ---- Gauss-point values: face m = tile u, Gauss point k = g ----------------------------
     #pragma unroll 2
@@ -388,13 +419,17 @@ __global__ void __launch_bounds__(512) k_recon_mfma(WorkList W, long Ntot, const
                 for (int s = 0; s < PR::kCoefSteps; ++s)
                     y = mac_coef<PR>(lds + lane, kMfmaOffA2 + u * 10 + s, acc[s >> 2][s & 3], y);
                 const int q = u >> 1;
-                const double xq = (u & 1) ? 0.5 : -0.5;
-                const double x0 = (q == 0) ? xq : ta;
-                const double x1 = (q == 1) ? xq : ((q == 0) ? ta : tb);
-                const double x2 = (q == 2) ? xq : tb;
-                const double val = q0 + chi * (double)y[0] + om * (bbar[0] * x0 + bbar[1] * x1 + bbar[2] * x2);
-                const double r0 = chi * (double)y[1] + om * bbar[0], r1 = chi * (double)y[2] + om * bbar[1],
-                             r2 = chi * (double)y[3] + om * bbar[2];
+                const RW xq = (u & 1) ? RW(0.5) : RW(-0.5);
+                const RW x0 = (q == 0) ? xq : RW(ta);
+                const RW x1 = (q == 1) ? xq : ((q == 0) ? RW(ta) : RW(tb));
+                const RW x2 = (q == 2) ? xq : RW(tb);
+                double val;
+                if constexpr (sizeof(RW) == 8)
+                    val = q0 + chi * (double)y[0] + om * (bbar[0] * x0 + bbar[1] * x1 + bbar[2] * x2);
+                else  // deviation from the cell average in FP32, added to the FP64 average
+                    val = q0 + (double)(chi * (RW)y[0] + om * (bbar[0] * x0 + bbar[1] * x1 + bbar[2] * x2));
+                const RW r0 = chi * (RW)y[1] + om * bbar[0], r1 = chi * (RW)y[2] + om * bbar[1],
+                         r2 = chi * (RW)y[3] + om * bbar[2];
                 long f;
                 int side;
                 if (u & 1) {
