@@ -175,18 +175,24 @@ __host__ __device__ inline void sym_mv_acc(const T S[15], const T x[5], T scale,
     }
 }
 
-// Solve <psi psi^T> x = b for the Maxwellian (U,V,W,lambda) in closed form.
+// Solve <psi psi^T> x = b for the Maxwellian (U,V,W,lambda) in closed form.  The factors that
+// depend on the state only are formed once per state (each state is solved for several b).
 template <class T>
-__host__ __device__ inline void slope_solve(const T b[5], T U, T V, T W, T lam, T K, T x[5]) {
-    const T B = U * U + V * V + W * W + (K + T(3.0)) * T(0.5) / lam;
-    const T r2 = b[1] - U * b[0], r3 = b[2] - V * b[0], r4 = b[3] - W * b[0];
-    const T r5 = T(2.0) * b[4] - B * b[0];
-    x[4] = T(4.0) * lam * lam / (K + T(3.0)) * (r5 - T(2.0) * (U * r2 + V * r3 + W * r4));
-    x[1] = T(2.0) * lam * r2 - U * x[4];
-    x[2] = T(2.0) * lam * r3 - V * x[4];
-    x[3] = T(2.0) * lam * r4 - W * x[4];
-    x[0] = b[0] - U * x[1] - V * x[2] - W * x[3] - T(0.5) * B * x[4];
-}
+struct SlopeSolver {
+    T U, V, W, B, twol, c5;
+    __host__ __device__ SlopeSolver(T U_, T V_, T W_, T lam, T K)
+        : U(U_), V(V_), W(W_), B(U_ * U_ + V_ * V_ + W_ * W_ + (K + T(3.0)) * T(0.5) / lam), twol(T(2.0) * lam),
+          c5(T(4.0) * lam * lam / (K + T(3.0))) {}
+    __host__ __device__ void solve(const T b[5], T x[5]) const {
+        const T r2 = b[1] - U * b[0], r3 = b[2] - V * b[0], r4 = b[3] - W * b[0];
+        const T r5 = T(2.0) * b[4] - B * b[0];
+        x[4] = c5 * (r5 - T(2.0) * (U * r2 + V * r3 + W * r4));
+        x[1] = twol * r2 - U * x[4];
+        x[2] = twol * r3 - V * x[4];
+        x[3] = twol * r4 - W * x[4];
+        x[0] = b[0] - U * x[1] - V * x[2] - W * x[3] - T(0.5) * B * x[4];
+    }
+};
 
 template <class X, class T>
 __host__ __device__ inline T dev_viscosity(const DevParams &P, T Tm) {
@@ -252,6 +258,7 @@ __host__ __device__ inline int gks_flux_pair(const DevParams &P, const int sd, c
     if (!(r > T(0.0))) err |= 1;
     if (!(p > T(0.0))) err |= 2;
     const T lm = T(0.5) * r / p;
+    const SlopeSolver<T> solk(U, V, W, lm, K);
 #pragma unroll
     for (int dir = 0; dir < 3; ++dir) {
         T dv[5], bb[5];
@@ -261,7 +268,7 @@ __host__ __device__ inline int gks_flux_pair(const DevParams &P, const int sd, c
         bb[4] = dv[4] * ir;
 #pragma unroll
         for (int d = 0; d < 3; ++d) bb[1 + d] = (fr[d][0] * dv[1] + fr[d][1] * dv[2] + fr[d][2] * dv[3]) * ir;
-        slope_solve<T>(bb, U, V, W, lm, K, a[dir]);
+        solk.solve(bb, a[dir]);
     }
     T Ak[5], dWk[5];
     {
@@ -271,7 +278,7 @@ __host__ __device__ inline int gks_flux_pair(const DevParams &P, const int sd, c
         psi_matrix<1, 0, 0>(mf, S); sym_mv_acc<X, T>(S, a[0], T(-1.0), rhs);
         psi_matrix<0, 1, 0>(mf, S); sym_mv_acc<X, T>(S, a[1], T(-1.0), rhs);
         psi_matrix<0, 0, 1>(mf, S); sym_mv_acc<X, T>(S, a[2], T(-1.0), rhs);
-        slope_solve<T>(rhs, U, V, W, lm, K, Ak);
+        solk.solve(rhs, Ak);
 #pragma unroll
         for (int v = 0; v < 5; ++v) dWk[v] = r * rhs[v];
     }
@@ -319,13 +326,14 @@ __host__ __device__ inline int gks_flux_pair(const DevParams &P, const int sd, c
     if (!(r0 > T(0.0))) err |= 1;
     if (!(p0 > T(0.0))) err |= 2;
     const T lam0 = T(0.5) * r0 / p0;
+    const SlopeSolver<T> sol0(U0, V0, Z0, lam0, K);
     T ab[3][5];
 #pragma unroll
     for (int dir = 0; dir < 3; ++dir) {
         T bb[5];
 #pragma unroll
         for (int v = 0; v < 5; ++v) bb[v] = Xs[1 + dir][v] * ir0;
-        slope_solve<T>(bb, U0, V0, Z0, lam0, K, ab[dir]);
+        sol0.solve(bb, ab[dir]);
     }
     // u-moments shifted by sd: psi-moments on the even lane, u psi-moments on the odd lane
     MomentsT<T> m0;
@@ -355,7 +363,7 @@ __host__ __device__ inline int gks_flux_pair(const DevParams &P, const int sd, c
             const T o = X::swap(e1[v]);
             rhs[v] = -(sd ? o : e1[v]);
         }
-        slope_solve<T>(rhs, U0, V0, Z0, lam0, K, Ab);
+        sol0.solve(rhs, Ab);
         psi_matrix<0, 0, 0>(m0, S);
 #pragma unroll
         for (int v = 0; v < 5; ++v) e0v[v] = S[sym_idx(v, 0)];
