@@ -441,10 +441,10 @@ __global__ void __launch_bounds__(512) k_recon_mfma(WorkList W, long Ntot, const
                 }
                 if (valid) {
                     TG *dst = gp + ((long)(((q * 2 + side) * 4 + g) * 20 + v * 4)) * Ntot + f;
-                    dst[0] = (TG)val;
-                    dst[Ntot] = (TG)(JiT[0][0] * r0 + JiT[0][1] * r1 + JiT[0][2] * r2);
-                    dst[2 * Ntot] = (TG)(JiT[1][0] * r0 + JiT[1][1] * r1 + JiT[1][2] * r2);
-                    dst[3 * Ntot] = (TG)(JiT[2][0] * r0 + JiT[2][1] * r1 + JiT[2][2] * r2);
+                    __builtin_nontemporal_store((TG)val, dst);
+                    __builtin_nontemporal_store((TG)(JiT[0][0] * r0 + JiT[0][1] * r1 + JiT[0][2] * r2), dst + Ntot);
+                    __builtin_nontemporal_store((TG)(JiT[1][0] * r0 + JiT[1][1] * r1 + JiT[1][2] * r2), dst + 2 * Ntot);
+                    __builtin_nontemporal_store((TG)(JiT[2][0] * r0 + JiT[2][1] * r1 + JiT[2][2] * r2), dst + 3 * Ntot);
                 }
             }
         }
@@ -710,10 +710,10 @@ __global__ void __launch_bounds__(512) k_recon_bf16(WorkList W, long Ntot, const
                 }
                 if (valid) {
                     TG *dst = gp + ((long)(((q * 2 + side) * 4 + g) * 20 + v * 4)) * Ntot + f;
-                    dst[0] = (TG)(q0 + (double)dv);
-                    dst[Ntot] = (TG)(JiT[0][0] * r0 + JiT[0][1] * r1 + JiT[0][2] * r2);
-                    dst[2 * Ntot] = (TG)(JiT[1][0] * r0 + JiT[1][1] * r1 + JiT[1][2] * r2);
-                    dst[3 * Ntot] = (TG)(JiT[2][0] * r0 + JiT[2][1] * r1 + JiT[2][2] * r2);
+                    __builtin_nontemporal_store((TG)(q0 + (double)dv), dst);
+                    __builtin_nontemporal_store((TG)(JiT[0][0] * r0 + JiT[0][1] * r1 + JiT[0][2] * r2), dst + Ntot);
+                    __builtin_nontemporal_store((TG)(JiT[1][0] * r0 + JiT[1][1] * r1 + JiT[1][2] * r2), dst + 2 * Ntot);
+                    __builtin_nontemporal_store((TG)(JiT[2][0] * r0 + JiT[2][1] * r1 + JiT[2][2] * r2), dst + 3 * Ntot);
                 }
             }
         }
