@@ -522,7 +522,7 @@ __device__ inline void update_cell(const BlockView &b, long cl, long Ntot, const
 #pragma unroll
                     for (int r = 0; r < 3; ++r) Gq[v][r] += wp * np_[r] * (qp - qb) - wm * nm_[r] * (qm - qb);
                     const double lb = qp - qm;
-                    stash[(20 + 12 * v + s) * Ntot + c] = lb;
+                    __builtin_nontemporal_store(lb, stash + ((20 + 12 * v + s) * Ntot + c));
                     L[(12 * v + s) * Ntot + c] = lb + 0.5 * dt * lt;
                 } else {
                     L[(12 * v + s) * Ntot + c] = stash[(20 + 12 * v + s) * Ntot + c] + dt * lt;
@@ -534,12 +534,12 @@ __device__ inline void update_cell(const BlockView &b, long cl, long Ntot, const
     for (int v = 0; v < 5; ++v) {
         if (STAGE == 1) {
             const double l1 = Lf[v] * iv, l2 = Lt[v] * iv, qn = Q[v * Ntot + c];
-            stash[v * Ntot + c] = qn + dt * l1 + (dt * dt / 6.0) * l2;
+            __builtin_nontemporal_store(qn + dt * l1 + (dt * dt / 6.0) * l2, stash + (v * Ntot + c));
             Q[v * Ntot + c] = qn + 0.5 * dt * l1 + 0.125 * dt * dt * l2;
 #pragma unroll
             for (int r = 0; r < 3; ++r) {
                 const double gb = Gq[v][r] * iv;
-                stash[(5 + 3 * v + r) * Ntot + c] = gb;
+                __builtin_nontemporal_store(gb, stash + ((5 + 3 * v + r) * Ntot + c));
                 G[(3 * v + r) * Ntot + c] = gb + 0.5 * dt * (Gt[v][r] * iv);
             }
         } else {
