@@ -98,13 +98,23 @@ def default_params(**kw) -> Params:
     return p
 
 
-def _ptr(t):
+def _ptr(t, numel=None, what="array"):
+    """Device pointer of a contiguous float64 CUDA tensor; with numel, its size is checked on the
+    host so that no kernel reads or writes past it."""
     if t is None:
         return None
     import torch
     if t.dtype != torch.float64 or not t.is_contiguous() or t.device.type != "cuda":
         raise ValueError("device arrays must be contiguous float64 CUDA tensors")
+    if numel is not None and t.numel() < numel:
+        raise ValueError(f"{what} has {t.numel()} elements, needs {numel}")
     return C.c_void_p(t.data_ptr())
+
+
+def _state(ctx, Q, G, L, dt_dev=None):
+    n = ctx.ncells
+    return (_ptr(Q, 5 * n, "Q"), _ptr(G, 15 * n, "G"), _ptr(L, 60 * n, "L"),
+            None if dt_dev is None else _ptr(dt_dev, 1, "dt"))
 
 
 def _stream(stream):
@@ -146,17 +156,17 @@ class Context:
 
 
 def cgks_dt(ctx: Context, Q, dt_dev, stream=None):
-    _check(lib().cgks_dt(ctx.h, _ptr(Q), _ptr(dt_dev), _stream(stream)), "cgks_dt")
+    _check(lib().cgks_dt(ctx.h, _ptr(Q, 5 * ctx.ncells, "Q"), _ptr(dt_dev, 1, "dt"), _stream(stream)), "cgks_dt")
 
 
 def cgks_stage(ctx: Context, stage: int, dt_dev, Q, G, L, stream=None):
-    _check(lib().cgks_stage(ctx.h, int(stage), _ptr(dt_dev), _ptr(Q), _ptr(G), _ptr(L), _stream(stream)),
-           "cgks_stage")
+    q, g, l, d = _state(ctx, Q, G, L, dt_dev)
+    _check(lib().cgks_stage(ctx.h, int(stage), d, q, g, l, _stream(stream)), "cgks_stage")
 
 
 def cgks_step(ctx: Context, Q, G, L, dt_dev, use_cfl=True, stream=None):
-    _check(lib().cgks_step(ctx.h, _ptr(Q), _ptr(G), _ptr(L), _ptr(dt_dev), int(bool(use_cfl)), _stream(stream)),
-           "cgks_step")
+    q, g, l, d = _state(ctx, Q, G, L, dt_dev)
+    _check(lib().cgks_step(ctx.h, q, g, l, d, int(bool(use_cfl)), _stream(stream)), "cgks_step")
 
 
 def cgks_check(ctx: Context):
@@ -167,17 +177,22 @@ def cgks_check(ctx: Context):
 
 
 def cgks_recon(ctx: Context, Q, G, L, gp, stream=None):
-    _check(lib().cgks_recon(ctx.h, _ptr(Q), _ptr(G), _ptr(L), _ptr(gp), _stream(stream)), "cgks_recon")
+    q, g, l, _ = _state(ctx, Q, G, L)
+    _check(lib().cgks_recon(ctx.h, q, g, l, _ptr(gp, 480 * ctx.ncells, "gp"), _stream(stream)), "cgks_recon")
 
 
 def cgks_flux(ctx: Context, ql, gl, qr, gr, nrm, dt_dev, F, Ft, sides, stream=None):
     n = ql.shape[0]
-    _check(lib().cgks_flux(ctx.h, n, _ptr(ql), _ptr(gl), _ptr(qr), _ptr(gr), _ptr(nrm), _ptr(dt_dev), _ptr(F),
-                           _ptr(Ft), _ptr(sides), _stream(stream)), "cgks_flux")
+    _check(lib().cgks_flux(ctx.h, n, _ptr(ql, 5 * n, "ql"), _ptr(gl, 15 * n, "gl"), _ptr(qr, 5 * n, "qr"),
+                           _ptr(gr, 15 * n, "gr"), _ptr(nrm, 3 * n, "nrm"), _ptr(dt_dev, 1, "dt"),
+                           _ptr(F, 5 * n, "F"), _ptr(Ft, 5 * n, "Ft"), _ptr(sides, 20 * n, "sides"),
+                           _stream(stream)), "cgks_flux")
 
 
 def cgks_metrics(ctx: Context, vol=None, J0=None, fn=None, fw=None, stream=None):
-    _check(lib().cgks_metrics(ctx.h, _ptr(vol), _ptr(J0), _ptr(fn), _ptr(fw), _stream(stream)), "cgks_metrics")
+    n = ctx.ncells
+    _check(lib().cgks_metrics(ctx.h, _ptr(vol, n, "vol"), _ptr(J0, 9 * n, "J0"), _ptr(fn, 36 * n, "fn"),
+                              _ptr(fw, 12 * n, "fw"), _stream(stream)), "cgks_metrics")
 
 
 KERNEL_KINDS = ("dt", "reconstruction", "flux", "update")
@@ -214,8 +229,8 @@ def cgks_autotune(ctx: Context, Q, G, L, dt_dev, reps=3, stream=None):
     """Run the autotuner; returns the timed candidates as a list of dicts."""
     n = 1 + 7 * 128
     rep = (C.c_double * n)()
-    _check(lib().cgks_autotune(ctx.h, _ptr(Q), _ptr(G), _ptr(L), _ptr(dt_dev), reps, rep, n, _stream(stream)),
-           "cgks_autotune")
+    q, g, l, d = _state(ctx, Q, G, L, dt_dev)
+    _check(lib().cgks_autotune(ctx.h, q, g, l, d, reps, rep, n, _stream(stream)), "cgks_autotune")
     out = []
     for i in range(int(rep[0])):
         k, t, g, x, by, bz, ms = rep[1 + 7 * i: 8 + 7 * i]
@@ -225,8 +240,8 @@ def cgks_autotune(ctx: Context, Q, G, L, dt_dev, reps=3, stream=None):
 
 
 def cgks_step_graph(ctx: Context, Q, G, L, dt_dev, use_cfl=True, stream=None):
-    _check(lib().cgks_step_graph(ctx.h, _ptr(Q), _ptr(G), _ptr(L), _ptr(dt_dev), 1 if use_cfl else 0,
-                                 _stream(stream)), "cgks_step_graph")
+    q, g, l, d = _state(ctx, Q, G, L, dt_dev)
+    _check(lib().cgks_step_graph(ctx.h, q, g, l, d, 1 if use_cfl else 0, _stream(stream)), "cgks_step_graph")
 
 
 # ---- learned blend weights -------------------------------------------------------------------
@@ -257,13 +272,22 @@ def cgks_mlp_get(ctx: Context):
     return a
 
 
+def _pairs(X, T):
+    if X.dim() != 2 or X.shape[1] != 18 or T.dim() != 2 or T.shape[1] != 7 or T.shape[0] != X.shape[0]:
+        raise ValueError("X must be [n, 18] and T [n, 7]")
+
+
 def cgks_mlp_grad(ctx: Context, X, T, grad, loss, stream=None):
+    _pairs(X, T)
+    if grad.numel() < MLP_PARAMS or loss.numel() < 1:
+        raise ValueError("grad needs 839 floats and loss 1")
     _check(lib().cgks_mlp_grad(ctx.h, _fptr(X), _fptr(T), X.shape[0], _fptr(grad), _fptr(loss), _stream(stream)),
            "cgks_mlp_grad")
 
 
 def cgks_mlp_train(ctx: Context, X, T, steps, batch, lr, history=True, stream=None):
     import numpy as np
+    _pairs(X, T)
     hist = np.zeros(max(steps, 1), dtype=np.float32) if history else None
     hp = hist.ctypes.data_as(C.POINTER(C.c_float)) if history else None
     _check(lib().cgks_mlp_train(ctx.h, _fptr(X), _fptr(T), X.shape[0], steps, batch, lr, hp, _stream(stream)),
@@ -272,13 +296,24 @@ def cgks_mlp_train(ctx: Context, X, T, steps, batch, lr, history=True, stream=No
 
 
 def cgks_mlp_infer(ctx: Context, X, Y, stream=None):
-    _check(lib().cgks_mlp_infer(ctx.h, _fptr(X), X.shape[0], _ptr(Y), _stream(stream)), "cgks_mlp_infer")
+    if X.dim() != 2 or X.shape[1] != 18:
+        raise ValueError("X must be [n, 18]")
+    _check(lib().cgks_mlp_infer(ctx.h, _fptr(X), X.shape[0], _ptr(Y, 7 * X.shape[0], "Y"), _stream(stream)),
+           "cgks_mlp_infer")
 
 
 def cgks_weights(ctx: Context, Q, G, L, X, Wt, jump=None, stream=None):
+    """Features X [5N, 18] (float32), weights used Wt [5N, 7] (float64) and jump flags [N] (uint8)."""
+    import torch
+    n = ctx.ncells
+    if tuple(X.shape) != (5 * n, 18) or tuple(Wt.shape) != (5 * n, 7):
+        raise ValueError("X must be [5N, 18] and Wt [5N, 7]")
+    if jump is not None and (jump.dtype != torch.uint8 or jump.numel() != n or not jump.is_contiguous()
+                             or jump.device.type != "cuda"):
+        raise ValueError("jump must be a contiguous uint8 CUDA tensor of N elements")
     jp = None if jump is None else C.c_void_p(jump.data_ptr())
-    _check(lib().cgks_weights(ctx.h, _ptr(Q), _ptr(G), _ptr(L), _fptr(X), _ptr(Wt), jp, _stream(stream)),
-           "cgks_weights")
+    q, g, l, _ = _state(ctx, Q, G, L)
+    _check(lib().cgks_weights(ctx.h, q, g, l, _fptr(X), _ptr(Wt), jp, _stream(stream)), "cgks_weights")
 
 
 def cgks_mlp_fallback(ctx: Context):
