@@ -102,6 +102,34 @@ def roofline(prof, N, peak_key, counters=False):
     return roof
 
 
+def kernel_table(prof, N, fp64=True):
+    """Every kernel kind of a step against its own roof: average launch time (HIP events), the
+    algorithmic work per launch and the achieved fraction (FP64 path: matrix / vector FP64 peaks
+    and 8 TB/s HBM; the update averages its two stages, the reconstruction of this table is
+    FP64 only)."""
+    hbm = 8.0  # TB/s
+    out = {}
+    for k, (ms, n) in prof.items():
+        if n == 0:
+            continue
+        avg = ms / n
+        if k == "reconstruction":
+            w = RECON_FLOP_PER_CELL * N
+            out[k] = {"avg_ms": avg, "bound": "mfma", "tflops": w / avg / 1e9, "frac": w / avg / 1e9 / PEAK["fp64"],
+                      "algorithmic_gbps": (98 + 480) * 8 * N / avg / 1e6}
+        elif k == "flux":
+            w = FLUX_FLOP_PER_GP * 12 * N
+            out[k] = {"avg_ms": avg, "bound": "alu", "tflops": w / avg / 1e9, "frac": w / avg / 1e9 / PEAK["fp64"],
+                      "algorithmic_gbps": 584 * 12 * N / avg / 1e6}
+        elif k == "update":
+            b = (4592 + 3112) / 2 * N
+            out[k] = {"avg_ms": avg, "bound": "hbm", "algorithmic_gbps": b / avg / 1e6, "frac": b / avg / 1e9 / hbm}
+        elif k == "dt":
+            b = 17 * 8 * N
+            out[k] = {"avg_ms": avg, "bound": "hbm", "algorithmic_gbps": b / avg / 1e6, "frac": b / avg / 1e9 / hbm}
+    return out if fp64 else None
+
+
 def hit_kw():
     # isotropic turbulence: rho 1, p 1/gamma (T = 1/gamma), Re_lambda 72 at u' = 0.2887, lambda 0.5
     T0 = 1.0 / GAM
@@ -458,6 +486,7 @@ def main():
                                "mesh (amp 0.05), nonlinear CGKS-5, FP64", "cells": N, "variant": "fp64"},
         "kernel_ms": {k: {"total_ms": v[0], "launches": v[1]} for k, v in prof.items()},
         "roofline": roof,
+        "kernels": kernel_table(prof, N),
         "parity_vs_oracle": parity,
         "variants": variants,
         "batching": batching,
