@@ -200,3 +200,20 @@ def test_graph_replay_matches_eager_every_replay():
         assert torch.equal(x, y)
     ctx_e.close()
     ctx_g.close()
+
+
+@pytest.mark.parametrize("recon_prec,flux_prec", [(1, 1), (2, 1), (2, 0)])
+def test_reduced_precision_batched_equals_per_block_and_bricks(recon_prec, flux_prec):
+    """The split-precision kernels also take their work from the tile list: batched, per-block
+    and brick launches agree bitwise, and stay close to the FP64 path."""
+    nodes, states = blocks_state()
+    kw = dict(recon_prec=recon_prec, flux_prec=flux_prec, **hit_kw())
+    a = run_gpu(K().default_params(**kw), nodes, states, 2)
+    b = run_gpu(K().default_params(per_block=1, **kw), nodes, states, 2)
+    c = run_gpu(K().default_params(**kw), nodes, states, 2,
+                configure=lambda ctx: K().cgks_set_launch(ctx, 1, 32, 0, 1, 3, 5))
+    ref = run_gpu(K().default_params(**hit_kw()), nodes, states, 2)
+    assert a[0] == b[0] == c[0] == (0, 0)
+    for x, y, z in zip(a[1:4], b[1:4], c[1:4]):
+        assert torch.equal(x, y) and torch.equal(x, z)
+    assert rel(a[1].numpy(), ref[1].numpy()) <= 1e-5
