@@ -261,11 +261,13 @@ def test_invalid_arguments_rejected():
     with pytest.raises(RuntimeError):
         K().Context([(0, 4, 4)], [W.cartesian_nodes((1, 4, 4))], K().default_params())
     ctx = K().Context([(4, 4, 4)], [W.cartesian_nodes((4, 4, 4))], K().default_params())
-    z = torch.zeros(5, 64, dtype=torch.float64, device=dev())
+    q = torch.zeros(5, 64, dtype=torch.float64, device=dev())
+    g = torch.zeros(5, 3, 64, dtype=torch.float64, device=dev())
+    l = torch.zeros(5, 12, 64, dtype=torch.float64, device=dev())
     with pytest.raises(RuntimeError):
-        K().cgks_stage(ctx, 2, torch.zeros(1, dtype=torch.float64, device=dev()), z, z, z)  # stage 2 first
+        K().cgks_stage(ctx, 2, torch.zeros(1, dtype=torch.float64, device=dev()), q, g, l)  # stage 2 first
     with pytest.raises(RuntimeError):
-        K().cgks_stage(ctx, 3, torch.zeros(1, dtype=torch.float64, device=dev()), z, z, z)
+        K().cgks_stage(ctx, 3, torch.zeros(1, dtype=torch.float64, device=dev()), q, g, l)
     ctx.close()
 
 
