@@ -98,7 +98,9 @@ void cgks_default_params(cgks_params *p);
  *   p            host, scheme parameters (copied)
  *   stream       hipStream_t used for the set-up work (may be NULL: the null stream)
  * Metrics are computed on the device.  Cells must have positive volume and positive
- * det J0.  On failure *out is NULL. */
+ * det J0.  The total number of cells must be below 2^27 (the kernels index one component
+ * array with 32-bit offsets; one MI355X holds about 33M cells of state and buffers).
+ * On failure *out is NULL. */
 int cgks_ctx_create(cgks_ctx **out, int nblocks, const int *dims, const double *const *nodes,
                     const cgks_params *p, void *stream);
 

@@ -338,6 +338,7 @@ int cgks_ctx_create(cgks_ctx **out, int nblocks, const int *dims, const double *
         blocks[b].N = (long)blocks[b].nx * blocks[b].ny * blocks[b].nz;
         blocks[b].off = Ntot;
         Ntot += blocks[b].N;
+        if (Ntot >= kMaxCells) return fail(CGKS_EINVAL, "total number of cells must be below 2^27");
     }
     hipStream_t s = (hipStream_t)stream;
     cgks_ctx *c = new cgks_ctx();

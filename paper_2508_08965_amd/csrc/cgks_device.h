@@ -7,6 +7,10 @@
 
 namespace cgks {
 
+// Meshes hold fewer than kMaxCells cells in total, so that a cell index and the byte offset of
+// an element of one component array (index x 8) fit in 32 bits.
+constexpr long kMaxCells = 1L << 27;
+
 struct BlockView {
     int nx, ny, nz;
     long N;    // cells of the block

@@ -65,11 +65,57 @@ struct PrecF32x3 {
 
 namespace {
 
-__device__ inline long wrap_cell(const BlockView &b, int i, int j, int k) {
-    i = (i < 0) ? i + b.nx : (i >= b.nx ? i - b.nx : i);
-    j = (j < 0) ? j + b.ny : (j >= b.ny ? j - b.ny : j);
-    k = (k < 0) ? k + b.nz : (k >= b.nz ? k - b.nz : k);
-    return b.off + (long)i + (long)b.nx * ((long)j + (long)b.ny * k);
+// A lane's cell (index in the mesh) and the index offsets of its six face neighbours on the
+// periodic block; an edge neighbour is the sum of two face offsets.  Every index is below
+// kMaxCells, so 32-bit integers and 32-bit byte offsets suffice.
+struct CellNb {
+    int c;
+    int dm[3], dp[3];  // offset of the - / + neighbour along x, y, z
+};
+__device__ inline CellNb cell_nb(const BlockView &b, int ci, int cj, int ck) {
+    const int nx = b.nx, nxy = b.nx * b.ny;
+    CellNb r;
+    r.c = (int)b.off + ci + nx * cj + nxy * ck;
+    r.dm[0] = (ci == 0) ? nx - 1 : -1;
+    r.dp[0] = (ci == nx - 1) ? 1 - nx : 1;
+    r.dm[1] = (cj == 0) ? nxy - nx : -nx;
+    r.dp[1] = (cj == b.ny - 1) ? nx - nxy : nx;
+    r.dm[2] = (ck == 0) ? (b.nz - 1) * nxy : -nxy;
+    r.dp[2] = (ck == b.nz - 1) ? (1 - b.nz) * nxy : nxy;
+    return r;
+}
+// Cell coordinates of this lane: tile of runs (ty = 0; the wave's first cell is decoded once,
+// the lanes step on along x) or brick.  Tail lanes take the last cell of the tile (valid =
+// false: they compute a copy and store nothing).
+__device__ inline void lane_cell(const Tile &tile, const BlockView &b, int cpr, int chunk, int col, int bx0, int by0,
+                                 int bz0, int &ci, int &cj, int &ck, bool &valid) {
+    if (tile.ty > 0) {
+        const int xo = 16 * (chunk % cpr) + col, row = chunk / cpr;
+        valid = xo < tile.count;
+        ci = bx0 + (valid ? xo : 0);
+        cj = by0 + row % tile.ty;
+        ck = bz0 + row / tile.ty;
+    } else {
+        const unsigned base = (unsigned)tile.start + 16u * (unsigned)chunk;
+        const unsigned nx = (unsigned)b.nx, t0 = base / nx;
+        valid = 16 * chunk + col < tile.count;
+        const int d = valid ? col : tile.count - 1 - 16 * chunk;
+        ci = (int)(base - t0 * nx) + d;
+        cj = (int)(t0 % (unsigned)b.ny);
+        ck = (int)(t0 / (unsigned)b.ny);
+        while (ci >= b.nx) {
+            ci -= b.nx;
+            if (++cj == b.ny) {
+                cj = 0;
+                ++ck;
+            }
+        }
+    }
+}
+// element i of a component array (32-bit byte offset from the array's base)
+template <class T>
+__device__ inline T ld32(const T *base, int i) {
+    return *(const T *)((const char *)base + (unsigned)i * (unsigned)sizeof(T));
 }
 
 // acc += K * x for an FP64 stencil value x (GEMM1 operand)
@@ -148,30 +194,14 @@ __global__ void __launch_bounds__(512) k_recon_mfma(WorkList W, long Ntot, const
             bz0 = (int)(t0 / b.ny);
         }
         const int nit = cpr * (tile.ty > 0 ? tile.ty * tile.tz : 1) * kNV;
-        for (int it = wave; it < nit; it += nwaves) {
+        for (int it = __builtin_amdgcn_readfirstlane(wave); it < nit; it += nwaves) {
             const int v = it % kNV;
             const int chunk = it / kNV;
             bool valid;
             int ci, cj, ck;
-            long cl;
-            if (tile.ty > 0) {
-                const int xo = 16 * (chunk % cpr) + col, row = chunk / cpr;
-                valid = xo < tile.count;
-                ci = bx0 + (valid ? xo : 0);  // tail lanes compute a copy, store nothing
-                cj = by0 + row % tile.ty;
-                ck = bz0 + row / tile.ty;
-                cl = ci + (long)b.nx * (cj + (long)b.ny * ck);
-            } else {
-                const long cl0 = tile.start + chunk * 16 + col;
-                const long cend = tile.start + tile.count;
-                valid = cl0 < cend;
-                cl = valid ? cl0 : cend - 1;
-                ci = (int)(cl % b.nx);
-                const long tt = cl / b.nx;
-                cj = (int)(tt % b.ny);
-                ck = (int)(tt / b.ny);
-            }
-            const long c = b.off + cl;
+            lane_cell(tile, b, cpr, chunk, col, bx0, by0, bz0, ci, cj, ck, valid);
+            const CellNb cn = cell_nb(b, ci, cj, ck);
+            const int c = cn.c;
             const double *Qv = Q + v * Ntot;
             const double *Gv = G + 3 * v * Ntot;
             const double *Lv = L + 12 * v * Ntot;
@@ -179,8 +209,8 @@ __global__ void __launch_bounds__(512) k_recon_mfma(WorkList W, long Ntot, const
     #pragma unroll
             for (int r = 0; r < 3; ++r)
     #pragma unroll
-                for (int s = 0; s < 3; ++s) J0[r][s] = M.J0[(3 * r + s) * Ntot + c];
-            const double q0 = Qv[c];
+                for (int s = 0; s < 3; ++s) J0[r][s] = ld32(M.J0 + (3 * r + s) * Ntot, c);
+            const double q0 = ld32(Qv, c);
 
             V acc[3] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
             double a32 = 0.0, a33 = 0.0;  // partial sums of coefficients 32, 33 (kTailOnValu)
@@ -199,35 +229,31 @@ __global__ void __launch_bounds__(512) k_recon_mfma(WorkList W, long Ntot, const
             // line derivatives of the cell (steps 15..17), loaded ahead of the neighbour gather
             double lval[3];
     #pragma unroll
-            for (int s = 0; s < 3; ++s) lval[s] = Lv[(4 * s + g) * Ntot + c];
+            for (int s = 0; s < 3; ++s) lval[s] = ld32(Lv + 4 * s * Ntot, g * (int)Ntot + c);
             // ---- steps 0..14: face neighbours m (steps m), then edge neighbours 4p+g (steps
-            // 6+p, 9+2p, 10+2p).  Gather step st+1 is loaded while step st is contracted.
-            auto nb_of = [&](int st) -> long {
-                int o[3] = {0, 0, 0};
+            // 6+p, 9+2p, 10+2p).  The average and gradient of all nine neighbours a lane needs are
+            // requested before the first contraction, so the wave waits for memory once.
+            double nq[9], ng[9][3];
+    #pragma unroll
+            for (int st = 0; st < 9; ++st) {
+                int nb;
                 if (st < 6) {
-                    o[st >> 1] = (st & 1) ? 1 : -1;
+                    nb = c + ((st & 1) ? cn.dp[st >> 1] : cn.dm[st >> 1]);
                 } else {
                     const int p = st - 6, pa = (p < 2) ? 0 : 1, pb = (p == 0) ? 1 : 2;
-                    o[pa] = sa;
-                    o[pb] = sb;
+                    nb = c + (sa > 0 ? cn.dp[pa] : cn.dm[pa]) + (sb > 0 ? cn.dp[pb] : cn.dm[pb]);
                 }
-                return wrap_cell(b, ci + o[0], cj + o[1], ck + o[2]);
-            };
-            long nb = nb_of(0);
-            double nq = Qv[nb], n0 = Gv[nb], n1 = Gv[Ntot + nb], n2 = Gv[2 * Ntot + nb];
-    #pragma unroll 1
+                nq[st] = ld32(Qv, nb);
+                ng[st][0] = ld32(Gv, nb);
+                ng[st][1] = ld32(Gv + Ntot, nb);
+                ng[st][2] = ld32(Gv + 2 * Ntot, nb);
+            }
+    #pragma unroll
             for (int st = 0; st < 9; ++st) {
-                const double d = nq - q0, g0 = n0, g1 = n1, g2 = n2;
-                if (st < 8) {
-                    nb = nb_of(st + 1);
-                    nq = Qv[nb];
-                    n0 = Gv[nb];
-                    n1 = Gv[Ntot + nb];
-                    n2 = Gv[2 * Ntot + nb];
-                }
+                const double d = nq[st] - q0;
                 double rg[3];
     #pragma unroll
-                for (int r = 0; r < 3; ++r) rg[r] = J0[0][r] * g0 + J0[1][r] * g1 + J0[2][r] * g2;
+                for (int r = 0; r < 3; ++r) rg[r] = J0[0][r] * ng[st][0] + J0[1][r] * ng[st][1] + J0[2][r] * ng[st][2];
                 if (st < 6) {
                     const double item = (g == 0) ? d : (g == 1) ? rg[0] : (g == 2) ? rg[1] : rg[2];
                     gemm1(st, item);
@@ -241,6 +267,7 @@ __global__ void __launch_bounds__(512) k_recon_mfma(WorkList W, long Ntot, const
                     gemm1(9 + 2 * p, e1);
                     gemm1(10 + 2 * p, e2);
                 }
+                __builtin_amdgcn_sched_barrier(0);  // keep each step's operand loads with its step
             }
             // ---- steps 15..17: line differences 4t+g ---------------------------------------------
             double lsum[3];
@@ -260,6 +287,14 @@ __global__ void __launch_bounds__(512) k_recon_mfma(WorkList W, long Ntot, const
                 acc[2] = V{(g == 0) ? a32 : ((g == 1) ? a33 : 0.0), 0.0, 0.0, 0.0};
             }
 
+            // back-transform of the Gauss-point gradients, requested here so that the smoothness forms
+            // and weights below cover its latency
+            typename PR::Blend JiT[3][3];
+    #pragma unroll
+            for (int r = 0; r < 3; ++r)
+    #pragma unroll
+                for (int s = 0; s < 3; ++s) JiT[r][s] = ld32(M.JiT + (3 * r + s) * Ntot, c);
+
             // ---- blend weights ------------------------------------------------------------------------
             // FP64 reconstruction: all in FP64.  FP32x3: the blend and the Gauss-point outputs run in
             // FP32 (the stored values are FP32 and the split products carry 2^-24 of the data).
@@ -268,13 +303,9 @@ __global__ void __launch_bounds__(512) k_recon_mfma(WorkList W, long Ntot, const
             if (!P.linear) {
                 // linear sub-polynomials of the six face sub-stencils (eq. compact-sub-2)
                 const RW lm[3] = {RW(0.25 * lsum[0]), RW(0.25 * lsum[1]), RW(0.25 * lsum[2])};
-                RW fdiff[6];
+                RW fdiff[6];  // face-neighbour differences: the averages gathered in steps 0..5
     #pragma unroll
-                for (int m = 0; m < 6; ++m) {
-                    int o[3] = {0, 0, 0};
-                    o[m >> 1] = (m & 1) ? 1 : -1;
-                    fdiff[m] = RW(Qv[wrap_cell(b, ci + o[0], cj + o[1], ck + o[2])] - q0);
-                }
+                for (int m = 0; m < 6; ++m) fdiff[m] = RW(nq[m] - q0);
                 // learned-weight inputs: differences and line derivatives over their largest magnitude
                 double fscale = 1.0;
                 if constexpr (WM == 1 || EXP) {
@@ -333,47 +364,57 @@ __global__ void __launch_bounds__(512) k_recon_mfma(WorkList W, long Ntot, const
                         ah = RW(1) + pow(rh, RW(P.geno_r));
                         al = RW(1) + pow(rl, RW(P.geno_r));
                     }
-                    chi_g = tanh(RW(P.geno_C) * (RW(2) * ah / (ah + al))) * RW(P.inv_tanhC);
-                    if constexpr (sizeof(RW) == 8) {
-                        double wsum = 0.0;
+                    // tanh(x) rounds to 1 once 2 exp(-2x) is below half an ulp of 1 (x > 19.1 in FP64,
+                    // x > 9.1 in FP32); the library call runs only if some lane of the wave is below
+                    const RW x = RW(P.geno_C) * (RW(2) * ah / (ah + al));
+                    const RW x_one = (sizeof(RW) == 8) ? RW(20) : RW(10);
+                    RW th = RW(1);
+                    if (__any(x <= x_one)) th = (x > x_one) ? RW(1) : tanh(x);
+                    chi_g = th * RW(P.inv_tanhC);
+                    // the linear weights enter only through (1 - chi); a wave whose cells all have
+                    // chi = 1 skips them (they are always formed when exported)
+                    if (EXP || __any(geno && chi_g != RW(1))) {
+                        if constexpr (sizeof(RW) == 8) {
+                            double wsum = 0.0;
+            #pragma unroll
+                            for (int m = 0; m < 6; ++m) {
+                                const int q = m >> 1;
+                                const double bn = (m & 1) ? fdiff[m] : -fdiff[m];
+                                double is = eps + bn * bn;
+            #pragma unroll
+                                for (int t = 0; t < 3; ++t)
+                                    if (t != q) is += lm[t] * lm[t];
+                                const double is2 = is * is;
+                                om_g[m] = (1.0 / 6.0) / (is2 * is2 * is);
+                                wsum += om_g[m];
+                            }
+                            const double iw = 1.0 / wsum;
+            #pragma unroll
+                            for (int m = 0; m < 6; ++m) om_g[m] *= iw;
+                        } else {
+                            // (1/6)/IS_m^5 normalised by the largest 1/IS_m (FP32 range)
+                            RW tmax = 0;
         #pragma unroll
-                        for (int m = 0; m < 6; ++m) {
-                            const int q = m >> 1;
-                            const double bn = (m & 1) ? fdiff[m] : -fdiff[m];
-                            double is = eps + bn * bn;
+                            for (int m = 0; m < 6; ++m) {
+                                const int q = m >> 1;
+                                RW is = eps + fdiff[m] * fdiff[m];
         #pragma unroll
-                            for (int t = 0; t < 3; ++t)
-                                if (t != q) is += lm[t] * lm[t];
-                            const double is2 = is * is;
-                            om_g[m] = (1.0 / 6.0) / (is2 * is2 * is);
-                            wsum += om_g[m];
-                        }
-                        const double iw = 1.0 / wsum;
+                                for (int t = 0; t < 3; ++t)
+                                    if (t != q) is += lm[t] * lm[t];
+                                om_g[m] = RW(1) / is;
+                                tmax = fmax(tmax, om_g[m]);
+                            }
+                            RW wsum = 0;
         #pragma unroll
-                        for (int m = 0; m < 6; ++m) om_g[m] *= iw;
-                    } else {
-                        // (1/6)/IS_m^5 normalised by the largest 1/IS_m (FP32 range)
-                        RW tmax = 0;
-    #pragma unroll
-                        for (int m = 0; m < 6; ++m) {
-                            const int q = m >> 1;
-                            RW is = eps + fdiff[m] * fdiff[m];
-    #pragma unroll
-                            for (int t = 0; t < 3; ++t)
-                                if (t != q) is += lm[t] * lm[t];
-                            om_g[m] = RW(1) / is;
-                            tmax = fmax(tmax, om_g[m]);
+                            for (int m = 0; m < 6; ++m) {
+                                const RW r = om_g[m] / tmax, r2 = r * r;
+                                om_g[m] = r2 * r2 * r;
+                                wsum += om_g[m];
+                            }
+                            const RW iw = RW(1) / wsum;
+        #pragma unroll
+                            for (int m = 0; m < 6; ++m) om_g[m] *= iw;
                         }
-                        RW wsum = 0;
-    #pragma unroll
-                        for (int m = 0; m < 6; ++m) {
-                            const RW r = om_g[m] / tmax, r2 = r * r;
-                            om_g[m] = r2 * r2 * r;
-                            wsum += om_g[m];
-                        }
-                        const RW iw = RW(1) / wsum;
-    #pragma unroll
-                        for (int m = 0; m < 6; ++m) om_g[m] *= iw;
                     }
                 }
                 chi = geno ? chi_g : RW(chi_l);
@@ -387,7 +428,7 @@ __global__ void __launch_bounds__(512) k_recon_mfma(WorkList W, long Ntot, const
                 }
                 if constexpr (EXP) {
                     if (valid) {
-                        const long sidx = c * kNV + v;
+                        const long sidx = (long)c * kNV + v;
                         if (g == 0) {
                             io.wexp[sidx * 7] = chi;
     #pragma unroll
@@ -404,11 +445,6 @@ __global__ void __launch_bounds__(512) k_recon_mfma(WorkList W, long Ntot, const
                     }
                 }
             }
-            RW JiT[3][3];
-    #pragma unroll
-            for (int r = 0; r < 3; ++r)
-    #pragma unroll
-                for (int s = 0; s < 3; ++s) JiT[r][s] = M.JiT[(3 * r + s) * Ntot + c];
             const RW om = RW(1) - chi;
 
             // ---- Gauss-point values: face m = tile u, Gauss point k = g ----------------------------
@@ -430,15 +466,9 @@ __global__ void __launch_bounds__(512) k_recon_mfma(WorkList W, long Ntot, const
                     val = q0 + (double)(chi * (RW)y[0] + om * (bbar[0] * x0 + bbar[1] * x1 + bbar[2] * x2));
                 const RW r0 = chi * (RW)y[1] + om * bbar[0], r1 = chi * (RW)y[2] + om * bbar[1],
                          r2 = chi * (RW)y[3] + om * bbar[2];
-                long f;
-                int side;
-                if (u & 1) {
-                    f = c;
-                    side = 0;
-                } else {
-                    f = wrap_cell(b, ci - (q == 0), cj - (q == 1), ck - (q == 2));
-                    side = 1;
-                }
+                // face u is the + face of this cell (side 0) or the + face of the - neighbour (side 1)
+                const int side = (u & 1) ? 0 : 1;
+                const int f = (u & 1) ? c : c + ((q == 0) ? cn.dm[0] : (q == 1) ? cn.dm[1] : cn.dm[2]);
                 if (valid) {
                     TG *dst = gp + ((long)(((q * 2 + side) * 4 + g) * 20 + v * 4)) * Ntot + f;
                     __builtin_nontemporal_store((TG)val, dst);
@@ -516,41 +546,25 @@ __global__ void __launch_bounds__(512) k_recon_bf16(WorkList W, long Ntot, const
             bz0 = (int)(t0 / b.ny);
         }
         const int nit = cpr * (tile.ty > 0 ? tile.ty * tile.tz : 1) * kNV;
-        for (int it = wave; it < nit; it += nwaves) {
+        for (int it = __builtin_amdgcn_readfirstlane(wave); it < nit; it += nwaves) {
             const int v = it % kNV;
             const int chunk = it / kNV;
             bool valid;
             int ci, cj, ck;
-            long cl;
-            if (tile.ty > 0) {
-                const int xo = 16 * (chunk % cpr) + col, row = chunk / cpr;
-                valid = xo < tile.count;
-                ci = bx0 + (valid ? xo : 0);  // tail lanes compute a copy, store nothing
-                cj = by0 + row % tile.ty;
-                ck = bz0 + row / tile.ty;
-                cl = ci + (long)b.nx * (cj + (long)b.ny * ck);
-            } else {
-                const long cl0 = tile.start + chunk * 16 + col;
-                const long cend = tile.start + tile.count;
-                valid = cl0 < cend;
-                cl = valid ? cl0 : cend - 1;
-                ci = (int)(cl % b.nx);
-                const long tt = cl / b.nx;
-                cj = (int)(tt % b.ny);
-                ck = (int)(tt / b.ny);
-            }
-            const long c = b.off + cl;
+            lane_cell(tile, b, cpr, chunk, col, bx0, by0, bz0, ci, cj, ck, valid);
+            const CellNb cn = cell_nb(b, ci, cj, ck);
+            const int c = cn.c;
             const double *Qv = Q + v * Ntot;
             const double *Gv = G + 3 * v * Ntot;
             const double *Lv = L + 12 * v * Ntot;
             // The split products carry 2^-17 of their operands, so the vector work here runs in
             // FP32 (2^-24); only the differences to the cell average are formed in FP64.
-            float J0[3][3];
+            double J0d[3][3];
     #pragma unroll
             for (int r = 0; r < 3; ++r)
     #pragma unroll
-                for (int s = 0; s < 3; ++s) J0[r][s] = (float)M.J0[(3 * r + s) * Ntot + c];
-            const double q0 = Qv[c];
+                for (int s = 0; s < 3; ++s) J0d[r][s] = ld32(M.J0 + (3 * r + s) * Ntot, c);
+            const double q0 = ld32(Qv, c);
 
             // ---- the 18 stencil slots of this lane, split into BF16 hi/lo, slot 8s + j ----------
             v8bf bh[3], bl[3];
@@ -561,14 +575,37 @@ __global__ void __launch_bounds__(512) k_recon_bf16(WorkList W, long Ntot, const
                     bh[s][j] = (__bf16)0.0f;
                     bl[s][j] = (__bf16)0.0f;
                 }
+            // all nine neighbours first (one wait for memory), then the slots
+            double nq[9], ng[9][3];
+    #pragma unroll
+            for (int st = 0; st < 9; ++st) {
+                int nb;
+                if (st < 6) {
+                    nb = c + ((st & 1) ? cn.dp[st >> 1] : cn.dm[st >> 1]);
+                } else {
+                    const int p = st - 6, pa = (p < 2) ? 0 : 1, pb = (p == 0) ? 1 : 2;
+                    nb = c + (sa > 0 ? cn.dp[pa] : cn.dm[pa]) + (sb > 0 ? cn.dp[pb] : cn.dm[pb]);
+                }
+                nq[st] = ld32(Qv, nb);
+                ng[st][0] = ld32(Gv, nb);
+                ng[st][1] = ld32(Gv + Ntot, nb);
+                ng[st][2] = ld32(Gv + 2 * Ntot, nb);
+            }
+            double lvd[3];
+    #pragma unroll
+            for (int s = 0; s < 3; ++s) lvd[s] = ld32(Lv + 4 * s * Ntot, g * (int)Ntot + c);
+            __builtin_amdgcn_sched_barrier(0);  // every request above is in flight before the first use
+            const float lv[3] = {(float)lvd[0], (float)lvd[1], (float)lvd[2]};
+            float J0[3][3];
+    #pragma unroll
+            for (int r = 0; r < 3; ++r)
+    #pragma unroll
+                for (int s = 0; s < 3; ++s) J0[r][s] = (float)J0d[r][s];
             float fdiff[6];
     #pragma unroll
             for (int m = 0; m < 6; ++m) {
-                int o[3] = {0, 0, 0};
-                o[m >> 1] = (m & 1) ? 1 : -1;
-                const long nb = wrap_cell(b, ci + o[0], cj + o[1], ck + o[2]);
-                const float g0 = (float)Gv[nb], g1 = (float)Gv[Ntot + nb], g2 = (float)Gv[2 * Ntot + nb];
-                fdiff[m] = (float)(Qv[nb] - q0);
+                const float g0 = (float)ng[m][0], g1 = (float)ng[m][1], g2 = (float)ng[m][2];
+                fdiff[m] = (float)(nq[m] - q0);
                 const float r0 = J0[0][0] * g0 + J0[1][0] * g1 + J0[2][0] * g2;
                 const float r1 = J0[0][1] * g0 + J0[1][1] * g1 + J0[2][1] * g2;
                 const float r2 = J0[0][2] * g0 + J0[1][2] * g1 + J0[2][2] * g2;
@@ -577,13 +614,9 @@ __global__ void __launch_bounds__(512) k_recon_bf16(WorkList W, long Ntot, const
     #pragma unroll
             for (int p = 0; p < 3; ++p) {
                 const int pa = (p < 2) ? 0 : 1, pb = (p == 0) ? 1 : 2, pc = 3 - pa - pb;
-                int o[3] = {0, 0, 0};
-                o[pa] = sa;
-                o[pb] = sb;
-                const long nb = wrap_cell(b, ci + o[0], cj + o[1], ck + o[2]);
                 const int s0 = 6 + p, s1 = 9 + 2 * p, s2 = 10 + 2 * p;
-                put_bf16f(bh, bl, s0, (float)(Qv[nb] - q0));
-                const float g0 = (float)Gv[nb], g1 = (float)Gv[Ntot + nb], g2 = (float)Gv[2 * Ntot + nb];
+                put_bf16f(bh, bl, s0, (float)(nq[6 + p] - q0));
+                const float g0 = (float)ng[6 + p][0], g1 = (float)ng[6 + p][1], g2 = (float)ng[6 + p][2];
                 float rg[3];
     #pragma unroll
                 for (int s = 0; s < 3; ++s) rg[s] = J0[0][s] * g0 + J0[1][s] * g1 + J0[2][s] * g2;
@@ -593,7 +626,7 @@ __global__ void __launch_bounds__(512) k_recon_bf16(WorkList W, long Ntot, const
             float lsum[3];
     #pragma unroll
             for (int s = 0; s < 3; ++s) {
-                const float ln = (float)Lv[(4 * s + g) * Ntot + c];
+                const float ln = lv[s];
                 put_bf16f(bh, bl, 15 + s, ln);
                 const float x = ln + __shfl_xor(ln, 16, 64);
                 lsum[s] = x + __shfl_xor(x, 32, 64);
@@ -617,6 +650,12 @@ __global__ void __launch_bounds__(512) k_recon_bf16(WorkList W, long Ntot, const
                     cl2[s][j] = (__bf16)(x - (float)h);
                 }
 
+            // back-transform of the Gauss-point gradients, requested before the smoothness forms
+            double JiTd[3][3];
+    #pragma unroll
+            for (int r = 0; r < 3; ++r)
+    #pragma unroll
+                for (int s = 0; s < 3; ++s) JiTd[r][s] = ld32(M.JiT + (3 * r + s) * Ntot, c);
             float chi = 1.0f, bbar[3] = {0.0f, 0.0f, 0.0f};
             if (!P.linear) {
                 float isl = 0.0f, ist = 0.0f;
@@ -645,44 +684,50 @@ __global__ void __launch_bounds__(512) k_recon_bf16(WorkList W, long Ntot, const
                     ah = 1.0f + powf(rh, (float)P.geno_r);
                     al = 1.0f + powf(rl, (float)P.geno_r);
                 }
-                chi = tanhf((float)P.geno_C * (2.0f * ah / (ah + al))) * (float)P.inv_tanhC;
+                // tanhf(x) rounds to 1 for x > 9.1; the library call runs only if a lane is below 10
+                const float x = (float)P.geno_C * (2.0f * ah / (ah + al));
+                float th = 1.0f;
+                if (__any(x <= 10.0f)) th = (x > 10.0f) ? 1.0f : tanhf(x);
+                chi = th * (float)P.inv_tanhC;
                 // linear weights (1/6)/IS_m^5, normalised by the largest 1/IS_m so that the fifth
-                // powers stay inside the FP32 range
+                // powers stay inside the FP32 range; they enter only through (1 - chi)
                 const float lm[3] = {0.25f * lsum[0], 0.25f * lsum[1], 0.25f * lsum[2]};
-                float ti[6], tmax = 0.0f;
-    #pragma unroll
-                for (int m = 0; m < 6; ++m) {
-                    const int q = m >> 1;
-                    const float bn = fdiff[m];
-                    float is = eps + bn * bn;
-    #pragma unroll
-                    for (int t = 0; t < 3; ++t)
-                        if (t != q) is += lm[t] * lm[t];
-                    ti[m] = 1.0f / is;
-                    tmax = fmaxf(tmax, ti[m]);
-                }
-                float wsum = 0.0f;
-    #pragma unroll
-                for (int m = 0; m < 6; ++m) {
-                    const float r = ti[m] / tmax, r2 = r * r;
-                    ti[m] = r2 * r2 * r;
-                    wsum += ti[m];
-                }
-                const float iw = 1.0f / wsum;
-    #pragma unroll
-                for (int m = 0; m < 6; ++m) {
-                    const int q = m >> 1;
-                    const float w = ti[m] * iw;
-                    const float bn = (m & 1) ? fdiff[m] : -fdiff[m];
-    #pragma unroll
-                    for (int t = 0; t < 3; ++t) bbar[t] += w * ((t == q) ? bn : lm[t]);
+                if (__any(chi != 1.0f)) {
+                    float ti[6], tmax = 0.0f;
+        #pragma unroll
+                    for (int m = 0; m < 6; ++m) {
+                        const int q = m >> 1;
+                        const float bn = fdiff[m];
+                        float is = eps + bn * bn;
+        #pragma unroll
+                        for (int t = 0; t < 3; ++t)
+                            if (t != q) is += lm[t] * lm[t];
+                        ti[m] = 1.0f / is;
+                        tmax = fmaxf(tmax, ti[m]);
+                    }
+                    float wsum = 0.0f;
+        #pragma unroll
+                    for (int m = 0; m < 6; ++m) {
+                        const float r = ti[m] / tmax, r2 = r * r;
+                        ti[m] = r2 * r2 * r;
+                        wsum += ti[m];
+                    }
+                    const float iw = 1.0f / wsum;
+        #pragma unroll
+                    for (int m = 0; m < 6; ++m) {
+                        const int q = m >> 1;
+                        const float w = ti[m] * iw;
+                        const float bn = (m & 1) ? fdiff[m] : -fdiff[m];
+        #pragma unroll
+                        for (int t = 0; t < 3; ++t) bbar[t] += w * ((t == q) ? bn : lm[t]);
+                    }
                 }
             }
             float JiT[3][3];
     #pragma unroll
             for (int r = 0; r < 3; ++r)
     #pragma unroll
-                for (int s = 0; s < 3; ++s) JiT[r][s] = (float)M.JiT[(3 * r + s) * Ntot + c];
+                for (int s = 0; s < 3; ++s) JiT[r][s] = (float)JiTd[r][s];
             const float om = 1.0f - chi;
             const float taf = (float)ta, tbf = (float)tb;
     #pragma unroll 2
@@ -699,15 +744,9 @@ __global__ void __launch_bounds__(512) k_recon_bf16(WorkList W, long Ntot, const
                 const float dv = chi * y[0] + om * (bbar[0] * x0 + bbar[1] * x1 + bbar[2] * x2);
                 const float r0 = chi * y[1] + om * bbar[0], r1 = chi * y[2] + om * bbar[1],
                             r2 = chi * y[3] + om * bbar[2];
-                long f;
-                int side;
-                if (u & 1) {
-                    f = c;
-                    side = 0;
-                } else {
-                    f = wrap_cell(b, ci - (q == 0), cj - (q == 1), ck - (q == 2));
-                    side = 1;
-                }
+                // face u is the + face of this cell (side 0) or the + face of the - neighbour (side 1)
+                const int side = (u & 1) ? 0 : 1;
+                const int f = (u & 1) ? c : c + ((q == 0) ? cn.dm[0] : (q == 1) ? cn.dm[1] : cn.dm[2]);
                 if (valid) {
                     TG *dst = gp + ((long)(((q * 2 + side) * 4 + g) * 20 + v * 4)) * Ntot + f;
                     __builtin_nontemporal_store((TG)(q0 + (double)dv), dst);
