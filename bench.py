@@ -198,7 +198,8 @@ def bench_batching(K, W, torch, steps, warmup):
 def bench_learned(K, W, torch, n_eval=256, n_train=64, eval_steps=50, train_steps=1500):
     """Learned blend weights on supersonic isotropic turbulence (Mt 1.0, k0 8, Re_lambda 100):
     pairs (features, GENO weights) from the plain FP64 scheme at n_train^3 (seeds 8967-8970, run
-    to t ~ lambda/u'), balanced between chi < 0.99 and chi ~ 1; FP32 Adam training on the GPU;
+    to t ~ lambda/u' or to the first non-physical state, which the scheme meets once shocklets
+    form), balanced between chi < 0.99 and chi ~ 1; FP32 Adam training on the GPU;
     then n_eval^3 (seed 8966) advanced eval_steps steps with learned and with GENO weights."""
     import numpy as np
     dev = torch.device("cuda:0")
@@ -215,25 +216,34 @@ def bench_learned(K, W, torch, n_eval=256, n_train=64, eval_steps=50, train_step
     X = torch.zeros(N * 5, 18, dtype=torch.float32, device=dev)
     Wt = torch.zeros(N * 5, 7, dtype=torch.float64, device=dev)
     rng = torch.Generator(device="cpu").manual_seed(8965)
+    runs = []
     for seed in (8967, 8968, 8969, 8970):
         Q, G, L = W.initial_state(nodes_m.to(dev), W.isotropic_turbulence(64, k0=8.0, Mt=1.0, seed=seed), GAM)
         dt = torch.zeros(1, dtype=torch.float64, device=dev)
-        t, k = 0.0, 0
+        t, k, flags = 0.0, 0, 0
         while t < t_end and k < 400:
             K.cgks_step(gen, Q, G, L, dt, use_cfl=True)
+            # once shocklets form (t ~ 0.13 at Mt 1.0) the scheme meets non-physical states; pairs
+            # are taken from the states before that only
+            flags = K.cgks_check(gen)[1]
+            if flags:
+                break
             t += dt.item()
             k += 1
-            if k % 10 == 0 or t >= t_end:
+            if k % 5 == 0 or t >= t_end:
                 K.cgks_weights(gen, Q, G, L, X, Wt)
-                low = (Wt[:, 0] < 0.99).nonzero().squeeze(1)
-                high = (Wt[:, 0] >= 0.99).nonzero().squeeze(1)
-                take = max(1, min(len(low), 20000))
-                pick_l = low[torch.randperm(len(low), generator=rng)[:take].to(dev)] if len(low) else low
+                ok = torch.isfinite(X).all(1) & torch.isfinite(Wt).all(1)
+                low = (ok & (Wt[:, 0] < 0.99)).nonzero().squeeze(1)
+                high = (ok & (Wt[:, 0] >= 0.99)).nonzero().squeeze(1)
+                take = min(len(low), len(high), 20000)
+                if take == 0:
+                    continue
+                pick_l = low[torch.randperm(len(low), generator=rng)[:take].to(dev)]
                 pick_h = high[torch.randperm(len(high), generator=rng)[:take].to(dev)]
                 idx = torch.cat([pick_l, pick_h])
                 Xs.append(X[idx].clone())
                 Ts.append(Wt[idx].float())
-        K.cgks_check(gen)
+        runs.append({"seed": seed, "steps": k, "t": t, "stopped_by_flags": int(flags)})
     gen.close()
     Xtr = torch.cat(Xs)
     Ttr = torch.cat(Ts)
@@ -285,10 +295,11 @@ def bench_learned(K, W, torch, n_eval=256, n_train=64, eval_steps=50, train_step
     speed = lambda q: torch.sqrt(q[1] ** 2 + q[2] ** 2 + q[3] ** 2) / q[0]
     return {
         "workload": f"isotropic turbulence Mt 1.0 k0 8 Re_lambda 100, {n_eval}^3 periodic Cartesian, FP64; MLP "
-                    f"18-32-7 trained on {Xtr.shape[0]} balanced pairs from {n_train}^3 runs (4 seeds, t <= {t_end:.3f})",
+                    f"18-32-7 trained on {Xtr.shape[0]} balanced pairs from {n_train}^3 runs (4 seeds, t <= "
+                    f"{max(r['t'] for r in runs):.3f}: before the first non-physical state)",
         "train": {"steps": train_steps, "batch": 4096, "lr": 1e-3, "seconds": t_train,
                   "loss_first10": float(np.mean(hist[:10])), "loss_last100": float(np.mean(hist[-100:])),
-                  "pairs": int(Xtr.shape[0]), "fraction_chi_below_0.99": frac_low},
+                  "pairs": int(Xtr.shape[0]), "fraction_chi_below_0.99": frac_low, "generator_runs": runs},
         "learned": {"value": Ne * eval_steps / el_m, "unit": "cell-updates/s", "ms_per_step": 1e3 * el_m / eval_steps,
                     "fallback_fraction": flagged / max(examined, 1), "device_flags": st_m[1]},
         "geno": {"value": Ne * eval_steps / el_p, "unit": "cell-updates/s", "ms_per_step": 1e3 * el_p / eval_steps,

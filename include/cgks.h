@@ -169,8 +169,9 @@ int cgks_profile_read(cgks_ctx *ctx, double *ms, long *launches);
  * The reconstruction, flux and update kernels walk a work list of tiles (runs of consecutive
  * cells of one block) that spans every block, so one launch per kernel advances the whole
  * multi-block mesh.  Launch configuration per kernel kind (1 reconstruction, 2 flux, 3 update):
- *   tile_cells  cells per tile.  Reconstruction: a multiple of 16 in [16, 4096] (one
- *               workgroup of 8 waves takes a tile; a wave takes 16 cells of one variable);
+ *   tile_cells  cells per tile.  Reconstruction: a multiple of 16 in [16, 4096], default
+ *               1536 (one workgroup of 8 waves takes a tile and first stages the constant
+ *               matrices in LDS; a wave takes 16 cells of one variable);
  *               flux 128 and update 256 are fixed by their workgroup size.
  *   ngroups     0: one workgroup per unit (tile, or tile and Gauss point for the flux);
  *               > 0: a persistent grid of that many workgroups striding over the units

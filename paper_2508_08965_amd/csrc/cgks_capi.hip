@@ -393,7 +393,7 @@ int cgks_ctx_create(cgks_ctx **out, int nblocks, const int *dims, const double *
         hipDeviceProp_t prop;
         if (hipGetDeviceProperties(&prop, c->device) == hipSuccess) c->ncu = prop.multiProcessorCount;
     }
-    c->wl[1].cfg = cgks_launch{512, 0, 0, 0, 0};
+    c->wl[1].cfg = cgks_launch{1536, 0, 0, 0, 0};  // fewer workgroups stage the constants
     c->wl[2].cfg = cgks_launch{kFluxTile, 0, 0, 0, 0};
     c->wl[3].cfg = cgks_launch{kUpdateTile, 0, 0, 0, 0};
     int rc = CGKS_OK;
@@ -644,11 +644,11 @@ int cgks_autotune(cgks_ctx *ctx, const double *Q, const double *G, const double 
             cgks_ctx::List &l = ctx->wl[1];
             const long lim[2] = {1L << 17, 1L << 19};
             auto cls = [&](long N) { return N < lim[0] ? 0 : (N < lim[1] ? 1 : 2); };
-            // candidates: runs of 64..512 cells and bricks (x, y, z extents) that march along z
-            const int ncand = 11;
-            const int cand[ncand][3] = {{64, 0, 0},  {128, 0, 0}, {256, 0, 0},  {512, 0, 0},
-                                        {1024, 0, 0}, {2048, 0, 0}, {16, 8, 16}, {16, 8, 64},
-                                        {32, 4, 32}, {16, 16, 16}, {64, 2, 32}};
+            // candidates: runs of 64..2048 cells and bricks (x, y, z extents) that march along z
+            const int ncand = 12;
+            const int cand[ncand][3] = {{64, 0, 0},   {128, 0, 0},  {256, 0, 0}, {512, 0, 0},
+                                        {1024, 0, 0}, {1536, 0, 0}, {2048, 0, 0}, {16, 8, 16},
+                                        {16, 8, 64},  {32, 4, 32},  {16, 16, 16}, {64, 2, 32}};
             const cgks_launch base = l.cfg;
             std::vector<int> best_c(3, -1);
             for (int k = 0; k < 3 && e == hipSuccess; ++k) {

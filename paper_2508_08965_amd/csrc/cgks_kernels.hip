@@ -488,12 +488,18 @@ __device__ inline void update_cell(const BlockView &b, long cl, long Ntot, const
 #pragma unroll
         for (int r = 0; r < 3; ++r) Gq[v][r] = Gt[v][r] = 0.0;
     const double iv = 1.0 / M.vol[c];
+    double qb[5];  // cell averages (stage 1: removed from the surface integral of the gradient)
+#pragma unroll
+    for (int v = 0; v < 5; ++v) qb[v] = (STAGE == 1) ? Q[v * Ntot + c] : 0.0;
 #pragma unroll 1
     for (int q = 0; q < 3; ++q) {
         int o[3] = {0, 0, 0};
         o[q] = -1;
         const long fm = cell_at(b, id.i + o[0], id.j + o[1], id.k + o[2]);
-#pragma unroll 1
+        // stage 1 with FP64 face records: the four Gauss points of a face in one block (the
+        // compiler then keeps the kernel at 3 waves per SIMD); otherwise one point at a time
+        constexpr int kUnrollPoints = (STAGE == 1 && sizeof(TF) == 8) ? 4 : 1;
+#pragma unroll kUnrollPoints
         for (int kk = 0; kk < 4; ++kk) {
             const TF *Dp = fo + (long)((q * 4 + kk) * 30) * Ntot + c;   // plus face: this cell is left
             const TF *Dm = fo + (long)((q * 4 + kk) * 30) * Ntot + fm;  // minus face: this cell is right
@@ -518,9 +524,9 @@ __device__ inline void update_cell(const BlockView &b, long cl, long Ntot, const
                 if (STAGE == 1) {
                     const double qp = (double)Dp[(10 + v) * Ntot], qm = (double)Dm[(20 + v) * Ntot];
                     // Gauss's theorem on the closed cell surface with the cell average removed
-                    const double qb = Q[v * Ntot + c];
 #pragma unroll
-                    for (int r = 0; r < 3; ++r) Gq[v][r] += wp * np_[r] * (qp - qb) - wm * nm_[r] * (qm - qb);
+                    for (int r = 0; r < 3; ++r)
+                        Gq[v][r] += wp * np_[r] * (qp - qb[v]) - wm * nm_[r] * (qm - qb[v]);
                     const double lb = qp - qm;
                     __builtin_nontemporal_store(lb, stash + ((20 + 12 * v + s) * Ntot + c));
                     L[(12 * v + s) * Ntot + c] = lb + 0.5 * dt * lt;
@@ -533,7 +539,7 @@ __device__ inline void update_cell(const BlockView &b, long cl, long Ntot, const
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
         if (STAGE == 1) {
-            const double l1 = Lf[v] * iv, l2 = Lt[v] * iv, qn = Q[v * Ntot + c];
+            const double l1 = Lf[v] * iv, l2 = Lt[v] * iv, qn = qb[v];
             __builtin_nontemporal_store(qn + dt * l1 + (dt * dt / 6.0) * l2, stash + (v * Ntot + c));
             Q[v * Ntot + c] = qn + 0.5 * dt * l1 + 0.125 * dt * dt * l2;
 #pragma unroll
