@@ -90,9 +90,19 @@ struct DevConsts {
 //   X::swap(v)  value of v held by the partner lane of the pair (lane id xor 1)
 //   X::sqrt, X::exp, X::erfc, X::fabs, X::fma, X::finite, X::pow
 // ------------------------------------------------------------------------------------------
+// Partner-lane exchange as a DPP register move (quad_perm [1,0,3,2], i.e. lane id xor 1)
+// rather than through LDS.  Both lanes of every pair are active wherever it is used.
+__device__ inline int pair_swap32(int v) { return __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false); }
+
 struct DevMath {
-    template <class T> __device__ static T swap(T v) { return __shfl_xor(v, 1, 64); }
-    __device__ static int swapi(int v) { return __shfl_xor(v, 1, 64); }
+    __device__ static double swap(double v) {
+        const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+        const unsigned lo = (unsigned)pair_swap32((int)(unsigned)b);
+        const unsigned hi = (unsigned)pair_swap32((int)(unsigned)(b >> 32));
+        return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+    }
+    __device__ static float swap(float v) { return __builtin_bit_cast(float, pair_swap32(__builtin_bit_cast(int, v))); }
+    __device__ static int swapi(int v) { return pair_swap32(v); }
     template <class T> __device__ static T sqrt(T x) { return ::sqrt(x); }
     template <class T> __device__ static T exp(T x) { return ::exp(x); }
     template <class T> __device__ static T erfc(T x) { return ::erfc(x); }
