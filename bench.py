@@ -309,6 +309,67 @@ def bench_learned(K, W, torch, n_eval=256, n_train=64, eval_steps=50, train_step
     }
 
 
+def bench_percell(K, W, torch, kw, n=128, steps=3):
+    """The paper's storage argument (Sec. 4) measured: the same TGV step with the shared
+    standard-cell matrix (matrix cores) and with per-cell stored matrices (recon_impl 2: each
+    cell's coefficient map and Gauss-point evaluation, 48,960 bytes per cell, read every
+    stage).  n^3 is chosen so that the per-cell matrices fit in HBM (256^3 would need 821 GB)."""
+    dev = torch.device("cuda:0")
+    m = (n,) * 3
+    N = n ** 3
+    nodes = W.perturbed_nodes(m, amp=0.05, device=dev)
+    Q0, G0, L0 = W.initial_state(nodes, W.taylor_green(Ma=0.1), GAM)
+    nodes = nodes.cpu()
+    res, finals = {}, {}
+    for name, impl in (("shared", 0), ("per_cell", 2)):
+        try:
+            ctx = K.Context([m], [nodes], K.default_params(recon_impl=impl, **kw))
+        except RuntimeError as e:
+            res[name] = {"error": str(e)}
+            continue
+        Q, G, L = Q0.clone(), G0.clone(), L0.clone()
+        dt = torch.zeros(1, dtype=torch.float64, device=dev)
+        K.cgks_step(ctx, Q, G, L, dt, use_cfl=True)
+        Q.copy_(Q0)
+        G.copy_(G0)
+        L.copy_(L0)
+        torch.cuda.synchronize()
+        K.cgks_profile_read(ctx)
+        K.cgks_profile(ctx, True)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            K.cgks_step(ctx, Q, G, L, dt, use_cfl=True)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        prof = K.cgks_profile_read(ctx)
+        K.cgks_profile(ctx, False)
+        rms, rn = prof["reconstruction"]
+        r_ms = rms / max(rn, 1)
+        matrix_bytes = 48960 * N if impl == 2 else 0
+        # algorithmic bytes of one reconstruction launch: the per-cell matrices (shared: the
+        # 84 KB constant block, negligible), Q G L J0 J0^-T in, 480 Gauss-point values out
+        alg = matrix_bytes + (98 + 480) * 8 * N
+        res[name] = {"value": N * steps / el, "unit": "cell-updates/s", "ms_per_step": 1e3 * el / steps,
+                     "reconstruction_ms": r_ms, "matrix_storage_bytes": matrix_bytes if impl == 2 else 83968,
+                     "reconstruction_algorithmic_GBps": alg / (r_ms * 1e-3) / 1e9,
+                     # time the algorithmic bytes alone take at the 8 TB/s HBM peak: a floor for
+                     # any implementation of this storage scheme
+                     "reconstruction_hbm_floor_ms": alg / 8e12 * 1e3,
+                     "device_flags": K.cgks_check(ctx)[1]}
+        finals[name] = Q.cpu()
+        ctx.close()
+        del Q, G, L
+        torch.cuda.empty_cache()
+    out = {"workload": f"taylor-green vortex Re1600 Ma0.1, {n}^3 periodic perturbed curvilinear mesh, FP64, "
+                       f"{steps} steps", "cells": N, "variants": res}
+    if len(finals) == 2:
+        a, b = finals["per_cell"], finals["shared"]
+        out["rel_l2_Q_per_cell_vs_shared"] = float(torch.linalg.norm(a - b) / torch.linalg.norm(b))
+        if "reconstruction_ms" in res.get("per_cell", {}):
+            out["reconstruction_time_ratio"] = res["per_cell"]["reconstruction_ms"] / res["shared"]["reconstruction_ms"]
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -320,6 +381,7 @@ def main():
     ap.add_argument("--error-steps", type=int, default=50, help="steps for the variant error against FP64")
     ap.add_argument("--no-batching", action="store_true", help="skip the multi-block batching measurement")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-weight measurement")
+    ap.add_argument("--no-percell", action="store_true", help="skip the per-cell matrix storage measurement")
     ap.add_argument("--dump-state", default=None,
                     help="write the initial state and parameters of the FP64 workload for cgks_runner, then exit")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -465,6 +527,11 @@ def main():
     if not args.no_learned:
         learned = bench_learned(K, W, torch)
 
+    # ---- per-cell stored matrices against the shared standard-cell matrix --------------------
+    percell = None
+    if not args.no_percell:
+        percell = bench_percell(K, W, torch, kw)
+
     # ---- CPU baseline: the oracle on a bounded sample of the same workload ------------------
     cpu = None
     if not args.no_oracle:
@@ -502,6 +569,7 @@ def main():
         "variants": variants,
         "batching": batching,
         "learned_weights": learned,
+        "per_cell_storage": percell,
         "cpu_baseline": cpu,
         "device_flags": flags,
     }

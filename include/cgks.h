@@ -77,7 +77,12 @@ typedef struct {
                             option stores Gauss-point data in FP32; metrics, the time step
                             and the S2O4 accumulation of Q, G, L stay FP64                  */
     int recon_impl;      /* reconstruction kernel: 0 matrix cores (MFMA, default),
-                            1 vector-ALU kernel (one thread per cell and variable)          */
+                            1 vector-ALU kernel (one thread per cell and variable),
+                            2 per-cell stored matrices: the cell's coefficient map from its
+                            physical-frame stencil data (34 x 84) and its Gauss-point
+                            evaluation (96 x 34), built at context creation and read every
+                            stage; 48,960 bytes per cell (the storage the shared standard
+                            cell of Sec. 4 avoids).  1 and 2 are FP64 only              */
     int per_block;       /* multi-block launches: 0 one launch per kernel covering every
                             block (work list of tiles over all blocks, default); 1 one
                             launch per kernel and block (the comparison baseline)          */

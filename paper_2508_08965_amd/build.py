@@ -10,7 +10,8 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "lib", "libcgks.so")
 RUNNER = os.path.join(HERE, "lib", "cgks_runner")
 
-SOURCES = ["cgks_capi.hip", "cgks_kernels.hip", "cgks_recon_mfma.hip", "cgks_mlp.hip", "cgks_consts.cpp"]
+SOURCES = ["cgks_capi.hip", "cgks_kernels.hip", "cgks_recon_mfma.hip", "cgks_mlp.hip", "cgks_percell.hip",
+           "cgks_consts.cpp"]
 
 FLAGS = ["-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC", "-shared",
          # packed FP32 instructions are disabled for every HIP translation unit

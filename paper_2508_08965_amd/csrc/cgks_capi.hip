@@ -48,6 +48,7 @@ struct cgks_ctx {
     double *fo = nullptr;     // [3][4][30][Ntot]
     double *stash = nullptr;  // [80][Ntot]
     double *Kmf = nullptr;    // constant blocks of the matrix-core reconstruction
+    double *pcm = nullptr;    // per-cell matrices (recon_impl 2), tiled by 12 cells
     double *dt_part = nullptr;
     int nparts = 1;
     int ncu = 256;
@@ -157,13 +158,13 @@ static int check_params(const cgks_params *p) {
     if (p->recon_prec < 0 || p->recon_prec > 2)
         return fail(CGKS_EUNSUPPORTED, "recon_prec must be 0 (FP64), 1 (FP32x3) or 2 (BF16x3)");
     if (p->flux_prec < 0 || p->flux_prec > 1) return fail(CGKS_EUNSUPPORTED, "flux_prec must be 0 (FP64) or 1 (FP32)");
-    if (p->recon_impl != 0 && p->recon_impl != 1) return fail(CGKS_EINVAL, "recon_impl must be 0 or 1");
+    if (p->recon_impl < 0 || p->recon_impl > 2) return fail(CGKS_EINVAL, "recon_impl must be 0, 1 or 2");
     if (p->per_block != 0 && p->per_block != 1) return fail(CGKS_EINVAL, "per_block must be 0 or 1");
     if (p->weights != 0 && p->weights != 1) return fail(CGKS_EINVAL, "weights must be 0 (GENO) or 1 (learned)");
     if (!(p->jump_thresh >= 0.0)) return fail(CGKS_EINVAL, "jump_thresh must be >= 0");
     if (p->weights == 1 && (p->recon_impl != 0 || p->recon_prec != 0 || p->linear))
         return fail(CGKS_EUNSUPPORTED, "learned weights need the nonlinear FP64 matrix-core reconstruction");
-    if (p->recon_impl == 1 && (p->recon_prec != 0 || p->flux_prec != 0))
+    if (p->recon_impl != 0 && (p->recon_prec != 0 || p->flux_prec != 0))
         return fail(CGKS_EUNSUPPORTED, "the vector-ALU reconstruction is FP64 only");
     return CGKS_OK;
 }
@@ -231,11 +232,14 @@ static void drop_graph(cgks_ctx *c) {
 }
 
 static hipError_t run_recon(cgks_ctx *ctx, int b, const double *Q, const double *G, const double *L, hipStream_t s) {
-    if (ctx->user.recon_impl == 1) {
-        // vector-ALU reference kernel: one launch per block
+    if (ctx->user.recon_impl != 0) {
+        // vector-ALU reference kernel (1) or per-cell stored matrices (2): one launch per block
         for (int i = 0; i < (int)ctx->blocks.size(); ++i) {
             if (b >= 0 && i != b) continue;
-            hipError_t e = launch_recon(ctx->blocks[i], ctx->Ntot, Q, G, L, ctx->M, ctx->K, ctx->P, ctx->gp, s);
+            hipError_t e = (ctx->user.recon_impl == 1)
+                               ? launch_recon(ctx->blocks[i], ctx->Ntot, Q, G, L, ctx->M, ctx->K, ctx->P, ctx->gp, s)
+                               : launch_recon_percell(ctx->blocks[i], ctx->Ntot, Q, G, L, ctx->M, ctx->K, ctx->P,
+                                                      ctx->pcm, ctx->gp, s);
             if (e != hipSuccess) return e;
         }
         return hipSuccess;
@@ -293,6 +297,7 @@ void cgks_ctx_destroy(cgks_ctx *ctx) {
     (void)hipFree(ctx->metric_mem);
     (void)hipFree(ctx->K);
     (void)hipFree(ctx->Kmf);
+    (void)hipFree(ctx->pcm);
     (void)hipFree(ctx->gp);
     (void)hipFree(ctx->fo);
     (void)hipFree(ctx->stash);
@@ -359,7 +364,10 @@ int cgks_ctx_create(cgks_ctx **out, int nblocks, const int *dims, const double *
               alloc((void **)&c->mlp_m, sizeof(float) * kMlpParams) &&
               alloc((void **)&c->mlp_v, sizeof(float) * kMlpParams) &&
               alloc((void **)&c->mlp_g, sizeof(float) * kMlpParams) && alloc((void **)&c->mlp_loss, sizeof(float)) &&
-              alloc((void **)&c->mlp_packed, kMlpPackBytes);
+              alloc((void **)&c->mlp_packed, kMlpPackBytes) &&
+              (p->recon_impl != 2 ||
+               alloc((void **)&c->pcm, sizeof(double) * kPcElems *
+                                           ((Ntot + kPcCellsPerWave - 1) / kPcCellsPerWave * kPcCellsPerWave)));
     if (!ok) {
         cgks_ctx_destroy(c);
         return fail(CGKS_ENOMEM, "device allocation failed");
@@ -423,6 +431,12 @@ int cgks_ctx_create(cgks_ctx **out, int nblocks, const int *dims, const double *
         e = hipMemcpy(&bad, c->flag, sizeof(int), hipMemcpyDeviceToHost);
         if (e != hipSuccess) { rc = hip_fail(e, "read flag"); break; }
         if (bad) { rc = fail(CGKS_EINVAL, "mesh has a cell with non-positive volume or det J0"); break; }
+        if (c->pcm) {
+            for (int b = 0; b < nblocks && e == hipSuccess; ++b)
+                e = launch_percell_setup(c->blocks[b], Ntot, c->M, c->K, c->pcm, s);
+            if (e == hipSuccess) e = hipStreamSynchronize(s);
+            if (e != hipSuccess) { rc = hip_fail(e, "per-cell matrices"); break; }
+        }
         e = hipMalloc((void **)&c->d_blocks, sizeof(BlockView) * nblocks);
         if (e == hipSuccess)
             e = hipMemcpy(c->d_blocks, c->blocks.data(), sizeof(BlockView) * nblocks, hipMemcpyHostToDevice);

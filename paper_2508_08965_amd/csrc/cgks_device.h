@@ -469,6 +469,16 @@ hipError_t launch_dt(long off, long N, long Ntot, const double *Q, const double 
 hipError_t launch_dt_final(const double *part, int n, double *dt, hipStream_t s);
 hipError_t launch_recon(const BlockView &b, long Ntot, const double *Q, const double *G, const double *L,
                         const Metrics &M, const DevConsts *K, const DevParams &P, double *gp, hipStream_t s);
+// Per-cell stored matrices (cgks_percell.hip): Rc (34 x 84) and Ec (96 x 34) per cell, tiled by
+// the 12 cells of a wave; the buffer holds kPcElems doubles per cell, for ceil(N / 12) * 12 cells.
+constexpr int kPcCols = 84;                                 // raw stencil items per variable
+constexpr long kPcElems = (long)kNB * kPcCols + 96L * kNB;  // 6120 doubles per cell
+constexpr int kPcCellsPerWave = 12;                         // 12 cells x 5 variables per wave
+hipError_t launch_percell_setup(const BlockView &b, long Ntot, const Metrics &M, const DevConsts *K, double *pcm,
+                                hipStream_t s);
+hipError_t launch_recon_percell(const BlockView &b, long Ntot, const double *Q, const double *G, const double *L,
+                                const Metrics &M, const DevConsts *K, const DevParams &P, const double *pcm,
+                                double *gp, hipStream_t s);
 // Inputs and outputs of the blend-weight modes of the matrix-core reconstruction.
 struct BlendIO {
     const unsigned char *jump;  // [Ntot] pressure-jump flags (learned weights)

@@ -56,6 +56,12 @@ def test_host_side_argument_errors():
     assert L.cgks_num_cells(None) == 0
     bad = K.default_params(per_block=2)
     assert L.cgks_ctx_create(C.byref(h), 1, dims, nodes, C.byref(bad), None) == K.EINVAL
+    # per-cell stored matrices: FP64 only; no fourth implementation
+    bad = K.default_params(recon_impl=3)
+    assert L.cgks_ctx_create(C.byref(h), 1, dims, nodes, C.byref(bad), None) == K.EINVAL
+    for kw in (dict(recon_prec=2), dict(recon_prec=1), dict(flux_prec=1)):
+        bad = K.default_params(recon_impl=2, **kw)
+        assert L.cgks_ctx_create(C.byref(h), 1, dims, nodes, C.byref(bad), None) == K.EUNSUPPORTED
     cfg = K.Launch(128, 0, 0)
     assert L.cgks_get_launch(None, 1, C.byref(cfg)) == K.EINVAL
     assert L.cgks_set_launch(None, 1, C.byref(cfg)) == K.EINVAL

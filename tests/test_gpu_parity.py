@@ -125,7 +125,7 @@ def test_metrics_parity():
     ctx.close()
 
 
-@pytest.mark.parametrize("impl", [0, 1], ids=["mfma", "valu"])
+@pytest.mark.parametrize("impl", [0, 1, 2], ids=["mfma", "valu", "percell"])
 @pytest.mark.parametrize("linear", [0, 1])
 def test_reconstruction_parity_curvilinear(linear, impl):
     n = (17, 12, 10)  # 2040 cells: several workgroups and a ragged tail
