@@ -370,6 +370,54 @@ def bench_percell(K, W, torch, kw, n=128, steps=3):
     return out
 
 
+def bench_supersonic_tgv(K, W, torch, n=128, t_end=10.0, Ma=1.25):
+    """Robustness run of Sec. 5: the supersonic Taylor-Green vortex (Ma 1.25, Re 1600, Pr 0.7,
+    Sutherland) with the nonlinear scheme on the paper's uniform n^3 mesh, to t_end, with the
+    kinetic energy and enstrophy history from the library's diagnostics."""
+    dev = torch.device("cuda:0")
+    m = (n,) * 3
+    nodes = W.cartesian_nodes(m, hi=(2.0 * math.pi,) * 3)
+    Q, G, L = W.initial_state(nodes.to(dev), W.taylor_green(Ma=Ma), GAM)
+    p0 = 1.0 / (GAM * Ma * Ma)
+    kw = dict(viscous=1, visc_law=1, mu0=1.0 / 1600, T_ref=p0, S_suth=p0 * 110.4 / 288.15, Pr=0.7, prandtl_fix=1)
+    ctx = K.Context([m], [nodes], K.default_params(**kw))
+    dt = torch.zeros(1, dtype=torch.float64, device=dev)
+    d = torch.zeros(6, dtype=torch.float64, device=dev)
+
+    def diag():
+        K.cgks_diagnostics(ctx, Q, G, d)
+        return d.tolist()
+
+    d0 = diag()
+    hist = [[0.0] + d0[:2]]
+    rho_min, p_min = d0[4], d0[5]
+    t, k, flags = 0.0, 0, 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    while t < t_end and k < 20000:
+        K.cgks_step(ctx, Q, G, L, dt, use_cfl=True)
+        t += dt.item()
+        k += 1
+        if k % 50 == 0 or t >= t_end:
+            x = diag()
+            rho_min, p_min = min(rho_min, x[4]), min(p_min, x[5])
+            if k % 100 == 0 or t >= t_end:
+                hist.append([t] + x[:2])
+            flags = K.cgks_check(ctx)[1]
+            if flags:
+                break
+    el = time.perf_counter() - t0
+    d1 = diag()
+    ctx.close()
+    torch.cuda.empty_cache()
+    return {"workload": f"supersonic taylor-green vortex Ma {Ma} Re 1600 Pr 0.7 Sutherland, {n}^3 uniform periodic "
+                        f"mesh, nonlinear CGKS-5 FP64, to t = {t_end}",
+            "steps": k, "t": t, "seconds": el, "cell_updates_per_s": n ** 3 * k / el, "device_flags": flags,
+            "min_rho": rho_min, "min_p_over_p0": p_min / p0,
+            "mass_rel_drift": (d1[2] - d0[2]) / d0[2], "energy_rel_drift": (d1[3] - d0[3]) / d0[3],
+            "history_t_Ek_epsS": hist}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -382,6 +430,7 @@ def main():
     ap.add_argument("--no-batching", action="store_true", help="skip the multi-block batching measurement")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-weight measurement")
     ap.add_argument("--no-percell", action="store_true", help="skip the per-cell matrix storage measurement")
+    ap.add_argument("--no-supersonic", action="store_true", help="skip the supersonic Taylor-Green robustness run")
     ap.add_argument("--dump-state", default=None,
                     help="write the initial state and parameters of the FP64 workload for cgks_runner, then exit")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -532,6 +581,11 @@ def main():
     if not args.no_percell:
         percell = bench_percell(K, W, torch, kw)
 
+    # ---- supersonic Taylor-Green vortex: robustness of the nonlinear scheme ------------------
+    supersonic = None
+    if not args.no_supersonic:
+        supersonic = bench_supersonic_tgv(K, W, torch)
+
     # ---- CPU baseline: the oracle on a bounded sample of the same workload ------------------
     cpu = None
     if not args.no_oracle:
@@ -570,6 +624,7 @@ def main():
         "batching": batching,
         "learned_weights": learned,
         "per_cell_storage": percell,
+        "supersonic_tgv": supersonic,
         "cpu_baseline": cpu,
         "device_flags": flags,
     }

@@ -112,6 +112,18 @@ int cgks_ctx_create(cgks_ctx **out, int nblocks, const int *dims, const double *
 /* Release every device buffer of the context (synchronises the device).  NULL is a no-op. */
 void cgks_ctx_destroy(cgks_ctx *ctx);
 
+/* Flow diagnostics of the Taylor-Green section (Sec. 5) over all cells of all blocks:
+ *   E_k   = 1/(rho0 |Omega|) int rho U.U / 2 dV      (volume-averaged kinetic energy)
+ *   eps_S = 1/(rho0 |Omega|) int mu |curl U|^2 dV     (integrated enstrophy)
+ * by the midpoint rule over the cells, from the cell averages Q and the cell-averaged
+ * gradients G (layouts of cgks_stage).  rho0 is the mean density (conserved by the scheme);
+ * the velocity gradient of a cell is (grad(rho U) - U grad rho) / rho; mu follows the
+ * viscosity law of the parameters at T = p / rho (mu0 when visc_law is 0).
+ *   out   device, 6 doubles: E_k, eps_S, mean rho, mean rho E, min rho, min p
+ * Deterministic (a fixed partition of the cells and a fixed summation tree); asynchronous on
+ * stream; errors: CGKS_EINVAL for NULL arguments. */
+int cgks_diagnostics(cgks_ctx *ctx, const double *Q, const double *G, double *out, void *stream);
+
 /* Total number of cells N of the context. */
 long cgks_num_cells(const cgks_ctx *ctx);
 

@@ -1376,3 +1376,54 @@ int oracle_recon_weights(const int dims[3], const double *nodes, const or_params
     mesh_free(&M);
     return OR_OK;
 }
+
+/* ---------------------------------------------------------------------------
+ * Flow diagnostics of the Taylor-Green section (Sec. 5, TGV):
+ *   E_k   = 1/(rho0 |Omega|) int 1/2 rho U.U dV            (volume-averaged kinetic energy)
+ *   eps_S = 1/(rho0 |Omega|) int mu |curl U|^2 dV           (integrated enstrophy)
+ * by the midpoint rule over the cells, from the cell averages and the evolved cell-averaged
+ * gradients.  Readings: rho0 is the mean density (conserved by the scheme); the velocity
+ * gradient of a cell is (grad(rho U) - U grad rho) / rho; mu follows the viscosity law of the
+ * parameters at T = p / rho.
+ * out[6]: E_k, eps_S, mean rho, mean rho E, min rho, min p.
+ * --------------------------------------------------------------------------- */
+int oracle_diagnostics(const int dims[3], const double *nodes, const or_params *P, const double *Q,
+                       const double *G, double *out) {
+    or_mesh M;
+    int st = mesh_build(&M, dims, nodes);
+    if (st) { if (M.n > 0) mesh_free(&M); return st; }
+    const long N = M.n;
+    double V = 0.0, mass = 0.0, ke = 0.0, ens = 0.0, en = 0.0, rmin = INFINITY, pmin = INFINITY;
+    for (long c = 0; c < N; ++c) {
+        const double vol = M.vol[c];
+        const double rho = Q[c];
+        double U[3], uu = 0.0;
+        for (int i = 0; i < 3; ++i) {
+            U[i] = Q[(1 + i) * N + c] / rho;
+            uu += U[i] * U[i];
+        }
+        const double k = 0.5 * rho * uu;
+        const double p = (P->gamma - 1.0) * (Q[4 * N + c] - k);
+        const double mu = sutherland(P, p / rho);
+        double dU[3][3]; /* dU[i][j] = d U_i / d x_j */
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j)
+                dU[i][j] = (G[(3 * (1 + i) + j) * N + c] - U[i] * G[j * N + c]) / rho;
+        const double w0 = dU[2][1] - dU[1][2], w1 = dU[0][2] - dU[2][0], w2 = dU[1][0] - dU[0][1];
+        V += vol;
+        mass += rho * vol;
+        ke += k * vol;
+        ens += mu * (w0 * w0 + w1 * w1 + w2 * w2) * vol;
+        en += Q[4 * N + c] * vol;
+        if (rho < rmin) rmin = rho;
+        if (p < pmin) pmin = p;
+    }
+    mesh_free(&M);
+    out[0] = ke / mass;
+    out[1] = ens / mass;
+    out[2] = mass / V;
+    out[3] = en / V;
+    out[4] = rmin;
+    out[5] = pmin;
+    return OR_OK;
+}

@@ -91,6 +91,7 @@ def lib():
         L.oracle_bf16.argtypes = [C.c_long, dp, dp]
         L.oracle_features.argtypes = [ip, dp, pp, dp, dp, lp, C.c_long, C.c_double, dp, ip]
         L.oracle_recon_weights.argtypes = [ip, dp, pp, dp, dp, dp, lp, C.c_long, dp, dp, dp]
+        L.oracle_diagnostics.argtypes = [ip, dp, pp, dp, dp, dp]
         _lib = L
     return _lib
 
@@ -271,3 +272,15 @@ def recon_weights(dims, nodes, prm, Q, G, L, cells, win=None):
     if st:
         raise ValueError(f"oracle_recon_weights status {st}")
     return out, wout
+
+
+def diagnostics(dims, nodes, prm, Q, G):
+    """Flow diagnostics of the Taylor-Green section (Sec. 5): midpoint-rule volume averages of
+    the kinetic energy E_k and the enstrophy eps_S (normalised by the mean density and the
+    domain volume), with the mean density and total energy and the minima of rho and p."""
+    nodes, Q, G = _arr(nodes), _arr(Q), _arr(G)
+    out = np.zeros(6)
+    st = lib().oracle_diagnostics(_dims(dims), _d(nodes), C.byref(prm), _d(Q), _d(G), _d(out))
+    if st:
+        raise ValueError(f"oracle_diagnostics status {st}")
+    return dict(Ek=out[0], epsS=out[1], rho_mean=out[2], rhoE_mean=out[3], rho_min=out[4], p_min=out[5])

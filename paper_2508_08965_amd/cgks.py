@@ -53,6 +53,7 @@ def lib():
         L.cgks_num_cells.argtypes = [vp]
         L.cgks_num_cells.restype = C.c_long
         L.cgks_dt.argtypes = [vp, vp, vp, vp]
+        L.cgks_diagnostics.argtypes = [vp, vp, vp, vp, vp]
         L.cgks_stage.argtypes = [vp, C.c_int, vp, vp, vp, vp, vp]
         L.cgks_step.argtypes = [vp, vp, vp, vp, vp, C.c_int, vp]
         L.cgks_check.argtypes = [vp, ip]
@@ -157,6 +158,17 @@ class Context:
 
 def cgks_dt(ctx: Context, Q, dt_dev, stream=None):
     _check(lib().cgks_dt(ctx.h, _ptr(Q, 5 * ctx.ncells, "Q"), _ptr(dt_dev, 1, "dt"), _stream(stream)), "cgks_dt")
+
+
+def cgks_diagnostics(ctx: Context, Q, G, out, stream=None):
+    """Flow diagnostics into the 6-element device tensor out: E_k, eps_S, mean rho, mean rho E,
+    min rho, min p (asynchronous)."""
+    n = ctx.ncells
+    _check(lib().cgks_diagnostics(ctx.h, _ptr(Q, 5 * n, "Q"), _ptr(G, 15 * n, "G"), _ptr(out, 6, "out"),
+                                  _stream(stream)), "cgks_diagnostics")
+
+
+DIAG_NAMES = ("Ek", "epsS", "rho_mean", "rhoE_mean", "rho_min", "p_min")
 
 
 def cgks_stage(ctx: Context, stage: int, dt_dev, Q, G, L, stream=None):

@@ -50,6 +50,7 @@ struct cgks_ctx {
     double *Kmf = nullptr;    // constant blocks of the matrix-core reconstruction
     double *pcm = nullptr;    // per-cell matrices (recon_impl 2), tiled by 12 cells
     double *dt_part = nullptr;
+    double *diag_part = nullptr;  // [nparts][7] partial sums of the flow diagnostics
     int nparts = 1;
     int ncu = 256;
     // work lists of the reconstruction (1), flux (2) and update (3) kernels
@@ -298,6 +299,7 @@ void cgks_ctx_destroy(cgks_ctx *ctx) {
     (void)hipFree(ctx->K);
     (void)hipFree(ctx->Kmf);
     (void)hipFree(ctx->pcm);
+    (void)hipFree(ctx->diag_part);
     (void)hipFree(ctx->gp);
     (void)hipFree(ctx->fo);
     (void)hipFree(ctx->stash);
@@ -359,6 +361,7 @@ int cgks_ctx_create(cgks_ctx **out, int nblocks, const int *dims, const double *
               alloc((void **)&c->gp, sizeof(double) * 480 * Ntot) && alloc((void **)&c->fo, sizeof(double) * 360 * Ntot) &&
               alloc((void **)&c->stash, sizeof(double) * 80 * Ntot) &&
               alloc((void **)&c->dt_part, sizeof(double) * kMaxDtParts) && alloc((void **)&c->flag, sizeof(int)) &&
+              alloc((void **)&c->diag_part, sizeof(double) * 7 * kMaxDtParts) &&
               alloc((void **)&c->jump, Ntot) && alloc((void **)&c->jcount, sizeof(unsigned long long)) &&
               alloc((void **)&c->mlp_w, sizeof(float) * kMlpParams) &&
               alloc((void **)&c->mlp_m, sizeof(float) * kMlpParams) &&
@@ -464,6 +467,15 @@ int cgks_dt(cgks_ctx *ctx, const double *Q, double *dt_dev, void *stream) {
     Timed t(ctx, s, 0);
     HIP_TRY(launch_dt(0, ctx->Ntot, ctx->Ntot, Q, ctx->M.dtm, ctx->P, ctx->dt_part, ctx->nparts, ctx->flag, s), "dt");
     HIP_TRY(launch_dt_final(ctx->dt_part, ctx->nparts, dt_dev, s), "dt final");
+    return CGKS_OK;
+}
+
+int cgks_diagnostics(cgks_ctx *ctx, const double *Q, const double *G, double *out, void *stream) {
+    if (!ctx || !Q || !G || !out) return fail(CGKS_EINVAL, "cgks_diagnostics: NULL argument");
+    hipStream_t s = (hipStream_t)stream;
+    ctx->last = s;
+    HIP_TRY(launch_diagnostics(ctx->Ntot, Q, G, ctx->M.vol, ctx->P, ctx->diag_part, ctx->nparts, out, s),
+            "diagnostics");
     return CGKS_OK;
 }
 

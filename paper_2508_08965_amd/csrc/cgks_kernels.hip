@@ -213,6 +213,92 @@ __global__ void __launch_bounds__(256) k_dt_final(const double *__restrict__ par
 }
 
 // ------------------------------------------------------------------------------------------
+// flow diagnostics of the Taylor-Green section (Sec. 5): volume sums of the kinetic energy and
+// the enstrophy (midpoint rule over cells, cell-averaged gradients), total mass and energy,
+// minima of rho and p.  Fixed partition of the cells over the workgroups and a fixed summation
+// tree: the result does not depend on timing.
+// ------------------------------------------------------------------------------------------
+constexpr int kDiagVals = 7;  // volume, mass, kinetic energy, enstrophy, energy; min rho, min p
+
+__global__ void __launch_bounds__(256) k_diag_partial(long Ntot, const double *__restrict__ Q,
+                                                      const double *__restrict__ G, const double *__restrict__ vol,
+                                                      DevParams P, double *__restrict__ part) {
+    __shared__ double red[kDiagVals][256];
+    double acc[kDiagVals] = {0.0, 0.0, 0.0, 0.0, 0.0, INFINITY, INFINITY};
+    for (long c = (long)blockIdx.x * blockDim.x + threadIdx.x; c < Ntot; c += (long)gridDim.x * blockDim.x) {
+        const double v = vol[c], rho = Q[c];
+        double U[3], uu = 0.0;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            U[i] = Q[(1 + i) * Ntot + c] / rho;
+            uu += U[i] * U[i];
+        }
+        const double k = 0.5 * rho * uu, re = Q[4 * Ntot + c];
+        const double p = (P.gamma - 1.0) * (re - k);
+        const double mu = viscosity_dt(P, p / rho);
+        // velocity gradient from the cell-averaged gradients of rho and rho U
+        double dU[3][3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) dU[i][j] = (G[(3 * (1 + i) + j) * Ntot + c] - U[i] * G[j * Ntot + c]) / rho;
+        const double w0 = dU[2][1] - dU[1][2], w1 = dU[0][2] - dU[2][0], w2 = dU[1][0] - dU[0][1];
+        acc[0] += v;
+        acc[1] += rho * v;
+        acc[2] += k * v;
+        acc[3] += mu * (w0 * w0 + w1 * w1 + w2 * w2) * v;
+        acc[4] += re * v;
+        acc[5] = fmin(acc[5], rho);
+        acc[6] = fmin(acc[6], p);
+    }
+#pragma unroll
+    for (int i = 0; i < kDiagVals; ++i) red[i][threadIdx.x] = acc[i];
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) {
+#pragma unroll
+            for (int i = 0; i < 5; ++i) red[i][threadIdx.x] += red[i][threadIdx.x + h];
+#pragma unroll
+            for (int i = 5; i < kDiagVals; ++i) red[i][threadIdx.x] = fmin(red[i][threadIdx.x], red[i][threadIdx.x + h]);
+        }
+        __syncthreads();
+    }
+    if ((int)threadIdx.x < kDiagVals) part[(long)blockIdx.x * kDiagVals + threadIdx.x] = red[threadIdx.x][0];
+}
+
+__global__ void __launch_bounds__(256) k_diag_final(const double *__restrict__ part, int n, double *__restrict__ out) {
+    __shared__ double red[kDiagVals][256];
+    double acc[kDiagVals] = {0.0, 0.0, 0.0, 0.0, 0.0, INFINITY, INFINITY};
+    for (int b = threadIdx.x; b < n; b += blockDim.x) {
+#pragma unroll
+        for (int i = 0; i < 5; ++i) acc[i] += part[(long)b * kDiagVals + i];
+#pragma unroll
+        for (int i = 5; i < kDiagVals; ++i) acc[i] = fmin(acc[i], part[(long)b * kDiagVals + i]);
+    }
+#pragma unroll
+    for (int i = 0; i < kDiagVals; ++i) red[i][threadIdx.x] = acc[i];
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) {
+#pragma unroll
+            for (int i = 0; i < 5; ++i) red[i][threadIdx.x] += red[i][threadIdx.x + h];
+#pragma unroll
+            for (int i = 5; i < kDiagVals; ++i) red[i][threadIdx.x] = fmin(red[i][threadIdx.x], red[i][threadIdx.x + h]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double V = red[0][0], m = red[1][0];
+        out[0] = red[2][0] / m;  // E_k = int rho U.U / 2 / (rho0 |Omega|), rho0 = m / V
+        out[1] = red[3][0] / m;  // eps_S = int mu |curl U|^2 / (rho0 |Omega|)
+        out[2] = m / V;
+        out[3] = red[4][0] / V;
+        out[4] = red[5][0];
+        out[5] = red[6][0];
+    }
+}
+
+// ------------------------------------------------------------------------------------------
 // reconstruction + GENO blend: one thread per (cell, conserved variable)
 // ------------------------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) k_recon(BlockView b, long Ntot, const double *__restrict__ Q,
@@ -581,6 +667,13 @@ hipError_t launch_metrics(const BlockView &b, const double *nodes, const Metrics
 hipError_t launch_dt(long off, long N, long Ntot, const double *Q, const double *dtm, const DevParams &P,
                      double *part, int nparts, int *flag, hipStream_t s) {
     hipLaunchKernelGGL(k_dt_partial, dim3(nparts), dim3(256), 0, s, off, N, Ntot, Q, dtm, P, part, flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_diagnostics(long Ntot, const double *Q, const double *G, const double *vol, const DevParams &P,
+                              double *part, int nparts, double *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_diag_partial, dim3(nparts), dim3(256), 0, s, Ntot, Q, G, vol, P, part);
+    hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(256), 0, s, part, nparts, out);
     return hipGetLastError();
 }
 

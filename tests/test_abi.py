@@ -67,6 +67,7 @@ def test_host_side_argument_errors():
     assert L.cgks_set_launch(None, 1, C.byref(cfg)) == K.EINVAL
     assert L.cgks_autotune(None, None, None, None, None, 1, None, 0, None) == K.EINVAL
     assert L.cgks_step_graph(None, None, None, None, None, 1, None) == K.EINVAL
+    assert L.cgks_diagnostics(None, None, None, None, None) == K.EINVAL
 
 
 def test_default_params_are_the_papers_constants():

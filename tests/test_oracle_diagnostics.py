@@ -1,0 +1,83 @@
+"""Pins of the oracle's flow diagnostics (Taylor-Green section, Sec. 5): kinetic energy
+E_k = (1/(rho0 |Omega|)) int rho U.U / 2 dV and enstrophy eps_S = (1/(rho0 |Omega|)) int mu
+|curl U|^2 dV, midpoint rule over cells with the cell-averaged gradients.
+
+Closed forms of the Taylor-Green initial field (U0 = L = rho0 = 1, any Mach number):
+  * <(u^2 + v^2)/2> = 1/8, and the density factor 1 + g Ma^2/16 (cos 2x + cos 2y)(cos 2z + 2)
+    adds (cos 2x + cos 2y)(1 - cos 2x cos 2y) / 2 times a z factor, whose mean vanishes, so
+    E_k(0) = 1/8 exactly;
+  * curl U = (-cos x sin y sin z, -sin x cos y sin z, 2 sin x sin y cos z), |curl U|^2 has mean
+    1/8 + 1/8 + 4/8 = 3/4, and T = p / rho = p0 / rho0 is uniform, so mu = mu(T_ref) and
+    eps_S(0) = 3 mu0 / 4.
+The midpoint rule on cell averages converges to both at second order.  At Ma 1.25 the density
+varies by 82 %, so a velocity gradient taken as grad(rho U) / rho (dropping U grad rho) would
+converge to a different enstrophy."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2508_08965_amd import workloads as W
+
+GAM = 1.4
+
+
+def tgv_diag(n, Ma):
+    dims = (n, n, n)
+    nodes = W.cartesian_nodes(dims, hi=(2 * math.pi,) * 3)
+    Q, G, L = W.initial_state(nodes, W.taylor_green(Ma=Ma), GAM)
+    p0 = 1.0 / (GAM * Ma * Ma)
+    prm = O.params(viscous=1, visc_law=1, mu0=1.0 / 1600, T_ref=p0, S_suth=p0 * 110.4 / 288.15, Pr=0.7)
+    return O.diagnostics(dims, nodes.numpy(), prm, Q.numpy(), G.numpy())
+
+
+@pytest.mark.parametrize("Ma", [0.1, 1.25])
+def test_tgv_initial_kinetic_energy_and_enstrophy_converge_at_second_order(Ma):
+    mu0 = 1.0 / 1600
+    d = {n: tgv_diag(n, Ma) for n in (12, 24, 48)}
+    ek = [abs(d[n]["Ek"] - 0.125) for n in (12, 24, 48)]
+    es = [abs(d[n]["epsS"] - 0.75 * mu0) / mu0 for n in (12, 24, 48)]
+    for e in (ek, es):
+        assert e[1] / e[2] > 3.5 and e[0] / e[1] > 3.3, e  # second order
+    assert ek[2] < 1e-3 and es[2] < 5e-3  # (midpoint error C h^2: 5.3e-4 and 3.2e-3 at 48^3)
+    # mean density and total energy are the field's means: rho0 = 1, rho E = p0 / (g - 1) + 1/8
+    p0 = 1.0 / (GAM * Ma * Ma)
+    assert d[48]["rho_mean"] == pytest.approx(1.0, abs=1e-10)  # 4^3 Gauss cell averages of the cosines
+    assert d[48]["rhoE_mean"] == pytest.approx(p0 / (GAM - 1) + 0.125, rel=1e-6)
+    # minimum of the density factor: 1 - 6 g Ma^2 / 16 (attained at cell centres to O(h^2))
+    assert d[48]["rho_min"] == pytest.approx(1 - 6 * GAM * Ma * Ma / 16, abs=0.02 * GAM * Ma * Ma)
+
+
+def test_uniform_flow_diagnostics_are_exact():
+    dims = (6, 5, 4)
+    nodes = W.perturbed_nodes(dims, amp=0.05)
+    rho, u, v, w, p = 1.3, 0.4, -0.2, 0.7, 2.5
+    Q, G, L = W.initial_state(nodes, W.uniform(rho, u, v, w, p), GAM)
+    d = O.diagnostics(dims, nodes.numpy(), O.params(viscous=1, mu0=1e-3, Pr=0.72), Q.numpy(), np.zeros_like(G.numpy()))
+    assert d["Ek"] == pytest.approx(0.5 * (u * u + v * v + w * w), rel=1e-14)
+    assert d["epsS"] == 0.0
+    assert d["rho_mean"] == pytest.approx(rho, rel=1e-14)
+    assert d["rho_min"] == pytest.approx(rho, rel=1e-14)
+    assert d["p_min"] == pytest.approx(p, rel=1e-12)
+
+
+def test_enstrophy_of_a_shear_layer_with_density_variation():
+    """u = sin(y) with rho = 2 + cos(y) (same p): curl U = (0, 0, -cos y), so int mu |curl U|^2
+    dV / |Omega| = mu <cos^2 y> = mu / 2 whatever the density, and with rho0 = <rho> = 2 the
+    exact eps_S is mu / 4; the momentum gradient alone, d(rho u)/dy / rho = cos y - sin^2 y /
+    (2 + cos y), would converge elsewhere."""
+    mu0 = 1e-3
+    errs = []
+    for n in (16, 32, 64):
+        dims = (4, n, 4)
+        nodes = W.cartesian_nodes(dims, hi=(2 * math.pi,) * 3)
+
+        def f(x, y, z):
+            import torch
+            return 2 + torch.cos(y), torch.sin(y), torch.zeros_like(x), torch.zeros_like(x), torch.ones_like(x)
+        Q, G, L = W.initial_state(nodes, f, GAM)
+        d = O.diagnostics(dims, nodes.numpy(), O.params(viscous=1, mu0=mu0, Pr=0.72), Q.numpy(), G.numpy())
+        errs.append(abs(d["epsS"] / mu0 - 0.25))
+    assert errs[0] / errs[1] > 3.5 and errs[1] / errs[2] > 3.5, errs
+    assert errs[2] < 1e-3
