@@ -244,7 +244,9 @@ __host__ __device__ inline void time_integrals(T Tw, T tau, T e, bool tau_zero, 
 // shifted by sd.  Outputs of lane sd: its one-sided interface value and time derivative
 // (Qs, dQs); the odd lane also returns F^n and F_t^n (Fo, Fto) in the global frame.
 // Returns a non-zero mask (1 rho <= 0, 2 p <= 0, 4 non-finite) for non-physical input.
-template <class X, class T>
+// FULL = false: only the time derivatives (Fto, dQs) are produced (the second stage's update
+// reads nothing else); Fo and Qs are left unset and the work that feeds only them is dropped.
+template <class X, class T, bool FULL = true>
 __host__ __device__ inline int gks_flux_pair(const DevParams &P, const int sd, const T q[5], const T g[5][3],
                                              const T n[3], const T dt, T Fo[5], T Fto[5], T Qs[5], T dQs[5]) {
     const T gam = T(P.gamma), K = T(P.K);
@@ -402,7 +404,7 @@ __host__ __device__ inline int gks_flux_pair(const DevParams &P, const int sd, c
     T cn[6], ct[6];
 #pragma unroll
     for (int i = 0; i < 6; ++i) {
-        cn[i] = (T(4.0) * C2[i] - C1[i]) * idt;
+        if constexpr (FULL) cn[i] = (T(4.0) * C2[i] - C1[i]) * idt;
         ct[i] = T(4.0) * (C1[i] - T(2.0) * C2[i]) * idt * idt;
     }
     // even lane: interface state W^n, W_t^n;  odd lane: flux F^n, F_t^n (face frame)
@@ -412,26 +414,30 @@ __host__ __device__ inline int gks_flux_pair(const DevParams &P, const int sd, c
         const T h0 = sd ? Xs[4][v] : Xs[0][v];
         const T h1 = sd ? Xs[5][v] : Xs[7][v];
         const T h2 = sd ? Xs[6][v] : Xs[8][v];
-        Yn[v] = r0 * (cn[0] * e0v[v] + cn[1] * e1[v] + cn[2] * e2[v]) + cn[3] * h0 - cn[4] * h1 - cn[5] * h2;
+        if constexpr (FULL)
+            Yn[v] = r0 * (cn[0] * e0v[v] + cn[1] * e1[v] + cn[2] * e2[v]) + cn[3] * h0 - cn[4] * h1 - cn[5] * h2;
         Yt[v] = r0 * (ct[0] * e0v[v] + ct[1] * e1[v] + ct[2] * e2[v]) + ct[3] * h0 - ct[4] * h1 - ct[5] * h2;
     }
     T Wn[5], Wt[5];
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
-        const T on = X::swap(Yn[v]), ot = X::swap(Yt[v]);
-        Wn[v] = sd ? on : Yn[v];
+        if constexpr (FULL) {
+            const T on = X::swap(Yn[v]);
+            Wn[v] = sd ? on : Yn[v];
+        }
+        const T ot = X::swap(Yt[v]);
         Wt[v] = sd ? ot : Yt[v];
     }
     if (P.viscous && P.prandtl_fix && !P.tau_zero) {
         // heat flux relative to the interface velocity, corrected to Pr (odd lane holds F)
         const T uu = U0 * U0 + V0 * V0 + Z0 * Z0, kf = T(1.0 / P.Pr - 1.0);
-        const T qn = Yn[4] - (U0 * Yn[1] + V0 * Yn[2] + Z0 * Yn[3]) + T(0.5) * uu * Yn[0] - U0 * Wn[4] +
-                     U0 * (U0 * Wn[1] + V0 * Wn[2] + Z0 * Wn[3]) - T(0.5) * U0 * uu * Wn[0];
         const T qt = Yt[4] - (U0 * Yt[1] + V0 * Yt[2] + Z0 * Yt[3]) + T(0.5) * uu * Yt[0] - U0 * Wt[4] +
                      U0 * (U0 * Wt[1] + V0 * Wt[2] + Z0 * Wt[3]) - T(0.5) * U0 * uu * Wt[0];
-        if (sd) {
-            Yn[4] += kf * qn;
-            Yt[4] += kf * qt;
+        if (sd) Yt[4] += kf * qt;
+        if constexpr (FULL) {
+            const T qn = Yn[4] - (U0 * Yn[1] + V0 * Yn[2] + Z0 * Yn[3]) + T(0.5) * uu * Yn[0] - U0 * Wn[4] +
+                         U0 * (U0 * Wn[1] + V0 * Wn[2] + Z0 * Wn[3]) - T(0.5) * U0 * uu * Wn[0];
+            if (sd) Yn[4] += kf * qn;
         }
     }
     // one-sided interface values (tau0 = tau)
@@ -439,25 +445,31 @@ __host__ __device__ inline int gks_flux_pair(const DevParams &P, const int sd, c
     T Sq[5], St[5];
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
-        Sq[v] = oe * Wn[v] + e0 * Wk[v];
+        if constexpr (FULL) Sq[v] = oe * Wn[v] + e0 * Wk[v];
         St[v] = oe * Wt[v] + e0 * dWk[v];
     }
     // back to the global frame
-    Qs[0] = Sq[0]; Qs[4] = Sq[4];
     dQs[0] = St[0]; dQs[4] = St[4];
-    Fo[0] = Yn[0]; Fo[4] = Yn[4];
     Fto[0] = Yt[0]; Fto[4] = Yt[4];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        Qs[1 + c] = n[c] * Sq[1] + t1[c] * Sq[2] + t2[c] * Sq[3];
         dQs[1 + c] = n[c] * St[1] + t1[c] * St[2] + t2[c] * St[3];
-        Fo[1 + c] = n[c] * Yn[1] + t1[c] * Yn[2] + t2[c] * Yn[3];
         Fto[1 + c] = n[c] * Yt[1] + t1[c] * Yt[2] + t2[c] * Yt[3];
     }
     bool finite = true;
 #pragma unroll
-    for (int v = 0; v < 5; ++v)
-        finite = finite && X::finite(Fo[v]) && X::finite(Fto[v]) && X::finite(Qs[v]) && X::finite(dQs[v]);
+    for (int v = 0; v < 5; ++v) finite = finite && X::finite(Fto[v]) && X::finite(dQs[v]);
+    if constexpr (FULL) {
+        Qs[0] = Sq[0]; Qs[4] = Sq[4];
+        Fo[0] = Yn[0]; Fo[4] = Yn[4];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            Qs[1 + c] = n[c] * Sq[1] + t1[c] * Sq[2] + t2[c] * Sq[3];
+            Fo[1 + c] = n[c] * Yn[1] + t1[c] * Yn[2] + t2[c] * Yn[3];
+        }
+#pragma unroll
+        for (int v = 0; v < 5; ++v) finite = finite && X::finite(Fo[v]) && X::finite(Qs[v]);
+    }
     if (!finite) err |= 4;
     return err;
 }

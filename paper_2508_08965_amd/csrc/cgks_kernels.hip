@@ -489,10 +489,10 @@ __global__ void __launch_bounds__(256) k_gp_export(BlockView b, long Ntot, const
 // ------------------------------------------------------------------------------------------
 // Two lanes per Gauss point.  A unit is (tile, owned-face Gauss point qk = 4q + kk); thread t of
 // the workgroup serves cell t / 2 of the tile (the face record of its plus face), side t & 1.
-template <class TC, class TG, class TF>
+template <class TC, class TG, class TF, bool FULL>
 __global__ void __launch_bounds__(256, 2) k_flux(WorkList W, long Ntot, const TG *__restrict__ gp, Metrics M,
                                               const double *__restrict__ dtp, DevParams P,
-                                              TF *__restrict__ fo, int *__restrict__ flag, int full) {
+                                              TF *__restrict__ fo, int *__restrict__ flag) {
     const long u = unit_once((long)W.ntiles * 12, W.xcd);
     if (u < 0) return;
     const Tile tile = W.tiles[u / 12];
@@ -511,16 +511,16 @@ __global__ void __launch_bounds__(256, 2) k_flux(WorkList W, long Ntot, const TG
 #pragma unroll
     for (int r = 0; r < 3; ++r) n[r] = (TC)M.fn[((q * 4 + kk) * 3 + r) * Ntot + f];
     TC F[5], Ft[5], Qs[5], dQs[5];
-    const int bad = gks_flux_pair<DevMath, TC>(P, sd, qv, gv, n, (TC)*dtp, F, Ft, Qs, dQs);
+    const int bad = gks_flux_pair<DevMath, TC, FULL>(P, sd, qv, gv, n, (TC)*dtp, F, Ft, Qs, dQs);
     if (bad && sd == 0) atomicOr(flag, bad);
     TF *dst = fo + (long)((q * 4 + kk) * 30) * Ntot + f;
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
         // the second stage's update reads only the time derivatives F_t and dQ/dt
-        if (full) dst[(10 + 10 * sd + v) * Ntot] = (TF)Qs[v];
+        if constexpr (FULL) dst[(10 + 10 * sd + v) * Ntot] = (TF)Qs[v];
         dst[(15 + 10 * sd + v) * Ntot] = (TF)dQs[v];
         if (sd) {
-            if (full) dst[v * Ntot] = (TF)F[v];
+            if constexpr (FULL) dst[v * Ntot] = (TF)F[v];
             dst[(5 + v) * Ntot] = (TF)Ft[v];
         }
     }
@@ -707,15 +707,22 @@ hipError_t launch_flux(int flux_prec, bool gp32, const WorkList &W, long Ntot, c
     if (W.ntiles <= 0) return hipSuccess;
     const long units = (long)W.ntiles * 12;
     const dim3 grid((unsigned)(W.xcd ? 8 * ((units + 7) / 8) : units));
+#define CGKS_FLUX(TC, TG, TF)                                                                              \
+    do {                                                                                                   \
+        if (full)                                                                                          \
+            hipLaunchKernelGGL((k_flux<TC, TG, TF, true>), grid, dim3(2 * kFluxTile), 0, s, W, Ntot,       \
+                               (const TG *)gp, M, dt, P, (TF *)fo, flag);                                  \
+        else                                                                                               \
+            hipLaunchKernelGGL((k_flux<TC, TG, TF, false>), grid, dim3(2 * kFluxTile), 0, s, W, Ntot,      \
+                               (const TG *)gp, M, dt, P, (TF *)fo, flag);                                  \
+    } while (0)
     if (flux_prec == 0 && !gp32)
-        hipLaunchKernelGGL((k_flux<double, double, double>), grid, dim3(2 * kFluxTile), 0, s, W, Ntot,
-                           (const double *)gp, M, dt, P, (double *)fo, flag, (int)full);
+        CGKS_FLUX(double, double, double);
     else if (flux_prec == 0)
-        hipLaunchKernelGGL((k_flux<double, float, double>), grid, dim3(2 * kFluxTile), 0, s, W, Ntot,
-                           (const float *)gp, M, dt, P, (double *)fo, flag, (int)full);
+        CGKS_FLUX(double, float, double);
     else
-        hipLaunchKernelGGL((k_flux<float, float, float>), grid, dim3(2 * kFluxTile), 0, s, W, Ntot,
-                           (const float *)gp, M, dt, P, (float *)fo, flag, (int)full);
+        CGKS_FLUX(float, float, float);
+#undef CGKS_FLUX
     return hipGetLastError();
 }
 

@@ -217,3 +217,30 @@ def test_reduced_precision_batched_equals_per_block_and_bricks(recon_prec, flux_
     for x, y, z in zip(a[1:4], b[1:4], c[1:4]):
         assert torch.equal(x, y) and torch.equal(x, z)
     assert rel(a[1].numpy(), ref[1].numpy()) <= 1e-5
+
+
+def test_degenerate_blocks_one_cell_thick_parity_with_oracle():
+    """Blocks one cell thick along x, y or z (periodic: the cell is its own neighbour there), in
+    one multi-block mesh: each block follows the oracle."""
+    dims = [(1, 9, 6), (13, 1, 4), (5, 6, 1)]
+    nodes, states = [], []
+    for b, n in enumerate(dims):
+        nd = W.perturbed_nodes(n, amp=0.0)  # Cartesian: a one-cell axis keeps a flat metric
+        nodes.append(nd)
+        states.append(W.initial_state(nd, W.isotropic_turbulence(16, k0=4.0, Mt=0.3, seed=9000 + b), GAM))
+    kw = hit_kw()
+    ctx = K().Context(dims, nodes, K().default_params(**kw))
+    Q, G, L = (t.to(dev()) for t in concat(states))
+    dt = torch.full((1,), 1e-3, dtype=torch.float64, device=dev())
+    K().cgks_step(ctx, Q, G, L, dt, use_cfl=False)
+    torch.cuda.synchronize()
+    assert K().cgks_check(ctx) == (0, 0)
+    ctx.close()
+    off = 0
+    for n, nd, s in zip(dims, nodes, states):
+        N = n[0] * n[1] * n[2]
+        so, Qo, Go, Lo, _, _ = O.run(n, nd.numpy(), O.params(**kw), s[0].numpy(), s[1].numpy(), s[2].numpy(), 1,
+                                     dt=1e-3)
+        assert so == 0
+        assert rel(Q[:, off:off + N].cpu().numpy(), Qo) <= TOL, n
+        off += N

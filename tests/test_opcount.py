@@ -19,3 +19,4 @@ def test_flux_flops_per_gauss_point_matches_bench(tmp_path):
     out = subprocess.run([exe, "1", "1", "1", "0"], capture_output=True, text=True, check=True).stdout.split()
     import bench
     assert int(out[0]) == bench.FLUX_FLOP_PER_GP
+    assert int(out[7]) == bench.FLUX_FLOP_PER_GP_DERIV  # second stage: time derivatives only
