@@ -48,7 +48,7 @@ struct cgks_ctx {
     double *fo = nullptr;     // [3][4][30][Ntot]
     double *stash = nullptr;  // [80][Ntot]
     double *Kmf = nullptr;    // constant blocks of the matrix-core reconstruction
-    double *pcm = nullptr;    // per-cell matrices (recon_impl 2), tiled by 12 cells
+    double *pcm = nullptr;    // per-cell matrices (recon_impl 2), tiled by 64 cells
     double *dt_part = nullptr;
     double *diag_part = nullptr;  // [nparts][7] partial sums of the flow diagnostics
     int nparts = 1;
@@ -370,7 +370,7 @@ int cgks_ctx_create(cgks_ctx **out, int nblocks, const int *dims, const double *
               alloc((void **)&c->mlp_packed, kMlpPackBytes) &&
               (p->recon_impl != 2 ||
                alloc((void **)&c->pcm, sizeof(double) * kPcElems *
-                                           ((Ntot + kPcCellsPerWave - 1) / kPcCellsPerWave * kPcCellsPerWave)));
+                                           ((Ntot + kPcTile - 1) / kPcTile * kPcTile)));
     if (!ok) {
         cgks_ctx_destroy(c);
         return fail(CGKS_ENOMEM, "device allocation failed");

@@ -485,10 +485,10 @@ hipError_t launch_diagnostics(long Ntot, const double *Q, const double *G, const
 hipError_t launch_recon(const BlockView &b, long Ntot, const double *Q, const double *G, const double *L,
                         const Metrics &M, const DevConsts *K, const DevParams &P, double *gp, hipStream_t s);
 // Per-cell stored matrices (cgks_percell.hip): Rc (34 x 84) and Ec (96 x 34) per cell, tiled by
-// the 12 cells of a wave; the buffer holds kPcElems doubles per cell, for ceil(N / 12) * 12 cells.
+// the 64 cells of a wave; the buffer holds kPcElems doubles per cell, for ceil(N / 64) * 64 cells.
 constexpr int kPcCols = 84;                                 // raw stencil items per variable
 constexpr long kPcElems = (long)kNB * kPcCols + 96L * kNB;  // 6120 doubles per cell
-constexpr int kPcCellsPerWave = 12;                         // 12 cells x 5 variables per wave
+constexpr int kPcTile = 64;                                 // cells per storage tile (one wave)
 hipError_t launch_percell_setup(const BlockView &b, long Ntot, const Metrics &M, const DevConsts *K, double *pcm,
                                 hipStream_t s);
 hipError_t launch_recon_percell(const BlockView &b, long Ntot, const double *Q, const double *G, const double *L,

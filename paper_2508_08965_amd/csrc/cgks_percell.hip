@@ -10,16 +10,17 @@
 //                  the gradients, tau . J0^T for the edge directional derivatives)
 //   Ec  (96 x 34)  value and physical gradient at the 24 face Gauss points: the value rows of
 //                  E and the gradient rows of E back-transformed with the cell's (J0^T)^-1
-// that is 6120 doubles (48,960 bytes) per cell.  Storage is tiled by the 12 cells a wave takes:
-// tile t = cell / 12 holds element e of its cells at ((t * 6120 + e) * 12 + cell % 12), with Rc
+// that is 6120 doubles (48,960 bytes) per cell.  Storage is tiled by the 64 cells a wave takes:
+// tile t = cell / 64 holds element e of its cells at ((t * 6120 + e) * 64 + cell % 64), with Rc
 // column-major (e = 34 j + i) and Ec after it (e = 2856 + 34 (4 g + r) + i), so that one load of
-// a wave reads 96 consecutive bytes at a constant offset from the lane's tile base.  The
+// a wave reads 512 consecutive bytes at a constant offset from the lane's tile base.  The
 // smoothness indicators keep the shared Gram
 // matrices (they act on the standard-cell coefficients) and the blend is the one of the other
 // reconstruction kernels, so all three produce the same Gauss-point values up to rounding.
 //
-// One lane per (cell, conserved variable); a wave holds 12 cells x 5 variables (lanes 60..63
-// idle), so the five lanes of a cell read each matrix element with one request.
+// One lane per (cell, conserved variable): a workgroup is one wave, 64 cells of one variable.
+// The five workgroups of a tile (one per variable) get numbers 8 apart, which places them on the
+// same XCD, so that the four after the first find the tile's matrices in that XCD's L2.
 #include <hip/hip_runtime.h>
 
 #include "cgks_device.h"
@@ -59,8 +60,8 @@ __global__ void __launch_bounds__(256) k_percell_setup(BlockView b, long Ntot, M
             J0[r][q] = M.J0[(3 * r + q) * Ntot + c];
             JiT[r][q] = M.JiT[(3 * r + q) * Ntot + c];
         }
-    double *t = pcm + (c / kPcCellsPerWave) * kPcElems * kPcCellsPerWave + c % kPcCellsPerWave;
-    auto rc = [&](int i, int j) -> double & { return t[(long)(j * kNB + i) * kPcCellsPerWave]; };
+    double *t = pcm + (c / kPcTile) * kPcElems * kPcTile + c % kPcTile;
+    auto rc = [&](int i, int j) -> double & { return t[(long)(j * kNB + i) * kPcTile]; };
     const double is2 = 0.70710678118654752440;
 #pragma unroll 1
     for (int i = 0; i < kNB; ++i) {
@@ -82,18 +83,18 @@ __global__ void __launch_bounds__(256) k_percell_setup(BlockView b, long Ntot, M
         }
         for (int s = 0; s < 12; ++s) rc(i, 72 + s) = Ri[kRowLine + s];
     }
-    double *ec = t + (long)kNB * kPcCols * kPcCellsPerWave;
+    double *ec = t + (long)kNB * kPcCols * kPcTile;
 #pragma unroll 1
     for (int g = 0; g < kNGP; ++g)
         for (int i = 0; i < kNB; ++i) {
-            ec[(long)((g * 4) * kNB + i) * kPcCellsPerWave] = K->E[g][0][i];
+            ec[(long)((g * 4) * kNB + i) * kPcTile] = K->E[g][0][i];
             for (int r = 0; r < 3; ++r)
-                ec[(long)((g * 4 + 1 + r) * kNB + i) * kPcCellsPerWave] =
+                ec[(long)((g * 4 + 1 + r) * kNB + i) * kPcTile] =
                     JiT[r][0] * K->E[g][1][i] + JiT[r][1] * K->E[g][2][i] + JiT[r][2] * K->E[g][3][i];
         }
 }
 
-__global__ void __launch_bounds__(256) k_recon_percell(BlockView b, long Ntot, const double *__restrict__ Q,
+__global__ void __launch_bounds__(64) k_recon_percell(BlockView b, long Ntot, const double *__restrict__ Q,
                                                        const double *__restrict__ G, const double *__restrict__ L,
                                                        Metrics M, const DevConsts *__restrict__ K, DevParams P,
                                                        const double *__restrict__ pcm, double *__restrict__ gp) {
@@ -104,11 +105,11 @@ __global__ void __launch_bounds__(256) k_recon_percell(BlockView b, long Ntot, c
         sGT[i] = (&K->GT[0][0])[i];
     }
     __syncthreads();
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    if (lane >= 5 * kPcCellsPerWave) return;
-    const long cl = (long)blockIdx.x * (kPcCellsPerWave * 4) + wave * kPcCellsPerWave + lane / 5;
+    // workgroup w -> (tile, variable): w = ((tile / 8) * 5 + v) * 8 + tile % 8
+    const int w = blockIdx.x, v = (w >> 3) % 5;
+    const long tile_b = (long)((w >> 3) / 5) * 8 + (w & 7);
+    const long cl = tile_b * kPcTile + threadIdx.x;
     if (cl >= b.N) return;
-    const int v = lane % 5;
     const int ci = (int)(cl % b.nx), cj = (int)((cl / b.nx) % b.ny), ck = (int)(cl / ((long)b.nx * b.ny));
     const long c = b.off + cl;
     const double *Qv = Q + v * Ntot;
@@ -120,11 +121,11 @@ __global__ void __launch_bounds__(256) k_recon_percell(BlockView b, long Ntot, c
     double a[kNB];
 #pragma unroll
     for (int i = 0; i < kNB; ++i) a[i] = 0.0;
-    const double *tile = pcm + (c / kPcCellsPerWave) * kPcElems * kPcCellsPerWave + c % kPcCellsPerWave;
+    const double *tile = pcm + (c / kPcTile) * kPcElems * kPcTile + c % kPcTile;
     auto column = [&](int j, double x) {
-        const double *col = tile + j * kNB * kPcCellsPerWave;
+        const double *col = tile + j * kNB * kPcTile;
 #pragma unroll
-        for (int i = 0; i < kNB; ++i) a[i] = fma(col[i * kPcCellsPerWave], x, a[i]);
+        for (int i = 0; i < kNB; ++i) a[i] = fma(col[i * kPcTile], x, a[i]);
     };
     double fd[6];
 #pragma unroll
@@ -215,12 +216,12 @@ __global__ void __launch_bounds__(256) k_recon_percell(BlockView b, long Ntot, c
     const double om = 1.0 - chi;
 #pragma unroll 1
     for (int g = 0; g < kNGP; ++g) {
-        const double *eg = tile + (long)(kNB * kPcCols + g * 4 * kNB) * kPcCellsPerWave;
+        const double *eg = tile + (long)(kNB * kPcCols + g * 4 * kNB) * kPcTile;
         double p[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
 #pragma unroll
-            for (int i = 0; i < kNB; ++i) p[r] = fma(eg[(r * kNB + i) * kPcCellsPerWave], a[i], p[r]);
+            for (int i = 0; i < kNB; ++i) p[r] = fma(eg[(r * kNB + i) * kPcTile], a[i], p[r]);
         }
         const double *xg = K->xg[g];
         const double low = bbar[0] * xg[0] + bbar[1] * xg[1] + bbar[2] * xg[2];
@@ -253,9 +254,9 @@ hipError_t launch_percell_setup(const BlockView &b, long Ntot, const Metrics &M,
 hipError_t launch_recon_percell(const BlockView &b, long Ntot, const double *Q, const double *G, const double *L,
                                 const Metrics &M, const DevConsts *K, const DevParams &P, const double *pcm,
                                 double *gp, hipStream_t s) {
-    const long per_block = 4L * kPcCellsPerWave;
-    const dim3 grid((unsigned)((b.N + per_block - 1) / per_block));
-    hipLaunchKernelGGL(k_recon_percell, grid, dim3(256), 0, s, b, Ntot, Q, G, L, M, K, P, pcm, gp);
+    const long tiles = (b.N + kPcTile - 1) / kPcTile;
+    const dim3 grid((unsigned)(((tiles + 7) / 8) * 8 * 5));  // tiles padded to a multiple of 8, x 5 variables
+    hipLaunchKernelGGL(k_recon_percell, grid, dim3(kPcTile), 0, s, b, Ntot, Q, G, L, M, K, P, pcm, gp);
     return hipGetLastError();
 }
 
