@@ -123,7 +123,8 @@ def kernel_table(prof, N, fp64=True):
         elif k == "flux":
             w = FLUX_FLOP_PER_GP_MEAN * 12 * N
             out[k] = {"avg_ms": avg, "bound": "alu", "tflops": w / avg / 1e9, "frac": w / avg / 1e9 / PEAK["fp64"],
-                      "algorithmic_gbps": 584 * 12 * N / avg / 1e6}
+                      # bytes per Gauss point: 344 in; 240 out in stage 1, 120 in stage 2
+                      "algorithmic_gbps": (584 + 464) / 2 * 12 * N / avg / 1e6}
         elif k == "update":
             b = (4592 + 3112) / 2 * N
             out[k] = {"avg_ms": avg, "bound": "hbm", "algorithmic_gbps": b / avg / 1e6, "frac": b / avg / 1e9 / hbm}
