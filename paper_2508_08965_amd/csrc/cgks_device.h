@@ -422,22 +422,28 @@ __host__ __device__ inline int gks_flux_pair(const DevParams &P, const int sd, c
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
         if constexpr (FULL) {
-            const T on = X::swap(Yn[v]);
+            const T on = X::swap(Yn[v]), ot = X::swap(Yt[v]);
             Wn[v] = sd ? on : Yn[v];
+            Wt[v] = sd ? ot : Yt[v];
+        } else {
+            const T ot = X::swap(Yt[v]);
+            Wt[v] = sd ? ot : Yt[v];
         }
-        const T ot = X::swap(Yt[v]);
-        Wt[v] = sd ? ot : Yt[v];
     }
     if (P.viscous && P.prandtl_fix && !P.tau_zero) {
         // heat flux relative to the interface velocity, corrected to Pr (odd lane holds F)
         const T uu = U0 * U0 + V0 * V0 + Z0 * Z0, kf = T(1.0 / P.Pr - 1.0);
         const T qt = Yt[4] - (U0 * Yt[1] + V0 * Yt[2] + Z0 * Yt[3]) + T(0.5) * uu * Yt[0] - U0 * Wt[4] +
                      U0 * (U0 * Wt[1] + V0 * Wt[2] + Z0 * Wt[3]) - T(0.5) * U0 * uu * Wt[0];
-        if (sd) Yt[4] += kf * qt;
         if constexpr (FULL) {
             const T qn = Yn[4] - (U0 * Yn[1] + V0 * Yn[2] + Z0 * Yn[3]) + T(0.5) * uu * Yn[0] - U0 * Wn[4] +
                          U0 * (U0 * Wn[1] + V0 * Wn[2] + Z0 * Wn[3]) - T(0.5) * U0 * uu * Wn[0];
-            if (sd) Yn[4] += kf * qn;
+            if (sd) {
+                Yn[4] += kf * qn;
+                Yt[4] += kf * qt;
+            }
+        } else {
+            if (sd) Yt[4] += kf * qt;
         }
     }
     // one-sided interface values (tau0 = tau)
@@ -449,26 +455,28 @@ __host__ __device__ inline int gks_flux_pair(const DevParams &P, const int sd, c
         St[v] = oe * Wt[v] + e0 * dWk[v];
     }
     // back to the global frame
+    if constexpr (FULL) {
+        Qs[0] = Sq[0]; Qs[4] = Sq[4];
+    }
     dQs[0] = St[0]; dQs[4] = St[4];
+    if constexpr (FULL) {
+        Fo[0] = Yn[0]; Fo[4] = Yn[4];
+    }
     Fto[0] = Yt[0]; Fto[4] = Yt[4];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
+        if constexpr (FULL) Qs[1 + c] = n[c] * Sq[1] + t1[c] * Sq[2] + t2[c] * Sq[3];
         dQs[1 + c] = n[c] * St[1] + t1[c] * St[2] + t2[c] * St[3];
+        if constexpr (FULL) Fo[1 + c] = n[c] * Yn[1] + t1[c] * Yn[2] + t2[c] * Yn[3];
         Fto[1 + c] = n[c] * Yt[1] + t1[c] * Yt[2] + t2[c] * Yt[3];
     }
     bool finite = true;
 #pragma unroll
-    for (int v = 0; v < 5; ++v) finite = finite && X::finite(Fto[v]) && X::finite(dQs[v]);
-    if constexpr (FULL) {
-        Qs[0] = Sq[0]; Qs[4] = Sq[4];
-        Fo[0] = Yn[0]; Fo[4] = Yn[4];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            Qs[1 + c] = n[c] * Sq[1] + t1[c] * Sq[2] + t2[c] * Sq[3];
-            Fo[1 + c] = n[c] * Yn[1] + t1[c] * Yn[2] + t2[c] * Yn[3];
-        }
-#pragma unroll
-        for (int v = 0; v < 5; ++v) finite = finite && X::finite(Fo[v]) && X::finite(Qs[v]);
+    for (int v = 0; v < 5; ++v) {
+        if constexpr (FULL)
+            finite = finite && X::finite(Fo[v]) && X::finite(Fto[v]) && X::finite(Qs[v]) && X::finite(dQs[v]);
+        else
+            finite = finite && X::finite(Fto[v]) && X::finite(dQs[v]);
     }
     if (!finite) err |= 4;
     return err;
