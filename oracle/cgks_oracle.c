@@ -74,6 +74,8 @@ typedef struct {
     int tau_zero;            /* 1: tau = 0, f = g0 (1 + A t) (accuracy test) */
     int linear;              /* 1: chi = 1, linear CGKS-5 */
     int prandtl_fix;         /* 1: heat-flux correction to Pr (viscous only) */
+    int bc[6];               /* sides x-, x+, y-, y+, z-, z+: 0 periodic, 1 symmetry plane
+                                (slip, adiabatic), 2 no-slip adiabatic wall (reading D26) */
 } or_params;
 
 enum { OR_OK = 0, OR_EINVAL = -1, OR_ENONPHYS = -4 };
@@ -312,6 +314,8 @@ typedef struct {
     double *JinvT;    /* N x 9, (J0^T)^-1 row-major */
     double *fn;       /* faces: (3N) x 4 GP x 3 unit normals, face f = 3c+q (plus face of c) */
     double *fw;       /* (3N) x 4 GP: quadrature weight times area element */
+    int bc[6];        /* side types as in or_params */
+    double *bfn, *bfw; /* minus-side wall faces: entry 3c+q for a cell c with index 0 along q */
 } or_mesh;
 
 static const double *node_at(const or_mesh *M, int i, int j, int k) {
@@ -323,6 +327,48 @@ static long cell_id(const or_mesh *M, int i, int j, int k) {
     j %= M->ny; if (j < 0) j += M->ny;
     k %= M->nz; if (k < 0) k += M->nz;
     return (long)i + (long)M->nx * ((long)j + (long)M->ny * k);
+}
+
+/* Neighbour of a cell at index idx (one step beyond the block at most).  Along an axis whose
+   sides are walls an index beyond the block is reflected to its mirror cell inside, and
+   side[q] records the wall side crossed (-1: none); periodic axes wrap (reading D26). */
+static long nb_cell(const or_mesh *M, const int idx[3], int side[3]) {
+    const int n[3] = {M->nx, M->ny, M->nz};
+    int r[3];
+    for (int q = 0; q < 3; ++q) {
+        r[q] = idx[q];
+        side[q] = -1;
+        if (M->bc[2 * q] && r[q] < 0) { r[q] = -1 - r[q]; side[q] = 2 * q; }
+        if (M->bc[2 * q + 1] && r[q] >= n[q]) { r[q] = 2 * n[q] - 1 - r[q]; side[q] = 2 * q + 1; }
+    }
+    return cell_id(M, r[0], r[1], r[2]);
+}
+
+/* Sign of conserved variable v in the mirror image across wall side s: the momentum normal to a
+   symmetry plane, and every momentum component at a no-slip wall, change sign (reading D26). */
+static double mirror_sign(const or_mesh *M, int s, int v) {
+    if (v >= 1 && v <= 3 && (M->bc[s] == 2 || v - 1 == s / 2)) return -1.0;
+    return 1.0;
+}
+
+/* A no-slip adiabatic wall is impermeable and, with the fluid at rest on it, does no work and
+   conducts no heat: the mass and energy components of its flux and of the flux's time
+   derivative are zero (reading D26).  The kinetic flux between the interior side and its
+   mirror image leaves them at the truncation level only, because the mirror image reverses the
+   velocity but not the tangential slopes of density and energy. */
+static void noslip_flux(double F[5], double Ft[5]) {
+    F[0] = F[4] = Ft[0] = Ft[4] = 0.0;
+}
+
+/* Mirror image of a value and physical gradient of every variable across wall side s (a plane
+   normal to axis s/2): q[v] -> sign q[v], grad q[v] -> sign (reflected vector). */
+static void mirror_state(const or_mesh *M, int s, const double q[5], const double g[5][3], double qm[5],
+                         double gm[5][3]) {
+    for (int v = 0; v < 5; ++v) {
+        double sg = mirror_sign(M, s, v);
+        qm[v] = sg * q[v];
+        for (int r = 0; r < 3; ++r) gm[v][r] = (r == s / 2) ? -sg * g[v][r] : sg * g[v][r];
+    }
 }
 
 /* trilinear map of a cell on [-1/2,1/2]^3 and its Jacobian (Appendix) */
@@ -406,9 +452,15 @@ static int cell_geom(const or_mesh *M, int i, int j, int k, double *volp, double
     return !(vol > 0) || !(dt > 0);
 }
 
-static int mesh_build(or_mesh *M, const int dims[3], const double *nodes) {
+static int mesh_build(or_mesh *M, const int dims[3], const double *nodes, const or_params *P) {
     M->nx = dims[0]; M->ny = dims[1]; M->nz = dims[2];
     M->n = 0;
+    M->bfn = M->bfw = NULL;
+    for (int s = 0; s < 6; ++s) M->bc[s] = P ? P->bc[s] : 0;
+    for (int q = 0; q < 3; ++q) {
+        if (M->bc[2 * q] < 0 || M->bc[2 * q] > 2 || M->bc[2 * q + 1] < 0 || M->bc[2 * q + 1] > 2) return OR_EINVAL;
+        if ((M->bc[2 * q] == 0) != (M->bc[2 * q + 1] == 0)) return OR_EINVAL; /* periodic pairs */
+    }
     if (M->nx < 1 || M->ny < 1 || M->nz < 1 || !nodes) return OR_EINVAL;
     M->n = (long)M->nx * M->ny * M->nz;
     M->nodes = nodes;
@@ -426,11 +478,55 @@ static int mesh_build(or_mesh *M, const int dims[3], const double *nodes) {
             for (int g = 0; g < 4; ++g)
                 face_gp_geom(M, i, j, k, q, g, &M->fn[((3 * c + q) * 4 + g) * 3], &M->fw[(3 * c + q) * 4 + g]);
     }
+    int walls = 0;
+    for (int s = 0; s < 6; ++s) walls |= M->bc[s] != 0;
+    if (walls && !bad) {
+        /* minus-side wall faces: the plus face of the mirror cell at index -1; every wall face must
+           lie in a plane normal to its axis (the reflection of the ghost data assumes it) */
+        M->bfn = calloc(3 * M->n * 4 * 3, sizeof(double));
+        M->bfw = calloc(3 * M->n * 4, sizeof(double));
+        const int n[3] = {M->nx, M->ny, M->nz};
+        for (long c = 0; c < M->n; ++c) {
+            int idx[3] = {(int)(c % M->nx), (int)((c / M->nx) % M->ny), (int)(c / ((long)M->nx * M->ny))};
+            for (int q = 0; q < 3; ++q) {
+                if (!M->bc[2 * q]) continue;
+                if (idx[q] == 0) {
+                    int o[3] = {idx[0], idx[1], idx[2]};
+                    o[q] = -1;
+                    for (int g = 0; g < 4; ++g) {
+                        double *nn = &M->bfn[((3 * c + q) * 4 + g) * 3];
+                        face_gp_geom(M, o[0], o[1], o[2], q, g, nn, &M->bfw[(3 * c + q) * 4 + g]);
+                        if (!(nn[q] > 1.0 - 1e-12)) bad = 1;
+                    }
+                }
+                if (idx[q] == n[q] - 1)
+                    for (int g = 0; g < 4; ++g)
+                        if (!(M->fn[((3 * c + q) * 4 + g) * 3 + q] > 1.0 - 1e-12)) bad = 1;
+            }
+        }
+    }
     return bad ? OR_EINVAL : OR_OK;
+}
+
+/* geometry (unit normals, weights) of face m of cell c, whose record is f: its own plus face,
+   the plus face of its minus neighbour, or at a minus-side wall the wall face itself (then the
+   return value is 1) */
+static int face_geom_of(const or_mesh *M, long c, int m, long f, const double **fn, const double **fw) {
+    int q = m / 2;
+    int idx[3] = {(int)(c % M->nx), (int)((c / M->nx) % M->ny), (int)(c / ((long)M->nx * M->ny))};
+    if (m % 2 == 0 && idx[q] == 0 && M->bc[m]) {
+        *fn = &M->bfn[(3 * c + q) * 4 * 3];
+        *fw = &M->bfw[(3 * c + q) * 4];
+        return 1;
+    }
+    *fn = &M->fn[(4 * f) * 3];
+    *fw = &M->fw[4 * f];
+    return 0;
 }
 
 static void mesh_free(or_mesh *M) {
     free(M->vol); free(M->J0); free(M->JinvT); free(M->fn); free(M->fw);
+    free(M->bfn); free(M->bfw);
 }
 
 /* face record of face m of cell c: the plus face of c (s=1) or of its minus neighbour (s=0) */
@@ -456,31 +552,50 @@ static void recon_cell(const or_mesh *M, const or_params *P, const double *Q, co
     const long N = M->n;
     int i = c % M->nx, j = (c / M->nx) % M->ny, k = c / ((long)M->nx * M->ny);
     long fnb[6], enb[12];
+    int fside[6][3], eside[12][3]; /* wall sides crossed by each neighbour (-1: none) */
     double t1[12][3], t2[12][3];
     for (int m = 0; m < 6; ++m) {
         double o[3]; face_offset(m, o);
-        fnb[m] = cell_id(M, i + (int)o[0], j + (int)o[1], k + (int)o[2]);
+        int idx[3] = {i + (int)o[0], j + (int)o[1], k + (int)o[2]};
+        fnb[m] = nb_cell(M, idx, fside[m]);
     }
     for (int n = 0; n < 12; ++n) {
         double o[3]; edge_geom(n, o, t1[n], t2[n]);
-        enb[n] = cell_id(M, i + (int)o[0], j + (int)o[1], k + (int)o[2]);
+        int idx[3] = {i + (int)o[0], j + (int)o[1], k + (int)o[2]};
+        enb[n] = nb_cell(M, idx, eside[n]);
     }
     for (int v = 0; v < NV; ++v) {
+        /* neighbour data, mirrored across the walls it lies behind: the ghost cell's average and
+           gradient are the mirror images of those of its mirror cell (reading D26) */
+        double nq[18], ngr[18][3];
+        for (int t = 0; t < 18; ++t) {
+            const long nb = (t < 6) ? fnb[t] : enb[t - 6];
+            const int *sd = (t < 6) ? fside[t] : eside[t - 6];
+            double sv = 1.0, sr[3] = {1.0, 1.0, 1.0};
+            for (int q = 0; q < 3; ++q)
+                if (sd[q] >= 0) {
+                    double m = mirror_sign(M, sd[q], v);
+                    sv *= m;
+                    for (int r = 0; r < 3; ++r) sr[r] *= (r == q) ? -m : m;
+                }
+            nq[t] = sv * Q[v * N + nb];
+            for (int r = 0; r < 3; ++r) ngr[t][r] = sr[r] * G[(v * 3 + r) * N + nb];
+        }
         double q0 = Q[v * N + c], b[NR], a[NB];
-        for (int m = 0; m < 6; ++m) b[m] = Q[v * N + fnb[m]] - q0;
-        for (int n = 0; n < 12; ++n) b[6 + n] = Q[v * N + enb[n]] - q0;
+        for (int m = 0; m < 6; ++m) b[m] = nq[m] - q0;
+        for (int n = 0; n < 12; ++n) b[6 + n] = nq[6 + n] - q0;
         /* neighbour gradients in the target's reference frame: (grad Q)' = J0^T grad Q */
         for (int m = 0; m < 6; ++m)
             for (int jj = 0; jj < 3; ++jj) {
                 double s = 0;
-                for (int r = 0; r < 3; ++r) s += J[3 * r + jj] * G[(v * 3 + r) * N + fnb[m]];
+                for (int r = 0; r < 3; ++r) s += J[3 * r + jj] * ngr[m][r];
                 b[18 + 3 * m + jj] = s;
             }
         for (int n = 0; n < 12; ++n) {
             double gr[3];
             for (int jj = 0; jj < 3; ++jj) {
                 double s = 0;
-                for (int r = 0; r < 3; ++r) s += J[3 * r + jj] * G[(v * 3 + r) * N + enb[n]];
+                for (int r = 0; r < 3; ++r) s += J[3 * r + jj] * ngr[6 + n][r];
                 gr[jj] = s;
             }
             b[36 + 2 * n] = t1[n][0] * gr[0] + t1[n][1] * gr[1] + t1[n][2] * gr[2];
@@ -826,9 +941,11 @@ static double cell_dt(const or_mesh *M, const or_params *P, const double *Q, lon
         double S[2][3], area[2];
         for (int s = 0; s < 2; ++s) {
             long f = face_of(M, c, 2 * q + s);
+            const double *fnp, *fwp;
+            face_geom_of(M, c, 2 * q + s, f, &fnp, &fwp);
             S[s][0] = S[s][1] = S[s][2] = 0;
             for (int g = 0; g < 4; ++g)
-                for (int r = 0; r < 3; ++r) S[s][r] += M->fw[4 * f + g] * M->fn[(4 * f + g) * 3 + r];
+                for (int r = 0; r < 3; ++r) S[s][r] += fwp[g] * fnp[3 * g + r];
             area[s] = sqrt(S[s][0] * S[s][0] + S[s][1] * S[s][1] + S[s][2] * S[s][2]);
         }
         double nb[3] = {S[0][0] + S[1][0], S[0][1] + S[1][1], S[0][2] + S[1][2]};
@@ -935,6 +1052,10 @@ static int run_stage(const or_mesh *M, const or_params *P, int stage, double dt,
     const long N = M->n;
     double (*rec)[NGP][NV][4] = malloc(sizeof(double) * NGP * NV * 4 * N);
     face_rec *fr = malloc(sizeof(face_rec) * 3 * N);
+    face_rec *frb = NULL; /* minus-side wall faces, at the record index of the face they replace */
+    int walls = 0;
+    for (int s = 0; s < 6; ++s) walls |= M->bc[s] != 0;
+    if (walls) frb = malloc(sizeof(face_rec) * 3 * N);
     int bad = 0;
 #pragma omp parallel for schedule(dynamic, 16)
     for (long c = 0; c < N; ++c) recon_cell(M, P, Q, G, L, c, &M->J0[9 * c], &M->JinvT[9 * c], NULL, NULL, rec[c]);
@@ -944,6 +1065,8 @@ static int run_stage(const or_mesh *M, const or_params *P, int stage, double dt,
         int q = f % 3;
         int i = c % M->nx, j = (c / M->nx) % M->ny, k = c / ((long)M->nx * M->ny);
         int idx[3] = {i, j, k};
+        const int nq = (q == 0) ? M->nx : (q == 1) ? M->ny : M->nz;
+        const int at_wall = M->bc[2 * q + 1] && idx[q] == nq - 1;
         idx[q] += 1;
         long cr = cell_id(M, idx[0], idx[1], idx[2]);
         for (int g = 0; g < 4; ++g) {
@@ -953,8 +1076,23 @@ static int run_stage(const or_mesh *M, const or_params *P, int stage, double dt,
                 ql[v] = rec[c][gpl][v][0]; qr[v] = rec[cr][gpr][v][0];
                 for (int r = 0; r < 3; ++r) { gl[v][r] = rec[c][gpl][v][1 + r]; gr[v][r] = rec[cr][gpr][v][1 + r]; }
             }
+            /* plus-side wall: the right state is the mirror image of the left one */
+            if (at_wall) mirror_state(M, 2 * q + 1, ql, (const double (*)[3])gl, qr, gr);
             if (gks_flux(P, ql, gl, qr, gr, &M->fn[(4 * f + g) * 3], dt, fr[f].F[g], fr[f].Ft[g], fr[f].side[g]))
                 bad = 1;
+            if (at_wall && M->bc[2 * q + 1] == 2) noslip_flux(fr[f].F[g], fr[f].Ft[g]);
+            if (at_wall && M->bc[2 * q]) {
+                /* minus-side wall of cell cr (index 0 on the same line): left state mirrored */
+                for (int v = 0; v < 5; ++v) {
+                    qr[v] = rec[cr][gpr][v][0];
+                    for (int r = 0; r < 3; ++r) gr[v][r] = rec[cr][gpr][v][1 + r];
+                }
+                mirror_state(M, 2 * q, qr, (const double (*)[3])gr, ql, gl);
+                if (gks_flux(P, ql, gl, qr, gr, &M->bfn[((3 * cr + q) * 4 + g) * 3], dt, frb[f].F[g], frb[f].Ft[g],
+                             frb[f].side[g]))
+                    bad = 1;
+                if (M->bc[2 * q] == 2) noslip_flux(frb[f].F[g], frb[f].Ft[g]);
+            }
         }
     }
     if (!bad) {
@@ -964,15 +1102,14 @@ static int run_stage(const or_mesh *M, const or_params *P, int stage, double dt,
             const double *fnp[6], *fwp[6];
             for (int m = 0; m < 6; ++m) {
                 long f = face_of(M, c, m);
-                fs[m] = &fr[f];
-                fnp[m] = &M->fn[(4 * f) * 3];
-                fwp[m] = &M->fw[4 * f];
+                fs[m] = face_geom_of(M, c, m, f, &fnp[m], &fwp[m]) ? &frb[f] : &fr[f];
             }
             cell_update(stage, dt, M->vol[c], fs, fnp, fwp, N, c, Q, G, L, stash, Q, G, L, c);
         }
     }
     free(rec);
     free(fr);
+    free(frb);
     return bad ? OR_ENONPHYS : OR_OK;
 }
 
@@ -1013,7 +1150,7 @@ int oracle_constants(double *R, double *ev, double *eg, double *gh, double *gl, 
 int oracle_metrics(const int dims[3], const double *nodes, double *vol, double *J0, double *JinvT,
                    double *fn, double *fw) {
     or_mesh M;
-    int st = mesh_build(&M, dims, nodes);
+    int st = mesh_build(&M, dims, nodes, NULL);
     if (M.n > 0) {
         if (vol) memcpy(vol, M.vol, sizeof(double) * M.n);
         if (J0) memcpy(J0, M.J0, sizeof(double) * 9 * M.n);
@@ -1030,7 +1167,7 @@ int oracle_recon(const int dims[3], const double *nodes, const or_params *P, con
                  const double *G, const double *L, const long *cells, long ncells, double *out) {
     init_consts();
     or_mesh M;
-    int st = mesh_build(&M, dims, nodes);
+    int st = mesh_build(&M, dims, nodes, P);
     if (st) { if (M.n > 0) mesh_free(&M); return st; }
 #pragma omp parallel for schedule(dynamic, 4)
     for (long t = 0; t < ncells; ++t)
@@ -1057,7 +1194,7 @@ int oracle_flux(const or_params *P, long npts, const double *ql, const double *g
 /* Global CFL time step (minimum over cells); returns status, writes *dt. */
 int oracle_dt(const int dims[3], const double *nodes, const or_params *P, const double *Q, double *dt) {
     or_mesh M;
-    int st = mesh_build(&M, dims, nodes);
+    int st = mesh_build(&M, dims, nodes, P);
     if (st) { if (M.n > 0) mesh_free(&M); return st; }
     double best = INFINITY;
     int bad = 0;
@@ -1079,7 +1216,7 @@ int oracle_stage(const int dims[3], const double *nodes, const or_params *P, int
     set_threads(nthreads);
     init_consts();
     or_mesh M;
-    int st = mesh_build(&M, dims, nodes);
+    int st = mesh_build(&M, dims, nodes, P);
     if (st) { if (M.n > 0) mesh_free(&M); return st; }
     st = run_stage(&M, P, stage, dt, Q, G, L, stash);
     mesh_free(&M);
@@ -1094,7 +1231,7 @@ int oracle_run(const int dims[3], const double *nodes, const or_params *P, doubl
     set_threads(nthreads);
     init_consts();
     or_mesh M;
-    int st = mesh_build(&M, dims, nodes);
+    int st = mesh_build(&M, dims, nodes, P);
     if (st) { if (M.n > 0) mesh_free(&M); return st; }
     double *stash = malloc(sizeof(double) * STASH * M.n);
     double fixed = *dt_inout, t = 0.0, dt = fixed;
@@ -1141,6 +1278,8 @@ int oracle_stage1_cells(const int dims[3], const double *nodes, const or_params 
                         const double *G, const double *L, const long *cells, long ncells, double *outQ,
                         double *outG, double *outL) {
     if (!(dt > 0) || !Q || !G || !L || !cells || ncells < 0) return OR_EINVAL;
+    for (int s = 0; s < 6; ++s)
+        if (P->bc[s]) return OR_EINVAL; /* periodic blocks only */
     init_consts();
     or_mesh M;
     memset(&M, 0, sizeof M);
@@ -1326,16 +1465,18 @@ static double pressure_of(const or_params *P, const double *Q, long N, long c) {
 int oracle_features(const int dims[3], const double *nodes, const or_params *P, const double *Q,
                     const double *L, const long *cells, long ncells, double thresh, double *X, int *jump) {
     or_mesh M;
-    int st = mesh_build(&M, dims, nodes);
+    int st = mesh_build(&M, dims, nodes, P);
     if (st) { if (M.n > 0) mesh_free(&M); return st; }
     const long N = M.n;
     for (long t = 0; t < ncells; ++t) {
         const long c = cells[t];
         int i = c % M.nx, j = (c / M.nx) % M.ny, k = c / ((long)M.nx * M.ny);
         long nb[6];
+        int sd[6][3];
         for (int m = 0; m < 6; ++m) {
             double o[3]; face_offset(m, o);
-            nb[m] = cell_id(&M, i + (int)o[0], j + (int)o[1], k + (int)o[2]);
+            int idx[3] = {i + (int)o[0], j + (int)o[1], k + (int)o[2]};
+            nb[m] = nb_cell(&M, idx, sd[m]);
         }
         const double p0 = pressure_of(P, Q, N, c);
         double ind = 0.0;
@@ -1348,7 +1489,12 @@ int oracle_features(const int dims[3], const double *nodes, const or_params *P, 
         if (X) {
             for (int v = 0; v < NV; ++v) {
                 double f[MLP_IN], mx = 0.0;
-                for (int m = 0; m < 6; ++m) f[m] = Q[v * N + nb[m]] - Q[v * N + c];
+                for (int m = 0; m < 6; ++m) {
+                    double sv = 1.0; /* mirrored neighbour behind a wall (the pressure is even) */
+                    for (int q = 0; q < 3; ++q)
+                        if (sd[m][q] >= 0) sv *= mirror_sign(&M, sd[m][q], v);
+                    f[m] = sv * Q[v * N + nb[m]] - Q[v * N + c];
+                }
                 for (int s = 0; s < 12; ++s) f[6 + s] = L[(v * 12 + s) * N + c];
                 for (int a = 0; a < MLP_IN; ++a) mx = fabs(f[a]) > mx ? fabs(f[a]) : mx;
                 for (int a = 0; a < MLP_IN; ++a) X[(t * NV + v) * MLP_IN + a] = f[a] / (mx + 1e-12);
@@ -1366,7 +1512,7 @@ int oracle_recon_weights(const int dims[3], const double *nodes, const or_params
                          double *out, double *wout) {
     init_consts();
     or_mesh M;
-    int st = mesh_build(&M, dims, nodes);
+    int st = mesh_build(&M, dims, nodes, P);
     if (st) { if (M.n > 0) mesh_free(&M); return st; }
 #pragma omp parallel for schedule(dynamic, 4)
     for (long t = 0; t < ncells; ++t)
@@ -1390,7 +1536,7 @@ int oracle_recon_weights(const int dims[3], const double *nodes, const or_params
 int oracle_diagnostics(const int dims[3], const double *nodes, const or_params *P, const double *Q,
                        const double *G, double *out) {
     or_mesh M;
-    int st = mesh_build(&M, dims, nodes);
+    int st = mesh_build(&M, dims, nodes, P);
     if (st) { if (M.n > 0) mesh_free(&M); return st; }
     const long N = M.n;
     double V = 0.0, mass = 0.0, ke = 0.0, ens = 0.0, en = 0.0, rmin = INFINITY, pmin = INFINITY;

@@ -41,6 +41,7 @@ class Params(C.Structure):
         ("tau_zero", C.c_int),
         ("linear", C.c_int),
         ("prandtl_fix", C.c_int),
+        ("bc", C.c_int * 6),
     ]
 
 
@@ -48,8 +49,9 @@ def params(**kw) -> Params:
     """Oracle parameters; defaults are the paper's constants (Sec. 3.3, Sec. 5)."""
     d = dict(gamma=1.4, cfl=0.5, tau_eps=0.05, tau_C=5.0, mu0=0.0, T_ref=1.0, S_suth=0.0,
              Pr=1.0, geno_C=150.0, geno_eps=1e-15, geno_r=2.0, viscous=0, visc_law=0,
-             tau_zero=0, linear=0, prandtl_fix=0)
+             tau_zero=0, linear=0, prandtl_fix=0, bc=(0, 0, 0, 0, 0, 0))
     d.update(kw)
+    d["bc"] = (C.c_int * 6)(*d["bc"])
     return Params(**d)
 
 

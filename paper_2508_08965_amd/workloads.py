@@ -60,6 +60,49 @@ def skewed_nodes(n, period=1.0, shear=(0.3, 0.2, 0.1), device="cpu"):
     return torch.stack([x + shear[0] * y, y + shear[1] * z, z + shear[2] * x], dim=-1).contiguous()
 
 
+def stretched_nodes(n, half=(math.pi, math.pi, math.pi), cells_per_half=None, amp=(0.1, 0.07, 0.05),
+                    device="cpu"):
+    """Stretched Cartesian nodes: along axis q, x_i = half_q (s + amp_q sin(pi s)) with
+    s = i / cells_per_half_q, i = 0..n_q.  The map is odd about s = 0 and s = 1, so with
+    n = cells_per_half the block [0, half] has mirror-symmetric spacing about its sides, and
+    with n = 2 cells_per_half it is the periodic box [0, 2 half] whose first octant carries the
+    same nodes (walls versus the doubled periodic domain)."""
+    m = cells_per_half or n
+    xs = []
+    for q in range(3):
+        s = torch.arange(n[q] + 1, dtype=F64, device=device) / m[q]
+        xs.append(half[q] * (s + amp[q] * torch.sin(math.pi * s)))
+    z, y, x = torch.meshgrid(xs[2], xs[1], xs[0], indexing="ij")
+    return torch.stack([x, y, z], dim=-1).contiguous()
+
+
+def wall_perturbed_nodes(n, length=math.pi, amp=0.05, device="cpu"):
+    """Curvilinear box [0, length]^3 whose six sides stay planes normal to the axes:
+    x_d = xi_d + amp (length/pi) sin(pi xi_d/length) prod_{e != d} cos(2 pi xi_e/length).
+    The tangential node coordinates agree on opposite sides (cos 0 = cos 2 pi)."""
+    xs = [torch.arange(n[q] + 1, dtype=F64, device=device) * (length / n[q]) for q in range(3)]
+    z, y, x = torch.meshgrid(xs[2], xs[1], xs[0], indexing="ij")
+    a, k = amp * length / math.pi, math.pi / length
+    cx, cy, cz = torch.cos(2 * k * x), torch.cos(2 * k * y), torch.cos(2 * k * z)
+    dx = a * torch.sin(k * x) * cy * cz
+    dy = a * torch.sin(k * y) * cx * cz
+    dz = a * torch.sin(k * z) * cx * cy
+    return torch.stack([x + dx, y + dy, z + dz], dim=-1).contiguous()
+
+
+def shear_wave(U=0.05, H=1.0, mode="sin", rho=1.0, p=1.0 / 1.4):
+    """Parallel shear flow u(y) = U sin(pi y/H) (no-slip walls at y = 0, H) or U cos(pi y/H)
+    (symmetry planes), v = w = 0, uniform rho and p.  For a constant viscosity its
+    incompressible decay is u(y) exp(-nu pi^2 t/H^2)."""
+
+    def f(x, y, z):
+        arg = math.pi * y / H
+        u = U * (torch.sin(arg) if mode == "sin" else torch.cos(arg))
+        zero = torch.zeros_like(x)
+        return rho + zero, u, zero, zero, p + zero
+    return f
+
+
 # ----------------------------------------------------------------------------- trilinear cells
 def _corners(nodes):
     c = {}
