@@ -91,6 +91,22 @@ typedef struct {
                             matrix-core reconstruction and the nonlinear scheme            */
     double jump_thresh;  /* jump indicator: max over face neighbours m of
                             |p_m - p_0| / (p_m + p_0) above this (default 0.05)            */
+    int bc[6];           /* side types of every block, sides x-, x+, y-, y+, z-, z+:
+                            0 periodic (default), 1 symmetry plane (slip, adiabatic),
+                            2 no-slip adiabatic wall.  The two sides of an axis are both
+                            periodic or both walls.  Sec. 5 names walls but gives no
+                            treatment for the compact stencil; here a neighbour behind a
+                            wall is the mirror image of its mirror cell inside (average and
+                            cell-averaged gradient reflected across the wall plane, with the
+                            normal momentum, or at a no-slip wall every momentum component,
+                            reversed) and a wall face takes the gas-kinetic flux between the
+                            interior Gauss-point state and its mirror image; at a no-slip
+                            wall the mass and energy components of F and F_t are zero.
+                            A wall side must be a plane normal to its axis, the axis pointing
+                            into the block, and the two sides of the axis must share their
+                            tangential node coordinates (EINVAL at creation otherwise).
+                            Walls need recon_impl 0 and GENO weights (EUNSUPPORTED), and
+                            cgks_weights refuses contexts with walls                      */
 } cgks_params;
 
 /* Fill *p with the defaults listed above (inviscid, nonlinear, FP64). */

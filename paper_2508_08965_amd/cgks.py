@@ -25,7 +25,7 @@ class Params(C.Structure):
         ("geno_C", C.c_double), ("geno_eps", C.c_double), ("geno_r", C.c_double),
         ("viscous", C.c_int), ("visc_law", C.c_int), ("tau_zero", C.c_int), ("linear", C.c_int),
         ("prandtl_fix", C.c_int), ("recon_prec", C.c_int), ("flux_prec", C.c_int), ("recon_impl", C.c_int),
-        ("per_block", C.c_int), ("weights", C.c_int), ("jump_thresh", C.c_double),
+        ("per_block", C.c_int), ("weights", C.c_int), ("jump_thresh", C.c_double), ("bc", C.c_int * 6),
     ]
 
 
@@ -95,7 +95,7 @@ def default_params(**kw) -> Params:
     for k, v in kw.items():
         if not hasattr(p, k):
             raise KeyError(k)
-        setattr(p, k, v)
+        setattr(p, k, (C.c_int * 6)(*v) if k == "bc" else v)
     return p
 
 

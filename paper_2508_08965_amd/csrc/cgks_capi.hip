@@ -51,6 +51,9 @@ struct cgks_ctx {
     double *pcm = nullptr;    // per-cell matrices (recon_impl 2), tiled by 64 cells
     double *dt_part = nullptr;
     double *diag_part = nullptr;  // [nparts][7] partial sums of the flow diagnostics
+    void *wallf = nullptr;        // wall sides: F, F_t of the minus-side wall faces [4 kk][10][Wtot]
+    long Wtot = 0;                // wall faces of the minus sides over every block and axis
+    bool walls = false;
     int nparts = 1;
     int ncu = 256;
     // work lists of the reconstruction (1), flux (2) and update (3) kernels
@@ -167,7 +170,48 @@ static int check_params(const cgks_params *p) {
         return fail(CGKS_EUNSUPPORTED, "learned weights need the nonlinear FP64 matrix-core reconstruction");
     if (p->recon_impl != 0 && (p->recon_prec != 0 || p->flux_prec != 0))
         return fail(CGKS_EUNSUPPORTED, "the vector-ALU reconstruction is FP64 only");
+    bool walls = false;
+    for (int q = 0; q < 3; ++q) {
+        const int a = p->bc[2 * q], b = p->bc[2 * q + 1];
+        if (a < 0 || a > 2 || b < 0 || b > 2) return fail(CGKS_EINVAL, "bc entries must be 0, 1 or 2");
+        if ((a == 0) != (b == 0)) return fail(CGKS_EINVAL, "the two sides of an axis are both periodic or both walls");
+        walls = walls || a != 0;
+    }
+    if (walls && p->recon_impl != 0)
+        return fail(CGKS_EUNSUPPORTED, "wall sides need the matrix-core reconstruction (recon_impl 0)");
+    if (walls && p->weights != 0) return fail(CGKS_EUNSUPPORTED, "wall sides need GENO weights");
     return CGKS_OK;
+}
+
+// A wall side must be a plane normal to its axis, with the axis pointing into the block, and
+// the tangential node coordinates of the two sides of the axis must agree: the wall faces of
+// both sides then have the geometry of the plus side's face records (unit normal e_q).
+static bool wall_geometry_ok(const double *nd, int nx, int ny, int nz, int q) {
+    const int n[3] = {nx, ny, nz};
+    auto at = [&](int i, int j, int k) {
+        return nd + 3 * ((long)i + (long)(nx + 1) * ((long)j + (long)(ny + 1) * (long)k));
+    };
+    const int ta = (q == 0) ? 1 : 0, tb = (q == 2) ? 1 : 2;
+    int idx[3] = {0, 0, 0};
+    const double x0 = at(0, 0, 0)[q];
+    idx[q] = n[q];
+    const double x1 = at(idx[0], idx[1], idx[2])[q];
+    double scale = 1.0;
+    for (int r = 0; r < 3; ++r) scale = std::max(scale, std::fabs(at(idx[0], idx[1], idx[2])[r]));
+    const double tol = 1e-12 * std::max(scale, std::fabs(x0));
+    if (!(x1 > x0)) return false;
+    for (int ib = 0; ib <= n[tb]; ++ib)
+        for (int ia = 0; ia <= n[ta]; ++ia) {
+            int lo[3], hi[3];
+            lo[ta] = hi[ta] = ia;
+            lo[tb] = hi[tb] = ib;
+            lo[q] = 0;
+            hi[q] = n[q];
+            const double *pl = at(lo[0], lo[1], lo[2]), *ph = at(hi[0], hi[1], hi[2]);
+            if (std::fabs(pl[q] - x0) > tol || std::fabs(ph[q] - x1) > tol) return false;
+            if (std::fabs(pl[ta] - ph[ta]) > tol || std::fabs(pl[tb] - ph[tb]) > tol) return false;
+        }
+    return true;
 }
 
 // Gauss-point buffer in FP32 whenever the reconstruction or the flux runs in reduced precision;
@@ -252,18 +296,27 @@ static hipError_t run_recon(cgks_ctx *ctx, int b, const double *Q, const double 
         ctx->jexamined += (b < 0) ? ctx->Ntot : ctx->blocks[b].N;
     }
     return launch_recon_mfma(ctx->user.recon_prec, gp32(ctx), work_list(ctx, 1, b), ctx->Ntot, Q, G, L, ctx->M,
-                             ctx->Kmf, ctx->P, ctx->gp, ctx->wl[1].cfg.ngroups, io, false, s);
+                             ctx->Kmf, ctx->P, ctx->gp, ctx->wl[1].cfg.ngroups, io, false, ctx->walls, s);
 }
 
 static hipError_t run_flux(cgks_ctx *ctx, int b, const double *dt_dev, hipStream_t s, bool full = true) {
-    return launch_flux(ctx->user.flux_prec, gp32(ctx), work_list(ctx, 2, b), ctx->Ntot, ctx->gp, ctx->M, dt_dev,
-                       ctx->P, ctx->fo, ctx->flag, full, s);
+    hipError_t e = launch_flux(ctx->user.flux_prec, gp32(ctx), work_list(ctx, 2, b), ctx->Ntot, ctx->gp, ctx->M,
+                               dt_dev, ctx->P, ctx->fo, ctx->flag, full, s);
+    // wall faces: recomputed against the mirrored interior state after the periodic pass
+    for (int i = 0; i < (int)ctx->blocks.size() && e == hipSuccess && ctx->walls; ++i) {
+        if (b >= 0 && i != b) continue;
+        for (int q = 0; q < 3 && e == hipSuccess; ++q)
+            if ((ctx->blocks[i].wall >> (2 * q)) & 1)
+                e = launch_flux_wall(ctx->user.flux_prec, gp32(ctx), ctx->blocks[i], q, ctx->Ntot, ctx->gp, ctx->M,
+                                     dt_dev, ctx->P, ctx->fo, ctx->wallf, ctx->Wtot, ctx->flag, full, s);
+    }
+    return e;
 }
 
 static hipError_t run_update(cgks_ctx *ctx, int stage, int b, const double *dt_dev, double *Q, double *G, double *L,
                              hipStream_t s) {
     return launch_update(stage, fo32(ctx), work_list(ctx, 3, b), ctx->Ntot, ctx->fo, ctx->M, dt_dev, Q, G, L,
-                         ctx->stash, ctx->wl[3].cfg.ngroups, s);
+                         ctx->stash, ctx->wl[3].cfg.ngroups, ctx->walls ? ctx->wallf : nullptr, ctx->Wtot, s);
 }
 
 extern "C" {
@@ -299,6 +352,7 @@ void cgks_ctx_destroy(cgks_ctx *ctx) {
     (void)hipFree(ctx->K);
     (void)hipFree(ctx->Kmf);
     (void)hipFree(ctx->pcm);
+    (void)hipFree(ctx->wallf);
     (void)hipFree(ctx->diag_part);
     (void)hipFree(ctx->gp);
     (void)hipFree(ctx->fo);
@@ -347,11 +401,32 @@ int cgks_ctx_create(cgks_ctx **out, int nblocks, const int *dims, const double *
         Ntot += blocks[b].N;
         if (Ntot >= kMaxCells) return fail(CGKS_EINVAL, "total number of cells must be below 2^27");
     }
+    // wall sides (the same for every block): geometry check on the host nodes, wall-face offsets
+    long Wtot = 0;
+    for (int b = 0; b < nblocks; ++b) {
+        BlockView &bv = blocks[b];
+        bv.wall = 0;
+        for (int q = 0; q < 3; ++q) {
+            bv.wbase[q] = -1;
+            if (!p->bc[2 * q]) continue;
+            if (!wall_geometry_ok(nodes[b], bv.nx, bv.ny, bv.nz, q))
+                return fail(CGKS_EINVAL, "a wall side is not a plane normal to its axis, or the two sides of the axis "
+                                         "do not share their tangential node coordinates");
+            for (int sd = 0; sd < 2; ++sd) {
+                bv.wall |= 1 << (2 * q + sd);
+                if (p->bc[2 * q + sd] == 2) bv.wall |= 1 << (8 + 2 * q + sd);
+            }
+            bv.wbase[q] = Wtot;
+            Wtot += bv.N / ((q == 0) ? bv.nx : (q == 1) ? bv.ny : bv.nz);
+        }
+    }
     hipStream_t s = (hipStream_t)stream;
     cgks_ctx *c = new cgks_ctx();
     HIP_TRY(hipGetDevice(&c->device), "hipGetDevice");
     c->blocks = blocks;
     c->Ntot = Ntot;
+    c->Wtot = Wtot;
+    c->walls = Wtot > 0;
     c->user = *p;
     c->P = make_dev_params(*p);
     auto alloc = [&](void **ptr, size_t bytes) -> bool { return hipMalloc(ptr, bytes) == hipSuccess; };
@@ -368,6 +443,7 @@ int cgks_ctx_create(cgks_ctx **out, int nblocks, const int *dims, const double *
               alloc((void **)&c->mlp_v, sizeof(float) * kMlpParams) &&
               alloc((void **)&c->mlp_g, sizeof(float) * kMlpParams) && alloc((void **)&c->mlp_loss, sizeof(float)) &&
               alloc((void **)&c->mlp_packed, kMlpPackBytes) &&
+              (Wtot == 0 || alloc(&c->wallf, sizeof(double) * 40 * Wtot)) &&
               (p->recon_impl != 2 ||
                alloc((void **)&c->pcm, sizeof(double) * kPcElems *
                                            ((Ntot + kPcTile - 1) / kPcTile * kPcTile)));
@@ -699,7 +775,7 @@ int cgks_autotune(cgks_ctx *ctx, const double *Q, const double *G, const double 
                         e = timeit([&] { return launch_recon_mfma(ctx->user.recon_prec, gp32(ctx), w, ctx->Ntot, Q, G, L,
                                                                   ctx->M, ctx->Kmf, ctx->P, ctx->gp, base.ngroups,
                                                                   BlendIO{ctx->jump, ctx->mlp_packed, nullptr, nullptr},
-                                                                  false, s); },
+                                                                  false, ctx->walls, s); },
                                    ms);
                         ms_sum += ms;
                     }
@@ -737,7 +813,7 @@ int cgks_autotune(cgks_ctx *ctx, const double *Q, const double *G, const double 
                     e = timeit([&] { return launch_recon_mfma(ctx->user.recon_prec, gp32(ctx), w, ctx->Ntot, Q, G, L,
                                                               ctx->M, ctx->Kmf, ctx->P, ctx->gp, grids[gi],
                                                               BlendIO{ctx->jump, ctx->mlp_packed, nullptr, nullptr},
-                                                              false, s); },
+                                                              false, ctx->walls, s); },
                                ms);
                     note(1, l.cfg, ms);
                     if (ms < best) {
@@ -938,6 +1014,7 @@ int cgks_weights(cgks_ctx *ctx, const double *Q, const double *G, const double *
     if (!ctx || !Q || !G || !L || !X || !Wt) return fail(CGKS_EINVAL, "cgks_weights: NULL argument");
     if (ctx->user.recon_impl != 0 || ctx->user.recon_prec != 0 || gp32(ctx) || ctx->user.linear)
         return fail(CGKS_EUNSUPPORTED, "cgks_weights: FP64 nonlinear matrix-core contexts only");
+    if (ctx->walls) return fail(CGKS_EUNSUPPORTED, "cgks_weights: periodic blocks only");
     if (ctx->P.weights == 1 && !ctx->mlp_ready) return fail(CGKS_EINVAL, "learned weights: no MLP parameters set");
     hipStream_t s = (hipStream_t)stream;
     ctx->last = s;
@@ -945,7 +1022,7 @@ int cgks_weights(cgks_ctx *ctx, const double *Q, const double *G, const double *
     ctx->jexamined += ctx->Ntot;
     BlendIO io{ctx->jump, ctx->mlp_packed, Wt, X};
     HIP_TRY(launch_recon_mfma(0, false, work_list(ctx, 1, -1), ctx->Ntot, Q, G, L, ctx->M, ctx->Kmf, ctx->P, ctx->gp,
-                              ctx->wl[1].cfg.ngroups, io, true, s),
+                              ctx->wl[1].cfg.ngroups, io, true, false, s),
             "recon export");
     if (jump) HIP_TRY(hipMemcpyAsync(jump, ctx->jump, ctx->Ntot, hipMemcpyDeviceToDevice, s), "copy jump flags");
     return CGKS_OK;

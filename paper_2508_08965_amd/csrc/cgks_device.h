@@ -15,7 +15,24 @@ struct BlockView {
     int nx, ny, nz;
     long N;    // cells of the block
     long off;  // offset of the block's first cell in the concatenated state
+    // Sides s = 2q + (0 minus, 1 plus) of axis q: bit s marks a wall (symmetry plane or no-slip
+    // wall), bit 8 + s a no-slip wall; 0 for a periodic block.  Walls come in pairs per axis.
+    int wall;
+    // Per axis with walls: offset of the block's minus-side wall faces in the wall-face buffer
+    // (one entry per face of that side, index i_a + n_a i_b over the tangential axes a < b).
+    long wbase[3];
 };
+
+// Sign of conserved variable v in the mirror image across wall side s: the momentum normal to
+// a symmetry plane, and every momentum component at a no-slip wall, change sign.
+__host__ __device__ inline double mirror_sign(int wall, int s, int v) {
+    return (v >= 1 && v <= 3 && (((wall >> (8 + s)) & 1) || v - 1 == (s >> 1))) ? -1.0 : 1.0;
+}
+
+// Index of a wall face of axis q within its side: i_a + n_a i_b over the tangential axes.
+__host__ __device__ inline long wall_face_index(const BlockView &b, int q, int i, int j, int k) {
+    return (q == 0) ? (long)j + (long)b.ny * k : (q == 1) ? (long)i + (long)b.nx * k : (long)i + (long)b.nx * j;
+}
 
 // A run of consecutive cells of one block (block-local linear index, x fastest): the unit of
 // the work lists that let one launch cover every block of a multi-block mesh.
@@ -511,7 +528,7 @@ struct BlendIO {
 };
 hipError_t launch_recon_mfma(int prec, bool gp32, const WorkList &W, long Ntot, const double *Q, const double *G,
                              const double *L, const Metrics &M, const double *Kblk, const DevParams &P, void *gp,
-                             int ngroups, const BlendIO &io, bool exp, hipStream_t s);
+                             int ngroups, const BlendIO &io, bool exp, bool walls, hipStream_t s);
 hipError_t launch_jump(const WorkList &W, long Ntot, const double *Q, const DevParams &P, unsigned char *flag,
                        unsigned long long *count, hipStream_t s);
 hipError_t launch_mlp_infer(const float *X, long n, const unsigned char *packed, double *Y, hipStream_t s);
@@ -535,6 +552,9 @@ hipError_t launch_flux_points(int flux_prec, long n, const double *ql, const dou
                               double *Ft, double *S, int *flag, hipStream_t s);
 hipError_t launch_update(int stage, bool fo32, const WorkList &W, long Ntot, const void *fo, const Metrics &M,
                          const double *dt, double *Q, double *G, double *L, double *stash, int ngroups,
-                         hipStream_t s);
+                         const void *wf, long Wtot, hipStream_t s);
+hipError_t launch_flux_wall(int flux_prec, bool gp32, const BlockView &b, int q, long Ntot, const void *gp,
+                            const Metrics &M, const double *dt, const DevParams &P, void *fo, void *wf, long Wtot,
+                            int *flag, bool full, hipStream_t s);
 
 }  // namespace cgks

@@ -526,6 +526,78 @@ __global__ void __launch_bounds__(256, 2) k_flux(WorkList W, long Ntot, const TG
     }
 }
 
+// Wall faces of axis q of one block, two lanes per Gauss point.  A pair serves (wall face p,
+// Gauss point kk, wall w: 0 minus side, 1 plus side).  The face record f of the cell at index
+// n_q - 1 (the plus wall) holds the Gauss-point data of both walls of its line: its left side is
+// that cell's, its right side was written by the cell at index 0 (the minus wall).  Both lanes
+// load the interior side; the ghost lane (left at the minus wall, right at the plus wall)
+// mirrors its copy across the wall.  The plus wall's flux replaces the record's F, F_t and left
+// side values; the minus wall's replaces the record's right side values and puts F, F_t into
+// the wall-face buffer wf [(kk 10 + item)][Wtot].  At a no-slip wall the mass and energy
+// components of F and F_t are zero (impermeable, at rest, adiabatic).  Runs after k_flux.
+template <class TC, class TG, class TF, bool FULL>
+__global__ void __launch_bounds__(256) k_flux_wall(BlockView b, int q, long Ntot, const TG *__restrict__ gp, Metrics M,
+                                                   const double *__restrict__ dtp, DevParams P, TF *__restrict__ fo,
+                                                   TF *__restrict__ wf, long Wtot, int *__restrict__ flag) {
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long pair = t >> 1;
+    const int sd = (int)(t & 1);
+    const long nfaces = b.N / ((q == 0) ? b.nx : (q == 1) ? b.ny : b.nz);
+    const long p = pair >> 3;
+    if (p >= nfaces) return;  // both lanes of a pair leave together
+    const int kk = (int)((pair >> 1) & 3), w = (int)(pair & 1);
+    int i, j, k;
+    if (q == 0) {
+        i = b.nx - 1; j = (int)(p % b.ny); k = (int)(p / b.ny);
+    } else if (q == 1) {
+        i = (int)(p % b.nx); j = b.ny - 1; k = (int)(p / b.nx);
+    } else {
+        i = (int)(p % b.nx); j = (int)(p / b.nx); k = b.nz - 1;
+    }
+    const long f = b.off + i + (long)b.nx * (j + (long)b.ny * k);
+    const int side = 2 * q + w;
+    TC qv[5], gv[5][3], n[3];
+    const TG *src = gp + (long)(((q * 2 + (1 - w)) * 4 + kk) * 20) * Ntot + f;
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+        qv[v] = (TC)src[(4 * v) * Ntot];
+#pragma unroll
+        for (int r = 0; r < 3; ++r) gv[v][r] = (TC)src[(4 * v + 1 + r) * Ntot];
+    }
+    if (sd == w) {
+#pragma unroll
+        for (int v = 0; v < 5; ++v) {
+            const TC m = (TC)mirror_sign(b.wall, side, v);
+            qv[v] *= m;
+#pragma unroll
+            for (int r = 0; r < 3; ++r) gv[v][r] *= (r == q) ? -m : m;
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < 3; ++r) n[r] = (TC)M.fn[((q * 4 + kk) * 3 + r) * Ntot + f];
+    TC F[5], Ft[5], Qs[5], dQs[5];
+    const int bad = gks_flux_pair<DevMath, TC, FULL>(P, sd, qv, gv, n, (TC)*dtp, F, Ft, Qs, dQs);
+    if (bad && sd == 0) atomicOr(flag, bad);
+    if ((b.wall >> (8 + side)) & 1) F[0] = F[4] = Ft[0] = Ft[4] = (TC)0;
+    TF *dst = fo + (long)((q * 4 + kk) * 30) * Ntot + f;
+    if (sd != w) {  // the interior lane: its one-sided values
+#pragma unroll
+        for (int v = 0; v < 5; ++v) {
+            if constexpr (FULL) dst[(10 + 10 * sd + v) * Ntot] = (TF)Qs[v];
+            dst[(15 + 10 * sd + v) * Ntot] = (TF)dQs[v];
+        }
+    }
+    if (sd) {
+        TF *fd = w ? dst : wf + (long)(kk * 10) * Wtot + b.wbase[q] + p;
+        const long st = w ? Ntot : Wtot;
+#pragma unroll
+        for (int v = 0; v < 5; ++v) {
+            if constexpr (FULL) fd[v * st] = (TF)F[v];
+            fd[(5 + v) * st] = (TF)Ft[v];
+        }
+    }
+}
+
 template <class TC>
 __global__ void __launch_bounds__(256) k_flux_points(long n, const double *__restrict__ ql_, const double *__restrict__ gl_,
                                                      const double *__restrict__ qr_, const double *__restrict__ gr_,
@@ -561,10 +633,11 @@ __global__ void __launch_bounds__(256) k_flux_points(long n, const double *__res
 // accumulation + S2O4 stage update: one thread per cell
 // stash [80][Ntot]: Qpre (5) = Q^n + dt L^n + dt^2/6 L_t^n, Gb (15), Lb (60)
 // ------------------------------------------------------------------------------------------
-template <int STAGE, class TF>
+template <int STAGE, class TF, bool WALLS>
 __device__ inline void update_cell(const BlockView &b, long cl, long Ntot, const TF *__restrict__ fo, const Metrics &M,
                                    const double dt, double *__restrict__ Q, double *__restrict__ G,
-                                   double *__restrict__ L, double *__restrict__ stash) {
+                                   double *__restrict__ L, double *__restrict__ stash, const TF *__restrict__ wf,
+                                   long Wtot) {
     Idx3 id = unflatten(b, cl);
     const long c = b.off + cl;
     double Lf[5] = {0, 0, 0, 0, 0}, Lt[5] = {0, 0, 0, 0, 0};
@@ -584,11 +657,21 @@ __device__ inline void update_cell(const BlockView &b, long cl, long Ntot, const
         const long fm = cell_at(b, id.i + o[0], id.j + o[1], id.k + o[2]);
         // stage 1 with FP64 face records: the four Gauss points of a face in one block (the
         // compiler then keeps the kernel at 3 waves per SIMD); otherwise one point at a time
-        constexpr int kUnrollPoints = (STAGE == 1 && sizeof(TF) == 8) ? 4 : 1;
+        constexpr int kUnrollPoints = (STAGE == 1 && sizeof(TF) == 8 && !WALLS) ? 4 : 1;
 #pragma unroll kUnrollPoints
         for (int kk = 0; kk < 4; ++kk) {
             const TF *Dp = fo + (long)((q * 4 + kk) * 30) * Ntot + c;   // plus face: this cell is left
             const TF *Dm = fo + (long)((q * 4 + kk) * 30) * Ntot + fm;  // minus face: this cell is right
+            // F and F_t of the minus face: from the wall-face buffer at a minus-side wall
+            const TF *DmF = Dm;
+            long sF = Ntot;
+            if constexpr (WALLS) {
+                const int iq = (q == 0) ? id.i : (q == 1) ? id.j : id.k;
+                if (((b.wall >> (2 * q)) & 1) && iq == 0) {
+                    DmF = wf + (long)(kk * 10) * Wtot + b.wbase[q] + wall_face_index(b, q, id.i, id.j, id.k);
+                    sF = Wtot;
+                }
+            }
             const double wp = M.fw[(q * 4 + kk) * Ntot + c], wm = M.fw[(q * 4 + kk) * Ntot + fm];
             double np_[3], nm_[3];
 #pragma unroll
@@ -600,9 +683,9 @@ __device__ inline void update_cell(const BlockView &b, long cl, long Ntot, const
 #pragma unroll
             for (int v = 0; v < 5; ++v) {
                 if (STAGE == 1) {
-                    Lf[v] += wm * (double)Dm[v * Ntot] - wp * (double)Dp[v * Ntot];
+                    Lf[v] += wm * (double)DmF[v * sF] - wp * (double)Dp[v * Ntot];
                 }
-                Lt[v] += wm * (double)Dm[(5 + v) * Ntot] - wp * (double)Dp[(5 + v) * Ntot];
+                Lt[v] += wm * (double)DmF[(5 + v) * sF] - wp * (double)Dp[(5 + v) * Ntot];
                 const double dqp = (double)Dp[(15 + v) * Ntot], dqm = (double)Dm[(25 + v) * Ntot];
 #pragma unroll
                 for (int r = 0; r < 3; ++r) Gt[v][r] += wp * np_[r] * dqp - wm * nm_[r] * dqm;
@@ -644,16 +727,17 @@ __device__ inline void update_cell(const BlockView &b, long cl, long Ntot, const
 }
 
 // A unit is one tile; thread t updates cell t of the tile.
-template <int STAGE, class TF>
+template <int STAGE, class TF, bool WALLS>
 __global__ void __launch_bounds__(256) k_update(WorkList W, long Ntot, const TF *__restrict__ fo, Metrics M,
                                                 const double *__restrict__ dtp, double *__restrict__ Q,
                                                 double *__restrict__ G, double *__restrict__ L,
-                                                double *__restrict__ stash) {
+                                                double *__restrict__ stash, const TF *__restrict__ wf, long Wtot) {
     const double dt = *dtp;
     for (UnitRange ur = unit_range(W.ntiles, W.xcd); ur.u < ur.end; ur.u += ur.step) {
         const Tile tile = W.tiles[ur.u];
         if ((int)threadIdx.x >= tile.count) continue;
-        update_cell<STAGE, TF>(W.blocks[tile.blk], tile.start + threadIdx.x, Ntot, fo, M, dt, Q, G, L, stash);
+        update_cell<STAGE, TF, WALLS>(W.blocks[tile.blk], tile.start + threadIdx.x, Ntot, fo, M, dt, Q, G, L, stash,
+                                      wf, Wtot);
     }
 }
 
@@ -739,20 +823,56 @@ hipError_t launch_flux_points(int flux_prec, long n, const double *ql, const dou
 
 hipError_t launch_update(int stage, bool fo32, const WorkList &W, long Ntot, const void *fo, const Metrics &M,
                          const double *dt, double *Q, double *G, double *L, double *stash, int ngroups,
-                         hipStream_t s) {
+                         const void *wf, long Wtot, hipStream_t s) {
+    // wf: the wall-face buffer, or NULL for work lists of periodic blocks only
     if (W.ntiles <= 0) return hipSuccess;
     const dim3 grid = work_grid(W.ntiles, ngroups), bl(kUpdateTile);
+#define CGKS_UPDATE(ST, TF, WL)                                                                                   \
+    hipLaunchKernelGGL((k_update<ST, TF, WL>), grid, bl, 0, s, W, Ntot, (const TF *)fo, M, dt, Q, G, L, stash, \
+                       (const TF *)wf, Wtot)
     if (fo32) {
-        if (stage == 1)
-            hipLaunchKernelGGL((k_update<1, float>), grid, bl, 0, s, W, Ntot, (const float *)fo, M, dt, Q, G, L, stash);
-        else
-            hipLaunchKernelGGL((k_update<2, float>), grid, bl, 0, s, W, Ntot, (const float *)fo, M, dt, Q, G, L, stash);
+        if (wf) {
+            if (stage == 1) CGKS_UPDATE(1, float, true);
+            else CGKS_UPDATE(2, float, true);
+        } else {
+            if (stage == 1) CGKS_UPDATE(1, float, false);
+            else CGKS_UPDATE(2, float, false);
+        }
     } else {
-        if (stage == 1)
-            hipLaunchKernelGGL((k_update<1, double>), grid, bl, 0, s, W, Ntot, (const double *)fo, M, dt, Q, G, L, stash);
-        else
-            hipLaunchKernelGGL((k_update<2, double>), grid, bl, 0, s, W, Ntot, (const double *)fo, M, dt, Q, G, L, stash);
+        if (wf) {
+            if (stage == 1) CGKS_UPDATE(1, double, true);
+            else CGKS_UPDATE(2, double, true);
+        } else {
+            if (stage == 1) CGKS_UPDATE(1, double, false);
+            else CGKS_UPDATE(2, double, false);
+        }
     }
+#undef CGKS_UPDATE
+    return hipGetLastError();
+}
+
+hipError_t launch_flux_wall(int flux_prec, bool gp32, const BlockView &b, int q, long Ntot, const void *gp,
+                            const Metrics &M, const double *dt, const DevParams &P, void *fo, void *wf, long Wtot,
+                            int *flag, bool full, hipStream_t s) {
+    const long nfaces = b.N / ((q == 0) ? b.nx : (q == 1) ? b.ny : b.nz);
+    const long threads = nfaces * 16;  // 4 Gauss points x 2 walls x 2 lanes per face
+    const dim3 grid((unsigned)((threads + 255) / 256)), bl(256);
+#define CGKS_FLUXW(TC, TG, TF)                                                                                   \
+    do {                                                                                                         \
+        if (full)                                                                                                \
+            hipLaunchKernelGGL((k_flux_wall<TC, TG, TF, true>), grid, bl, 0, s, b, q, Ntot, (const TG *)gp, M,   \
+                               dt, P, (TF *)fo, (TF *)wf, Wtot, flag);                                           \
+        else                                                                                                     \
+            hipLaunchKernelGGL((k_flux_wall<TC, TG, TF, false>), grid, bl, 0, s, b, q, Ntot, (const TG *)gp, M,  \
+                               dt, P, (TF *)fo, (TF *)wf, Wtot, flag);                                           \
+    } while (0)
+    if (flux_prec == 0 && !gp32)
+        CGKS_FLUXW(double, double, double);
+    else if (flux_prec == 0)
+        CGKS_FLUXW(double, float, double);
+    else
+        CGKS_FLUXW(float, float, float);
+#undef CGKS_FLUXW
     return hipGetLastError();
 }
 

@@ -84,6 +84,40 @@ __device__ inline CellNb cell_nb(const BlockView &b, int ci, int cj, int ck) {
     r.dp[2] = (ck == b.nz - 1) ? (1 - b.nz) * nxy : nxy;
     return r;
 }
+// Wall sides the cell (ci, cj, ck) lies on (bit s = 2q + side), with the offsets of gn toward
+// them set to zero: the neighbour behind a wall is the mirror image of the cell beside it on the
+// inside (the cell itself for a face neighbour).
+__device__ inline int wall_touch(const BlockView &b, int ci, int cj, int ck, CellNb &gn) {
+    const int w = b.wall;
+    int t = 0;
+    if ((w & 1) && ci == 0) { t |= 1; gn.dm[0] = 0; }
+    if ((w & 2) && ci == b.nx - 1) { t |= 2; gn.dp[0] = 0; }
+    if ((w & 4) && cj == 0) { t |= 4; gn.dm[1] = 0; }
+    if ((w & 8) && cj == b.ny - 1) { t |= 8; gn.dp[1] = 0; }
+    if ((w & 16) && ck == 0) { t |= 16; gn.dm[2] = 0; }
+    if ((w & 32) && ck == b.nz - 1) { t |= 32; gn.dp[2] = 0; }
+    return t;
+}
+// Mirror image of a neighbour's average and physical gradient of variable v across the wall
+// sides in `crossed`: the average changes sign with the variable (mirror_sign), the gradient
+// also in its component normal to each wall.
+__device__ inline void ghost_mirror(int wall, int crossed, int v, double &q, double g[3]) {
+#pragma unroll
+    for (int s = 0; s < 6; ++s)
+        if ((crossed >> s) & 1) {
+            const double m = mirror_sign(wall, s, v);
+            q *= m;
+#pragma unroll
+            for (int r = 0; r < 3; ++r) g[r] *= (r == (s >> 1)) ? -m : m;
+        }
+}
+// Wall sides crossed by gather step st of a lane whose edge signs are (sa, sb).
+__device__ inline int step_crossed(int touch, int st, int sa, int sb) {
+    if (st < 6) return touch & (1 << st);
+    const int p = st - 6, pa = (p < 2) ? 0 : 1, pb = (p == 0) ? 1 : 2;
+    return touch & ((1 << (2 * pa + (sa > 0))) | (1 << (2 * pb + (sb > 0))));
+}
+
 // Cell coordinates of this lane: tile of runs (ty = 0; the wave's first cell is decoded once,
 // the lanes step on along x) or brick.  Tail lanes take the last cell of the tile (valid =
 // false: they compute a copy and store nothing).
@@ -148,7 +182,7 @@ __device__ inline typename PR::V mac_coef(const typename PR::T *Ablk, int blk, t
 // where the pressure-jump flag of the cell is set.  EXP: also write the weights used
 // (wexp [N][5][7]: chi, omega_1..6) and the MLP input features (xexp [N][5][18]).
 
-template <class PR, class TG, int WM, bool EXP>
+template <class PR, class TG, int WM, bool EXP, bool WALLS>
 __global__ void __launch_bounds__(512) k_recon_mfma(WorkList W, long Ntot, const double *__restrict__ Q,
                                                     const double *__restrict__ G, const double *__restrict__ L,
                                                     Metrics M, const double *__restrict__ Kblk, DevParams P,
@@ -233,20 +267,31 @@ __global__ void __launch_bounds__(512) k_recon_mfma(WorkList W, long Ntot, const
             // ---- steps 0..14: face neighbours m (steps m), then edge neighbours 4p+g (steps
             // 6+p, 9+2p, 10+2p).  The average and gradient of all nine neighbours a lane needs are
             // requested before the first contraction, so the wave waits for memory once.
+            // ghost neighbours behind wall sides: their mirror cells, mirrored below
+            CellNb gn = cn;
+            int touch = 0;
+            if constexpr (WALLS) touch = wall_touch(b, ci, cj, ck, gn);
             double nq[9], ng[9][3];
     #pragma unroll
             for (int st = 0; st < 9; ++st) {
                 int nb;
                 if (st < 6) {
-                    nb = c + ((st & 1) ? cn.dp[st >> 1] : cn.dm[st >> 1]);
+                    nb = c + ((st & 1) ? gn.dp[st >> 1] : gn.dm[st >> 1]);
                 } else {
                     const int p = st - 6, pa = (p < 2) ? 0 : 1, pb = (p == 0) ? 1 : 2;
-                    nb = c + (sa > 0 ? cn.dp[pa] : cn.dm[pa]) + (sb > 0 ? cn.dp[pb] : cn.dm[pb]);
+                    nb = c + (sa > 0 ? gn.dp[pa] : gn.dm[pa]) + (sb > 0 ? gn.dp[pb] : gn.dm[pb]);
                 }
                 nq[st] = ld32(Qv, nb);
                 ng[st][0] = ld32(Gv, nb);
                 ng[st][1] = ld32(Gv + Ntot, nb);
                 ng[st][2] = ld32(Gv + 2 * Ntot, nb);
+            }
+            if constexpr (WALLS) {
+    #pragma unroll
+                for (int st = 0; st < 9; ++st) {
+                    const int crossed = step_crossed(touch, st, sa, sb);
+                    if (crossed) ghost_mirror(b.wall, crossed, v, nq[st], ng[st]);
+                }
             }
     #pragma unroll
             for (int st = 0; st < 9; ++st) {
@@ -512,7 +557,7 @@ __device__ inline v4f mma3(const v8bf *Kb, int blk, const v8bf &xh, const v8bf &
 }
 }  // namespace
 
-template <class TG>
+template <class TG, bool WALLS>
 __global__ void __launch_bounds__(512) k_recon_bf16(WorkList W, long Ntot, const double *__restrict__ Q,
                                                     const double *__restrict__ G, const double *__restrict__ L,
                                                     Metrics M, const double *__restrict__ Kbf, DevParams P,
@@ -576,20 +621,31 @@ __global__ void __launch_bounds__(512) k_recon_bf16(WorkList W, long Ntot, const
                     bl[s][j] = (__bf16)0.0f;
                 }
             // all nine neighbours first (one wait for memory), then the slots
+            // ghost neighbours behind wall sides: their mirror cells, mirrored below
+            CellNb gn = cn;
+            int touch = 0;
+            if constexpr (WALLS) touch = wall_touch(b, ci, cj, ck, gn);
             double nq[9], ng[9][3];
     #pragma unroll
             for (int st = 0; st < 9; ++st) {
                 int nb;
                 if (st < 6) {
-                    nb = c + ((st & 1) ? cn.dp[st >> 1] : cn.dm[st >> 1]);
+                    nb = c + ((st & 1) ? gn.dp[st >> 1] : gn.dm[st >> 1]);
                 } else {
                     const int p = st - 6, pa = (p < 2) ? 0 : 1, pb = (p == 0) ? 1 : 2;
-                    nb = c + (sa > 0 ? cn.dp[pa] : cn.dm[pa]) + (sb > 0 ? cn.dp[pb] : cn.dm[pb]);
+                    nb = c + (sa > 0 ? gn.dp[pa] : gn.dm[pa]) + (sb > 0 ? gn.dp[pb] : gn.dm[pb]);
                 }
                 nq[st] = ld32(Qv, nb);
                 ng[st][0] = ld32(Gv, nb);
                 ng[st][1] = ld32(Gv + Ntot, nb);
                 ng[st][2] = ld32(Gv + 2 * Ntot, nb);
+            }
+            if constexpr (WALLS) {
+    #pragma unroll
+                for (int st = 0; st < 9; ++st) {
+                    const int crossed = step_crossed(touch, st, sa, sb);
+                    if (crossed) ghost_mirror(b.wall, crossed, v, nq[st], ng[st]);
+                }
             }
             double lvd[3];
     #pragma unroll
@@ -761,18 +817,27 @@ __global__ void __launch_bounds__(512) k_recon_bf16(WorkList W, long Ntot, const
 
 hipError_t launch_recon_mfma(int prec, bool gp32, const WorkList &W, long Ntot, const double *Q, const double *G,
                              const double *L, const Metrics &M, const double *Kblk, const DevParams &P, void *gp,
-                             int ngroups, const BlendIO &io, bool exp, hipStream_t s) {
+                             int ngroups, const BlendIO &io, bool exp, bool walls, hipStream_t s) {
     // prec: 0 FP64, 1 FP32x3, 2 BF16x3 (Kblk holds the blocks packed for that instruction).
     // A workgroup takes whole tiles; ngroups <= 0 launches one workgroup per tile.  Learned
     // weights (P.weights = 1) and the export exist for the FP64 reconstruction only.
     if (W.ntiles <= 0) return hipSuccess;
     if ((P.weights == 1 || exp) && prec != 0) return hipErrorInvalidValue;
     if (exp && gp32) return hipErrorInvalidValue;
+    if (walls && (P.weights == 1 || exp)) return hipErrorInvalidValue;
     const int grid = (ngroups <= 0 || ngroups > W.ntiles) ? W.ntiles : ngroups;
     const dim3 gr((unsigned)grid), bl(512);
 #define CGKS_RECON(PRC, TGT, WMV, EXV) \
-    hipLaunchKernelGGL((k_recon_mfma<PRC, TGT, WMV, EXV>), gr, bl, 0, s, W, Ntot, Q, G, L, M, Kblk, P, (TGT *)gp, io)
-    if (prec == 0 && !gp32) {
+    hipLaunchKernelGGL((k_recon_mfma<PRC, TGT, WMV, EXV, false>), gr, bl, 0, s, W, Ntot, Q, G, L, M, Kblk, P, (TGT *)gp, io)
+#define CGKS_RECON_WALLS(PRC, TGT) \
+    hipLaunchKernelGGL((k_recon_mfma<PRC, TGT, 0, false, true>), gr, bl, 0, s, W, Ntot, Q, G, L, M, Kblk, P, (TGT *)gp, io)
+    if (walls) {
+        // blocks with wall sides: GENO weights, no export
+        if (prec == 0 && !gp32) CGKS_RECON_WALLS(PrecF64, double);
+        else if (prec == 0) CGKS_RECON_WALLS(PrecF64, float);
+        else if (prec == 1) CGKS_RECON_WALLS(PrecF32x3, float);
+        else hipLaunchKernelGGL((k_recon_bf16<float, true>), gr, bl, 0, s, W, Ntot, Q, G, L, M, Kblk, P, (float *)gp);
+    } else if (prec == 0 && !gp32) {
         if (P.weights == 1) {
             if (exp) CGKS_RECON(PrecF64, double, 1, true);
             else CGKS_RECON(PrecF64, double, 1, false);
@@ -786,9 +851,10 @@ hipError_t launch_recon_mfma(int prec, bool gp32, const WorkList &W, long Ntot, 
     } else if (prec == 1) {
         CGKS_RECON(PrecF32x3, float, 0, false);
     } else {
-        hipLaunchKernelGGL((k_recon_bf16<float>), gr, bl, 0, s, W, Ntot, Q, G, L, M, Kblk, P, (float *)gp);
+        hipLaunchKernelGGL((k_recon_bf16<float, false>), gr, bl, 0, s, W, Ntot, Q, G, L, M, Kblk, P, (float *)gp);
     }
 #undef CGKS_RECON
+#undef CGKS_RECON_WALLS
     return hipGetLastError();
 }
 

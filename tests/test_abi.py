@@ -76,3 +76,32 @@ def test_default_params_are_the_papers_constants():
     p = K.default_params()
     assert p.gamma == 1.4 and p.cfl == 0.5 and p.tau_eps == 0.05 and p.tau_C == 5.0
     assert p.geno_eps == 1e-15 and p.geno_r == 2.0
+
+
+def test_wall_sides_rejected_on_the_host():
+    """Side types and wall geometry are checked before the device is touched."""
+    if not os.path.exists(K.LIB_PATH):
+        pytest.skip("library not built")
+    import numpy as np
+    from paper_2508_08965_amd import workloads as W
+    L = K.lib()
+    h = C.c_void_p()
+    dims = (C.c_int * 3)(4, 4, 4)
+
+    def create(nodes, **kw):
+        a = np.ascontiguousarray(nodes.numpy(), dtype=np.float64)
+        ptrs = (C.POINTER(C.c_double) * 1)(a.ctypes.data_as(C.POINTER(C.c_double)))
+        return L.cgks_ctx_create(C.byref(h), 1, dims, ptrs, C.byref(K.default_params(**kw)), None)
+
+    box = W.cartesian_nodes((4, 4, 4))
+    for bc in ((1, 0, 0, 0, 0, 0), (0, 0, 2, 0, 0, 0), (3, 3, 0, 0, 0, 0), (-1, -1, 0, 0, 0, 0)):
+        assert create(box, bc=bc) == K.EINVAL, bc
+    assert create(box, bc=(1, 1, 0, 0, 0, 0), recon_impl=1) == K.EUNSUPPORTED
+    assert create(box, bc=(2, 2, 0, 0, 0, 0), weights=1) == K.EUNSUPPORTED
+    # sides that are planes but not normal to their axis
+    assert create(W.skewed_nodes((4, 4, 4)), bc=(1, 1, 0, 0, 0, 0)) == K.EINVAL
+    # x sides whose tangential node coordinates differ (one side moved in y)
+    moved = box.clone()
+    moved[:, :, 4, 1] += 0.01
+    assert create(moved, bc=(1, 1, 0, 0, 0, 0)) == K.EINVAL
+    assert "wall side" in K.last_error()
