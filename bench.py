@@ -374,6 +374,43 @@ def bench_percell(K, W, torch, kw, n=128, steps=3):
     return out
 
 
+def bench_walls(K, W, torch, kw, n=256, steps=5, warmup=2):
+    """Wall sides at the headline size: the Taylor-Green vortex in the box [0, pi]^3 (bounded by
+    its own symmetry planes: the octant of the periodic vortex on [0, 2 pi]^3 at twice the
+    resolution) on a curvilinear mesh whose sides stay planar, once with symmetry planes and
+    once with no-slip adiabatic walls on every side.  The headline line is the same step on a
+    periodic mesh of the same size."""
+    dev = torch.device("cuda:0")
+    m = (n,) * 3
+    N = n ** 3
+    nodes = W.wall_perturbed_nodes(m, device=dev)
+    Q0, G0, L0 = W.initial_state(nodes, W.taylor_green(Ma=0.1), GAM)
+    nodes = nodes.cpu()
+    res = {}
+    for name, bc in (("symmetry_planes", 1), ("noslip_walls", 2)):
+        ctx = K.Context([m], [nodes], K.default_params(bc=(bc,) * 6, **kw))
+        vol = torch.zeros(N, dtype=torch.float64, device=dev)
+        K.cgks_metrics(ctx, vol=vol)
+        Q, G, L = Q0.clone(), G0.clone(), L0.clone()
+        dt = torch.zeros(1, dtype=torch.float64, device=dev)
+        mass0, energy0 = float((vol * Q[0]).sum()), float((vol * Q[4]).sum())
+        for _ in range(warmup):
+            K.cgks_step(ctx, Q, G, L, dt, use_cfl=True)
+        torch.cuda.synchronize()
+        K.cgks_profile_read(ctx)
+        elapsed, prof = timed_steps(K, ctx, Q, G, L, dt, steps)
+        res[name] = {"value": N * steps / elapsed, "unit": "cell-updates/s", "ms_per_step": 1e3 * elapsed / steps,
+                     "kernel_ms": {k: {"total_ms": v[0], "launches": v[1]} for k, v in prof.items()},
+                     "mass_rel_drift": abs(float((vol * Q[0]).sum()) - mass0) / mass0,
+                     "energy_rel_drift": abs(float((vol * Q[4]).sum()) - energy0) / energy0,
+                     "device_flags": K.cgks_check(ctx)[1]}
+        ctx.close()
+        del Q, G, L, vol
+        torch.cuda.empty_cache()
+    return {"workload": f"taylor-green vortex Re1600 Ma0.1 in [0, pi]^3, {n}^3 curvilinear mesh with planar sides, "
+                        f"FP64, {steps} steps after {warmup}", "cells": N, "variants": res}
+
+
 def bench_supersonic_tgv(K, W, torch, n=128, t_end=10.0, Ma=1.25):
     """Robustness run of Sec. 5: the supersonic Taylor-Green vortex (Ma 1.25, Re 1600, Pr 0.7,
     Sutherland) with the nonlinear scheme on the paper's uniform n^3 mesh, to t_end, with the
@@ -435,6 +472,7 @@ def main():
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-weight measurement")
     ap.add_argument("--no-percell", action="store_true", help="skip the per-cell matrix storage measurement")
     ap.add_argument("--no-supersonic", action="store_true", help="skip the supersonic Taylor-Green robustness run")
+    ap.add_argument("--no-walls", action="store_true", help="skip the wall-side measurement")
     ap.add_argument("--dump-state", default=None,
                     help="write the initial state and parameters of the FP64 workload for cgks_runner, then exit")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -585,6 +623,11 @@ def main():
     if not args.no_percell:
         percell = bench_percell(K, W, torch, kw)
 
+    # ---- wall sides (symmetry planes, no-slip walls) at the headline size -------------------
+    walls = None
+    if not args.no_walls:
+        walls = bench_walls(K, W, torch, kw, n=args.n, steps=args.steps, warmup=args.warmup)
+
     # ---- supersonic Taylor-Green vortex: robustness of the nonlinear scheme ------------------
     supersonic = None
     if not args.no_supersonic:
@@ -628,6 +671,7 @@ def main():
         "batching": batching,
         "learned_weights": learned,
         "per_cell_storage": percell,
+        "walls": walls,
         "supersonic_tgv": supersonic,
         "cpu_baseline": cpu,
         "device_flags": flags,
