@@ -374,12 +374,13 @@ def bench_percell(K, W, torch, kw, n=128, steps=3):
     return out
 
 
-def bench_walls(K, W, torch, kw, n=256, steps=5, warmup=2):
+def bench_walls(K, W, torch, kw, n=256, steps=5, warmup=2, check_oracle=True):
     """Wall sides at the headline size: the Taylor-Green vortex in the box [0, pi]^3 (bounded by
     its own symmetry planes: the octant of the periodic vortex on [0, 2 pi]^3 at twice the
     resolution) on a curvilinear mesh whose sides stay planar, once with symmetry planes and
     once with no-slip adiabatic walls on every side.  The headline line is the same step on a
     periodic mesh of the same size."""
+    import numpy as np
     dev = torch.device("cuda:0")
     m = (n,) * 3
     N = n ** 3
@@ -404,6 +405,32 @@ def bench_walls(K, W, torch, kw, n=256, steps=5, warmup=2):
                      "mass_rel_drift": abs(float((vol * Q[0]).sum()) - mass0) / mass0,
                      "energy_rel_drift": abs(float((vol * Q[4]).sum()) - energy0) / energy0,
                      "device_flags": K.cgks_check(ctx)[1]}
+        if check_oracle:
+            # untimed: stage 1 from the initial state on corner and side cells against the oracle
+            from oracle import oracle as O
+            rng = np.random.default_rng(8965 + bc)
+            sides = rng.integers(0, n, size=(24, 3))
+            sides[np.arange(24), rng.integers(0, 3, size=24)] = rng.choice([0, n - 1], size=24)
+            cells = np.unique(np.concatenate([sides[:, 0] + n * (sides[:, 1] + n * sides[:, 2]),
+                                              [0, n - 1, N - n, N - 1]])).astype(np.int64)
+            dt_fix = 3.5e-4 * 256 / n
+            Qh, Gh, Lh = Q0.cpu().numpy(), G0.cpu().numpy(), L0.cpu().numpy()
+            st, oq, og, ol = O.stage1_cells(m, nodes.numpy(), O.params(bc=(bc,) * 6, **kw), dt_fix, Qh, Gh, Lh,
+                                            cells)
+            del Qh, Gh, Lh
+            Q.copy_(Q0)
+            G.copy_(G0)
+            L.copy_(L0)
+            dt.fill_(dt_fix)
+            K.cgks_stage(ctx, 1, dt, Q, G, L)
+            torch.cuda.synchronize()
+            ci = torch.from_numpy(cells).to(dev)
+            rel = lambda a, b: float(np.linalg.norm(a - b) / np.linalg.norm(b))
+            res[name]["parity_vs_oracle"] = {
+                "stage": 1, "cells": int(len(cells)), "oracle_status": int(st),
+                "rel_l2_Q": rel(Q[:, ci].T.cpu().numpy(), oq),
+                "rel_l2_G": rel(G[:, :, ci].permute(2, 0, 1).cpu().numpy(), og),
+                "rel_l2_L": rel(L[:, :, ci].permute(2, 0, 1).cpu().numpy(), ol)}
         ctx.close()
         del Q, G, L, vol
         torch.cuda.empty_cache()
@@ -626,7 +653,8 @@ def main():
     # ---- wall sides (symmetry planes, no-slip walls) at the headline size -------------------
     walls = None
     if not args.no_walls:
-        walls = bench_walls(K, W, torch, kw, n=args.n, steps=args.steps, warmup=args.warmup)
+        walls = bench_walls(K, W, torch, kw, n=args.n, steps=args.steps, warmup=args.warmup,
+                            check_oracle=not args.no_oracle)
 
     # ---- supersonic Taylor-Green vortex: robustness of the nonlinear scheme ------------------
     supersonic = None

@@ -1272,17 +1272,22 @@ int oracle_s2o4(long n, double dt, const double *q, const double *Ln, const doub
 
 /* Stage 1 (from the given state at t^n with step dt) for the listed cells only, without
    metrics of the whole mesh: each cell reconstructs itself and its six face neighbours,
-   evaluates the fluxes of its 24 face Gauss points and applies the stage-1 update.
+   evaluates the fluxes of its 24 face Gauss points and applies the stage-1 update.  A face on
+   a wall side takes the flux of the cell's own face values against their mirror image.
    outQ [n][5], outG [n][5][3], outL [n][5][12]. */
 int oracle_stage1_cells(const int dims[3], const double *nodes, const or_params *P, double dt, const double *Q,
                         const double *G, const double *L, const long *cells, long ncells, double *outQ,
                         double *outG, double *outL) {
     if (!(dt > 0) || !Q || !G || !L || !cells || ncells < 0) return OR_EINVAL;
-    for (int s = 0; s < 6; ++s)
-        if (P->bc[s]) return OR_EINVAL; /* periodic blocks only */
     init_consts();
     or_mesh M;
     memset(&M, 0, sizeof M);
+    for (int s = 0; s < 6; ++s) {
+        if (P->bc[s] < 0 || P->bc[s] > 2) return OR_EINVAL;
+        M.bc[s] = P->bc[s];
+    }
+    for (int q = 0; q < 3; ++q)
+        if ((M.bc[2 * q] == 0) != (M.bc[2 * q + 1] == 0)) return OR_EINVAL;
     M.nx = dims[0]; M.ny = dims[1]; M.nz = dims[2];
     if (M.nx < 1 || M.ny < 1 || M.nz < 1 || !nodes) return OR_EINVAL;
     M.n = (long)M.nx * M.ny * M.nz;
@@ -1295,14 +1300,18 @@ int oracle_stage1_cells(const int dims[3], const double *nodes, const or_params 
         int i = c % M.nx, j = (c / M.nx) % M.ny, k = c / ((long)M.nx * M.ny);
         double rec[7][NGP][NV][4];
         long who[7];
+        int wallf[6]; /* face m is a wall side of the block */
+        const int nd[3] = {M.nx, M.ny, M.nz};
         who[0] = c;
         for (int m = 0; m < 6; ++m) {
             int idx[3] = {i, j, k};
+            wallf[m] = M.bc[m] && idx[m / 2] == ((m % 2) ? nd[m / 2] - 1 : 0);
             idx[m / 2] += (m % 2) ? 1 : -1;
             who[1 + m] = cell_id(&M, idx[0], idx[1], idx[2]);
         }
         double vol0 = 0;
         for (int w = 0; w < 7; ++w) {
+            if (w > 0 && wallf[w - 1]) continue; /* no neighbour behind a wall face */
             long cw = who[w];
             int iw = cw % M.nx, jw = (cw / M.nx) % M.ny, kw = cw / ((long)M.nx * M.ny);
             double vol, J[9], JiT[9];
@@ -1319,16 +1328,35 @@ int oracle_stage1_cells(const int dims[3], const double *nodes, const or_params 
             const double (*lrec)[NV][4] = (m % 2) ? rec[0] : rec[1 + m];
             const double (*rrec)[NV][4] = (m % 2) ? rec[1 + m] : rec[0];
             int io = owner % M.nx, jo = (owner / M.nx) % M.ny, ko = owner / ((long)M.nx * M.ny);
+            if (wallf[m] && m % 2 == 0) { io = i; jo = j; ko = k; if (q == 0) io = -1; else if (q == 1) jo = -1; else ko = -1; }
             for (int g = 0; g < 4; ++g) {
                 face_gp_geom(&M, io, jo, ko, q, g, &fn[m][3 * g], &fw[m][g]);
                 double ql[5], qr[5], gl[5][3], gr[5][3];
                 int gpl = 4 * (2 * q + 1) + g, gpr = 4 * (2 * q) + g;
-                for (int v = 0; v < 5; ++v) {
-                    ql[v] = lrec[gpl][v][0]; qr[v] = rrec[gpr][v][0];
-                    for (int r = 0; r < 3; ++r) { gl[v][r] = lrec[gpl][v][1 + r]; gr[v][r] = rrec[gpr][v][1 + r]; }
+                if (wallf[m]) {
+                    /* wall face: the own side against its mirror image */
+                    if (m % 2) {
+                        for (int v = 0; v < 5; ++v) {
+                            ql[v] = rec[0][gpl][v][0];
+                            for (int r = 0; r < 3; ++r) gl[v][r] = rec[0][gpl][v][1 + r];
+                        }
+                        mirror_state(&M, m, ql, (const double (*)[3])gl, qr, gr);
+                    } else {
+                        for (int v = 0; v < 5; ++v) {
+                            qr[v] = rec[0][gpr][v][0];
+                            for (int r = 0; r < 3; ++r) gr[v][r] = rec[0][gpr][v][1 + r];
+                        }
+                        mirror_state(&M, m, qr, (const double (*)[3])gr, ql, gl);
+                    }
+                } else {
+                    for (int v = 0; v < 5; ++v) {
+                        ql[v] = lrec[gpl][v][0]; qr[v] = rrec[gpr][v][0];
+                        for (int r = 0; r < 3; ++r) { gl[v][r] = lrec[gpl][v][1 + r]; gr[v][r] = rrec[gpr][v][1 + r]; }
+                    }
                 }
                 if (gks_flux(P, ql, gl, qr, gr, &fn[m][3 * g], dt, fr[m].F[g], fr[m].Ft[g], fr[m].side[g]))
                     bad |= 2;
+                if (wallf[m] && M.bc[m] == 2) noslip_flux(fr[m].F[g], fr[m].Ft[g]);
             }
         }
         const face_rec *fs[6];

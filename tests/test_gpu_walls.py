@@ -201,3 +201,53 @@ def test_graph_replay_with_walls_matches_eager():
         torch.cuda.synchronize()
     ctx.close()
     assert torch.equal(Qd, Qe) and torch.equal(Gd, Ge) and torch.equal(Ld, Le)
+
+
+def _boundary_sample(n, rng, k=40):
+    """Cells on every wall side, edge and corner of an n^3 block, plus random interior cells."""
+    nx = ny = nz = n
+    pick = set()
+    for i in (0, nx - 1):
+        for j in (0, ny - 1):
+            for kk in (0, nz - 1):
+                pick.add(i + nx * (j + ny * kk))  # corners
+    for _ in range(k):
+        c = [int(x) for x in rng.integers(0, n, size=3)]
+        c[int(rng.integers(0, 3))] = int(rng.choice([0, n - 1]))  # on a side
+        pick.add(c[0] + nx * (c[1] + ny * c[2]))
+    pick.update(int(x) for x in rng.choice(n ** 3, size=8, replace=False))
+    return np.array(sorted(pick), dtype=np.int64)
+
+
+@pytest.mark.parametrize("bc", [1, 2])
+def test_walls_stage1_sampled_parity_full_size(bc):
+    """Stage 1 of the 256^3 wall box (the bench's wall workload and launch configuration) on
+    corner, side and interior cells that the oracle evaluates one by one."""
+    n = (256, 256, 256)
+    print(f"walls full size bc {bc}", flush=True)
+    nodes = W.wall_perturbed_nodes(n, device=dev())
+    Q, G, L = W.initial_state(nodes, W.taylor_green(Ma=0.1), GAM)
+    nodes_h = nodes.cpu()
+    del nodes
+    kw = tgv_kw(Ma=0.1, bc=(bc,) * 6)
+    cells = _boundary_sample(256, np.random.default_rng(29))
+    dt = 3.5e-4
+    Qh, Gh, Lh = Q.cpu().numpy(), G.cpu().numpy(), L.cpu().numpy()
+    st, oq, og, ol = O.stage1_cells(n, nodes_h.numpy(), O.params(**kw), dt, Qh, Gh, Lh, cells)
+    assert st == 0
+    ctx = K().Context([n], [nodes_h], K().default_params(**kw))
+    dtd = torch.full((1,), dt, dtype=torch.float64, device=dev())
+    K().cgks_stage(ctx, 1, dtd, Q, G, L)
+    torch.cuda.synchronize()
+    assert K().cgks_check(ctx) == (0, 0)
+    ci = torch.from_numpy(cells).to(dev())
+    gq = Q[:, ci].cpu().numpy()
+    gg = G[:, :, ci].cpu()
+    gl = L[:, :, ci].cpu()
+    ctx.close()
+    del Q, G, L
+    torch.cuda.empty_cache()
+    Qs = Qh[:, cells]
+    assert rel_l2(gq, oq.T) <= TOL, rel_l2(gq, oq.T)
+    assert_derived(gg, og.transpose(1, 2, 0), Qs, "G", h=math.pi / 256)
+    assert_derived(gl, ol.transpose(1, 2, 0), Qs, "L")

@@ -171,3 +171,26 @@ def test_walls_on_sides_that_are_not_axis_planes_are_refused():
         O.cfl_dt(dims, nodes.numpy(), O.params(bc=(1, 1, 0, 0, 0, 0)), Q)
     # the same mesh is accepted with periodic sides
     assert O.cfl_dt(dims, nodes.numpy(), O.params(), Q) > 0
+
+
+@pytest.mark.parametrize("bc", [(1, 1, 2, 2, 1, 1), (2, 2, 1, 1, 0, 0)])
+def test_sampled_stage1_with_walls_matches_the_whole_mesh_stage(bc):
+    """The per-cell stage-1 entry point (used for sampled parity at full size) against a stage
+    over the whole mesh, for corner, edge, face and interior cells."""
+    dims = (7, 6, 5)
+    nodes = W.wall_perturbed_nodes(dims)
+    if bc[4] == 0:
+        nodes[..., 2] *= 2.0  # periodic z spans the field's period
+    Q, G, L = _state(nodes, W.taylor_green(Ma=0.3))
+    P = _tgv_prm(bc)
+    dt = 0.5 * O.cfl_dt(dims, nodes.numpy(), P, Q)
+    N = Q.shape[1]
+    cells = np.array([0, dims[0] - 1, N - 1, N - dims[0], 3 + 7 * 2 + 42 * 2, 7 * 3, 42 * 4 + 6, 5], dtype=np.int64)
+    st, oq, og, ol = O.stage1_cells(dims, nodes.numpy(), P, dt, Q, G, L, cells)
+    assert st == 0
+    Qs, Gs, Ls = Q.copy(), G.copy(), L.copy()
+    stash = np.zeros((90, N))
+    assert O.stage(dims, nodes.numpy(), P, 1, dt, Qs, Gs, Ls, stash) == 0
+    assert np.max(np.abs(oq - Qs[:, cells].T)) <= 1e-14 * np.max(np.abs(Qs))
+    assert np.max(np.abs(og - Gs[:, :, cells].transpose(2, 0, 1))) <= 1e-12 * np.max(np.abs(Gs))
+    assert np.max(np.abs(ol - Ls[:, :, cells].transpose(2, 0, 1))) <= 1e-12 * np.max(np.abs(Ls))
