@@ -93,8 +93,10 @@ typedef struct {
                             |p_m - p_0| / (p_m + p_0) above this (default 0.05)            */
     int bc[6];           /* side types of every block, sides x-, x+, y-, y+, z-, z+:
                             0 periodic (default), 1 symmetry plane (slip, adiabatic),
-                            2 no-slip adiabatic wall.  The two sides of an axis are both
-                            periodic or both walls.  Sec. 5 names walls but gives no
+                            2 no-slip adiabatic wall, 3 far field (the ghost data are the
+                            uniform state farfield, and a far-field face takes the
+                            gas-kinetic flux between the interior Gauss-point state and
+                            it).  The two sides of an axis are both periodic or both not.  Sec. 5 names walls but gives no
                             treatment for the compact stencil; here a neighbour behind a
                             wall is the mirror image of its mirror cell inside (average and
                             cell-averaged gradient reflected across the wall plane, with the
@@ -107,6 +109,8 @@ typedef struct {
                             tangential node coordinates (EINVAL at creation otherwise).
                             Walls need recon_impl 0 and GENO weights (EUNSUPPORTED), and
                             cgks_weights refuses contexts with walls                      */
+    double farfield[5];  /* far-field state (rho, rho U, rho V, rho W, rho E) of bc 3 sides;
+                            positive density and pressure (EINVAL otherwise)             */
 } cgks_params;
 
 /* Fill *p with the defaults listed above (inviscid, nonlinear, FP64). */

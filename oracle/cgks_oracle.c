@@ -75,7 +75,9 @@ typedef struct {
     int linear;              /* 1: chi = 1, linear CGKS-5 */
     int prandtl_fix;         /* 1: heat-flux correction to Pr (viscous only) */
     int bc[6];               /* sides x-, x+, y-, y+, z-, z+: 0 periodic, 1 symmetry plane
-                                (slip, adiabatic), 2 no-slip adiabatic wall (reading D26) */
+                                (slip, adiabatic), 2 no-slip adiabatic wall (reading D26),
+                                3 far field (reading D27) */
+    double far[5];           /* far-field state (conserved variables) */
 } or_params;
 
 enum { OR_OK = 0, OR_EINVAL = -1, OR_ENONPHYS = -4 };
@@ -371,6 +373,20 @@ static void mirror_state(const or_mesh *M, int s, const double q[5], const doubl
     }
 }
 
+/* Ghost state across side s: the mirror image at a symmetry plane or no-slip wall; at a far-field
+   side the prescribed far-field state, uniform (zero gradient), reading D27. */
+static void ghost_state(const or_mesh *M, const or_params *P, int s, const double q[5], const double g[5][3],
+                        double qm[5], double gm[5][3]) {
+    if (M->bc[s] == 3) {
+        for (int v = 0; v < 5; ++v) {
+            qm[v] = P->far[v];
+            gm[v][0] = gm[v][1] = gm[v][2] = 0.0;
+        }
+    } else {
+        mirror_state(M, s, q, g, qm, gm);
+    }
+}
+
 /* trilinear map of a cell on [-1/2,1/2]^3 and its Jacobian (Appendix) */
 static void trilinear(const or_mesh *M, int i, int j, int k, const double xi[3], double X[3], double Jm[3][3]) {
     for (int r = 0; r < 3; ++r) { X[r] = 0; Jm[r][0] = Jm[r][1] = Jm[r][2] = 0; }
@@ -458,7 +474,7 @@ static int mesh_build(or_mesh *M, const int dims[3], const double *nodes, const 
     M->bfn = M->bfw = NULL;
     for (int s = 0; s < 6; ++s) M->bc[s] = P ? P->bc[s] : 0;
     for (int q = 0; q < 3; ++q) {
-        if (M->bc[2 * q] < 0 || M->bc[2 * q] > 2 || M->bc[2 * q + 1] < 0 || M->bc[2 * q + 1] > 2) return OR_EINVAL;
+        if (M->bc[2 * q] < 0 || M->bc[2 * q] > 3 || M->bc[2 * q + 1] < 0 || M->bc[2 * q + 1] > 3) return OR_EINVAL;
         if ((M->bc[2 * q] == 0) != (M->bc[2 * q + 1] == 0)) return OR_EINVAL; /* periodic pairs */
     }
     if (M->nx < 1 || M->ny < 1 || M->nz < 1 || !nodes) return OR_EINVAL;
@@ -572,14 +588,20 @@ static void recon_cell(const or_mesh *M, const or_params *P, const double *Q, co
             const long nb = (t < 6) ? fnb[t] : enb[t - 6];
             const int *sd = (t < 6) ? fside[t] : eside[t - 6];
             double sv = 1.0, sr[3] = {1.0, 1.0, 1.0};
+            int far = 0;
             for (int q = 0; q < 3; ++q)
                 if (sd[q] >= 0) {
+                    far |= M->bc[sd[q]] == 3;
                     double m = mirror_sign(M, sd[q], v);
                     sv *= m;
                     for (int r = 0; r < 3; ++r) sr[r] *= (r == q) ? -m : m;
                 }
             nq[t] = sv * Q[v * N + nb];
             for (int r = 0; r < 3; ++r) ngr[t][r] = sr[r] * G[(v * 3 + r) * N + nb];
+            if (far) { /* behind a far-field side: the uniform far-field state */
+                nq[t] = P->far[v];
+                ngr[t][0] = ngr[t][1] = ngr[t][2] = 0.0;
+            }
         }
         double q0 = Q[v * N + c], b[NR], a[NB];
         for (int m = 0; m < 6; ++m) b[m] = nq[m] - q0;
@@ -1077,7 +1099,7 @@ static int run_stage(const or_mesh *M, const or_params *P, int stage, double dt,
                 for (int r = 0; r < 3; ++r) { gl[v][r] = rec[c][gpl][v][1 + r]; gr[v][r] = rec[cr][gpr][v][1 + r]; }
             }
             /* plus-side wall: the right state is the mirror image of the left one */
-            if (at_wall) mirror_state(M, 2 * q + 1, ql, (const double (*)[3])gl, qr, gr);
+            if (at_wall) ghost_state(M, P, 2 * q + 1, ql, (const double (*)[3])gl, qr, gr);
             if (gks_flux(P, ql, gl, qr, gr, &M->fn[(4 * f + g) * 3], dt, fr[f].F[g], fr[f].Ft[g], fr[f].side[g]))
                 bad = 1;
             if (at_wall && M->bc[2 * q + 1] == 2) noslip_flux(fr[f].F[g], fr[f].Ft[g]);
@@ -1087,7 +1109,7 @@ static int run_stage(const or_mesh *M, const or_params *P, int stage, double dt,
                     qr[v] = rec[cr][gpr][v][0];
                     for (int r = 0; r < 3; ++r) gr[v][r] = rec[cr][gpr][v][1 + r];
                 }
-                mirror_state(M, 2 * q, qr, (const double (*)[3])gr, ql, gl);
+                ghost_state(M, P, 2 * q, qr, (const double (*)[3])gr, ql, gl);
                 if (gks_flux(P, ql, gl, qr, gr, &M->bfn[((3 * cr + q) * 4 + g) * 3], dt, frb[f].F[g], frb[f].Ft[g],
                              frb[f].side[g]))
                     bad = 1;
@@ -1283,7 +1305,7 @@ int oracle_stage1_cells(const int dims[3], const double *nodes, const or_params 
     or_mesh M;
     memset(&M, 0, sizeof M);
     for (int s = 0; s < 6; ++s) {
-        if (P->bc[s] < 0 || P->bc[s] > 2) return OR_EINVAL;
+        if (P->bc[s] < 0 || P->bc[s] > 3) return OR_EINVAL;
         M.bc[s] = P->bc[s];
     }
     for (int q = 0; q < 3; ++q)
@@ -1340,13 +1362,13 @@ int oracle_stage1_cells(const int dims[3], const double *nodes, const or_params 
                             ql[v] = rec[0][gpl][v][0];
                             for (int r = 0; r < 3; ++r) gl[v][r] = rec[0][gpl][v][1 + r];
                         }
-                        mirror_state(&M, m, ql, (const double (*)[3])gl, qr, gr);
+                        ghost_state(&M, P, m, ql, (const double (*)[3])gl, qr, gr);
                     } else {
                         for (int v = 0; v < 5; ++v) {
                             qr[v] = rec[0][gpr][v][0];
                             for (int r = 0; r < 3; ++r) gr[v][r] = rec[0][gpr][v][1 + r];
                         }
-                        mirror_state(&M, m, qr, (const double (*)[3])gr, ql, gl);
+                        ghost_state(&M, P, m, qr, (const double (*)[3])gr, ql, gl);
                     }
                 } else {
                     for (int v = 0; v < 5; ++v) {
@@ -1519,9 +1541,13 @@ int oracle_features(const int dims[3], const double *nodes, const or_params *P, 
                 double f[MLP_IN], mx = 0.0;
                 for (int m = 0; m < 6; ++m) {
                     double sv = 1.0; /* mirrored neighbour behind a wall (the pressure is even) */
+                    int far = 0;
                     for (int q = 0; q < 3; ++q)
-                        if (sd[m][q] >= 0) sv *= mirror_sign(&M, sd[m][q], v);
-                    f[m] = sv * Q[v * N + nb[m]] - Q[v * N + c];
+                        if (sd[m][q] >= 0) {
+                            sv *= mirror_sign(&M, sd[m][q], v);
+                            far |= M.bc[sd[m][q]] == 3;
+                        }
+                    f[m] = (far ? P->far[v] : sv * Q[v * N + nb[m]]) - Q[v * N + c];
                 }
                 for (int s = 0; s < 12; ++s) f[6 + s] = L[(v * 12 + s) * N + c];
                 for (int a = 0; a < MLP_IN; ++a) mx = fabs(f[a]) > mx ? fabs(f[a]) : mx;

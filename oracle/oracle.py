@@ -42,6 +42,7 @@ class Params(C.Structure):
         ("linear", C.c_int),
         ("prandtl_fix", C.c_int),
         ("bc", C.c_int * 6),
+        ("far", C.c_double * 5),
     ]
 
 
@@ -49,9 +50,10 @@ def params(**kw) -> Params:
     """Oracle parameters; defaults are the paper's constants (Sec. 3.3, Sec. 5)."""
     d = dict(gamma=1.4, cfl=0.5, tau_eps=0.05, tau_C=5.0, mu0=0.0, T_ref=1.0, S_suth=0.0,
              Pr=1.0, geno_C=150.0, geno_eps=1e-15, geno_r=2.0, viscous=0, visc_law=0,
-             tau_zero=0, linear=0, prandtl_fix=0, bc=(0, 0, 0, 0, 0, 0))
+             tau_zero=0, linear=0, prandtl_fix=0, bc=(0, 0, 0, 0, 0, 0), far=(1.0, 0.0, 0.0, 0.0, 2.5))
     d.update(kw)
     d["bc"] = (C.c_int * 6)(*d["bc"])
+    d["far"] = (C.c_double * 5)(*d["far"])
     return Params(**d)
 
 

@@ -26,6 +26,7 @@ class Params(C.Structure):
         ("viscous", C.c_int), ("visc_law", C.c_int), ("tau_zero", C.c_int), ("linear", C.c_int),
         ("prandtl_fix", C.c_int), ("recon_prec", C.c_int), ("flux_prec", C.c_int), ("recon_impl", C.c_int),
         ("per_block", C.c_int), ("weights", C.c_int), ("jump_thresh", C.c_double), ("bc", C.c_int * 6),
+        ("farfield", C.c_double * 5),
     ]
 
 
@@ -95,7 +96,11 @@ def default_params(**kw) -> Params:
     for k, v in kw.items():
         if not hasattr(p, k):
             raise KeyError(k)
-        setattr(p, k, (C.c_int * 6)(*v) if k == "bc" else v)
+        if k == "bc":
+            v = (C.c_int * 6)(*v)
+        elif k == "farfield":
+            v = (C.c_double * 5)(*v)
+        setattr(p, k, v)
     return p
 
 

@@ -148,6 +148,7 @@ static DevParams make_dev_params(const cgks_params &p) {
     d.prandtl_fix = p.prandtl_fix;
     d.weights = p.weights;
     d.jump_thresh = p.jump_thresh;
+    for (int v = 0; v < 5; ++v) d.far[v] = p.farfield[v];
     return d;
 }
 
@@ -173,13 +174,20 @@ static int check_params(const cgks_params *p) {
     bool walls = false;
     for (int q = 0; q < 3; ++q) {
         const int a = p->bc[2 * q], b = p->bc[2 * q + 1];
-        if (a < 0 || a > 2 || b < 0 || b > 2) return fail(CGKS_EINVAL, "bc entries must be 0, 1 or 2");
+        if (a < 0 || a > 3 || b < 0 || b > 3) return fail(CGKS_EINVAL, "bc entries must be 0, 1, 2 or 3");
         if ((a == 0) != (b == 0)) return fail(CGKS_EINVAL, "the two sides of an axis are both periodic or both walls");
         walls = walls || a != 0;
     }
     if (walls && p->recon_impl != 0)
         return fail(CGKS_EUNSUPPORTED, "wall sides need the matrix-core reconstruction (recon_impl 0)");
     if (walls && p->weights != 0) return fail(CGKS_EUNSUPPORTED, "wall sides need GENO weights");
+    for (int sd = 0; sd < 6; ++sd)
+        if (p->bc[sd] == 3) {
+            const double *f = p->farfield;
+            const double ke = 0.5 * (f[1] * f[1] + f[2] * f[2] + f[3] * f[3]) / f[0];
+            if (!(f[0] > 0.0) || !((p->gamma - 1.0) * (f[4] - ke) > 0.0))
+                return fail(CGKS_EINVAL, "far-field state needs positive density and pressure");
+        }
     return CGKS_OK;
 }
 
@@ -415,6 +423,7 @@ int cgks_ctx_create(cgks_ctx **out, int nblocks, const int *dims, const double *
             for (int sd = 0; sd < 2; ++sd) {
                 bv.wall |= 1 << (2 * q + sd);
                 if (p->bc[2 * q + sd] == 2) bv.wall |= 1 << (8 + 2 * q + sd);
+                if (p->bc[2 * q + sd] == 3) bv.wall |= 1 << (16 + 2 * q + sd);
             }
             bv.wbase[q] = Wtot;
             Wtot += bv.N / ((q == 0) ? bv.nx : (q == 1) ? bv.ny : bv.nz);

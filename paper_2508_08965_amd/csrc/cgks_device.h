@@ -15,8 +15,9 @@ struct BlockView {
     int nx, ny, nz;
     long N;    // cells of the block
     long off;  // offset of the block's first cell in the concatenated state
-    // Sides s = 2q + (0 minus, 1 plus) of axis q: bit s marks a wall (symmetry plane or no-slip
-    // wall), bit 8 + s a no-slip wall; 0 for a periodic block.  Walls come in pairs per axis.
+    // Sides s = 2q + (0 minus, 1 plus) of axis q: bit s marks a non-periodic side (symmetry
+    // plane, no-slip wall or far field), bit 8 + s a no-slip wall, bit 16 + s a far-field side;
+    // 0 for a periodic block.  Non-periodic sides come in pairs per axis.
     int wall;
     // Per axis with walls: offset of the block's minus-side wall faces in the wall-face buffer
     // (one entry per face of that side, index i_a + n_a i_b over the tangential axes a < b).

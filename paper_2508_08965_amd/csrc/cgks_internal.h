@@ -72,6 +72,7 @@ struct DevParams {
     double jump_thresh;          // pressure-jump indicator of the learned-weight fallback
     int viscous, visc_law, tau_zero, linear, prandtl_fix;
     int weights;                 // 0 GENO weights, 1 learned weights with GENO fallback
+    double far[5];               // far-field state (conserved variables) of far-field sides
 };
 
 }  // namespace cgks

@@ -565,12 +565,13 @@ __global__ void __launch_bounds__(256) k_flux_wall(BlockView b, int q, long Ntot
         for (int r = 0; r < 3; ++r) gv[v][r] = (TC)src[(4 * v + 1 + r) * Ntot];
     }
     if (sd == w) {
+        const bool far = (b.wall >> (16 + side)) & 1;  // far field: the uniform far-field state
 #pragma unroll
         for (int v = 0; v < 5; ++v) {
             const TC m = (TC)mirror_sign(b.wall, side, v);
-            qv[v] *= m;
+            qv[v] = far ? (TC)P.far[v] : qv[v] * m;
 #pragma unroll
-            for (int r = 0; r < 3; ++r) gv[v][r] *= (r == q) ? -m : m;
+            for (int r = 0; r < 3; ++r) gv[v][r] = far ? (TC)0 : ((r == q) ? -m : m) * gv[v][r];
         }
     }
 #pragma unroll

@@ -98,10 +98,11 @@ __device__ inline int wall_touch(const BlockView &b, int ci, int cj, int ck, Cel
     if ((w & 32) && ck == b.nz - 1) { t |= 32; gn.dp[2] = 0; }
     return t;
 }
-// Mirror image of a neighbour's average and physical gradient of variable v across the wall
-// sides in `crossed`: the average changes sign with the variable (mirror_sign), the gradient
-// also in its component normal to each wall.
-__device__ inline void ghost_mirror(int wall, int crossed, int v, double &q, double g[3]) {
+// Ghost neighbour behind the sides in `crossed`: behind a far-field side the uniform far-field
+// state (zero gradient); otherwise the mirror image of its mirror cell's average and physical
+// gradient of variable v: the average changes sign with the variable (mirror_sign), the
+// gradient also in its component normal to each wall.
+__device__ inline void ghost_mirror(int wall, int crossed, int v, double farv, double &q, double g[3]) {
 #pragma unroll
     for (int s = 0; s < 6; ++s)
         if ((crossed >> s) & 1) {
@@ -110,6 +111,10 @@ __device__ inline void ghost_mirror(int wall, int crossed, int v, double &q, dou
 #pragma unroll
             for (int r = 0; r < 3; ++r) g[r] *= (r == (s >> 1)) ? -m : m;
         }
+    const bool far = ((wall >> 16) & crossed) != 0;
+    q = far ? farv : q;
+#pragma unroll
+    for (int r = 0; r < 3; ++r) g[r] = far ? 0.0 : g[r];
 }
 // Wall sides crossed by gather step st of a lane whose edge signs are (sa, sb).
 __device__ inline int step_crossed(int touch, int st, int sa, int sb) {
@@ -273,6 +278,12 @@ __global__ void __launch_bounds__(512) k_recon_mfma(WorkList W, long Ntot, const
             // (32.5 against 33.5 ms per FP64 launch at 256^3, bitwise equal results).
             CellNb gn = cn;
             const int touch = wall_touch(b, ci, cj, ck, gn);
+            // far-field value of this wave's variable (wave-uniform selects, no indexed access)
+            const double farv = (v == 0)   ? P.far[0]
+                                : (v == 1) ? P.far[1]
+                                : (v == 2) ? P.far[2]
+                                : (v == 3) ? P.far[3]
+                                           : P.far[4];
             double nq[9], ng[9][3];
     #pragma unroll
             for (int st = 0; st < 9; ++st) {
@@ -291,7 +302,7 @@ __global__ void __launch_bounds__(512) k_recon_mfma(WorkList W, long Ntot, const
     #pragma unroll
             for (int st = 0; st < 9; ++st) {
                 const int crossed = step_crossed(touch, st, sa, sb);
-                if (crossed) ghost_mirror(b.wall, crossed, v, nq[st], ng[st]);
+                if (crossed) ghost_mirror(b.wall, crossed, v, farv, nq[st], ng[st]);
             }
     #pragma unroll
             for (int st = 0; st < 9; ++st) {
@@ -627,6 +638,12 @@ __global__ void __launch_bounds__(512) k_recon_bf16(WorkList W, long Ntot, const
             // (32.5 against 33.5 ms per FP64 launch at 256^3, bitwise equal results).
             CellNb gn = cn;
             const int touch = wall_touch(b, ci, cj, ck, gn);
+            // far-field value of this wave's variable (wave-uniform selects, no indexed access)
+            const double farv = (v == 0)   ? P.far[0]
+                                : (v == 1) ? P.far[1]
+                                : (v == 2) ? P.far[2]
+                                : (v == 3) ? P.far[3]
+                                           : P.far[4];
             double nq[9], ng[9][3];
     #pragma unroll
             for (int st = 0; st < 9; ++st) {
@@ -645,7 +662,7 @@ __global__ void __launch_bounds__(512) k_recon_bf16(WorkList W, long Ntot, const
     #pragma unroll
             for (int st = 0; st < 9; ++st) {
                 const int crossed = step_crossed(touch, st, sa, sb);
-                if (crossed) ghost_mirror(b.wall, crossed, v, nq[st], ng[st]);
+                if (crossed) ghost_mirror(b.wall, crossed, v, farv, nq[st], ng[st]);
             }
             double lvd[3];
     #pragma unroll

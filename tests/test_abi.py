@@ -94,7 +94,7 @@ def test_wall_sides_rejected_on_the_host():
         return L.cgks_ctx_create(C.byref(h), 1, dims, ptrs, C.byref(K.default_params(**kw)), None)
 
     box = W.cartesian_nodes((4, 4, 4))
-    for bc in ((1, 0, 0, 0, 0, 0), (0, 0, 2, 0, 0, 0), (3, 3, 0, 0, 0, 0), (-1, -1, 0, 0, 0, 0)):
+    for bc in ((1, 0, 0, 0, 0, 0), (0, 0, 2, 0, 0, 0), (4, 4, 0, 0, 0, 0), (-1, -1, 0, 0, 0, 0)):
         assert create(box, bc=bc) == K.EINVAL, bc
     assert create(box, bc=(1, 1, 0, 0, 0, 0), recon_impl=1) == K.EUNSUPPORTED
     assert create(box, bc=(2, 2, 0, 0, 0, 0), weights=1) == K.EUNSUPPORTED
@@ -105,3 +105,20 @@ def test_wall_sides_rejected_on_the_host():
     moved[:, :, 4, 1] += 0.01
     assert create(moved, bc=(1, 1, 0, 0, 0, 0)) == K.EINVAL
     assert "wall side" in K.last_error()
+
+
+def test_far_field_state_checked_on_the_host():
+    if not os.path.exists(K.LIB_PATH):
+        pytest.skip("library not built")
+    import numpy as np
+    from paper_2508_08965_amd import workloads as W
+    L = K.lib()
+    h = C.c_void_p()
+    dims = (C.c_int * 3)(4, 4, 4)
+    a = np.ascontiguousarray(W.cartesian_nodes((4, 4, 4)).numpy())
+    ptrs = (C.POINTER(C.c_double) * 1)(a.ctypes.data_as(C.POINTER(C.c_double)))
+    for far in ((0.0, 0, 0, 0, 2.5), (1.0, 0, 0, 0, 0.0), (1.0, 3.0, 0, 0, 2.5)):  # rho 0, p 0, p < 0
+        p = K.default_params(bc=(3, 3, 0, 0, 0, 0), farfield=far)
+        assert L.cgks_ctx_create(C.byref(h), 1, dims, ptrs, C.byref(p), None) == K.EINVAL, far
+    p = K.default_params(bc=(4, 4, 0, 0, 0, 0))
+    assert L.cgks_ctx_create(C.byref(h), 1, dims, ptrs, C.byref(p), None) == K.EINVAL

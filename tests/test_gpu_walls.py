@@ -251,3 +251,46 @@ def test_walls_stage1_sampled_parity_full_size(bc):
     assert rel_l2(gq, oq.T) <= TOL, rel_l2(gq, oq.T)
     assert_derived(gg, og.transpose(1, 2, 0), Qs, "G", h=math.pi / 256)
     assert_derived(gl, ol.transpose(1, 2, 0), Qs, "L")
+
+
+def _pulse3d(rho0=1.0, p0=1.0 / GAM, amp=0.02, u=(0.2, 0.0, 0.0)):
+    """Gaussian pressure/density pulse at the centre of [0, pi]^3 in a uniform stream."""
+    def f(x, y, z):
+        r2 = (x - 1.6) ** 2 + (y - 1.5) ** 2 + (z - 1.55) ** 2
+        g = amp * torch.exp(-r2 / 0.3 ** 2)
+        return rho0 + g, u[0] + 0.0 * x, u[1] + 0.0 * x, u[2] + 0.0 * x, p0 * (1.0 + GAM * g)
+    e = p0 / (GAM - 1.0) + 0.5 * rho0 * sum(c * c for c in u)
+    return f, (rho0, rho0 * u[0], rho0 * u[1], rho0 * u[2], e)
+
+
+@pytest.mark.parametrize("bc", [(3,) * 6, (3, 3, 2, 2, 0, 0)])
+def test_far_field_parity_with_oracle(bc):
+    dims = (20, 18, 16)
+    nodes = W.wall_perturbed_nodes(dims)
+    if bc[4] == 0:
+        nodes[..., 2] *= 2.0
+    f, far = _pulse3d(u=(0.2, 0.0, 0.0))
+    Q, G, L = W.initial_state(nodes, f, GAM)
+    kw = dict(viscous=1, mu0=2e-3, bc=bc)
+    st, Qd, Gd, Ld, dts = run_gpu([dims], [nodes], K().default_params(farfield=far, **kw), Q, G, L, 6)
+    assert st == (0, 0)
+    sto, Qo, Go, Lo, dto, t = O.run(dims, nodes.numpy(), O.params(far=far, **kw), Q.numpy(), G.numpy(),
+                                    L.numpy(), 6)
+    assert sto == 0
+    assert dts[-1] == pytest.approx(dto, rel=1e-13)
+    assert rel_l2(Qd, Qo) <= TOL, rel_l2(Qd, Qo)
+    assert_derived(Gd, Go, Qo, "G", h=math.pi / max(dims))
+    assert_derived(Ld, Lo, Qo, "L")
+
+
+def test_far_field_keeps_its_free_stream_on_the_gpu():
+    dims = (24, 20, 16)
+    nodes = W.wall_perturbed_nodes(dims)
+    rho, u, p = 1.2, (0.3, -0.2, 0.1), 0.9
+    far = (rho, rho * u[0], rho * u[1], rho * u[2], p / (GAM - 1.0) + 0.5 * rho * sum(c * c for c in u))
+    Q, G, L = W.initial_state(nodes, W.uniform(rho=rho, u=u[0], v=u[1], w=u[2], p=p), GAM)
+    st, Qd, Gd, Ld, _ = run_gpu([dims], [nodes], K().default_params(viscous=1, mu0=0.01, bc=(3,) * 6, farfield=far),
+                                Q, G, L, 10)
+    assert st == (0, 0)
+    assert (Qd.cpu() - Q).abs().max().item() < 1e-13
+    assert Gd.abs().max().item() < 1e-11 and Ld.abs().max().item() < 1e-12
