@@ -144,6 +144,14 @@ void cgks_ctx_destroy(cgks_ctx *ctx);
  * stream; errors: CGKS_EINVAL for NULL arguments. */
 int cgks_diagnostics(cgks_ctx *ctx, const double *Q, const double *G, double *out, void *stream);
 
+/* Q-criterion of every cell, the vortex-identification field of the Taylor-Green section
+ * (Sec. 5): q = (|Omega|^2 - |S|^2) / 2 with S, Omega the symmetric and antisymmetric parts of
+ * the velocity gradient (Frobenius norms), the velocity gradient of a cell being
+ * (grad(rho U) - U grad rho) / rho from its cell averages and cell-averaged gradients.
+ * Q [5][N], G [5][3][N]: device state; out: device array of N doubles, overwritten.
+ * Enqueued on `stream`; EINVAL on a NULL argument. */
+int cgks_qcriterion(cgks_ctx *ctx, const double *Q, const double *G, double *out, void *stream);
+
 /* Total number of cells N of the context. */
 long cgks_num_cells(const cgks_ctx *ctx);
 

@@ -1627,3 +1627,29 @@ int oracle_diagnostics(const int dims[3], const double *nodes, const or_params *
     out[5] = pmin;
     return OR_OK;
 }
+
+/* Q-criterion of every cell (the vortex-identification field of the Taylor-Green section):
+ *   q = (|Omega|^2 - |S|^2) / 2 with S and Omega the symmetric and antisymmetric parts of the
+ * velocity gradient, |.| the Frobenius norm; the velocity gradient of a cell is
+ * (grad(rho U) - U grad rho) / rho from its cell averages and cell-averaged gradients (as for
+ * the enstrophy).  out[N]. */
+int oracle_qcriterion(const int dims[3], const double *Q, const double *G, double *out) {
+    if (!dims || !Q || !G || !out || dims[0] < 1 || dims[1] < 1 || dims[2] < 1) return OR_EINVAL;
+    const long N = (long)dims[0] * dims[1] * dims[2];
+    for (long c = 0; c < N; ++c) {
+        const double rho = Q[c];
+        double U[3], dU[3][3];
+        for (int i = 0; i < 3; ++i) U[i] = Q[(1 + i) * N + c] / rho;
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) dU[i][j] = (G[(3 * (1 + i) + j) * N + c] - U[i] * G[j * N + c]) / rho;
+        double s2 = 0.0, o2 = 0.0;
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) {
+                const double sij = 0.5 * (dU[i][j] + dU[j][i]), oij = 0.5 * (dU[i][j] - dU[j][i]);
+                s2 += sij * sij;
+                o2 += oij * oij;
+            }
+        out[c] = 0.5 * (o2 - s2);
+    }
+    return OR_OK;
+}

@@ -96,6 +96,7 @@ def lib():
         L.oracle_features.argtypes = [ip, dp, pp, dp, dp, lp, C.c_long, C.c_double, dp, ip]
         L.oracle_recon_weights.argtypes = [ip, dp, pp, dp, dp, dp, lp, C.c_long, dp, dp, dp]
         L.oracle_diagnostics.argtypes = [ip, dp, pp, dp, dp, dp]
+        L.oracle_qcriterion.argtypes = [ip, dp, dp, dp]
         _lib = L
     return _lib
 
@@ -288,3 +289,13 @@ def diagnostics(dims, nodes, prm, Q, G):
     if st:
         raise ValueError(f"oracle_diagnostics status {st}")
     return dict(Ek=out[0], epsS=out[1], rho_mean=out[2], rhoE_mean=out[3], rho_min=out[4], p_min=out[5])
+
+
+def qcriterion(dims, Q, G):
+    """Q-criterion of every cell, (|Omega|^2 - |S|^2) / 2 of the velocity gradient: [N]."""
+    Q, G = _arr(Q), _arr(G)
+    out = np.zeros(int(np.prod(dims)))
+    st = lib().oracle_qcriterion(_dims(dims), _d(Q), _d(G), _d(out))
+    if st:
+        raise ValueError(f"oracle_qcriterion status {st}")
+    return out

@@ -55,6 +55,7 @@ def lib():
         L.cgks_num_cells.restype = C.c_long
         L.cgks_dt.argtypes = [vp, vp, vp, vp]
         L.cgks_diagnostics.argtypes = [vp, vp, vp, vp, vp]
+        L.cgks_qcriterion.argtypes = [vp, vp, vp, vp, vp]
         L.cgks_stage.argtypes = [vp, C.c_int, vp, vp, vp, vp, vp]
         L.cgks_step.argtypes = [vp, vp, vp, vp, vp, C.c_int, vp]
         L.cgks_check.argtypes = [vp, ip]
@@ -174,6 +175,12 @@ def cgks_diagnostics(ctx: Context, Q, G, out, stream=None):
 
 
 DIAG_NAMES = ("Ek", "epsS", "rho_mean", "rhoE_mean", "rho_min", "p_min")
+
+
+def cgks_qcriterion(ctx: Context, Q, G, out, stream=None):
+    """Q-criterion of every cell into the device tensor out [N] (float64)."""
+    _check(lib().cgks_qcriterion(ctx.h, _ptr(Q, 5 * ctx.ncells, "Q"), _ptr(G, 15 * ctx.ncells, "G"),
+                                 _ptr(out, ctx.ncells, "out"), _stream(stream)), "cgks_qcriterion")
 
 
 def cgks_stage(ctx: Context, stage: int, dt_dev, Q, G, L, stream=None):

@@ -564,6 +564,14 @@ int cgks_diagnostics(cgks_ctx *ctx, const double *Q, const double *G, double *ou
     return CGKS_OK;
 }
 
+int cgks_qcriterion(cgks_ctx *ctx, const double *Q, const double *G, double *out, void *stream) {
+    if (!ctx || !Q || !G || !out) return fail(CGKS_EINVAL, "cgks_qcriterion: NULL argument");
+    hipStream_t s = (hipStream_t)stream;
+    ctx->last = s;
+    HIP_TRY(launch_qcriterion(ctx->Ntot, Q, G, out, s), "qcriterion");
+    return CGKS_OK;
+}
+
 int cgks_stage(cgks_ctx *ctx, int stage, const double *dt_dev, double *Q, double *G, double *L, void *stream) {
     if (!ctx || !dt_dev || !Q || !G || !L) return fail(CGKS_EINVAL, "cgks_stage: NULL argument");
     if (stage != 1 && stage != 2) return fail(CGKS_EINVAL, "cgks_stage: stage must be 1 or 2");

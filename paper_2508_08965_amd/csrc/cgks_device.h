@@ -508,6 +508,7 @@ hipError_t launch_dt_final(const double *part, int n, double *dt, hipStream_t s)
 // Flow diagnostics: part holds nparts * 7 doubles; out 6 doubles (see cgks_diagnostics).
 hipError_t launch_diagnostics(long Ntot, const double *Q, const double *G, const double *vol, const DevParams &P,
                               double *part, int nparts, double *out, hipStream_t s);
+hipError_t launch_qcriterion(long Ntot, const double *Q, const double *G, double *out, hipStream_t s);
 hipError_t launch_recon(const BlockView &b, long Ntot, const double *Q, const double *G, const double *L,
                         const Metrics &M, const DevConsts *K, const DevParams &P, double *gp, hipStream_t s);
 // Per-cell stored matrices (cgks_percell.hip): Rc (34 x 84) and Ec (96 x 34) per cell, tiled by

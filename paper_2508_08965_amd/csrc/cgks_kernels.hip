@@ -266,6 +266,37 @@ __global__ void __launch_bounds__(256) k_diag_partial(long Ntot, const double *_
     if ((int)threadIdx.x < kDiagVals) part[(long)blockIdx.x * kDiagVals + threadIdx.x] = red[threadIdx.x][0];
 }
 
+// Q-criterion of every cell: (|Omega|^2 - |S|^2) / 2 of the velocity gradient
+// (grad(rho U) - U grad rho) / rho; one thread per cell.
+__global__ void __launch_bounds__(256) k_qcrit(long Ntot, const double *__restrict__ Q, const double *__restrict__ G,
+                                               double *__restrict__ out) {
+    const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= Ntot) return;
+    const double rho = Q[c];
+    double U[3], dU[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) U[i] = Q[(1 + i) * Ntot + c] / rho;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) dU[i][j] = (G[(3 * (1 + i) + j) * Ntot + c] - U[i] * G[j * Ntot + c]) / rho;
+    double s2 = 0.0, o2 = 0.0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            const double sij = 0.5 * (dU[i][j] + dU[j][i]), oij = 0.5 * (dU[i][j] - dU[j][i]);
+            s2 += sij * sij;
+            o2 += oij * oij;
+        }
+    out[c] = 0.5 * (o2 - s2);
+}
+
+hipError_t launch_qcriterion(long Ntot, const double *Q, const double *G, double *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_qcrit, dim3((unsigned)((Ntot + 255) / 256)), dim3(256), 0, s, Ntot, Q, G, out);
+    return hipGetLastError();
+}
+
 __global__ void __launch_bounds__(256) k_diag_final(const double *__restrict__ part, int n, double *__restrict__ out) {
     __shared__ double red[kDiagVals][256];
     double acc[kDiagVals] = {0.0, 0.0, 0.0, 0.0, 0.0, INFINITY, INFINITY};

@@ -101,3 +101,25 @@ def test_supersonic_taylor_green_stays_physical_and_conservative():
     assert abs(d1[3] - d0[3]) <= 1e-13 * d0[3]  # total energy
     assert d0[0] == pytest.approx(0.125, abs=3e-3) and d1[0] < d0[0]  # kinetic energy dissipated
     assert d1[4] > 0 and d1[5] > 0
+
+
+def test_qcriterion_parity_with_oracle():
+    """Q-criterion of an evolved TGV state (perturbed mesh, several tiles and a ragged tail)
+    against the oracle's cell by cell."""
+    from paper_2508_08965_amd import cgks as K
+    n = (21, 18, 17)
+    nodes = W.perturbed_nodes(n, amp=0.05)
+    Q, G, L = W.initial_state(nodes, W.taylor_green(Ma=0.3), 1.4)
+    ctx = K.Context([n], [nodes], K.default_params(viscous=1, mu0=1.0 / 1600))
+    dev = torch.device("cuda:0")
+    Qd, Gd, Ld = Q.to(dev), G.to(dev), L.to(dev)
+    dt = torch.zeros(1, dtype=torch.float64, device=dev)
+    for _ in range(3):
+        K.cgks_step(ctx, Qd, Gd, Ld, dt, use_cfl=True)
+    out = torch.full((Qd.shape[1],), float("nan"), dtype=torch.float64, device=dev)
+    K.cgks_qcriterion(ctx, Qd, Gd, out)
+    torch.cuda.synchronize()
+    ref = O.qcriterion(n, Qd.cpu().numpy(), Gd.cpu().numpy())
+    ctx.close()
+    got = out.cpu().numpy()
+    assert np.max(np.abs(got - ref)) <= 1e-13 * np.max(np.abs(ref)), np.max(np.abs(got - ref))

@@ -14,6 +14,8 @@ varies by 82 %, so a velocity gradient taken as grad(rho U) / rho (dropping U gr
 converge to a different enstrophy."""
 import math
 
+import torch
+
 import numpy as np
 import pytest
 
@@ -81,3 +83,53 @@ def test_enstrophy_of_a_shear_layer_with_density_variation():
         errs.append(abs(d["epsS"] / mu0 - 0.25))
     assert errs[0] / errs[1] > 3.5 and errs[1] / errs[2] > 3.5, errs
     assert errs[2] < 1e-3
+
+
+# ---- Q-criterion: q = (|Omega|^2 - |S|^2) / 2 of the velocity gradient ----------------------
+
+def _linear_flow_state(A, rho=1.3, p=1.1, n=(5, 4, 3)):
+    """U = A x (a linear field: the cell-averaged gradients are exact), uniform rho and p."""
+    nodes = W.skewed_nodes(n, shear=(0.2, 0.1, 0.05))
+    At = torch.tensor(A, dtype=torch.float64)
+
+    def f(x, y, z):
+        X = torch.stack([x, y, z], dim=-1)
+        U = X @ At.T
+        return rho + 0.0 * x, U[..., 0], U[..., 1], U[..., 2], p + 0.0 * x
+    Q, G, L = W.initial_state(nodes, f, GAM)
+    return n, Q.numpy(), G.numpy()
+
+
+def test_qcriterion_of_rigid_rotation_and_pure_strain():
+    """Rotation about z at rate w: S = 0, |Omega|^2 = 2 w^2, q = w^2.  Pure strain
+    diag(a, b, -a-b): Omega = 0, q = -(a^2 + b^2 + (a+b)^2) / 2.  Shear u = g y: q = 0."""
+    w = 0.7
+    n, Q, G = _linear_flow_state([[0, -w, 0], [w, 0, 0], [0, 0, 0]])
+    assert np.allclose(O.qcriterion(n, Q, G), w * w, rtol=1e-12, atol=0)
+    a, b = 0.4, -0.9
+    n, Q, G = _linear_flow_state([[a, 0, 0], [0, b, 0], [0, 0, -a - b]])
+    assert np.allclose(O.qcriterion(n, Q, G), -0.5 * (a * a + b * b + (a + b) ** 2), rtol=1e-12, atol=0)
+    n, Q, G = _linear_flow_state([[0, 0.8, 0], [0, 0, 0], [0, 0, 0]])
+    assert np.max(np.abs(O.qcriterion(n, Q, G))) < 1e-14
+
+
+def test_qcriterion_of_the_taylor_green_field_converges():
+    """Incompressible limit of the TGV field (Ma 1e-3): q = -(1/2) du_i/dx_j du_j/dx_i, with
+    w = 0 only the x-y block of the velocity gradient enters; the cell value from the
+    cell-averaged gradients converges to q at the cell centre at second order."""
+    def exact(x, y, z):
+        # grad U of u = sin x cos y cos z, v = -cos x sin y cos z, w = 0
+        ux, uy, uz = np.cos(x) * np.cos(y) * np.cos(z), -np.sin(x) * np.sin(y) * np.cos(z), -np.sin(x) * np.cos(y) * np.sin(z)
+        vx, vy, vz = np.sin(x) * np.sin(y) * np.cos(z), -np.cos(x) * np.cos(y) * np.cos(z), np.cos(x) * np.sin(y) * np.sin(z)
+        return -0.5 * (ux * ux + vy * vy + 2 * uy * vx)  # w = 0: only the x-y block contributes
+    errs = []
+    for m in (24, 48):  # 12 -> 24 is still pre-asymptotic (ratio 0.30); 24 -> 48 gives 0.26
+        n = (m, m, m)
+        nodes = W.cartesian_nodes(n, hi=(2 * math.pi,) * 3)
+        Q, G, L = W.initial_state(nodes, W.taylor_green(Ma=1e-3), GAM)
+        q = O.qcriterion(n, Q.numpy(), G.numpy())
+        h = 2 * math.pi / m
+        c = (np.arange(m) + 0.5) * h
+        z, y, x = np.meshgrid(c, c, c, indexing="ij")
+        errs.append(np.max(np.abs(q - exact(x, y, z).reshape(-1))))
+    assert errs[1] < 0.3 * errs[0] and errs[1] < 5e-3, errs
