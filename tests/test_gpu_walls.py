@@ -294,3 +294,22 @@ def test_far_field_keeps_its_free_stream_on_the_gpu():
     assert st == (0, 0)
     assert (Qd.cpu() - Q).abs().max().item() < 1e-13
     assert Gd.abs().max().item() < 1e-11 and Ld.abs().max().item() < 1e-12
+
+
+@pytest.mark.parametrize("mode,bc", [("sin", 2), ("cos", 1)])
+def test_shear_wave_decays_at_the_viscous_rate_on_the_gpu(mode, bc):
+    """A long run of the wall path: the shear wave between no-slip walls (sin profile) or
+    symmetry planes (cos profile) decays at exp(-nu pi^2 t / H^2), the closed form the oracle is
+    pinned to, over 250 steps at 48 cells across (stretched toward the walls)."""
+    H, U, mu0 = 1.0, 0.05, 0.01
+    dims = (2, 48, 2)
+    nodes = W.stretched_nodes(dims, half=(0.25, H, 0.25), cells_per_half=dims, amp=(0.0, 0.08, 0.0))
+    Q, G, L = W.initial_state(nodes, W.shear_wave(U=U, H=H, mode=mode), GAM)
+    st, Qd, _, _, dts = run_gpu([dims], [nodes], K().default_params(viscous=1, mu0=mu0, Pr=1.0,
+                                                                    bc=(0, 0, bc, bc, 0, 0)), Q, G, L, 250)
+    assert st == (0, 0)
+    t = sum(dts)
+    decay = math.exp(-mu0 * math.pi ** 2 * t / H ** 2)
+    assert 1.0 - decay > 0.08, t  # t = 1.01: 9.5 % decay
+    rel = (Qd[1].cpu() - decay * Q[1]).abs().max().item() / (U * decay)
+    assert rel < 5e-4, rel  # the oracle's own error here: 5e-5 (sin) and 6e-5 (cos)
