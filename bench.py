@@ -29,8 +29,8 @@ PEAK = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}  # TFLOP/s, MI355X dense (F
 #   reconstruction: the products the method needs per cell and stage, 5 variables x 2 flops x
 #         (34 x 72 for a = R b, 96 x 34 for the Gauss-point values and gradients E a, and the two
 #         smoothness forms through their triangular factors, 34 x 35 / 2 + 31 x 32 / 2)
-FLUX_FLOP_PER_GP = 8250        # first stage: flux, its time derivative, one-sided values and rates
-FLUX_FLOP_PER_GP_DERIV = 7960  # second stage: time derivatives only (the update reads nothing else)
+FLUX_FLOP_PER_GP = 8240        # first stage: flux, its time derivative, one-sided values and rates
+FLUX_FLOP_PER_GP_DERIV = 7950  # second stage: time derivatives only (the update reads nothing else)
 # a step launches the flux once per stage: the mean is the work of an average flux launch
 FLUX_FLOP_PER_GP_MEAN = (FLUX_FLOP_PER_GP + FLUX_FLOP_PER_GP_DERIV) / 2
 RECON_FLOP_PER_CELL = 2 * 5 * (34 * 72 + 96 * 34 + 34 * 35 // 2 + 31 * 32 // 2)

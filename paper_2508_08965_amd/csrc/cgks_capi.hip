@@ -149,6 +149,8 @@ static DevParams make_dev_params(const cgks_params &p) {
     d.weights = p.weights;
     d.jump_thresh = p.jump_thresh;
     for (int v = 0; v < 5; ++v) d.far[v] = p.farfield[v];
+    d.inv_K3 = 1.0 / (d.K + 3.0);
+    d.inv_Tref = (p.T_ref > 0.0) ? 1.0 / p.T_ref : 0.0;
     return d;
 }
 

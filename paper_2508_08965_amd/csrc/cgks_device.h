@@ -147,8 +147,7 @@ __host__ __device__ inline void line_moments(T c, T i2l, T *m, int n) {
 
 // half: +1 -> u > 0, -1 -> u < 0, 0 -> full line
 template <class X, class T>
-__host__ __device__ inline void maxwell_moments(T U, T V, T W, T lam, T K, int half, MomentsT<T> &M) {
-    const T i2l = T(0.5) / lam;
+__host__ __device__ inline void maxwell_moments(T U, T V, T W, T lam, T i2l, T K, int half, MomentsT<T> &M) {
     if (half == 0) {
         line_moments<T>(U, i2l, M.u, 7);
     } else {
@@ -212,9 +211,9 @@ __host__ __device__ inline void sym_mv_acc(const T S[15], const T x[5], T scale,
 template <class T>
 struct SlopeSolver {
     T U, V, W, B, twol, c5;
-    __host__ __device__ SlopeSolver(T U_, T V_, T W_, T lam, T K)
-        : U(U_), V(V_), W(W_), B(U_ * U_ + V_ * V_ + W_ * W_ + (K + T(3.0)) * T(0.5) / lam), twol(T(2.0) * lam),
-          c5(T(4.0) * lam * lam / (K + T(3.0))) {}
+    __host__ __device__ SlopeSolver(T U_, T V_, T W_, T lam, T i2l, T K, T invK3)
+        : U(U_), V(V_), W(W_), B(U_ * U_ + V_ * V_ + W_ * W_ + (K + T(3.0)) * i2l), twol(T(2.0) * lam),
+          c5(T(4.0) * lam * lam * invK3) {}
     __host__ __device__ void solve(const T b[5], T x[5]) const {
         const T r2 = b[1] - U * b[0], r3 = b[2] - V * b[0], r4 = b[3] - W * b[0];
         const T r5 = T(2.0) * b[4] - B * b[0];
@@ -229,7 +228,7 @@ struct SlopeSolver {
 template <class X, class T>
 __host__ __device__ inline T dev_viscosity(const DevParams &P, T Tm) {
     if (!P.visc_law) return T(P.mu0);
-    const T r = Tm / T(P.T_ref);
+    const T r = Tm * T(P.inv_Tref);
     return T(P.mu0) * r * X::sqrt(r) * (T(P.T_ref) + T(P.S_suth)) / (Tm + T(P.S_suth));
 }
 
@@ -291,8 +290,8 @@ __host__ __device__ inline int gks_flux_pair(const DevParams &P, const int sd, c
     const T p = (gam - T(1.0)) * (Wk[4] - T(0.5) * r * (U * U + V * V + W * W));
     if (!(r > T(0.0))) err |= 1;
     if (!(p > T(0.0))) err |= 2;
-    const T lm = T(0.5) * r / p;
-    const SlopeSolver<T> solk(U, V, W, lm, K);
+    const T lm = T(0.5) * r / p, i2lk = p * ir;  // lambda and 1 / (2 lambda)
+    const SlopeSolver<T> solk(U, V, W, lm, i2lk, K, T(P.inv_K3));
 #pragma unroll
     for (int dir = 0; dir < 3; ++dir) {
         T dv[5], bb[5];
@@ -307,7 +306,7 @@ __host__ __device__ inline int gks_flux_pair(const DevParams &P, const int sd, c
     T Ak[5], dWk[5];
     {
         MomentsT<T> mf;
-        maxwell_moments<X, T>(U, V, W, lm, K, 0, mf);
+        maxwell_moments<X, T>(U, V, W, lm, i2lk, K, 0, mf);
         T S[15], rhs[5] = {T(0.0), T(0.0), T(0.0), T(0.0), T(0.0)};
         psi_matrix<1, 0, 0>(mf, S); sym_mv_acc<X, T>(S, a[0], T(-1.0), rhs);
         psi_matrix<0, 1, 0>(mf, S); sym_mv_acc<X, T>(S, a[1], T(-1.0), rhs);
@@ -325,7 +324,7 @@ __host__ __device__ inline int gks_flux_pair(const DevParams &P, const int sd, c
         for (int v = 0; v < 5; ++v) Xs[i][v] = T(0.0);
     {
         MomentsT<T> mh;
-        maxwell_moments<X, T>(U, V, W, lm, K, sd ? -1 : 1, mh);
+        maxwell_moments<X, T>(U, V, W, lm, i2lk, K, sd ? -1 : 1, mh);
         T S[15];
         psi_matrix<0, 0, 0>(mh, S);
 #pragma unroll
@@ -359,8 +358,8 @@ __host__ __device__ inline int gks_flux_pair(const DevParams &P, const int sd, c
     const T p0 = (gam - T(1.0)) * (Xs[0][4] - T(0.5) * r0 * (U0 * U0 + V0 * V0 + Z0 * Z0));
     if (!(r0 > T(0.0))) err |= 1;
     if (!(p0 > T(0.0))) err |= 2;
-    const T lam0 = T(0.5) * r0 / p0;
-    const SlopeSolver<T> sol0(U0, V0, Z0, lam0, K);
+    const T lam0 = T(0.5) * r0 / p0, i2l0 = p0 * ir0;  // lambda and 1 / (2 lambda)
+    const SlopeSolver<T> sol0(U0, V0, Z0, lam0, i2l0, K, T(P.inv_K3));
     T ab[3][5];
 #pragma unroll
     for (int dir = 0; dir < 3; ++dir) {
@@ -373,7 +372,6 @@ __host__ __device__ inline int gks_flux_pair(const DevParams &P, const int sd, c
     MomentsT<T> m0;
     {
         T us[8];
-        const T i2l0 = T(0.5) / lam0;
         line_moments<T>(U0, i2l0, us, 8);
 #pragma unroll
         for (int k = 0; k < 7; ++k) m0.u[k] = sd ? us[k + 1] : us[k];

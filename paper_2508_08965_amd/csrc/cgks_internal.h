@@ -73,6 +73,7 @@ struct DevParams {
     int viscous, visc_law, tau_zero, linear, prandtl_fix;
     int weights;                 // 0 GENO weights, 1 learned weights with GENO fallback
     double far[5];               // far-field state (conserved variables) of far-field sides
+    double inv_K3, inv_Tref;     // 1 / (K + 3), 1 / T_ref
 };
 
 }  // namespace cgks

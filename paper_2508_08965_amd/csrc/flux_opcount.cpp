@@ -59,6 +59,8 @@ int main(int argc, char **argv) {
     P.T_ref = 71.4285714;
     P.S_suth = P.T_ref * 110.4 / 288.15;
     P.Pr = 0.72;
+    P.inv_K3 = 1.0 / (P.K + 3.0);
+    P.inv_Tref = 1.0 / P.T_ref;
     P.viscous = argc > 1 ? std::atoi(argv[1]) : 1;
     P.prandtl_fix = argc > 2 ? std::atoi(argv[2]) : 1;
     P.visc_law = argc > 3 ? std::atoi(argv[3]) : 1;
