@@ -107,8 +107,9 @@ typedef struct {
                             A wall side must be a plane normal to its axis, the axis pointing
                             into the block, and the two sides of the axis must share their
                             tangential node coordinates (EINVAL at creation otherwise).
-                            Walls need recon_impl 0 and GENO weights (EUNSUPPORTED), and
-                            cgks_weights refuses contexts with walls                      */
+                            Walls need recon_impl 0 (EUNSUPPORTED).  With learned weights
+                            the jump indicator takes a neighbour behind a wall as the cell's
+                            mirror image and one behind a far-field side as the far field */
     double farfield[5];  /* far-field state (rho, rho U, rho V, rho W, rho E) of bc 3 sides;
                             positive density and pressure (EINVAL otherwise)             */
 } cgks_params;

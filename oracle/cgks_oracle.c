@@ -1531,7 +1531,12 @@ int oracle_features(const int dims[3], const double *nodes, const or_params *P, 
         const double p0 = pressure_of(P, Q, N, c);
         double ind = 0.0;
         for (int m = 0; m < 6; ++m) {
-            const double pm = pressure_of(P, Q, N, nb[m]);
+            int farm = 0; /* behind a far-field side: the far-field pressure */
+            for (int q = 0; q < 3; ++q)
+                if (sd[m][q] >= 0 && M.bc[sd[m][q]] == 3) farm = 1;
+            const double pm = farm ? (P->gamma - 1.0) * (P->far[4] - 0.5 * (P->far[1] * P->far[1] + P->far[2] * P->far[2] +
+                                                                          P->far[3] * P->far[3]) / P->far[0])
+                                   : pressure_of(P, Q, N, nb[m]);
             const double r = fabs(pm - p0) / (pm + p0);
             ind = r > ind ? r : ind;
         }

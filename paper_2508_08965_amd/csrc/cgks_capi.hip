@@ -182,7 +182,6 @@ static int check_params(const cgks_params *p) {
     }
     if (walls && p->recon_impl != 0)
         return fail(CGKS_EUNSUPPORTED, "wall sides need the matrix-core reconstruction (recon_impl 0)");
-    if (walls && p->weights != 0) return fail(CGKS_EUNSUPPORTED, "wall sides need GENO weights");
     for (int sd = 0; sd < 6; ++sd)
         if (p->bc[sd] == 3) {
             const double *f = p->farfield;
@@ -1033,7 +1032,6 @@ int cgks_weights(cgks_ctx *ctx, const double *Q, const double *G, const double *
     if (!ctx || !Q || !G || !L || !X || !Wt) return fail(CGKS_EINVAL, "cgks_weights: NULL argument");
     if (ctx->user.recon_impl != 0 || ctx->user.recon_prec != 0 || gp32(ctx) || ctx->user.linear)
         return fail(CGKS_EUNSUPPORTED, "cgks_weights: FP64 nonlinear matrix-core contexts only");
-    if (ctx->walls) return fail(CGKS_EUNSUPPORTED, "cgks_weights: periodic blocks only");
     if (ctx->P.weights == 1 && !ctx->mlp_ready) return fail(CGKS_EINVAL, "learned weights: no MLP parameters set");
     hipStream_t s = (hipStream_t)stream;
     ctx->last = s;

@@ -41,9 +41,11 @@ __device__ inline double pressure(const double *Q, long Ntot, long c, double gm1
 }
 
 // flag[c] = max over the six face neighbours of |p_m - p_0| / (p_m + p_0) > thresh; count[0]
-// accumulates the number of flagged cells.
+// accumulates the number of flagged cells.  Behind a symmetry plane or no-slip wall the
+// neighbour is the mirror image of the cell itself (same pressure); behind a far-field side it
+// is the far-field state (pressure pfar).
 __global__ void __launch_bounds__(256) k_jump(WorkList W, long Ntot, const double *__restrict__ Q, double gm1,
-                                              double thresh, unsigned char *__restrict__ flag,
+                                              double thresh, double pfar, unsigned char *__restrict__ flag,
                                               unsigned long long *__restrict__ count) {
     __shared__ int nflag;
     if (threadIdx.x == 0) nflag = 0;
@@ -68,7 +70,10 @@ __global__ void __launch_bounds__(256) k_jump(WorkList W, long Ntot, const doubl
             ii = ii < 0 ? ii + b.nx : (ii >= b.nx ? ii - b.nx : ii);
             jj = jj < 0 ? jj + b.ny : (jj >= b.ny ? jj - b.ny : jj);
             kk = kk < 0 ? kk + b.nz : (kk >= b.nz ? kk - b.nz : kk);
-            const double pm = pressure(Q, Ntot, b.off + ii + (long)b.nx * (jj + (long)b.ny * kk), gm1);
+            const int iq = (m < 2) ? i : (m < 4) ? j : k, nq = (m < 2) ? b.nx : (m < 4) ? b.ny : b.nz;
+            const bool at_wall = ((b.wall >> m) & 1) && iq == ((m & 1) ? nq - 1 : 0);
+            const double pm = !at_wall ? pressure(Q, Ntot, b.off + ii + (long)b.nx * (jj + (long)b.ny * kk), gm1)
+                                       : (((b.wall >> (16 + m)) & 1) ? pfar : p0);
             const double r = fabs(pm - p0) / (pm + p0);
             ind = r > ind ? r : ind;
         }
@@ -83,8 +88,12 @@ __global__ void __launch_bounds__(256) k_jump(WorkList W, long Ntot, const doubl
 hipError_t launch_jump(const WorkList &W, long Ntot, const double *Q, const DevParams &P, unsigned char *flag,
                        unsigned long long *count, hipStream_t s) {
     if (W.ntiles <= 0) return hipSuccess;
+    const double pfar = (P.far[0] > 0.0)
+                            ? (P.gamma - 1.0) * (P.far[4] - 0.5 * (P.far[1] * P.far[1] + P.far[2] * P.far[2] +
+                                                                   P.far[3] * P.far[3]) / P.far[0])
+                            : 0.0;
     hipLaunchKernelGGL(k_jump, dim3((unsigned)W.ntiles), dim3(kUpdateTile), 0, s, W, Ntot, Q, P.gamma - 1.0,
-                       P.jump_thresh, flag, count);
+                       P.jump_thresh, pfar, flag, count);
     return hipGetLastError();
 }
 

@@ -841,7 +841,7 @@ hipError_t launch_recon_mfma(int prec, bool gp32, const WorkList &W, long Ntot, 
     if (W.ntiles <= 0) return hipSuccess;
     if ((P.weights == 1 || exp) && prec != 0) return hipErrorInvalidValue;
     if (exp && gp32) return hipErrorInvalidValue;
-    if (walls && (P.weights == 1 || exp)) return hipErrorInvalidValue;  // blocks with walls: GENO, no export
+    (void)walls;  // one kernel form serves periodic blocks and blocks with wall sides
     const int grid = (ngroups <= 0 || ngroups > W.ntiles) ? W.ntiles : ngroups;
     const dim3 gr((unsigned)grid), bl(512);
 #define CGKS_RECON(PRC, TGT, WMV, EXV) \

@@ -97,7 +97,6 @@ def test_wall_sides_rejected_on_the_host():
     for bc in ((1, 0, 0, 0, 0, 0), (0, 0, 2, 0, 0, 0), (4, 4, 0, 0, 0, 0), (-1, -1, 0, 0, 0, 0)):
         assert create(box, bc=bc) == K.EINVAL, bc
     assert create(box, bc=(1, 1, 0, 0, 0, 0), recon_impl=1) == K.EUNSUPPORTED
-    assert create(box, bc=(2, 2, 0, 0, 0, 0), weights=1) == K.EUNSUPPORTED
     # sides that are planes but not normal to their axis
     assert create(W.skewed_nodes((4, 4, 4)), bc=(1, 1, 0, 0, 0, 0)) == K.EINVAL
     # x sides whose tangential node coordinates differ (one side moved in y)

@@ -247,3 +247,41 @@ def test_learned_weights_with_fp32_flux_and_graph_replay():
         ctx.close()
     rel = float(torch.linalg.vector_norm(outs[1] - outs[0]) / torch.linalg.vector_norm(outs[0]))
     assert rel <= 1e-5, rel
+
+
+def test_learned_weights_with_wall_and_far_field_sides():
+    """Export and learned blend on a box with no-slip (x), far-field (y) and symmetry (z) sides:
+    features, jump flags (a neighbour behind a wall is the cell's mirror image, behind a
+    far-field side the far field) and GENO weights equal the oracle's; the learned blend equals
+    the oracle's reconstruction with the weights the GPU used."""
+    n = (14, 11, 9)
+    nodes = W.wall_perturbed_nodes(n)
+    Q, G, L = W.initial_state(nodes, W.isotropic_turbulence(32, k0=8.0, Mt=1.0, seed=8967, period=math.pi), GAM)
+    far = (1.0, 0.0, 0.0, 0.0, (1.0 / GAM) / (GAM - 1.0))
+    kw = dict(HIT_KW, bc=(2, 2, 3, 3, 1, 1))
+    Qd, Gd, Ld = _evolve(n, nodes, Q, G, L, 2, farfield=far, **kw)
+    Qh, Gh, Lh = (t.cpu().numpy() for t in (Qd, Gd, Ld))
+    cells = np.arange(Qh.shape[1])
+    po = O.params(far=far, **kw)
+    ctx = K().Context([n], [nodes], K().default_params(farfield=far, **kw))
+    X, Wt, jump = _export(ctx, Qd, Gd, Ld)
+    Xo, jo = O.features(n, nodes.numpy(), po, Qh, Lh, cells, thresh=0.05)
+    _, wo = O.recon_weights(n, nodes.numpy(), po, Qh, Gh, Lh, cells)
+    np.testing.assert_array_equal(jump.cpu().numpy().astype(bool), jo)
+    assert np.abs(X.cpu().numpy() - Xo.reshape(-1, 18)).max() <= 2.0 ** -23
+    assert np.abs(Wt.cpu().numpy() - wo.reshape(-1, 7)).max() <= 1e-9
+    ctx.close()
+    ctx = K().Context([n], [nodes], K().default_params(weights=1, farfield=far, **kw))
+    K().cgks_mlp_init(ctx, 11)
+    X, Wt, jump = _export(ctx, Qd, Gd, Ld)
+    Wg = Wt.cpu().numpy().reshape(-1, 5, 7)
+    gp = torch.zeros(Qh.shape[1], 24, 5, 4, dtype=torch.float64, device=dev())
+    K().cgks_recon(ctx, Qd, Gd, Ld, gp)
+    torch.cuda.synchronize()
+    ref, _ = O.recon_weights(n, nodes.numpy(), po, Qh, Gh, Lh, cells, win=Wg)
+    out = gp.cpu().numpy()
+    for v in range(5):
+        for c in range(4):
+            scale = max(np.abs(ref[:, :, v, c]).max(), 1e-300)
+            assert np.abs(out[:, :, v, c] - ref[:, :, v, c]).max() <= 1e-12 * scale, (v, c)
+    ctx.close()
