@@ -474,6 +474,8 @@ def bench_supersonic_tgv(K, W, torch, n=128, t_end=10.0, Ma=1.25):
             flags = K.cgks_check(ctx)[1]
             if flags:
                 break
+        if k % 500 == 0:
+            print(f"supersonic TGV {n}^3: step {k}, t = {t:.3f}", file=sys.stderr, flush=True)
     el = time.perf_counter() - t0
     d1 = diag()
     ctx.close()
@@ -500,6 +502,8 @@ def main():
     ap.add_argument("--no-percell", action="store_true", help="skip the per-cell matrix storage measurement")
     ap.add_argument("--no-supersonic", action="store_true", help="skip the supersonic Taylor-Green robustness run")
     ap.add_argument("--no-walls", action="store_true", help="skip the wall-side measurement")
+    ap.add_argument("--supersonic-n", type=int, default=128, help="cells per axis of the supersonic TGV run")
+    ap.add_argument("--supersonic-t", type=float, default=10.0, help="end time of the supersonic TGV run")
     ap.add_argument("--dump-state", default=None,
                     help="write the initial state and parameters of the FP64 workload for cgks_runner, then exit")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -659,7 +663,7 @@ def main():
     # ---- supersonic Taylor-Green vortex: robustness of the nonlinear scheme ------------------
     supersonic = None
     if not args.no_supersonic:
-        supersonic = bench_supersonic_tgv(K, W, torch)
+        supersonic = bench_supersonic_tgv(K, W, torch, n=args.supersonic_n, t_end=args.supersonic_t)
 
     # ---- CPU baseline: the oracle on a bounded sample of the same workload ------------------
     cpu = None
