@@ -477,6 +477,13 @@ static int mesh_build(or_mesh *M, const int dims[3], const double *nodes, const 
         if (M->bc[2 * q] < 0 || M->bc[2 * q] > 3 || M->bc[2 * q + 1] < 0 || M->bc[2 * q + 1] > 3) return OR_EINVAL;
         if ((M->bc[2 * q] == 0) != (M->bc[2 * q + 1] == 0)) return OR_EINVAL; /* periodic pairs */
     }
+    for (int s = 0; s < 6 && P; ++s)
+        if (M->bc[s] == 3) { /* the far-field state needs positive density and pressure */
+            const double *f = P->far;
+            if (!(f[0] > 0.0)) return OR_EINVAL;
+            if (!((P->gamma - 1.0) * (f[4] - 0.5 * (f[1] * f[1] + f[2] * f[2] + f[3] * f[3]) / f[0]) > 0.0))
+                return OR_EINVAL;
+        }
     if (M->nx < 1 || M->ny < 1 || M->nz < 1 || !nodes) return OR_EINVAL;
     M->n = (long)M->nx * M->ny * M->nz;
     M->nodes = nodes;

@@ -254,3 +254,12 @@ def test_acoustic_pulse_leaves_through_far_field_sides():
     wall = _pulse_run((1, 1, 0, 0, 0, 0))
     assert far < 0.01, far  # 1.5e-3 measured
     assert wall > 0.3, wall  # each reflected half carries half the amplitude: 0.46 measured
+
+
+@pytest.mark.parametrize("far", [(0.0, 0, 0, 0, 2.5), (1.0, 0, 0, 0, 0.0), (1.0, 3.0, 0, 0, 2.5)])
+def test_far_field_state_must_be_physical(far):
+    dims = (4, 4, 4)
+    nodes = W.cartesian_nodes(dims)
+    Q, G, L = _state(nodes, W.uniform())
+    with pytest.raises(ValueError):
+        O.cfl_dt(dims, nodes.numpy(), O.params(bc=(3, 3, 0, 0, 0, 0), far=far), Q)
