@@ -303,7 +303,12 @@ def _brute_flux(ql, gl, qr, gr, dt, tau):
     Ft = 4 * (Fb1 - 2 * Fb2) / dt ** 2
     Wn = (4 * Wb2 - Wb1) / dt
     Wt = 4 * (Wb1 - 2 * Wb2) / dt ** 2
-    return F, Ft, Wn, Wt
+    # time derivative of the moments of each side's own Maxwellian evolution g_k (1 + A^k t):
+    # int psi A^k g_k over all velocities, which the compatibility condition makes equal to
+    # minus the moments of the slope term (a^k . u) g_k; taken here by quadrature of the latter
+    dWl = -moments(gL, laml, sL)
+    dWr = -moments(gR, lamr, sR)
+    return F, Ft, Wn, Wt, dWl, dWr
 
 
 @pytest.mark.parametrize("mode", ["inviscid", "tau_zero"])
@@ -320,9 +325,16 @@ def test_discontinuous_flux_against_velocity_space_quadrature(mode):
         assert st == 0
         pl, pr = prim(ql)[2], prim(qr)[2]
         tau = 0.0 if mode == "tau_zero" else (0.05 * dt + 5.0 * abs((pl - pr) / (pl + pr)) * dt)
-        Fb, Ftb, Wn, Wt = _brute_flux(ql, gl, qr, gr, dt, tau)
+        Fb, Ftb, Wn, Wt, dWl, dWr = _brute_flux(ql, gl, qr, gr, dt, tau)
         np.testing.assert_allclose(F[0], Fb, rtol=1e-9, atol=1e-9)
         np.testing.assert_allclose(Ft[0], Ftb, rtol=1e-7, atol=1e-7 * np.abs(Ftb).max())
         e0 = 0.0 if tau == 0 else math.exp(-dt / tau)
+        if mode == "inviscid":
+            assert e0 > 0.05  # the one-sided terms carry real weight in these cases
+        # one-sided interface values and their time derivatives (section "Temporal
+        # discretization"): Q^k = (1 - e0) W(t) + e0 W^k, dQ^k/dt = (1 - e0) W_t + e0 dW^k/dt
         np.testing.assert_allclose(S[0, 0], (1 - e0) * Wn + e0 * ql, rtol=1e-9, atol=1e-9)
         np.testing.assert_allclose(S[0, 2], (1 - e0) * Wn + e0 * qr, rtol=1e-9, atol=1e-9)
+        for k, dW in ((1, dWl), (3, dWr)):
+            want = (1 - e0) * Wt + e0 * dW
+            np.testing.assert_allclose(S[0, k], want, rtol=1e-7, atol=1e-7 * np.abs(want).max())
