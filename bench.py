@@ -24,16 +24,23 @@ GAM = 1.4
 PEAK = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}  # TFLOP/s, MI355X dense (FP64 vector and matrix: 78.6)
 
 # Algorithmic work per unit:
-#   flux: source-level operation count of the gas-kinetic flux per Gauss point (flux_opcount.cpp);
-#         one stage evaluates 12 Gauss points per cell (3 owned faces x 4 points)
+#   flux: source-level operation count of the gas-kinetic flux per Gauss point (flux_opcount.cpp),
+#         the method's work counted once per Gauss point: each side's own moments and slopes
+#         twice (left and right), the work both lanes of a pair repeat (frame, pair sums,
+#         equilibrium state and slopes, collision time, time integrals) once; one stage
+#         evaluates 12 Gauss points per cell (3 owned faces x 4 points)
 #   reconstruction: the products the method needs per cell and stage, 5 variables x 2 flops x
 #         (34 x 72 for a = R b, 96 x 34 for the Gauss-point values and gradients E a, and the two
 #         smoothness forms through their triangular factors, 34 x 35 / 2 + 31 x 32 / 2)
-FLUX_FLOP_PER_GP = 8240        # first stage: flux, its time derivative, one-sided values and rates
-FLUX_FLOP_PER_GP_DERIV = 7950  # second stage: time derivatives only (the update reads nothing else)
-# a step launches the flux once per stage: the mean is the work of an average flux launch
-FLUX_FLOP_PER_GP_MEAN = (FLUX_FLOP_PER_GP + FLUX_FLOP_PER_GP_DERIV) / 2
+FLUX_FLOP_PER_GP = 7733        # first stage: flux, its time derivative, one-sided values and rates
+FLUX_FLOP_PER_GP_DERIV = 7498  # second stage: time derivatives only (the update reads nothing else)
+# what the lane pairs issue (the shared work twice): the hardware's view, for context only
+FLUX_ISSUED_PER_GP, FLUX_ISSUED_PER_GP_DERIV = 8240, 7950
 RECON_FLOP_PER_CELL = 2 * 5 * (34 * 72 + 96 * 34 + 34 * 35 // 2 + 31 * 32 // 2)
+# algorithmic HBM bytes per cell of the update (state, stash, metrics, face records) and per
+# Gauss point of the flux (344 in; 240 out in stage 1, 120 in stage 2)
+UPDATE_BYTES = {1: 4592, 2: 3112}
+FLUX_BYTES_PER_GP = {1: 584, 2: 464}
 COUNTERS = os.path.join(ROOT, "profiles", "counters_tgv256_fp64.md")
 
 
@@ -85,12 +92,30 @@ def timed_steps(K, ctx, Q, G, L, dt, steps):
     return t1 - t0, K.cgks_profile_read(ctx)
 
 
+def merged(prof):
+    """Kernel kinds with both stages' flux (and update) launches taken together: total ms,
+    launches, and the algorithmic work of all those launches."""
+    out = {}
+    for k, (ms, n) in prof.items():
+        base = k.split("_s")[0]
+        m, c = out.get(base, (0.0, 0))
+        out[base] = (m + ms, c + n)
+    return out
+
+
+def flux_work(prof, N):
+    """Method flops of every flux launch in prof (stage-1 and stage-2 counts differ)."""
+    return 12 * N * (FLUX_FLOP_PER_GP * prof.get("flux_s1", (0, 0))[1]
+                     + FLUX_FLOP_PER_GP_DERIV * prof.get("flux_s2", (0, 0))[1])
+
+
 def roofline(prof, N, peak_key, counters=False):
-    kinds = {k: v for k, v in prof.items() if v[1] > 0}
+    kinds = {k: v for k, v in merged(prof).items() if v[1] > 0}
     dom = max(kinds, key=lambda k: kinds[k][0])
     avg_ms = kinds[dom][0] / kinds[dom][1]
     if dom == "flux":
-        work = FLUX_FLOP_PER_GP_MEAN * 12 * N
+        # the work of an average flux launch (the stages alternate)
+        work = flux_work(prof, N) / kinds[dom][1]
         roof = {"bound": "alu", "peak": PEAK[peak_key]}
     elif dom == "reconstruction":
         work = RECON_FLOP_PER_CELL * N
@@ -105,33 +130,90 @@ def roofline(prof, N, peak_key, counters=False):
     return roof
 
 
-def kernel_table(prof, N, fp64=True):
-    """Every kernel kind of a step against its own roof: average launch time (HIP events), the
-    algorithmic work per launch and the achieved fraction (FP64 path: matrix / vector FP64 peaks
-    and 8 TB/s HBM; the update averages its two stages, the reconstruction of this table is
-    FP64 only)."""
+def kernel_table(prof, N, ms_per_step=None):
+    """Every kernel kind of an FP64 step against its own roof: average launch time (HIP events),
+    the algorithmic work per launch and the achieved fraction (FP64 matrix / vector peaks and
+    8 TB/s HBM), the flux and the update per stage; then the whole step: its algorithmic flops
+    against the FP64 peak."""
     hbm = 8.0  # TB/s
     out = {}
     for k, (ms, n) in prof.items():
         if n == 0:
             continue
         avg = ms / n
+        stage = 2 if k.endswith("_s2") else 1
         if k == "reconstruction":
             w = RECON_FLOP_PER_CELL * N
             out[k] = {"avg_ms": avg, "bound": "mfma", "tflops": w / avg / 1e9, "frac": w / avg / 1e9 / PEAK["fp64"],
                       "algorithmic_gbps": (98 + 480) * 8 * N / avg / 1e6}
-        elif k == "flux":
-            w = FLUX_FLOP_PER_GP_MEAN * 12 * N
+        elif k.startswith("flux"):
+            w = (FLUX_FLOP_PER_GP if stage == 1 else FLUX_FLOP_PER_GP_DERIV) * 12 * N
+            wi = (FLUX_ISSUED_PER_GP if stage == 1 else FLUX_ISSUED_PER_GP_DERIV) * 12 * N
             out[k] = {"avg_ms": avg, "bound": "alu", "tflops": w / avg / 1e9, "frac": w / avg / 1e9 / PEAK["fp64"],
-                      # bytes per Gauss point: 344 in; 240 out in stage 1, 120 in stage 2
-                      "algorithmic_gbps": (584 + 464) / 2 * 12 * N / avg / 1e6}
-        elif k == "update":
-            b = (4592 + 3112) / 2 * N
+                      "issued_frac": wi / avg / 1e9 / PEAK["fp64"],
+                      "algorithmic_gbps": FLUX_BYTES_PER_GP[stage] * 12 * N / avg / 1e6,
+                      "hbm_frac": FLUX_BYTES_PER_GP[stage] * 12 * N / avg / 1e9 / hbm}
+        elif k.startswith("update"):
+            b = UPDATE_BYTES[stage] * N
             out[k] = {"avg_ms": avg, "bound": "hbm", "algorithmic_gbps": b / avg / 1e6, "frac": b / avg / 1e9 / hbm}
         elif k == "dt":
             b = 17 * 8 * N
             out[k] = {"avg_ms": avg, "bound": "hbm", "algorithmic_gbps": b / avg / 1e6, "frac": b / avg / 1e9 / hbm}
-    return out if fp64 else None
+    if ms_per_step:
+        steps = max(prof.get("flux_s2", (0, 0))[1], 1)
+        w = (RECON_FLOP_PER_CELL * N * prof.get("reconstruction", (0, 0))[1] + flux_work(prof, N)) / steps
+        out["step"] = {"ms": ms_per_step, "flops": w, "tflops": w / ms_per_step / 1e9,
+                       "frac_fp64": w / ms_per_step / 1e9 / PEAK["fp64"],
+                       "kernel_ms": sum(v[0] for v in prof.values()) / steps}
+    return out
+
+
+def oracle_rate(O, dims, nodes, prm, Q, G, L, steps, nthreads=0):
+    """Cell-updates/s of the oracle over `steps` S2O4 steps with its set-up (metrics, work
+    arrays) excluded: the time of a zero-step call on the same mesh is subtracted."""
+    ncell = dims[0] * dims[1] * dims[2]
+    t0 = time.perf_counter()
+    O.run(dims, nodes, prm, Q, G, L, 0, nthreads=nthreads)
+    t_setup = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    st, *_ = O.run(dims, nodes, prm, Q, G, L, steps, nthreads=nthreads)
+    t_run = time.perf_counter() - t0
+    return {"value": steps * ncell / (t_run - t_setup), "seconds": t_run - t_setup, "setup_seconds": t_setup,
+            "status": st}
+
+
+def cpu_baseline(W, kw):
+    """The oracle as it is (C, OpenMP), timed on this host: a bounded sample of the headline
+    workload on every thread, the same on one thread, and the 2D density wave in full."""
+    from oracle import oracle as O
+    cores = O.num_threads()
+    m, ksteps = 96, 3
+    ns = (m, m, m)
+    nd = W.perturbed_nodes(ns, amp=0.05)
+    Qs, Gs, Ls = W.initial_state(nd, W.taylor_green(Ma=0.1), GAM)
+    r = oracle_rate(O, ns, nd.numpy(), O.params(**kw), Qs.numpy(), Gs.numpy(), Ls.numpy(), ksteps, nthreads=cores)
+    cpu = {"value": r["value"], "unit": "cell-updates/s", "cores": cores, "kind": "oracle",
+           "sample": f"{ksteps} S2O4 steps (CFL dt + 2 stages each) of the same TGV workload on a {m}^3 "
+                     f"perturbed mesh, {r['seconds']:.1f} s (mesh set-up, {r['setup_seconds']:.1f} s, excluded)",
+           "status": r["status"]}
+    # the 2D density wave (40 x 40, tau = 0, 10 steps) in full
+    n2 = (40, 40, 1)
+    nd2 = W.cartesian_nodes(n2, (0, 0, 0), (2, 2, 2.0 / 40))
+    q2, g2, l2 = W.initial_state(nd2, W.density_wave(dim=2), GAM)
+    r2 = oracle_rate(O, n2, nd2.numpy(), O.params(tau_zero=1), q2.numpy(), g2.numpy(), l2.numpy(), 10,
+                     nthreads=cores)
+    cpu["density_wave_2d_40x40_10_steps"] = {"value": r2["value"], "seconds": r2["seconds"], "cores": cores}
+    # one thread: the same TGV workload on a 48^3 mesh, one step
+    m1 = 48
+    n1 = (m1, m1, m1)
+    nd1 = W.perturbed_nodes(n1, amp=0.05)
+    q1, g1, l1 = W.initial_state(nd1, W.taylor_green(Ma=0.1), GAM)
+    r1 = oracle_rate(O, n1, nd1.numpy(), O.params(**kw), q1.numpy(), g1.numpy(), l1.numpy(), 1, nthreads=1)
+    O.run(n1, nd1.numpy(), O.params(**kw), q1.numpy(), g1.numpy(), l1.numpy(), 0, nthreads=cores)  # restore
+    cpu["single_thread"] = {"value": r1["value"], "unit": "cell-updates/s", "cores": 1,
+                            "sample": f"1 S2O4 step of the TGV workload on a {m1}^3 perturbed mesh, "
+                                      f"{r1['seconds']:.1f} s (set-up excluded)"}
+    return cpu
 
 
 def hit_kw():
@@ -628,7 +710,9 @@ def main():
                 "speedup_vs_fp64": v_value / value,
                 "kernel_ms": {k: {"total_ms": v[0], "launches": v[1]} for k, v in v_prof.items()},
                 "roofline": roofline(v_prof, N, "bf16" if rp == 2 else "fp32"),
-                "error_vs_fp64": {"steps": ne, "reference": "GPU FP64 path (matches the oracle, see parity)",
+                "error_vs_fp64": {"steps": ne, "reference": "GPU FP64 path at this size; its whole-state parity "
+                                  "with the FP64 oracle is a GPU test at 128^3 x 20 steps and 64^3 x 50 steps "
+                                  "(tests/test_gpu_fullsize.py)",
                                   "rho": errs(Qv[0], Qr[0]), "speed": errs(speed(Qv), speed(Qr)),
                                   "rhoE": errs(Qv[4], Qr[4])},
                 "device_flags": v_status[1],
@@ -668,17 +752,7 @@ def main():
     # ---- CPU baseline: the oracle on a bounded sample of the same workload ------------------
     cpu = None
     if not args.no_oracle:
-        from oracle import oracle as O
-        m, ksteps = 96, 3
-        ns = (m, m, m)
-        nd = W.perturbed_nodes(ns, amp=0.05)
-        Qs, Gs, Ls = W.initial_state(nd, W.taylor_green(Ma=0.1), GAM)
-        tc = time.perf_counter()
-        st, *_ = O.run(ns, nd.numpy(), O.params(**kw), Qs.numpy(), Gs.numpy(), Ls.numpy(), ksteps)
-        tc = time.perf_counter() - tc
-        cpu = {"value": ksteps * m ** 3 / tc, "unit": "cell-updates/s", "cores": O.num_threads(), "kind": "oracle",
-               "sample": f"{ksteps} S2O4 steps (CFL dt + 2 stages each) of the same TGV workload on a {m}^3 "
-                         f"perturbed mesh, {tc:.1f} s", "status": st}
+        cpu = cpu_baseline(W, kw)
 
     out = {
         "metric": "cell-updates/sec per S2O4 step at 256^3 TGV + L2 error vs FP64 oracle",
@@ -697,7 +771,7 @@ def main():
                                "mesh (amp 0.05), nonlinear CGKS-5, FP64", "cells": N, "variant": "fp64"},
         "kernel_ms": {k: {"total_ms": v[0], "launches": v[1]} for k, v in prof.items()},
         "roofline": roof,
-        "kernels": kernel_table(prof, N),
+        "kernels": kernel_table(prof, N, ms_per_step),
         "parity_vs_oracle": parity,
         "variants": variants,
         "batching": batching,

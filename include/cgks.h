@@ -205,9 +205,11 @@ int cgks_metrics(cgks_ctx *ctx, double *vol, double *J0, double *fn, double *fw,
 /* Kernel timing (tracing aid).  When enabled, every kernel launch of cgks_dt / cgks_stage is
  * bracketed by HIP events recorded on the caller's stream; cgks_profile_read synchronises and
  * returns, per kernel kind, the summed elapsed milliseconds and the launch count since the
- * last read, then resets them.  Kinds: 0 dt, 1 reconstruction, 2 flux, 3 update.
- * Not for use under HIP graph capture.  ms and launches: host arrays of CGKS_NKINDS. */
-#define CGKS_NKINDS 4
+ * last read, then resets them.  Kinds: 0 dt, 1 reconstruction (both stages), 2 flux of stage 1,
+ * 3 update of stage 1, 4 flux of stage 2, 5 update of stage 2 (the two stages' flux and update
+ * kernels do different work).  Not for use under HIP graph capture.  ms and launches: host
+ * arrays of CGKS_NKINDS. */
+#define CGKS_NKINDS 6
 int cgks_profile(cgks_ctx *ctx, int enable);
 int cgks_profile_read(cgks_ctx *ctx, double *ms, long *launches);
 

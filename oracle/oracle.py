@@ -4,7 +4,11 @@ Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
 ``bench.py`` may import this module.  The GPU library never does.
 
 The shared object is built from ``oracle/cgks_oracle.c`` with gcc and OpenMP,
-in plain IEEE double precision (no fast-math, no FMA contraction).
+in plain IEEE double precision (no fast-math, no FMA contraction).  A second build of the
+same source, ``liboracle_fma.so``, lets the compiler fuse multiply-adds (``-mfma
+-ffp-contract=fast``): an equally valid FP64 evaluation whose rounding differs.  The spread
+between the two measures how far rounding alone moves a result, which sets the parity bar
+of quantities formed by cancellation (the gradients and line derivatives).
 """
 from __future__ import annotations
 
@@ -17,6 +21,8 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "cgks_oracle.c")
 LIB = os.path.join(HERE, "liboracle.so")
+LIBS = {"ieee": LIB, "fma": os.path.join(HERE, "liboracle_fma.so")}
+_FLAGS = {"ieee": ["-ffp-contract=off"], "fma": ["-mfma", "-ffp-contract=fast"]}
 
 OK, EINVAL, ENONPHYS = 0, -1, -4
 
@@ -57,25 +63,30 @@ def params(**kw) -> Params:
     return Params(**d)
 
 
+def _stale(path):
+    return not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(SRC)
+
+
 def build(force: bool = True) -> str:
-    """Compile the oracle shared object (gcc -O2 -fopenmp, IEEE double)."""
-    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
-        tmp = LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=gnu99", "-fopenmp", "-ffp-contract=off",
-                               "-fPIC", "-shared", "-o", tmp, SRC, "-lm"])
-        os.replace(tmp, LIB)
+    """Compile both oracle builds (gcc -O2 -fopenmp; IEEE double, and FMA-contracted)."""
+    for variant, path in LIBS.items():
+        if force or _stale(path):
+            tmp = path + ".tmp"
+            subprocess.check_call(["gcc", "-O2", "-std=gnu99", "-fopenmp"] + _FLAGS[variant]
+                                  + ["-fPIC", "-shared", "-o", tmp, SRC, "-lm"])
+            os.replace(tmp, path)
     return LIB
 
 
-_lib = None
+_libs = {}
 
 
-def lib():
-    global _lib
-    if _lib is None:
-        if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
-            build(force=True)
-        L = C.CDLL(LIB)
+def lib(variant: str = "ieee"):
+    if variant not in _libs:
+        path = LIBS[variant]
+        if _stale(path):
+            build(force=False)
+        L = C.CDLL(path)
         dp, ip, lp = C.POINTER(C.c_double), C.POINTER(C.c_int), C.POINTER(C.c_long)
         pp = C.POINTER(Params)
         L.oracle_constants.argtypes = [dp, dp, dp, dp, dp, dp, ip]
@@ -97,8 +108,8 @@ def lib():
         L.oracle_recon_weights.argtypes = [ip, dp, pp, dp, dp, dp, lp, C.c_long, dp, dp, dp]
         L.oracle_diagnostics.argtypes = [ip, dp, pp, dp, dp, dp]
         L.oracle_qcriterion.argtypes = [ip, dp, dp, dp]
-        _lib = L
-    return _lib
+        _libs[variant] = L
+    return _libs[variant]
 
 
 def _d(a):
@@ -139,12 +150,12 @@ def metrics(dims, nodes):
     return dict(vol=vol, J0=J0, JinvT=JiT, fn=fn, fw=fw)
 
 
-def recon(dims, nodes, prm, Q, G, L, cells):
+def recon(dims, nodes, prm, Q, G, L, cells, variant="ieee"):
     """Gauss-point values and physical gradients: [ncells, 24, 5, 4]."""
     nodes, Q, G, L = _arr(nodes), _arr(Q), _arr(G), _arr(L)
     cells = np.ascontiguousarray(cells, dtype=np.int64)
     out = np.zeros((len(cells), 24, 5, 4))
-    st = lib().oracle_recon(_dims(dims), _d(nodes), C.byref(prm), _d(Q), _d(G), _d(L),
+    st = lib(variant).oracle_recon(_dims(dims), _d(nodes), C.byref(prm), _d(Q), _d(G), _d(L),
                             cells.ctypes.data_as(C.POINTER(C.c_long)), len(cells), _d(out))
     if st:
         raise ValueError(f"oracle_recon status {st}")
@@ -170,22 +181,22 @@ def cfl_dt(dims, nodes, prm, Q):
     return out.value
 
 
-def stage(dims, nodes, prm, s, dt, Q, G, L, stash, nthreads=0):
+def stage(dims, nodes, prm, s, dt, Q, G, L, stash, nthreads=0, variant="ieee"):
     """One stage in place on caller arrays (float64, C-contiguous)."""
     nodes = _arr(nodes)
     for a in (Q, G, L, stash):
         assert a.dtype == np.float64 and a.flags.c_contiguous
-    return lib().oracle_stage(_dims(dims), _d(nodes), C.byref(prm), int(s), float(dt), _d(Q), _d(G),
+    return lib(variant).oracle_stage(_dims(dims), _d(nodes), C.byref(prm), int(s), float(dt), _d(Q), _d(G),
                               _d(L), _d(stash), int(nthreads))
 
 
-def run(dims, nodes, prm, Q, G, L, nsteps, dt=0.0, nthreads=0):
+def run(dims, nodes, prm, Q, G, L, nsteps, dt=0.0, nthreads=0, variant="ieee"):
     """nsteps S2O4 steps on copies; returns (status, Q, G, L, last dt, elapsed t)."""
     nodes = _arr(nodes)
     Q, G, L = _arr(Q).copy(), _arr(G).copy(), _arr(L).copy()
     d = C.c_double(float(dt))
     t = C.c_double(0)
-    st = lib().oracle_run(_dims(dims), _d(nodes), C.byref(prm), _d(Q), _d(G), _d(L), int(nsteps),
+    st = lib(variant).oracle_run(_dims(dims), _d(nodes), C.byref(prm), _d(Q), _d(G), _d(L), int(nsteps),
                           C.byref(d), C.byref(t), int(nthreads))
     return st, Q, G, L, d.value, t.value
 
@@ -197,13 +208,13 @@ def s2o4(dt, q, Ln, Ltn, Lts):
     return qs, qn
 
 
-def stage1_cells(dims, nodes, prm, dt, Q, G, L, cells):
+def stage1_cells(dims, nodes, prm, dt, Q, G, L, cells, variant="ieee"):
     """Stage-1 outputs (Q*, G*, L*) of the listed cells only: [n,5], [n,5,3], [n,5,12]."""
     nodes, Q, G, L = _arr(nodes), _arr(Q), _arr(G), _arr(L)
     cells = np.ascontiguousarray(cells, dtype=np.int64)
     n = len(cells)
     oq = np.zeros((n, 5)); og = np.zeros((n, 5, 3)); ol = np.zeros((n, 5, 12))
-    st = lib().oracle_stage1_cells(_dims(dims), _d(nodes), C.byref(prm), float(dt), _d(Q), _d(G), _d(L),
+    st = lib(variant).oracle_stage1_cells(_dims(dims), _d(nodes), C.byref(prm), float(dt), _d(Q), _d(G), _d(L),
                                    cells.ctypes.data_as(C.POINTER(C.c_long)), n, _d(oq), _d(og), _d(ol))
     return st, oq, og, ol
 

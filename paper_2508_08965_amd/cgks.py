@@ -219,7 +219,7 @@ def cgks_metrics(ctx: Context, vol=None, J0=None, fn=None, fw=None, stream=None)
                               _ptr(fw, 12 * n, "fw"), _stream(stream)), "cgks_metrics")
 
 
-KERNEL_KINDS = ("dt", "reconstruction", "flux", "update")
+KERNEL_KINDS = ("dt", "reconstruction", "flux_s1", "update_s1", "flux_s2", "update_s2")
 
 
 def cgks_profile(ctx: Context, enable: bool):
@@ -228,8 +228,8 @@ def cgks_profile(ctx: Context, enable: bool):
 
 def cgks_profile_read(ctx: Context):
     """{kind: (total ms, launches)} since the last read (synchronises)."""
-    ms = (C.c_double * 4)()
-    n = (C.c_long * 4)()
+    ms = (C.c_double * len(KERNEL_KINDS))()
+    n = (C.c_long * len(KERNEL_KINDS))()
     _check(lib().cgks_profile_read(ctx.h, ms, n), "cgks_profile_read")
     return {k: (ms[i], n[i]) for i, k in enumerate(KERNEL_KINDS)}
 

@@ -588,11 +588,11 @@ int cgks_stage(cgks_ctx *ctx, int stage, const double *dt_dev, double *Q, double
             HIP_TRY(run_recon(ctx, b, Q, G, L, s), "recon");
         }
         {
-            Timed t(ctx, s, 2);
+            Timed t(ctx, s, stage == 1 ? 2 : 4);
             HIP_TRY(run_flux(ctx, b, dt_dev, s, stage == 1), "flux");
         }
         {
-            Timed t(ctx, s, 3);
+            Timed t(ctx, s, stage == 1 ? 3 : 5);
             HIP_TRY(run_update(ctx, stage, b, dt_dev, Q, G, L, s), "update");
         }
     }

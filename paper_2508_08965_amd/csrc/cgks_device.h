@@ -128,6 +128,10 @@ struct DevMath {
     template <class T> __device__ static T fma(T a, T b, T c) { return ::fma(a, b, c); }
     template <class T> __device__ static T pow(T a, T b) { return ::pow(a, b); }
     template <class T> __device__ static bool finite(T x) { return isfinite(x); }
+    // Marks the start (true) and end (false) of work that both lanes of a pair perform
+    // identically (or that only one lane's result uses); free on the device, it lets a host
+    // instantiation count the flux's work once per Gauss point.
+    __device__ static void pair_shared(bool) {}
 };
 
 // Maxwellian moments normalised to unit density: <u^k> over the full line or a half line,
@@ -267,6 +271,7 @@ template <class X, class T, bool FULL = true>
 __host__ __device__ inline int gks_flux_pair(const DevParams &P, const int sd, const T q[5], const T g[5][3],
                                              const T n[3], const T dt, T Fo[5], T Fto[5], T Qs[5], T dQs[5]) {
     const T gam = T(P.gamma), K = T(P.K);
+    X::pair_shared(true);
     T t1[3];
     if (X::fabs(n[0]) > X::fabs(n[2])) {
         const T r = T(1.0) / X::sqrt(n[0] * n[0] + n[1] * n[1]);
@@ -278,6 +283,7 @@ __host__ __device__ inline int gks_flux_pair(const DevParams &P, const int sd, c
     const T t2[3] = {n[1] * t1[2] - n[2] * t1[1], n[2] * t1[0] - n[0] * t1[2], n[0] * t1[1] - n[1] * t1[0]};
     const T *fr[3] = {n, t1, t2};
     int err = 0;
+    X::pair_shared(false);
 
     // ---- own side: state and directional derivatives in the face frame -----------------
     T Wk[5], a[3][5];
@@ -345,6 +351,7 @@ __host__ __device__ inline int gks_flux_pair(const DevParams &P, const int sd, c
         psi_matrix<1, 0, 1>(mh, S); sym_mv_acc<X, T>(S, a[2], r, Xs[5]);
     }
     // pair sums (a + b is order independent, so both lanes hold identical totals)
+    X::pair_shared(true);
 #pragma unroll
     for (int i = 0; i < 9; ++i)
 #pragma unroll
@@ -381,6 +388,7 @@ __host__ __device__ inline int gks_flux_pair(const DevParams &P, const int sd, c
         m0.x[1] = K * i2l0;
         m0.x[2] = K * (K + T(2.0)) * i2l0 * i2l0;
     }
+    X::pair_shared(false);
     T e1[5] = {T(0.0), T(0.0), T(0.0), T(0.0), T(0.0)}, e0v[5], e2[5] = {T(0.0), T(0.0), T(0.0), T(0.0), T(0.0)}, Ab[5];
     {
         T S[15];
@@ -390,18 +398,21 @@ __host__ __device__ inline int gks_flux_pair(const DevParams &P, const int sd, c
         // time-derivative coefficient of g0 from the compatibility condition: needs the
         // psi-moment (even lane) version of e1
         T rhs[5];
+        X::pair_shared(true);
 #pragma unroll
         for (int v = 0; v < 5; ++v) {
             const T o = X::swap(e1[v]);
             rhs[v] = -(sd ? o : e1[v]);
         }
         sol0.solve(rhs, Ab);
+        X::pair_shared(false);
         psi_matrix<0, 0, 0>(m0, S);
 #pragma unroll
         for (int v = 0; v < 5; ++v) e0v[v] = S[sym_idx(v, 0)];
         sym_mv_acc<X, T>(S, Ab, T(1.0), e2);
     }
     // collision time (Sec. 5)
+    X::pair_shared(true);
     T tau;
     if (P.tau_zero) {
         tau = T(0.0);
@@ -423,6 +434,7 @@ __host__ __device__ inline int gks_flux_pair(const DevParams &P, const int sd, c
         if constexpr (FULL) cn[i] = (T(4.0) * C2[i] - C1[i]) * idt;
         ct[i] = T(4.0) * (C1[i] - T(2.0) * C2[i]) * idt * idt;
     }
+    X::pair_shared(false);
     // even lane: interface state W^n, W_t^n;  odd lane: flux F^n, F_t^n (face frame)
     T Yn[5], Yt[5];
 #pragma unroll
@@ -448,6 +460,7 @@ __host__ __device__ inline int gks_flux_pair(const DevParams &P, const int sd, c
     }
     if (P.viscous && P.prandtl_fix && !P.tau_zero) {
         // heat flux relative to the interface velocity, corrected to Pr (odd lane holds F)
+        X::pair_shared(true);
         const T uu = U0 * U0 + V0 * V0 + Z0 * Z0, kf = T(1.0 / P.Pr - 1.0);
         const T qt = Yt[4] - (U0 * Yt[1] + V0 * Yt[2] + Z0 * Yt[3]) + T(0.5) * uu * Yt[0] - U0 * Wt[4] +
                      U0 * (U0 * Wt[1] + V0 * Wt[2] + Z0 * Wt[3]) - T(0.5) * U0 * uu * Wt[0];
@@ -461,6 +474,7 @@ __host__ __device__ inline int gks_flux_pair(const DevParams &P, const int sd, c
         } else {
             if (sd) Yt[4] += kf * qt;
         }
+        X::pair_shared(false);
     }
     // one-sided interface values (tau0 = tau)
     const T e0 = ef, oe = T(1.0) - e0;
@@ -483,8 +497,11 @@ __host__ __device__ inline int gks_flux_pair(const DevParams &P, const int sd, c
     for (int c = 0; c < 3; ++c) {
         if constexpr (FULL) Qs[1 + c] = n[c] * Sq[1] + t1[c] * Sq[2] + t2[c] * Sq[3];
         dQs[1 + c] = n[c] * St[1] + t1[c] * St[2] + t2[c] * St[3];
+        // the flux rotation is used from the odd lane only
+        X::pair_shared(true);
         if constexpr (FULL) Fo[1 + c] = n[c] * Yn[1] + t1[c] * Yn[2] + t2[c] * Yn[3];
         Fto[1 + c] = n[c] * Yt[1] + t1[c] * Yt[2] + t2[c] * Yt[3];
+        X::pair_shared(false);
     }
     bool finite = true;
 #pragma unroll

@@ -4,9 +4,17 @@
 // type gives the number of additions, multiplications, fused multiply-adds, divisions and
 // transcendental calls (sqrt, exp, erfc, pow) of one lane.  Both lanes of a pair execute the
 // same instruction stream (the code has no lane-dependent branches; the pair exchange is a
-// value swap), so a Gauss point costs twice the count of one lane.  Prints one line:
-//   <flops per Gauss point> <adds> <muls> <fmas> <divs> <transcendentals>   (per lane)
-// with flops = adds + muls + 2 fmas + divs + transcendentals, times two lanes.
+// value swap), so the hardware issues twice the count of one lane per Gauss point.  Part of
+// that stream is the same on both lanes (the face frame, the pair sums, the equilibrium
+// state and its slopes, the time-derivative coefficient, the collision time and the time
+// integrals) or is used from one lane only (the heat-flux correction, the rotation of the
+// flux back to the global frame); the template marks those sections, and the method's work
+// per Gauss point counts them once: 2 x (per-side work) + 1 x (shared work).
+// Prints one line:
+//   <issued flops per Gauss point, stage 1> <adds> <muls> <fmas> <divs> <transcendentals>
+//   <status> <issued flops, stage 2> <method flops, stage 1> <method flops, stage 2>
+// (adds ... transcendentals per lane, stage 1) with flops = adds + muls + 2 fmas + divs +
+// transcendentals.  Stage 2 computes only the time derivatives.
 // Usage: flux_opcount [viscous] [prandtl_fix] [sutherland] [tau_zero]   (0/1 each)
 #include <cmath>
 #include <cstdio>
@@ -18,34 +26,44 @@ namespace {
 
 struct Tally {
     long add = 0, mul = 0, fma = 0, div = 0, trans = 0;
+    long flops() const { return add + mul + 2 * fma + div + trans; }
 };
-Tally tally;
+Tally own, shared;   // per-side work / work both lanes repeat
+Tally *cur = &own;
 
 struct Cnt {
     double v;
     Cnt() : v(0.0) {}
     Cnt(double x) : v(x) {}
 };
-inline Cnt operator+(Cnt a, Cnt b) { ++tally.add; return Cnt(a.v + b.v); }
-inline Cnt operator-(Cnt a, Cnt b) { ++tally.add; return Cnt(a.v - b.v); }
-inline Cnt operator*(Cnt a, Cnt b) { ++tally.mul; return Cnt(a.v * b.v); }
-inline Cnt operator/(Cnt a, Cnt b) { ++tally.div; return Cnt(a.v / b.v); }
+inline Cnt operator+(Cnt a, Cnt b) { ++cur->add; return Cnt(a.v + b.v); }
+inline Cnt operator-(Cnt a, Cnt b) { ++cur->add; return Cnt(a.v - b.v); }
+inline Cnt operator*(Cnt a, Cnt b) { ++cur->mul; return Cnt(a.v * b.v); }
+inline Cnt operator/(Cnt a, Cnt b) { ++cur->div; return Cnt(a.v / b.v); }
 inline Cnt operator-(Cnt a) { return Cnt(-a.v); }
-inline Cnt &operator+=(Cnt &a, Cnt b) { ++tally.add; a.v += b.v; return a; }
+inline Cnt &operator+=(Cnt &a, Cnt b) { ++cur->add; a.v += b.v; return a; }
 inline bool operator>(Cnt a, Cnt b) { return a.v > b.v; }
 inline bool operator<(Cnt a, Cnt b) { return a.v < b.v; }
 
 struct HostCount {
     static Cnt swap(Cnt v) { return v; }
     static int swapi(int v) { return v; }
-    static Cnt sqrt(Cnt x) { ++tally.trans; return Cnt(std::sqrt(x.v)); }
-    static Cnt exp(Cnt x) { ++tally.trans; return Cnt(std::exp(x.v)); }
-    static Cnt erfc(Cnt x) { ++tally.trans; return Cnt(std::erfc(x.v)); }
-    static Cnt pow(Cnt a, Cnt b) { ++tally.trans; return Cnt(std::pow(a.v, b.v)); }
+    static Cnt sqrt(Cnt x) { ++cur->trans; return Cnt(std::sqrt(x.v)); }
+    static Cnt exp(Cnt x) { ++cur->trans; return Cnt(std::exp(x.v)); }
+    static Cnt erfc(Cnt x) { ++cur->trans; return Cnt(std::erfc(x.v)); }
+    static Cnt pow(Cnt a, Cnt b) { ++cur->trans; return Cnt(std::pow(a.v, b.v)); }
     static Cnt fabs(Cnt x) { return Cnt(std::fabs(x.v)); }
-    static Cnt fma(Cnt a, Cnt b, Cnt c) { ++tally.fma; return Cnt(a.v * b.v + c.v); }
+    static Cnt fma(Cnt a, Cnt b, Cnt c) { ++cur->fma; return Cnt(a.v * b.v + c.v); }
     static bool finite(Cnt x) { return std::isfinite(x.v); }
+    static void pair_shared(bool on) { cur = on ? &shared : &own; }
 };
+
+Tally sum(const Tally &a, const Tally &b) {
+    Tally t;
+    t.add = a.add + b.add; t.mul = a.mul + b.mul; t.fma = a.fma + b.fma; t.div = a.div + b.div;
+    t.trans = a.trans + b.trans;
+    return t;
+}
 
 }  // namespace
 
@@ -75,12 +93,14 @@ int main(int argc, char **argv) {
     Cnt Fo[5], Fto[5], Qs[5], dQs[5];
     // full flux (first stage), then the time derivatives only (second stage)
     const int err = cgks::gks_flux_pair<HostCount, Cnt, true>(P, 0, q, g, n, Cnt(4e-4), Fo, Fto, Qs, dQs);
-    const long flops_lane = tally.add + tally.mul + 2 * tally.fma + tally.div + tally.trans;
-    const Tally full = tally;
-    tally = Tally{};
+    const Tally lane1 = sum(own, shared);
+    const long method1 = 2 * own.flops() + shared.flops();
+    own = Tally{};
+    shared = Tally{};
     const int err2 = cgks::gks_flux_pair<HostCount, Cnt, false>(P, 0, q, g, n, Cnt(4e-4), Fo, Fto, Qs, dQs);
-    const long flops_lane2 = tally.add + tally.mul + 2 * tally.fma + tally.div + tally.trans;
-    std::printf("%ld %ld %ld %ld %ld %ld %d %ld\n", 2 * flops_lane, full.add, full.mul, full.fma, full.div, full.trans,
-                err, 2 * flops_lane2);
+    const long lane2 = sum(own, shared).flops();
+    const long method2 = 2 * own.flops() + shared.flops();
+    std::printf("%ld %ld %ld %ld %ld %ld %d %ld %ld %ld\n", 2 * lane1.flops(), lane1.add, lane1.mul, lane1.fma,
+                lane1.div, lane1.trans, err, 2 * lane2, method1, method2);
     return err | err2;
 }

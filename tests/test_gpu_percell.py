@@ -2,7 +2,6 @@
 shared standard-cell matrix of Sec. 4: whole steps agree with the FP64 oracle and with the
 matrix-core path, on single and multi-block meshes whose cell counts are not multiples of the
 12-cell storage tiles."""
-import math
 
 import numpy as np
 import pytest
@@ -10,7 +9,8 @@ import torch
 
 from oracle import oracle as O
 from paper_2508_08965_amd import workloads as W
-from test_gpu_parity import assert_derived_parity, assert_line_parity
+import parity_bar as PB
+from test_gpu_parity import assert_whole_run
 
 pytestmark = pytest.mark.gpu
 GAM = 1.4
@@ -55,12 +55,9 @@ def test_percell_steps_match_oracle_curvilinear():
     Q, G, L = W.initial_state(nodes, W.taylor_green(Ma=0.3), GAM)
     st, Qg, Gg, Lg = steps([n], [nodes], K().default_params(recon_impl=2, **tgv_kw()), (Q, G, L), 3)
     assert st == (0, 0)
-    so, Qo, Go, Lo, _, _ = O.run(n, nodes.numpy(), O.params(**tgv_kw()), Q.numpy(), G.numpy(), L.numpy(), 3)
-    assert so == 0
-    assert rel(Qg, Qo) <= TOL
-    # G and L are built from interface values: the derived bar of the other whole-step tests
-    assert_derived_parity(Gg, Go, Qo, "G", h=2 * math.pi / max(n))
-    assert_line_parity(Lg, Lo, Qo)
+    ref, sp, _ = PB.oracle_run_pair(n, nodes, O.params(**tgv_kw()), Q, G, L, 3)
+    # G and L are built from interface values: the measured bar of the other whole-step tests
+    assert_whole_run(Qg, Gg, Lg, ref, sp)
 
 
 @pytest.mark.parametrize("linear", [0, 1])
@@ -77,5 +74,24 @@ def test_percell_matches_matrix_cores_multiblock(linear):
     b = steps(dims, nodes, K().default_params(**kw), state, 2)
     assert a[0] == b[0] == (0, 0)
     assert rel(a[1], b[1]) <= TOL
-    assert rel(a[2], b[2]) <= 1e-10  # G, L: differences of face values (cancellation)
-    assert rel(a[3], b[3]) <= 1e-10
+    # each block against the oracle (global CFL step: the minimum over the blocks), G and L
+    # within the oracle's measured spread
+    prm = O.params(**kw)
+    cur = [tuple(t.numpy() for t in s) for s in states]
+    alt = [PB.jitter_state(*c) for c in cur]
+    for _ in range(2):
+        dt = min(O.cfl_dt(n, nd.numpy(), prm, c[0]) for n, nd, c in zip(dims, nodes, cur))
+        da = min(O.cfl_dt(n, nd.numpy(), prm, c[0]) for n, nd, c in zip(dims, nodes, alt))
+        nxt, nxa = [], []
+        for n, nd, c, ca in zip(dims, nodes, cur, alt):
+            so, *r = O.run(n, nd.numpy(), prm, *c, 1, dt=dt)[:4]
+            sa, *ra = O.run(n, nd.numpy(), prm, *ca, 1, dt=da, variant="fma")[:4]
+            assert so == sa == 0
+            nxt.append(tuple(r))
+            nxa.append(tuple(ra))
+        cur, alt = nxt, nxa
+    ref = [np.concatenate([c[i] for c in cur], axis=-1) for i in range(3)]
+    oth = [np.concatenate([c[i] for c in alt], axis=-1) for i in range(3)]
+    sp = {k: PB.spread(x, y) for k, x, y in zip("QGL", ref, oth)}
+    for got in (a, b):
+        assert_whole_run(*got[1:], ref, sp)
