@@ -162,6 +162,20 @@ long cgks_num_cells(const cgks_ctx *ctx);
  * dt_dev: device, one double, written on the stream. */
 int cgks_dt(cgks_ctx *ctx, const double *Q, double *dt_dev, void *stream);
 
+/* cgks_dt for callers that cannot allocate device memory at call time (code under stream
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same result, bitwise (the
+ * same partition of the cells into partial minima), with the partial minima in a static
+ * device array of the library (1024 doubles, 8 KB per GPU, held until the process ends)
+ * instead of context memory.  It launches two kernels and calls no hipMalloc, hipFree or
+ * other allocating routine; nothing needs clearing (every partial is written before it is
+ * read).  Every call on a GPU shares that GPU's array: calls that overlap on one GPU (other
+ * streams, other contexts, other threads) race and must be ordered by the caller.  Q, dt_dev
+ * and stream as for cgks_dt.  Errors: CGKS_EINVAL for a NULL argument or a context whose
+ * partition needs more than 1024 partial minima (never, for partitions of at most 1024
+ * workgroups, which the context uses); CGKS_EHIP if the array's address could not be
+ * looked up on this device when the context was created. */
+int cgks_dt_noalloc(cgks_ctx *ctx, const double *Q, double *dt_dev, void *stream);
+
 /* One S2O4 stage in place (temporal-discretisation section of the paper).
  *   stage 1: Q* = Q + dt/2 L(Q) + dt^2/8 dL/dt;  G*, L* from the interface values evolved to
  *            t + dt/2; saves what stage 2 needs in the context.

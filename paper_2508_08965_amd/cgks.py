@@ -54,6 +54,7 @@ def lib():
         L.cgks_num_cells.argtypes = [vp]
         L.cgks_num_cells.restype = C.c_long
         L.cgks_dt.argtypes = [vp, vp, vp, vp]
+        L.cgks_dt_noalloc.argtypes = [vp, vp, vp, vp]
         L.cgks_diagnostics.argtypes = [vp, vp, vp, vp, vp]
         L.cgks_qcriterion.argtypes = [vp, vp, vp, vp, vp]
         L.cgks_stage.argtypes = [vp, C.c_int, vp, vp, vp, vp, vp]
@@ -164,6 +165,12 @@ class Context:
 
 def cgks_dt(ctx: Context, Q, dt_dev, stream=None):
     _check(lib().cgks_dt(ctx.h, _ptr(Q, 5 * ctx.ncells, "Q"), _ptr(dt_dev, 1, "dt"), _stream(stream)), "cgks_dt")
+
+
+def cgks_dt_noalloc(ctx: Context, Q, dt_dev, stream=None):
+    """cgks_dt with its partial minima in the library's static device array (no allocation)."""
+    _check(lib().cgks_dt_noalloc(ctx.h, _ptr(Q, 5 * ctx.ncells, "Q"), _ptr(dt_dev, 1, "dt"), _stream(stream)),
+           "cgks_dt_noalloc")
 
 
 def cgks_diagnostics(ctx: Context, Q, G, out, stream=None):

@@ -4,6 +4,8 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -35,6 +37,32 @@ int hip_fail(hipError_t e, const char *where) {
 constexpr int kMaxDtParts = 1024;
 }  // namespace
 
+// Partial minima of cgks_dt_noalloc: a file-scope device array (one copy per GPU, held until
+// the process ends) instead of context memory.  In host code its name is not a device address;
+// each device's copy is looked up once, with that device current, by hipGetSymbolAddress, and
+// only that pointer is used.
+constexpr int kNoallocDtParts = 1024;  // 8 KB
+static __device__ __align__(256) double scratch[kNoallocDtParts];
+
+namespace {
+std::mutex g_scratch_mu;
+std::map<int, double *> g_scratch;  // device -> address of its copy of `scratch`
+
+// Address of `scratch` on the current device `dev` (looked up on the first call per device).
+int scratch_address(int dev, double **out) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch.find(dev);
+    if (it == g_scratch.end()) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) return e != hipSuccess ? e : hipErrorInvalidSymbol;
+        it = g_scratch.emplace(dev, (double *)p).first;
+    }
+    *out = it->second;
+    return hipSuccess;
+}
+}  // namespace
+
 struct cgks_ctx {
     int device = 0;
     std::vector<BlockView> blocks;
@@ -50,6 +78,7 @@ struct cgks_ctx {
     double *Kmf = nullptr;    // constant blocks of the matrix-core reconstruction
     double *pcm = nullptr;    // per-cell matrices (recon_impl 2), tiled by 64 cells
     double *dt_part = nullptr;
+    double *dt_static = nullptr;  // this device's copy of `scratch` (cgks_dt_noalloc)
     double *diag_part = nullptr;  // [nparts][7] partial sums of the flow diagnostics
     void *wallf = nullptr;        // wall sides: F, F_t of the minus-side wall faces [4 kk][10][Wtot]
     long Wtot = 0;                // wall faces of the minus sides over every block and axis
@@ -433,6 +462,13 @@ int cgks_ctx_create(cgks_ctx **out, int nblocks, const int *dims, const double *
     hipStream_t s = (hipStream_t)stream;
     cgks_ctx *c = new cgks_ctx();
     HIP_TRY(hipGetDevice(&c->device), "hipGetDevice");
+    {
+        const int e = scratch_address(c->device, &c->dt_static);
+        if (e != hipSuccess) {
+            delete c;
+            return hip_fail((hipError_t)e, "hipGetSymbolAddress(scratch)");
+        }
+    }
     c->blocks = blocks;
     c->Ntot = Ntot;
     c->Wtot = Wtot;
@@ -553,6 +589,19 @@ int cgks_dt(cgks_ctx *ctx, const double *Q, double *dt_dev, void *stream) {
     Timed t(ctx, s, 0);
     HIP_TRY(launch_dt(0, ctx->Ntot, ctx->Ntot, Q, ctx->M.dtm, ctx->P, ctx->dt_part, ctx->nparts, ctx->flag, s), "dt");
     HIP_TRY(launch_dt_final(ctx->dt_part, ctx->nparts, dt_dev, s), "dt final");
+    return CGKS_OK;
+}
+
+int cgks_dt_noalloc(cgks_ctx *ctx, const double *Q, double *dt_dev, void *stream) {
+    if (!ctx || !Q || !dt_dev) return fail(CGKS_EINVAL, "cgks_dt_noalloc: NULL argument");
+    if (ctx->nparts > kNoallocDtParts)
+        return fail(CGKS_EINVAL, "cgks_dt_noalloc: partition larger than the static scratch (1024 partial minima)");
+    if (!ctx->dt_static) return fail(CGKS_EHIP, "cgks_dt_noalloc: no static scratch on this device");
+    hipStream_t s = (hipStream_t)stream;
+    ctx->last = s;
+    HIP_TRY(launch_dt(0, ctx->Ntot, ctx->Ntot, Q, ctx->M.dtm, ctx->P, ctx->dt_static, ctx->nparts, ctx->flag, s),
+            "dt (static scratch)");
+    HIP_TRY(launch_dt_final(ctx->dt_static, ctx->nparts, dt_dev, s), "dt final (static scratch)");
     return CGKS_OK;
 }
 
