@@ -276,21 +276,77 @@ def bench_batching(K, W, torch, steps, warmup):
     out["autotune"] = {"candidates": tune, "picked": {K.KIND_NAMES[k]: K.cgks_get_launch(ctx, k) for k in (1, 2, 3)}}
     run(ctx, "one launch per kernel over all blocks, autotuned")
     run(ctx, "one launch per kernel over all blocks, autotuned, HIP graph of dt + 2 stages", graph=True)
+
+    def kernel_ns_per_cell(c, Q, G, L, ncell):
+        """Per kernel kind, average launch time per cell (HIP events), over `steps` steps."""
+        _, prof = timed_steps(K, c, Q, G, L, dt, steps)
+        return {k: 1e6 * ms / max(n, 1) / ncell for k, (ms, n) in prof.items() if n}
+
+    Q, G, L = Q0.clone(), G0.clone(), L0.clone()
+    out["kernel_ns_per_cell"] = {"batched_24_blocks": kernel_ns_per_cell(ctx, Q, G, L, N)}
+    # time between kernels: the step's wall time less its kernels' HIP-event times (all that one
+    # persistent launch per stage could remove besides the kernels' own tails)
+    el, prof = timed_steps(K, ctx, Q, G, L, dt, steps)
+    kms = sum(v[0] for v in prof.values()) / steps
+    out["between_kernels_ms_per_step"] = {"step_ms": 1e3 * el / steps, "kernels_ms": kms,
+                                          "gap_ms": 1e3 * el / steps - kms,
+                                          "launches_per_step": sum(v[1] for v in prof.values()) / steps}
     ctx.close()
+    del Q, G, L
+    torch.cuda.empty_cache()
+    # the same flow on one cubic block of about the same number of cells: separates what the
+    # flow costs (more cells with an active nonlinear blend than in the Taylor-Green vortex at
+    # Ma 0.1) from what the batching costs
+    m = int(round(N ** (1.0 / 3.0)))
+    n1 = (m, m, m)
+    nd = W.perturbed_nodes(n1, amp=0.05, device=dev)
+    Q, G, L = W.initial_state(nd, W.isotropic_turbulence(64, k0=4.0, Mt=0.5, seed=8965), GAM)
+    nd_h = nd.cpu()
+    ctx = K.Context([n1], [nd_h], K.default_params(**hit_kw()))
+    del nd
+    for _ in range(warmup):
+        K.cgks_step(ctx, Q, G, L, dt, use_cfl=True)
+    torch.cuda.synchronize()
+    Q0s, G0s, L0s = Q.clone(), G.clone(), L.clone()
+    el, _ = timed_steps(K, ctx, Q, G, L, dt, steps)
+    out["single_block_same_flow"] = {"cells": m ** 3, "dims": list(n1), "value": m ** 3 * steps / el,
+                                     "unit": "cell-updates/s", "ms_per_step": 1e3 * el / steps,
+                                     "device_flags": K.cgks_check(ctx)[1]}
+    out["kernel_ns_per_cell"]["single_block_same_flow"] = kernel_ns_per_cell(ctx, Q, G, L, m ** 3)
+    ctx.close()
+    # the linear scheme (chi = 1 everywhere: every wave of the reconstruction takes one path)
+    # on both layouts: the per-cell cost of the batching and the block shapes alone, apart from
+    # the flow's share of cells with an active nonlinear blend, which the coarser small blocks
+    # raise
+    lin = {}
+    for label, dl, nl, (q0, g0, l0), nc in (("batched_24_blocks", dims, nodes_h, (Q0, G0, L0), N),
+                                            ("single_block", [n1], [nd_h], (Q0s, G0s, L0s), m ** 3)):
+        c = K.Context(dl, nl, K.default_params(linear=1, **hit_kw()))
+        q, g, l = q0.clone(), g0.clone(), l0.clone()
+        for _ in range(warmup):
+            K.cgks_step(c, q, g, l, dt, use_cfl=True)
+        lin[label] = kernel_ns_per_cell(c, q, g, l, nc)
+        c.close()
+        del q, g, l
+    out["kernel_ns_per_cell_linear_scheme"] = lin
+    del Q, G, L, Q0s, G0s, L0s
     torch.cuda.empty_cache()
     return out
 
 
-def bench_learned(K, W, torch, n_eval=256, n_train=64, eval_steps=50, train_steps=1500):
-    """Learned blend weights on supersonic isotropic turbulence (Mt 1.0, k0 8, Re_lambda 100):
-    pairs (features, GENO weights) from the plain FP64 scheme at n_train^3 (seeds 8967-8970, run
-    to t ~ lambda/u' or to the first non-physical state, which the scheme meets once shocklets
-    form), balanced between chi < 0.99 and chi ~ 1; FP32 Adam training on the GPU;
-    then n_eval^3 (seed 8966) advanced eval_steps steps with learned and with GENO weights."""
+def bench_learned(K, W, torch, n_eval=256, n_train=64, eval_t=0.2, train_steps=1500):
+    """Learned blend weights on supersonic isotropic turbulence (Mt 1.0, k0 8, Re_lambda 100),
+    with the interface-state limiter (positivity = 1: local Mach numbers reach ~2.8, and without
+    it the scheme meets a non-physical state once shocklets form, t ~ 0.09 at 64^3): pairs
+    (features, GENO weights) from the FP64 scheme at n_train^3 (seeds 8967-8970, run to
+    t = lambda/u'), balanced between chi < 0.99 and chi ~ 1; FP32 Adam training on the GPU;
+    then n_eval^3 (seed 8966) advanced past the formation of shocklets (to t >= eval_t) with
+    learned and with GENO weights, the same number of steps each."""
     import numpy as np
     dev = torch.device("cuda:0")
     T0 = 1.0 / GAM
-    kw = dict(viscous=1, visc_law=1, mu0=1.44e-3, T_ref=T0, S_suth=T0 * 110.4 / 288.15, Pr=0.72, prandtl_fix=1)
+    kw = dict(viscous=1, visc_law=1, mu0=1.44e-3, T_ref=T0, S_suth=T0 * 110.4 / 288.15, Pr=0.72, prandtl_fix=1,
+              positivity=1)
     two_pi = 2.0 * math.pi
     t_end = 0.25 / 0.5774
     # ---- training pairs -------------------------------------------------------------------------
@@ -309,8 +365,6 @@ def bench_learned(K, W, torch, n_eval=256, n_train=64, eval_steps=50, train_step
         t, k, flags = 0.0, 0, 0
         while t < t_end and k < 400:
             K.cgks_step(gen, Q, G, L, dt, use_cfl=True)
-            # once shocklets form (t ~ 0.13 at Mt 1.0) the scheme meets non-physical states; pairs
-            # are taken from the states before that only
             flags = K.cgks_check(gen)[1]
             if flags:
                 break
@@ -350,27 +404,35 @@ def bench_learned(K, W, torch, n_eval=256, n_train=64, eval_steps=50, train_step
     Ne = n_eval ** 3
     dt = torch.zeros(1, dtype=torch.float64, device=dev)
 
-    def run(c):
+    def run(c, nsteps=None):
+        """Steps to t >= eval_t (or nsteps steps); the time per step is taken over all of them
+        (the device scalar dt is read back every 10 steps only)."""
         Q, G, L = Q0.clone(), G0.clone(), L0.clone()
         K.cgks_step(c, Q, G, L, dt, use_cfl=True)
         torch.cuda.synchronize()
         Q.copy_(Q0)
         G.copy_(G0)
         L.copy_(L0)
+        tsum = torch.zeros(1, dtype=torch.float64, device=dev)
+        k = 0
         t0 = time.perf_counter()
-        for _ in range(eval_steps):
+        while (nsteps is None and k < 1000) or (nsteps is not None and k < nsteps):
             K.cgks_step(c, Q, G, L, dt, use_cfl=True)
+            tsum += dt
+            k += 1
+            if k % 10 == 0 and tsum.item() >= eval_t and nsteps is None:  # both runs sync alike
+                break
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
-        return Q, el, K.cgks_check(c)
+        return Q, el, K.cgks_check(c), k, tsum.item()
 
     K.cgks_mlp_fallback(ctx)
-    Qm, el_m, st_m = run(ctx)
+    Qm, el_m, st_m, eval_steps, t_m = run(ctx)
     flagged, examined = K.cgks_mlp_fallback(ctx)
     ctx.close()
     torch.cuda.empty_cache()
     plain = K.Context([e], [nodes_e], K.default_params(**kw))
-    Qp, el_p, st_p = run(plain)
+    Qp, el_p, st_p, _, t_p = run(plain, eval_steps)
     plain.close()
 
     def errs(a, b):
@@ -380,9 +442,9 @@ def bench_learned(K, W, torch, n_eval=256, n_train=64, eval_steps=50, train_step
 
     speed = lambda q: torch.sqrt(q[1] ** 2 + q[2] ** 2 + q[3] ** 2) / q[0]
     return {
-        "workload": f"isotropic turbulence Mt 1.0 k0 8 Re_lambda 100, {n_eval}^3 periodic Cartesian, FP64; MLP "
-                    f"18-32-7 trained on {Xtr.shape[0]} balanced pairs from {n_train}^3 runs (4 seeds, t <= "
-                    f"{max(r['t'] for r in runs):.3f}: before the first non-physical state)",
+        "workload": f"isotropic turbulence Mt 1.0 k0 8 Re_lambda 100, {n_eval}^3 periodic Cartesian, FP64, "
+                    f"interface-state limiter on; MLP 18-32-7 trained on {Xtr.shape[0]} balanced pairs from "
+                    f"{n_train}^3 runs (4 seeds, t <= {max(r['t'] for r in runs):.3f})",
         "train": {"steps": train_steps, "batch": 4096, "lr": 1e-3, "seconds": t_train,
                   "loss_first10": float(np.mean(hist[:10])), "loss_last100": float(np.mean(hist[-100:])),
                   "pairs": int(Xtr.shape[0]), "fraction_chi_below_0.99": frac_low, "generator_runs": runs},
@@ -390,7 +452,8 @@ def bench_learned(K, W, torch, n_eval=256, n_train=64, eval_steps=50, train_step
                     "fallback_fraction": flagged / max(examined, 1), "device_flags": st_m[1]},
         "geno": {"value": Ne * eval_steps / el_p, "unit": "cell-updates/s", "ms_per_step": 1e3 * el_p / eval_steps,
                  "device_flags": st_p[1]},
-        "learned_vs_geno_after_steps": {"steps": eval_steps, "rho": errs(Qm[0], Qp[0]),
+        "learned_vs_geno_after_steps": {"steps": eval_steps, "t_learned": t_m, "t_geno": t_p,
+                                        "rho": errs(Qm[0], Qp[0]),
                                         "speed": errs(speed(Qm), speed(Qp)), "rhoE": errs(Qm[4], Qp[4])},
     }
 
@@ -523,7 +586,8 @@ def bench_walls(K, W, torch, kw, n=256, steps=5, warmup=2, check_oracle=True):
 def bench_supersonic_tgv(K, W, torch, n=128, t_end=10.0, Ma=1.25):
     """Robustness run of Sec. 5: the supersonic Taylor-Green vortex (Ma 1.25, Re 1600, Pr 0.7,
     Sutherland) with the nonlinear scheme on the paper's uniform n^3 mesh, to t_end, with the
-    kinetic energy and enstrophy history from the library's diagnostics."""
+    kinetic energy and enstrophy history from the library's diagnostics: cell-centre midpoint
+    sums, and 3^3 Gauss points per cell on the compact reconstruction."""
     dev = torch.device("cuda:0")
     m = (n,) * 3
     nodes = W.cartesian_nodes(m, hi=(2.0 * math.pi,) * 3)
@@ -538,8 +602,12 @@ def bench_supersonic_tgv(K, W, torch, n=128, t_end=10.0, Ma=1.25):
         K.cgks_diagnostics(ctx, Q, G, d)
         return d.tolist()
 
+    def diag_hq():
+        K.cgks_diagnostics_hq(ctx, Q, G, L, d)
+        return d.tolist()
+
     d0 = diag()
-    hist = [[0.0] + d0[:2]]
+    hist = [[0.0] + d0[:2] + diag_hq()[:2]]
     rho_min, p_min = d0[4], d0[5]
     t, k, flags = 0.0, 0, 0
     torch.cuda.synchronize()
@@ -552,7 +620,7 @@ def bench_supersonic_tgv(K, W, torch, n=128, t_end=10.0, Ma=1.25):
             x = diag()
             rho_min, p_min = min(rho_min, x[4]), min(p_min, x[5])
             if k % 100 == 0 or t >= t_end:
-                hist.append([t] + x[:2])
+                hist.append([t] + x[:2] + diag_hq()[:2])
             flags = K.cgks_check(ctx)[1]
             if flags:
                 break
@@ -567,7 +635,7 @@ def bench_supersonic_tgv(K, W, torch, n=128, t_end=10.0, Ma=1.25):
             "steps": k, "t": t, "seconds": el, "cell_updates_per_s": n ** 3 * k / el, "device_flags": flags,
             "min_rho": rho_min, "min_p_over_p0": p_min / p0,
             "mass_rel_drift": (d1[2] - d0[2]) / d0[2], "energy_rel_drift": (d1[3] - d0[3]) / d0[3],
-            "history_t_Ek_epsS": hist}
+            "history_t_Ek_epsS_EkGauss_epsSGauss": hist}
 
 
 def main():
@@ -584,6 +652,8 @@ def main():
     ap.add_argument("--no-percell", action="store_true", help="skip the per-cell matrix storage measurement")
     ap.add_argument("--no-supersonic", action="store_true", help="skip the supersonic Taylor-Green robustness run")
     ap.add_argument("--no-walls", action="store_true", help="skip the wall-side measurement")
+    ap.add_argument("--only", choices=["batching"], default=None,
+                    help="run one leg alone and print its record (for profiling that workload)")
     ap.add_argument("--supersonic-n", type=int, default=128, help="cells per axis of the supersonic TGV run")
     ap.add_argument("--supersonic-t", type=float, default=10.0, help="end time of the supersonic TGV run")
     ap.add_argument("--dump-state", default=None,
@@ -602,6 +672,9 @@ def main():
     from paper_2508_08965_amd import workloads as W
 
     dev = torch.device("cuda:0")
+    if args.only == "batching":
+        print(json.dumps({"batching": bench_batching(K, W, torch, args.steps, args.warmup)}))
+        return
     if args.copy_calibration:
         a = torch.ones(1 << 27, dtype=torch.float64, device=dev)
         b = torch.empty_like(a)

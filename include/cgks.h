@@ -112,6 +112,15 @@ typedef struct {
                             mirror image and one behind a far-field side as the far field */
     double farfield[5];  /* far-field state (rho, rho U, rho V, rho W, rho E) of bc 3 sides;
                             positive density and pressure (EINVAL otherwise)             */
+    int positivity;      /* 1: interface-state limiter (not in the paper; for flows whose
+                            local Mach number reaches ~3, where internal energy is a small
+                            part of the total): at each face Gauss point, a cell's
+                            reconstructed state (value q, gradient g) becomes
+                            qbar + theta (q - qbar) and theta g, theta the largest value in
+                            [0, 1] keeping its density and pressure at or above pos_eps times
+                            the cell average qbar's own.  Periodic blocks only (EUNSUPPORTED
+                            with wall sides).  Default 0                                 */
+    double pos_eps;      /* floor of the limiter, in (0, 1) (default 1e-3)               */
 } cgks_params;
 
 /* Fill *p with the defaults listed above (inviscid, nonlinear, FP64). */
@@ -152,6 +161,20 @@ int cgks_diagnostics(cgks_ctx *ctx, const double *Q, const double *G, double *ou
  * Q [5][N], G [5][3][N]: device state; out: device array of N doubles, overwritten.
  * Enqueued on `stream`; EINVAL on a NULL argument. */
 int cgks_qcriterion(cgks_ctx *ctx, const double *Q, const double *G, double *out, void *stream);
+
+/* The diagnostics of cgks_diagnostics from the compact reconstruction (Sec. 5, Taylor-Green
+ * vortex, with the velocity derivatives taken from the reconstruction at quadrature points):
+ * each cell is integrated by 3^3 Gauss points of its trilinear map (volume element |det J|),
+ * with the conserved variables and their gradients at the points from the cell's
+ * reconstruction blended as at the face Gauss points, Q = chi P^4 + (1 - chi)(Q_0 + bbar . xi)
+ * (eq. weno-new), reference gradients likewise, physical ones by (J0^T)^-1.  Converges at
+ * fourth order or better on smooth fields (the midpoint rule of cgks_diagnostics: second).
+ * Q, G, L: device state; out: device array of 6 doubles, written on the stream, as for
+ * cgks_diagnostics (minima over the quadrature points).  Periodic blocks only
+ * (CGKS_EUNSUPPORTED with wall sides; at most 1024 blocks); deterministic; overwrites the
+ * context's Gauss-point buffer (no stage needs it across calls).  EINVAL on a NULL argument. */
+int cgks_diagnostics_hq(cgks_ctx *ctx, const double *Q, const double *G, const double *L, double *out,
+                        void *stream);
 
 /* Total number of cells N of the context. */
 long cgks_num_cells(const cgks_ctx *ctx);
@@ -231,9 +254,11 @@ int cgks_profile_read(cgks_ctx *ctx, double *ms, long *launches);
  * The reconstruction, flux and update kernels walk a work list of tiles (runs of consecutive
  * cells of one block) that spans every block, so one launch per kernel advances the whole
  * multi-block mesh.  Launch configuration per kernel kind (1 reconstruction, 2 flux, 3 update):
- *   tile_cells  cells per tile.  Reconstruction: a multiple of 16 in [16, 4096], default
- *               1536 (one workgroup of 8 waves takes a tile and first stages the constant
- *               matrices in LDS; a wave takes 16 cells of one variable);
+ *   tile_cells  cells per tile.  Reconstruction: a multiple of 16 in [16, 4096] (one
+ *               workgroup of 8 waves takes a tile and first stages the constant matrices in
+ *               LDS; a wave takes 16 cells of one variable).  Default: bricks of 16 x 8 x 10
+ *               cells staged in LDS (stage 1) for the FP64 and FP32x3 reconstruction, runs of
+ *               1536 cells for BF16x3;
  *               flux 128 and update 256 are fixed by their workgroup size.
  *   ngroups     0: one workgroup per unit (tile, or tile and Gauss point for the flux);
  *               > 0: a persistent grid of that many workgroups striding over the units
@@ -249,6 +274,11 @@ typedef struct {
     int brick_y, brick_z;  /* reconstruction only: 0, 0 for runs of tile_cells cells; both > 0 for
                               bricks of tile_cells x brick_y x brick_z cells (clipped to the
                               block) whose workgroup walks its planes in order of z */
+    int stage;             /* reconstruction only: 1 stages each brick with its one-cell halo in
+                              LDS, one conserved variable at a time, and gathers the neighbours
+                              from there; needs bricks with tile_cells = 16 and
+                              (brick_y + 2) (brick_z + 2) <= 120, and the FP64 or FP32x3
+                              reconstruction.  0: neighbours gathered from memory */
 } cgks_launch;
 
 /* Read the launch configuration of a kernel kind (1, 2 or 3) into *out (host). */

@@ -78,6 +78,8 @@ typedef struct {
                                 (slip, adiabatic), 2 no-slip adiabatic wall (reading D26),
                                 3 far field (reading D27) */
     double far[5];           /* far-field state (conserved variables) */
+    int positivity;          /* 1: interface states kept physical (reading D28, not in the paper) */
+    double pos_eps;          /* floor of that limiter, a fraction of the cell average's rho, p */
 } or_params;
 
 enum { OR_OK = 0, OR_EINVAL = -1, OR_ENONPHYS = -4 };
@@ -358,6 +360,44 @@ static double mirror_sign(const or_mesh *M, int s, int v) {
    derivative are zero (reading D26).  The kinetic flux between the interior side and its
    mirror image leaves them at the truncation level only, because the mirror image reverses the
    velocity but not the tangential slopes of density and energy. */
+/* Positivity of one interface state (reading D28: an addition to the paper, whose cases stay
+   below Mach ~1.3).  The reconstructed state of a cell at a face Gauss point, value q and
+   gradient g, is moved toward the cell average qbar, q <- qbar + theta (q - qbar) and
+   g <- theta g, with the largest theta in [0, 1] that keeps its density and pressure at or
+   above eps times those of the cell average.  The density bound is linear in theta.  Along
+   the segment, rho p / (gamma - 1) = rho E - |m|^2 / 2 is a quadratic in theta that is
+   positive at theta = 0; its one root in (0, 1) is taken in closed form,
+   t = 2c / (-b + sqrt(b^2 - 4 a c)) for a t^2 + b t + c.  States at or above the floor, and
+   cells whose own average is not physical, are left unchanged. */
+static void positivity_state(const or_params *P, const double qbar[5], double q[5], double g[5][3]) {
+    const double gm1 = P->gamma - 1.0;
+    const double rb = qbar[0];
+    const double pb = gm1 * (qbar[4] - 0.5 * (qbar[1] * qbar[1] + qbar[2] * qbar[2] + qbar[3] * qbar[3]) / rb);
+    if (!(rb > 0.0) || !(pb > 0.0)) return;
+    const double er = P->pos_eps * rb, ep = P->pos_eps * pb;
+    double th = 1.0;
+    if (q[0] < er) th = (rb - er) / (rb - q[0]);
+    double d[5], z[5];
+    for (int v = 0; v < 5; ++v) {
+        d[v] = th * (q[v] - qbar[v]);
+        z[v] = qbar[v] + d[v];
+    }
+    const double pz = gm1 * (z[4] - 0.5 * (z[1] * z[1] + z[2] * z[2] + z[3] * z[3]) / z[0]);
+    if (pz < ep) {
+        const double e1 = ep / gm1;
+        const double a = d[0] * d[4] - 0.5 * (d[1] * d[1] + d[2] * d[2] + d[3] * d[3]);
+        const double b = rb * d[4] + qbar[4] * d[0] - (qbar[1] * d[1] + qbar[2] * d[2] + qbar[3] * d[3]) - e1 * d[0];
+        const double c = rb * qbar[4] - 0.5 * (qbar[1] * qbar[1] + qbar[2] * qbar[2] + qbar[3] * qbar[3]) - e1 * rb;
+        th *= 2.0 * c / (-b + sqrt(b * b - 4.0 * a * c));
+    }
+    if (th < 1.0) {
+        for (int v = 0; v < 5; ++v) {
+            q[v] = qbar[v] + th * (q[v] - qbar[v]);
+            for (int r = 0; r < 3; ++r) g[v][r] *= th;
+        }
+    }
+}
+
 static void noslip_flux(double F[5], double Ft[5]) {
     F[0] = F[4] = Ft[0] = Ft[4] = 0.0;
 }
@@ -478,6 +518,8 @@ static int mesh_build(or_mesh *M, const int dims[3], const double *nodes, const 
         if ((M->bc[2 * q] == 0) != (M->bc[2 * q + 1] == 0)) return OR_EINVAL; /* periodic pairs */
     }
     for (int s = 0; s < 6 && P; ++s)
+        if (P->positivity && M->bc[s]) return OR_EINVAL; /* the limiter is for periodic blocks */
+    for (int s = 0; s < 6 && P; ++s)
         if (M->bc[s] == 3) { /* the far-field state needs positive density and pressure */
             const double *f = P->far;
             if (!(f[0] > 0.0)) return OR_EINVAL;
@@ -566,6 +608,136 @@ static long face_of(const or_mesh *M, long c, int m) {
 /*  Compact reconstruction with GENO blend: Sec. 3.2, 3.3, 4          */
 /* ================================================================== */
 
+/* The compact stencil of a cell: its 6 face and 12 edge neighbours (the cell itself, or the
+   mirror cell inside, behind wall sides), the wall sides each lies behind (-1: none), and the
+   two directions of each edge neighbour's directional derivatives. */
+typedef struct {
+    long fnb[6], enb[12];
+    int fside[6][3], eside[12][3];
+    double t1[12][3], t2[12][3];
+} stencil_t;
+
+static void stencil_of(const or_mesh *M, long c, stencil_t *S) {
+    int i = c % M->nx, j = (c / M->nx) % M->ny, k = c / ((long)M->nx * M->ny);
+    for (int m = 0; m < 6; ++m) {
+        double o[3]; face_offset(m, o);
+        int idx[3] = {i + (int)o[0], j + (int)o[1], k + (int)o[2]};
+        S->fnb[m] = nb_cell(M, idx, S->fside[m]);
+    }
+    for (int n = 0; n < 12; ++n) {
+        double o[3]; edge_geom(n, o, S->t1[n], S->t2[n]);
+        int idx[3] = {i + (int)o[0], j + (int)o[1], k + (int)o[2]};
+        S->enb[n] = nb_cell(M, idx, S->eside[n]);
+    }
+}
+
+/* Stencil data b of variable v of cell c (eq. compact-big-ref: face and edge differences,
+   neighbour gradients in the target's reference frame, line derivatives) and the quartic's
+   coefficients a = R b. */
+static void cell_coeffs(const or_mesh *M, const or_params *P, const double *Q, const double *G, const double *L,
+                        long c, const double *J, const stencil_t *S, int v, double b[NR], double a[NB]) {
+    const long N = M->n;
+    /* neighbour data, mirrored across the walls it lies behind: the ghost cell's average and
+       gradient are the mirror images of those of its mirror cell (reading D26) */
+    double nq[18], ngr[18][3];
+    for (int t = 0; t < 18; ++t) {
+        const long nb = (t < 6) ? S->fnb[t] : S->enb[t - 6];
+        const int *sd = (t < 6) ? S->fside[t] : S->eside[t - 6];
+        double sv = 1.0, sr[3] = {1.0, 1.0, 1.0};
+        int far = 0;
+        for (int q = 0; q < 3; ++q)
+            if (sd[q] >= 0) {
+                far |= M->bc[sd[q]] == 3;
+                double m = mirror_sign(M, sd[q], v);
+                sv *= m;
+                for (int r = 0; r < 3; ++r) sr[r] *= (r == q) ? -m : m;
+            }
+        nq[t] = sv * Q[v * N + nb];
+        for (int r = 0; r < 3; ++r) ngr[t][r] = sr[r] * G[(v * 3 + r) * N + nb];
+        if (far) { /* behind a far-field side: the uniform far-field state */
+            nq[t] = P->far[v];
+            ngr[t][0] = ngr[t][1] = ngr[t][2] = 0.0;
+        }
+    }
+    double q0 = Q[v * N + c];
+    for (int m = 0; m < 6; ++m) b[m] = nq[m] - q0;
+    for (int n = 0; n < 12; ++n) b[6 + n] = nq[6 + n] - q0;
+    /* neighbour gradients in the target's reference frame: (grad Q)' = J0^T grad Q */
+    for (int m = 0; m < 6; ++m)
+        for (int jj = 0; jj < 3; ++jj) {
+            double s2 = 0;
+            for (int r = 0; r < 3; ++r) s2 += J[3 * r + jj] * ngr[m][r];
+            b[18 + 3 * m + jj] = s2;
+        }
+    for (int n = 0; n < 12; ++n) {
+        double gr[3];
+        for (int jj = 0; jj < 3; ++jj) {
+            double s2 = 0;
+            for (int r = 0; r < 3; ++r) s2 += J[3 * r + jj] * ngr[6 + n][r];
+            gr[jj] = s2;
+        }
+        b[36 + 2 * n] = S->t1[n][0] * gr[0] + S->t1[n][1] * gr[1] + S->t1[n][2] * gr[2];
+        b[36 + 2 * n + 1] = S->t2[n][0] * gr[0] + S->t2[n][1] * gr[1] + S->t2[n][2] * gr[2];
+    }
+    for (int s = 0; s < 12; ++s) b[60 + s] = L[(v * 12 + s) * N + c];
+
+    for (int r = 0; r < NB; ++r) {
+        double s2 = 0;
+        for (int col = 0; col < NR; ++col) s2 += Rm[r][col] * b[col];
+        a[r] = s2;
+    }
+}
+
+/* Blend of variable v of cell c (eq. weno-new): the path function chi (GENO with IS^L from
+   P^4, readings D1, D3), the weights omega of the linear sub-polynomials P_m^1 (eq.
+   compact-sub-2, reading D4) and their weighted gradient bbar = sum_m omega_m b^m.
+   win: NULL, or per variable the weights (chi, omega_1..6) to use instead of GENO's. */
+static void cell_blend(const or_mesh *M, const or_params *P, const double *L, long c, int v, const double b[NR],
+                       const double a[NB], const double *win, double *chi_out, double om[6], double bbar[3]) {
+    const long N = M->n;
+    double chi = 1.0;
+    bbar[0] = bbar[1] = bbar[2] = 0.0;
+    for (int m = 0; m < 6; ++m) om[m] = 1.0 / 6.0;
+    if (!P->linear || win) {
+        double ish = 0, isl = 0, ist = 0;
+        for (int r = 0; r < NB; ++r)
+            for (int s = 0; s < NB; ++s) {
+                ish += a[r] * GH[r][s] * a[s];
+                isl += a[r] * GL[r][s] * a[s];
+                ist += a[r] * GT[r][s] * a[s];
+            }
+        double eps = P->geno_eps, rr = P->geno_r;
+        double ah = 1.0 + pow(ist / (ish + eps), rr);
+        double al = 1.0 + pow(ist / (isl + eps), rr);
+        double alpha = 2.0 * ah / (ah + al);
+        chi = tanh(P->geno_C * alpha) / tanh(P->geno_C);
+        double bm[6][3], wsum = 0, wb[6];
+        for (int m = 0; m < 6; ++m) {
+            int q = m / 2;
+            double sg = (m % 2) ? 1.0 : -1.0;
+            for (int t = 0; t < 3; ++t) {
+                if (t == q) bm[m][t] = sg * b[m];
+                else {
+                    double s = 0;
+                    for (int kk = 0; kk < 4; ++kk) s += L[(v * 12 + 4 * t + kk) * N + c];
+                    bm[m][t] = 0.25 * s;
+                }
+            }
+            double is = bm[m][0] * bm[m][0] + bm[m][1] * bm[m][1] + bm[m][2] * bm[m][2];
+            wb[m] = (1.0 / 6.0) / pow(is + eps, 5.0);
+            wsum += wb[m];
+        }
+        for (int m = 0; m < 6; ++m) om[m] = wb[m] / wsum;
+        if (win) { /* learned weights given from outside (extension of Sec. 3.3) */
+            chi = win[7 * v];
+            for (int m = 0; m < 6; ++m) om[m] = win[7 * v + 1 + m];
+        }
+        for (int m = 0; m < 6; ++m)
+            for (int t = 0; t < 3; ++t) bbar[t] += om[m] * bm[m][t];
+    }
+    *chi_out = chi;
+}
+
 /* out[g][v][0..3]: value and physical gradient at Gauss point g (=4m+k) of cell c.
    win: NULL, or per variable the blend weights (chi, omega_1..6) to use instead of GENO's;
    wout: NULL, or per variable the weights (chi, omega_1..6) the blend used. */
@@ -573,112 +745,13 @@ static void recon_cell(const or_mesh *M, const or_params *P, const double *Q, co
                        const double *L, long c, const double *J, const double *JiT, const double *win,
                        double *wout, double out[NGP][NV][4]) {
     const long N = M->n;
-    int i = c % M->nx, j = (c / M->nx) % M->ny, k = c / ((long)M->nx * M->ny);
-    long fnb[6], enb[12];
-    int fside[6][3], eside[12][3]; /* wall sides crossed by each neighbour (-1: none) */
-    double t1[12][3], t2[12][3];
-    for (int m = 0; m < 6; ++m) {
-        double o[3]; face_offset(m, o);
-        int idx[3] = {i + (int)o[0], j + (int)o[1], k + (int)o[2]};
-        fnb[m] = nb_cell(M, idx, fside[m]);
-    }
-    for (int n = 0; n < 12; ++n) {
-        double o[3]; edge_geom(n, o, t1[n], t2[n]);
-        int idx[3] = {i + (int)o[0], j + (int)o[1], k + (int)o[2]};
-        enb[n] = nb_cell(M, idx, eside[n]);
-    }
+    stencil_t S;
+    stencil_of(M, c, &S);
     for (int v = 0; v < NV; ++v) {
-        /* neighbour data, mirrored across the walls it lies behind: the ghost cell's average and
-           gradient are the mirror images of those of its mirror cell (reading D26) */
-        double nq[18], ngr[18][3];
-        for (int t = 0; t < 18; ++t) {
-            const long nb = (t < 6) ? fnb[t] : enb[t - 6];
-            const int *sd = (t < 6) ? fside[t] : eside[t - 6];
-            double sv = 1.0, sr[3] = {1.0, 1.0, 1.0};
-            int far = 0;
-            for (int q = 0; q < 3; ++q)
-                if (sd[q] >= 0) {
-                    far |= M->bc[sd[q]] == 3;
-                    double m = mirror_sign(M, sd[q], v);
-                    sv *= m;
-                    for (int r = 0; r < 3; ++r) sr[r] *= (r == q) ? -m : m;
-                }
-            nq[t] = sv * Q[v * N + nb];
-            for (int r = 0; r < 3; ++r) ngr[t][r] = sr[r] * G[(v * 3 + r) * N + nb];
-            if (far) { /* behind a far-field side: the uniform far-field state */
-                nq[t] = P->far[v];
-                ngr[t][0] = ngr[t][1] = ngr[t][2] = 0.0;
-            }
-        }
         double q0 = Q[v * N + c], b[NR], a[NB];
-        for (int m = 0; m < 6; ++m) b[m] = nq[m] - q0;
-        for (int n = 0; n < 12; ++n) b[6 + n] = nq[6 + n] - q0;
-        /* neighbour gradients in the target's reference frame: (grad Q)' = J0^T grad Q */
-        for (int m = 0; m < 6; ++m)
-            for (int jj = 0; jj < 3; ++jj) {
-                double s = 0;
-                for (int r = 0; r < 3; ++r) s += J[3 * r + jj] * ngr[m][r];
-                b[18 + 3 * m + jj] = s;
-            }
-        for (int n = 0; n < 12; ++n) {
-            double gr[3];
-            for (int jj = 0; jj < 3; ++jj) {
-                double s = 0;
-                for (int r = 0; r < 3; ++r) s += J[3 * r + jj] * ngr[6 + n][r];
-                gr[jj] = s;
-            }
-            b[36 + 2 * n] = t1[n][0] * gr[0] + t1[n][1] * gr[1] + t1[n][2] * gr[2];
-            b[36 + 2 * n + 1] = t2[n][0] * gr[0] + t2[n][1] * gr[1] + t2[n][2] * gr[2];
-        }
-        for (int s = 0; s < 12; ++s) b[60 + s] = L[(v * 12 + s) * N + c];
-
-        for (int r = 0; r < NB; ++r) {
-            double s = 0;
-            for (int col = 0; col < NR; ++col) s += Rm[r][col] * b[col];
-            a[r] = s;
-        }
-
-        /* path function chi (GENO with IS^L from P^4), readings D1, D3 */
-        double chi = 1.0, bbar[3] = {0, 0, 0}, om[6];
-        for (int m = 0; m < 6; ++m) om[m] = 1.0 / 6.0;
-        if (!P->linear || win) {
-            double ish = 0, isl = 0, ist = 0;
-            for (int r = 0; r < NB; ++r)
-                for (int s = 0; s < NB; ++s) {
-                    ish += a[r] * GH[r][s] * a[s];
-                    isl += a[r] * GL[r][s] * a[s];
-                    ist += a[r] * GT[r][s] * a[s];
-                }
-            double eps = P->geno_eps, rr = P->geno_r;
-            double ah = 1.0 + pow(ist / (ish + eps), rr);
-            double al = 1.0 + pow(ist / (isl + eps), rr);
-            double alpha = 2.0 * ah / (ah + al);
-            chi = tanh(P->geno_C * alpha) / tanh(P->geno_C);
-            /* linear sub-polynomials P_m^1, eq. (compact-sub-2), and weights, reading D4 */
-            double bm[6][3], wsum = 0, wb[6];
-            for (int m = 0; m < 6; ++m) {
-                int q = m / 2;
-                double sg = (m % 2) ? 1.0 : -1.0;
-                for (int t = 0; t < 3; ++t) {
-                    if (t == q) bm[m][t] = sg * b[m];
-                    else {
-                        double s = 0;
-                        for (int kk = 0; kk < 4; ++kk) s += L[(v * 12 + 4 * t + kk) * N + c];
-                        bm[m][t] = 0.25 * s;
-                    }
-                }
-                double is = bm[m][0] * bm[m][0] + bm[m][1] * bm[m][1] + bm[m][2] * bm[m][2];
-                wb[m] = (1.0 / 6.0) / pow(is + eps, 5.0);
-                wsum += wb[m];
-            }
-            for (int m = 0; m < 6; ++m) om[m] = wb[m] / wsum;
-            if (win) { /* learned weights given from outside (extension of Sec. 3.3) */
-                chi = win[7 * v];
-                for (int m = 0; m < 6; ++m) om[m] = win[7 * v + 1 + m];
-            }
-            for (int m = 0; m < 6; ++m)
-                for (int t = 0; t < 3; ++t) bbar[t] += om[m] * bm[m][t];
-        }
+        cell_coeffs(M, P, Q, G, L, c, J, &S, v, b, a);
+        double chi, om[6], bbar[3];
+        cell_blend(M, P, L, c, v, b, a, win, &chi, om, bbar);
         if (wout) {
             wout[7 * v] = chi;
             for (int m = 0; m < 6; ++m) wout[7 * v + 1 + m] = om[m];
@@ -1076,8 +1149,10 @@ static void cell_update(int stage, double dt, double vol, const face_rec *const 
     }
 }
 
+/* win: NULL (GENO weights), or blend weights given per cell and variable, [N][5][7]
+   (chi, omega_1..6), for the learned-weight extension of Sec. 3.3. */
 static int run_stage(const or_mesh *M, const or_params *P, int stage, double dt, double *Q, double *G,
-                     double *L, double *stash) {
+                     double *L, double *stash, const double *win) {
     const long N = M->n;
     double (*rec)[NGP][NV][4] = malloc(sizeof(double) * NGP * NV * 4 * N);
     face_rec *fr = malloc(sizeof(face_rec) * 3 * N);
@@ -1087,7 +1162,8 @@ static int run_stage(const or_mesh *M, const or_params *P, int stage, double dt,
     if (walls) frb = malloc(sizeof(face_rec) * 3 * N);
     int bad = 0;
 #pragma omp parallel for schedule(dynamic, 16)
-    for (long c = 0; c < N; ++c) recon_cell(M, P, Q, G, L, c, &M->J0[9 * c], &M->JinvT[9 * c], NULL, NULL, rec[c]);
+    for (long c = 0; c < N; ++c)
+        recon_cell(M, P, Q, G, L, c, &M->J0[9 * c], &M->JinvT[9 * c], win ? win + 35 * c : NULL, NULL, rec[c]);
 #pragma omp parallel for schedule(dynamic, 16) reduction(| : bad)
     for (long f = 0; f < 3 * N; ++f) {
         long c = f / 3;
@@ -1104,6 +1180,12 @@ static int run_stage(const or_mesh *M, const or_params *P, int stage, double dt,
             for (int v = 0; v < 5; ++v) {
                 ql[v] = rec[c][gpl][v][0]; qr[v] = rec[cr][gpr][v][0];
                 for (int r = 0; r < 3; ++r) { gl[v][r] = rec[c][gpl][v][1 + r]; gr[v][r] = rec[cr][gpr][v][1 + r]; }
+            }
+            if (P->positivity) {
+                double qbl[5], qbr[5];
+                for (int v = 0; v < 5; ++v) { qbl[v] = Q[v * N + c]; qbr[v] = Q[v * N + cr]; }
+                positivity_state(P, qbl, ql, gl);
+                positivity_state(P, qbr, qr, gr);
             }
             /* plus-side wall: the right state is the mirror image of the left one */
             if (at_wall) ghost_state(M, P, 2 * q + 1, ql, (const double (*)[3])gl, qr, gr);
@@ -1208,6 +1290,14 @@ int oracle_recon(const int dims[3], const double *nodes, const or_params *P, con
 
 /* Gas-kinetic flux at npts independent points.
    in: ql[npts][5], gl[npts][5][3], qr, gr, nrm[npts][3]; out: F, Ft [npts][5], sides [npts][4][5]. */
+/* The interface-state limiter of reading D28 on independent states: qbar [n][5] cell averages,
+   q [n][5] values and g [n][5][3] gradients, changed in place. */
+int oracle_positivity(const or_params *P, long n, const double *qbar, double *q, double *g) {
+    if (!P || n < 0 || !qbar || !q || !g) return OR_EINVAL;
+    for (long i = 0; i < n; ++i) positivity_state(P, qbar + 5 * i, q + 5 * i, (double (*)[3])(g + 15 * i));
+    return OR_OK;
+}
+
 int oracle_flux(const or_params *P, long npts, const double *ql, const double *gl, const double *qr,
                 const double *gr, const double *nrm, double dt, double *F, double *Ft, double *sides) {
     int bad = 0;
@@ -1247,7 +1337,21 @@ int oracle_stage(const int dims[3], const double *nodes, const or_params *P, int
     or_mesh M;
     int st = mesh_build(&M, dims, nodes, P);
     if (st) { if (M.n > 0) mesh_free(&M); return st; }
-    st = run_stage(&M, P, stage, dt, Q, G, L, stash);
+    st = run_stage(&M, P, stage, dt, Q, G, L, stash, NULL);
+    mesh_free(&M);
+    return st;
+}
+
+/* One stage in place with the blend weights given per cell and variable, win [N][5][7]
+   (chi, omega_1..6): the learned-weight extension, whose weights the caller computes. */
+int oracle_stage_weights(const int dims[3], const double *nodes, const or_params *P, int stage, double dt,
+                         double *Q, double *G, double *L, double *stash, const double *win) {
+    if ((stage != 1 && stage != 2) || !(dt > 0) || !Q || !G || !L || !stash || !win) return OR_EINVAL;
+    init_consts();
+    or_mesh M;
+    int st = mesh_build(&M, dims, nodes, P);
+    if (st) { if (M.n > 0) mesh_free(&M); return st; }
+    st = run_stage(&M, P, stage, dt, Q, G, L, stash, win);
     mesh_free(&M);
     return st;
 }
@@ -1277,8 +1381,8 @@ int oracle_run(const int dims[3], const double *nodes, const or_params *P, doubl
             if (bad) { st = OR_ENONPHYS; break; }
             dt = best;
         }
-        st = run_stage(&M, P, 1, dt, Q, G, L, stash);
-        if (st == OR_OK) st = run_stage(&M, P, 2, dt, Q, G, L, stash);
+        st = run_stage(&M, P, 1, dt, Q, G, L, stash, NULL);
+        if (st == OR_OK) st = run_stage(&M, P, 2, dt, Q, G, L, stash, NULL);
         t += dt;
     }
     free(stash);
@@ -1317,6 +1421,8 @@ int oracle_stage1_cells(const int dims[3], const double *nodes, const or_params 
     }
     for (int q = 0; q < 3; ++q)
         if ((M.bc[2 * q] == 0) != (M.bc[2 * q + 1] == 0)) return OR_EINVAL;
+    for (int s2 = 0; s2 < 6; ++s2)
+        if (P->positivity && M.bc[s2]) return OR_EINVAL;
     M.nx = dims[0]; M.ny = dims[1]; M.nz = dims[2];
     if (M.nx < 1 || M.ny < 1 || M.nz < 1 || !nodes) return OR_EINVAL;
     M.n = (long)M.nx * M.ny * M.nz;
@@ -1381,6 +1487,13 @@ int oracle_stage1_cells(const int dims[3], const double *nodes, const or_params 
                     for (int v = 0; v < 5; ++v) {
                         ql[v] = lrec[gpl][v][0]; qr[v] = rrec[gpr][v][0];
                         for (int r = 0; r < 3; ++r) { gl[v][r] = lrec[gpl][v][1 + r]; gr[v][r] = rrec[gpr][v][1 + r]; }
+                    }
+                    if (P->positivity) {
+                        const long cl = (m % 2) ? c : who[1 + m], cr = (m % 2) ? who[1 + m] : c;
+                        double qbl[5], qbr[5];
+                        for (int v = 0; v < 5; ++v) { qbl[v] = Q[v * N + cl]; qbr[v] = Q[v * N + cr]; }
+                        positivity_state(P, qbl, ql, gl);
+                        positivity_state(P, qbr, qr, gr);
                     }
                 }
                 if (gks_flux(P, ql, gl, qr, gr, &fn[m][3 * g], dt, fr[m].F[g], fr[m].Ft[g], fr[m].side[g]))
@@ -1629,6 +1742,90 @@ int oracle_diagnostics(const int dims[3], const double *nodes, const or_params *
         en += Q[4 * N + c] * vol;
         if (rho < rmin) rmin = rho;
         if (p < pmin) pmin = p;
+    }
+    mesh_free(&M);
+    out[0] = ke / mass;
+    out[1] = ens / mass;
+    out[2] = mass / V;
+    out[3] = en / V;
+    out[4] = rmin;
+    out[5] = pmin;
+    return OR_OK;
+}
+
+/* The same diagnostics from the compact reconstruction (reading D24, high-order form): the
+   volume integrals of E_k and eps_S are taken by 3^3-point Gauss quadrature over each cell's
+   trilinear map, with the conserved variables and their gradients at the quadrature points
+   from the cell's reconstruction, blended as at the face Gauss points (eq. weno-new):
+   Q(x) = chi P^4(x) + (1 - chi) (Q_0 + bbar . xi), reference gradients likewise, physical
+   gradients by J0^-T (reading D13).  Periodic blocks and the outputs of oracle_diagnostics,
+   out[6]: E_k, eps_S, mean density, mean total energy, minima of rho and p over the quadrature
+   points. */
+int oracle_diagnostics_hq(const int dims[3], const double *nodes, const or_params *P, const double *Q,
+                          const double *G, const double *L, double *out) {
+    if (!Q || !G || !L || !out) return OR_EINVAL;
+    init_consts();
+    or_mesh M;
+    int st = mesh_build(&M, dims, nodes, P);
+    if (st) { if (M.n > 0) mesh_free(&M); return st; }
+    for (int s2 = 0; s2 < 6; ++s2)
+        if (M.bc[s2]) { mesh_free(&M); return OR_EINVAL; }
+    const long N = M.n;
+    const double gx[3] = {-0.5 * sqrt(0.6), 0.0, 0.5 * sqrt(0.6)}, gw[3] = {5.0 / 18.0, 8.0 / 18.0, 5.0 / 18.0};
+    double V = 0.0, mass = 0.0, ke = 0.0, ens = 0.0, en = 0.0, rmin = INFINITY, pmin = INFINITY;
+#pragma omp parallel for schedule(static) reduction(+ : V, mass, ke, ens, en) reduction(min : rmin, pmin)
+    for (long c = 0; c < N; ++c) {
+        const int i = c % M.nx, j = (c / M.nx) % M.ny, k = c / ((long)M.nx * M.ny);
+        const double *J = &M.J0[9 * c], *JiT = &M.JinvT[9 * c];
+        stencil_t S;
+        stencil_of(&M, c, &S);
+        double a[NV][NB], chi[NV], bbar[NV][3], q0[NV];
+        for (int v = 0; v < NV; ++v) {
+            double b[NR], om[6];
+            q0[v] = Q[v * N + c];
+            cell_coeffs(&M, P, Q, G, L, c, J, &S, v, b, a[v]);
+            cell_blend(&M, P, L, c, v, b, a[v], NULL, &chi[v], om, bbar[v]);
+        }
+        for (int g = 0; g < 27; ++g) {
+            const double xi[3] = {gx[g % 3], gx[(g / 3) % 3], gx[g / 9]};
+            const double w = gw[g % 3] * gw[(g / 3) % 3] * gw[g / 9];
+            double X[3], Jm[3][3];
+            trilinear(&M, i, j, k, xi, X, Jm);
+            const double dV = w * fabs(det3(Jm));
+            double qv[NV], gr[NV][3];
+            for (int v = 0; v < NV; ++v) {
+                double pv = q0[v], pg[3] = {0, 0, 0};
+                for (int r = 0; r < NB; ++r) {
+                    pv += a[v][r] * val_p(r, xi);
+                    for (int jj = 0; jj < 3; ++jj) pg[jj] += a[v][r] * val_dp(r, jj, xi);
+                }
+                qv[v] = chi[v] * pv + (1.0 - chi[v]) * (q0[v] + bbar[v][0] * xi[0] + bbar[v][1] * xi[1] +
+                                                         bbar[v][2] * xi[2]);
+                double rg[3];
+                for (int jj = 0; jj < 3; ++jj) rg[jj] = chi[v] * pg[jj] + (1.0 - chi[v]) * bbar[v][jj];
+                for (int r = 0; r < 3; ++r) gr[v][r] = JiT[3 * r] * rg[0] + JiT[3 * r + 1] * rg[1] + JiT[3 * r + 2] * rg[2];
+            }
+            const double rho = qv[0];
+            double U[3], uu = 0.0;
+            for (int d = 0; d < 3; ++d) {
+                U[d] = qv[1 + d] / rho;
+                uu += U[d] * U[d];
+            }
+            const double kin = 0.5 * rho * uu;
+            const double p = (P->gamma - 1.0) * (qv[4] - kin);
+            const double mu = sutherland(P, p / rho);
+            double dU[3][3]; /* dU[d][e] = d U_d / d x_e */
+            for (int d = 0; d < 3; ++d)
+                for (int e = 0; e < 3; ++e) dU[d][e] = (gr[1 + d][e] - U[d] * gr[0][e]) / rho;
+            const double w0 = dU[2][1] - dU[1][2], w1 = dU[0][2] - dU[2][0], w2 = dU[1][0] - dU[0][1];
+            V += dV;
+            mass += rho * dV;
+            ke += kin * dV;
+            ens += mu * (w0 * w0 + w1 * w1 + w2 * w2) * dV;
+            en += qv[4] * dV;
+            if (rho < rmin) rmin = rho;
+            if (p < pmin) pmin = p;
+        }
     }
     mesh_free(&M);
     out[0] = ke / mass;

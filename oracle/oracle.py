@@ -49,6 +49,8 @@ class Params(C.Structure):
         ("prandtl_fix", C.c_int),
         ("bc", C.c_int * 6),
         ("far", C.c_double * 5),
+        ("positivity", C.c_int),
+        ("pos_eps", C.c_double),
     ]
 
 
@@ -56,7 +58,8 @@ def params(**kw) -> Params:
     """Oracle parameters; defaults are the paper's constants (Sec. 3.3, Sec. 5)."""
     d = dict(gamma=1.4, cfl=0.5, tau_eps=0.05, tau_C=5.0, mu0=0.0, T_ref=1.0, S_suth=0.0,
              Pr=1.0, geno_C=150.0, geno_eps=1e-15, geno_r=2.0, viscous=0, visc_law=0,
-             tau_zero=0, linear=0, prandtl_fix=0, bc=(0, 0, 0, 0, 0, 0), far=(1.0, 0.0, 0.0, 0.0, 2.5))
+             tau_zero=0, linear=0, prandtl_fix=0, bc=(0, 0, 0, 0, 0, 0), far=(1.0, 0.0, 0.0, 0.0, 2.5),
+             positivity=0, pos_eps=1e-3)
     d.update(kw)
     d["bc"] = (C.c_int * 6)(*d["bc"])
     d["far"] = (C.c_double * 5)(*d["far"])
@@ -93,8 +96,10 @@ def lib(variant: str = "ieee"):
         L.oracle_metrics.argtypes = [ip, dp, dp, dp, dp, dp, dp]
         L.oracle_recon.argtypes = [ip, dp, pp, dp, dp, dp, lp, C.c_long, dp]
         L.oracle_flux.argtypes = [pp, C.c_long, dp, dp, dp, dp, dp, C.c_double, dp, dp, dp]
+        L.oracle_positivity.argtypes = [pp, C.c_long, dp, dp, dp]
         L.oracle_dt.argtypes = [ip, dp, pp, dp, dp]
         L.oracle_stage.argtypes = [ip, dp, pp, C.c_int, C.c_double, dp, dp, dp, dp, C.c_int]
+        L.oracle_stage_weights.argtypes = [ip, dp, pp, C.c_int, C.c_double, dp, dp, dp, dp, dp]
         L.oracle_run.argtypes = [ip, dp, pp, dp, dp, dp, C.c_int, dp, dp, C.c_int]
         L.oracle_s2o4.argtypes = [C.c_long, C.c_double, dp, dp, dp, dp, dp, dp]
         L.oracle_stage1_cells.argtypes = [ip, dp, pp, C.c_double, dp, dp, dp, lp, C.c_long, dp, dp, dp]
@@ -107,6 +112,7 @@ def lib(variant: str = "ieee"):
         L.oracle_features.argtypes = [ip, dp, pp, dp, dp, lp, C.c_long, C.c_double, dp, ip]
         L.oracle_recon_weights.argtypes = [ip, dp, pp, dp, dp, dp, lp, C.c_long, dp, dp, dp]
         L.oracle_diagnostics.argtypes = [ip, dp, pp, dp, dp, dp]
+        L.oracle_diagnostics_hq.argtypes = [ip, dp, pp, dp, dp, dp, dp]
         L.oracle_qcriterion.argtypes = [ip, dp, dp, dp]
         _libs[variant] = L
     return _libs[variant]
@@ -172,6 +178,17 @@ def flux(prm, ql, gl, qr, gr, nrm, dt):
     return st, F, Ft, S
 
 
+def positivity(prm, qbar, q, g):
+    """The interface-state limiter (reading D28) on independent states: qbar, q [n,5],
+    g [n,5,3] -> limited (q, g) copies."""
+    qbar = _arr(qbar)
+    q, g = _arr(q).copy(), _arr(g).copy()
+    st = lib().oracle_positivity(C.byref(prm), q.shape[0], _d(qbar), _d(q), _d(g))
+    if st:
+        raise ValueError(f"oracle_positivity status {st}")
+    return q, g
+
+
 def cfl_dt(dims, nodes, prm, Q):
     nodes, Q = _arr(nodes), _arr(Q)
     out = C.c_double(0)
@@ -188,6 +205,17 @@ def stage(dims, nodes, prm, s, dt, Q, G, L, stash, nthreads=0, variant="ieee"):
         assert a.dtype == np.float64 and a.flags.c_contiguous
     return lib(variant).oracle_stage(_dims(dims), _d(nodes), C.byref(prm), int(s), float(dt), _d(Q), _d(G),
                               _d(L), _d(stash), int(nthreads))
+
+
+def stage_weights(dims, nodes, prm, s, dt, Q, G, L, stash, win, variant="ieee"):
+    """One stage in place with given blend weights win [N, 5, 7] (chi, omega_1..6)."""
+    nodes = _arr(nodes)
+    win = _arr(win)
+    for a in (Q, G, L, stash):
+        assert a.dtype == np.float64 and a.flags.c_contiguous
+    assert win.size == 35 * Q.shape[1]
+    return lib(variant).oracle_stage_weights(_dims(dims), _d(nodes), C.byref(prm), int(s), float(dt), _d(Q), _d(G),
+                                             _d(L), _d(stash), _d(win))
 
 
 def run(dims, nodes, prm, Q, G, L, nsteps, dt=0.0, nthreads=0, variant="ieee"):
@@ -299,6 +327,17 @@ def diagnostics(dims, nodes, prm, Q, G):
     st = lib().oracle_diagnostics(_dims(dims), _d(nodes), C.byref(prm), _d(Q), _d(G), _d(out))
     if st:
         raise ValueError(f"oracle_diagnostics status {st}")
+    return dict(Ek=out[0], epsS=out[1], rho_mean=out[2], rhoE_mean=out[3], rho_min=out[4], p_min=out[5])
+
+
+def diagnostics_hq(dims, nodes, prm, Q, G, L):
+    """The same diagnostics by 3^3-point Gauss quadrature of each cell, with the state and its
+    velocity gradient from the cell's compact reconstruction (periodic blocks)."""
+    nodes, Q, G, L = _arr(nodes), _arr(Q), _arr(G), _arr(L)
+    out = np.zeros(6)
+    st = lib().oracle_diagnostics_hq(_dims(dims), _d(nodes), C.byref(prm), _d(Q), _d(G), _d(L), _d(out))
+    if st:
+        raise ValueError(f"oracle_diagnostics_hq status {st}")
     return dict(Ek=out[0], epsS=out[1], rho_mean=out[2], rhoE_mean=out[3], rho_min=out[4], p_min=out[5])
 
 

@@ -26,7 +26,7 @@ class Params(C.Structure):
         ("viscous", C.c_int), ("visc_law", C.c_int), ("tau_zero", C.c_int), ("linear", C.c_int),
         ("prandtl_fix", C.c_int), ("recon_prec", C.c_int), ("flux_prec", C.c_int), ("recon_impl", C.c_int),
         ("per_block", C.c_int), ("weights", C.c_int), ("jump_thresh", C.c_double), ("bc", C.c_int * 6),
-        ("farfield", C.c_double * 5),
+        ("farfield", C.c_double * 5), ("positivity", C.c_int), ("pos_eps", C.c_double),
     ]
 
 
@@ -34,7 +34,7 @@ class Launch(C.Structure):
     """Mirror of cgks_launch."""
 
     _fields_ = [("tile_cells", C.c_int), ("ngroups", C.c_int), ("xcd", C.c_int), ("brick_y", C.c_int),
-                ("brick_z", C.c_int)]
+                ("brick_z", C.c_int), ("stage", C.c_int)]
 
 
 _lib = None
@@ -57,6 +57,7 @@ def lib():
         L.cgks_dt_noalloc.argtypes = [vp, vp, vp, vp]
         L.cgks_diagnostics.argtypes = [vp, vp, vp, vp, vp]
         L.cgks_qcriterion.argtypes = [vp, vp, vp, vp, vp]
+        L.cgks_diagnostics_hq.argtypes = [vp, vp, vp, vp, vp, vp]
         L.cgks_stage.argtypes = [vp, C.c_int, vp, vp, vp, vp, vp]
         L.cgks_step.argtypes = [vp, vp, vp, vp, vp, C.c_int, vp]
         L.cgks_check.argtypes = [vp, ip]
@@ -184,6 +185,13 @@ def cgks_diagnostics(ctx: Context, Q, G, out, stream=None):
 DIAG_NAMES = ("Ek", "epsS", "rho_mean", "rhoE_mean", "rho_min", "p_min")
 
 
+def cgks_diagnostics_hq(ctx: Context, Q, G, L, out, stream=None):
+    """E_k, eps_S, mean rho, mean rho E, min rho, min p (6 doubles into out) by 3^3 Gauss points
+    per cell on the compact reconstruction."""
+    q, g, l, _ = _state(ctx, Q, G, L)
+    _check(lib().cgks_diagnostics_hq(ctx.h, q, g, l, _ptr(out, 6, "out"), _stream(stream)), "cgks_diagnostics_hq")
+
+
 def cgks_qcriterion(ctx: Context, Q, G, out, stream=None):
     """Q-criterion of every cell into the device tensor out [N] (float64)."""
     _check(lib().cgks_qcriterion(ctx.h, _ptr(Q, 5 * ctx.ncells, "Q"), _ptr(G, 15 * ctx.ncells, "G"),
@@ -248,11 +256,12 @@ def cgks_get_launch(ctx: Context, kind: int) -> dict:
     c = Launch()
     _check(lib().cgks_get_launch(ctx.h, kind, C.byref(c)), "cgks_get_launch")
     return {"tile_cells": c.tile_cells, "ngroups": c.ngroups, "xcd": c.xcd, "brick_y": c.brick_y,
-            "brick_z": c.brick_z}
+            "brick_z": c.brick_z, "stage": c.stage}
 
 
-def cgks_set_launch(ctx: Context, kind: int, tile_cells: int, ngroups: int, xcd: int, brick_y=0, brick_z=0):
-    c = Launch(tile_cells, ngroups, xcd, brick_y, brick_z)
+def cgks_set_launch(ctx: Context, kind: int, tile_cells: int, ngroups: int, xcd: int, brick_y=0, brick_z=0,
+                    stage=0):
+    c = Launch(tile_cells, ngroups, xcd, brick_y, brick_z, stage)
     _check(lib().cgks_set_launch(ctx.h, kind, C.byref(c)), "cgks_set_launch")
 
 

@@ -66,6 +66,7 @@ int scratch_address(int dev, double **out) {
 struct cgks_ctx {
     int device = 0;
     std::vector<BlockView> blocks;
+    std::vector<double *> dnodes;  // per block: its nodes on the device (diagnostics at Gauss points)
     long Ntot = 0;
     cgks_params user{};
     DevParams P{};
@@ -180,6 +181,8 @@ static DevParams make_dev_params(const cgks_params &p) {
     for (int v = 0; v < 5; ++v) d.far[v] = p.farfield[v];
     d.inv_K3 = 1.0 / (d.K + 3.0);
     d.inv_Tref = (p.T_ref > 0.0) ? 1.0 / p.T_ref : 0.0;
+    d.positivity = p.positivity;
+    d.pos_eps = p.pos_eps;
     return d;
 }
 
@@ -196,6 +199,8 @@ static int check_params(const cgks_params *p) {
     if (p->flux_prec < 0 || p->flux_prec > 1) return fail(CGKS_EUNSUPPORTED, "flux_prec must be 0 (FP64) or 1 (FP32)");
     if (p->recon_impl < 0 || p->recon_impl > 2) return fail(CGKS_EINVAL, "recon_impl must be 0, 1 or 2");
     if (p->per_block != 0 && p->per_block != 1) return fail(CGKS_EINVAL, "per_block must be 0 or 1");
+    if (p->positivity != 0 && p->positivity != 1) return fail(CGKS_EINVAL, "positivity must be 0 or 1");
+    if (p->positivity && !(p->pos_eps > 0.0 && p->pos_eps < 1.0)) return fail(CGKS_EINVAL, "pos_eps must be in (0, 1)");
     if (p->weights != 0 && p->weights != 1) return fail(CGKS_EINVAL, "weights must be 0 (GENO) or 1 (learned)");
     if (!(p->jump_thresh >= 0.0)) return fail(CGKS_EINVAL, "jump_thresh must be >= 0");
     if (p->weights == 1 && (p->recon_impl != 0 || p->recon_prec != 0 || p->linear))
@@ -211,6 +216,8 @@ static int check_params(const cgks_params *p) {
     }
     if (walls && p->recon_impl != 0)
         return fail(CGKS_EUNSUPPORTED, "wall sides need the matrix-core reconstruction (recon_impl 0)");
+    if (walls && p->positivity)
+        return fail(CGKS_EUNSUPPORTED, "the interface-state limiter is for periodic blocks");
     for (int sd = 0; sd < 6; ++sd)
         if (p->bc[sd] == 3) {
             const double *f = p->farfield;
@@ -334,12 +341,15 @@ static hipError_t run_recon(cgks_ctx *ctx, int b, const double *Q, const double 
         ctx->jexamined += (b < 0) ? ctx->Ntot : ctx->blocks[b].N;
     }
     return launch_recon_mfma(ctx->user.recon_prec, gp32(ctx), work_list(ctx, 1, b), ctx->Ntot, Q, G, L, ctx->M,
-                             ctx->Kmf, ctx->P, ctx->gp, ctx->wl[1].cfg.ngroups, io, false, ctx->walls, s);
+                             ctx->Kmf, ctx->P, ctx->gp, ctx->wl[1].cfg.ngroups, io, false, ctx->wl[1].cfg.stage != 0,
+                             s);
 }
 
-static hipError_t run_flux(cgks_ctx *ctx, int b, const double *dt_dev, hipStream_t s, bool full = true) {
+// Q: the stage's cell averages (read only by the interface-state limiter, positivity = 1)
+static hipError_t run_flux(cgks_ctx *ctx, int b, const double *dt_dev, const double *Q, hipStream_t s,
+                           bool full = true) {
     hipError_t e = launch_flux(ctx->user.flux_prec, gp32(ctx), work_list(ctx, 2, b), ctx->Ntot, ctx->gp, ctx->M,
-                               dt_dev, ctx->P, ctx->fo, ctx->flag, full, s);
+                               dt_dev, ctx->P, ctx->fo, ctx->flag, full, Q, s);
     // wall faces: recomputed against the mirrored interior state after the periodic pass
     for (int i = 0; i < (int)ctx->blocks.size() && e == hipSuccess && ctx->walls; ++i) {
         if (b >= 0 && i != b) continue;
@@ -374,6 +384,8 @@ void cgks_default_params(cgks_params *p) {
     p->geno_eps = 1e-15;
     p->geno_r = 2.0;
     p->jump_thresh = 0.05;
+    p->positivity = 0;
+    p->pos_eps = 1e-3;
 }
 
 const char *cgks_last_error(void) { return g_err.c_str(); }
@@ -386,6 +398,7 @@ void cgks_ctx_destroy(cgks_ctx *ctx) {
     (void)hipGetDevice(&cur);
     (void)hipSetDevice(ctx->device);
     (void)hipDeviceSynchronize();
+    for (double *dn : ctx->dnodes) (void)hipFree(dn);
     (void)hipFree(ctx->metric_mem);
     (void)hipFree(ctx->K);
     (void)hipFree(ctx->Kmf);
@@ -515,6 +528,9 @@ int cgks_ctx_create(cgks_ctx **out, int nblocks, const int *dims, const double *
     std::memcpy(dk.GL, hk->GL, sizeof dk.GL);
     std::memcpy(dk.GT, hk->GT, sizeof dk.GT);
     std::memcpy(dk.xg, hk->xg, sizeof dk.xg);
+    std::memcpy(dk.V, hk->V, sizeof dk.V);
+    std::memcpy(dk.xv, hk->xv, sizeof dk.xv);
+    std::memcpy(dk.wv, hk->wv, sizeof dk.wv);
     std::vector<double> kmf(std::max(kMfmaBlocks * 64, kBfBlocks * 512));
     const bool packed = (p->recon_prec == 2) ? pack_mfma_bf16(*hk, kmf.data()) : pack_mfma(*hk, kmf.data(), p->recon_prec == 0);
     delete hk;
@@ -526,9 +542,13 @@ int cgks_ctx_create(cgks_ctx **out, int nblocks, const int *dims, const double *
         hipDeviceProp_t prop;
         if (hipGetDeviceProperties(&prop, c->device) == hipSuccess) c->ncu = prop.multiProcessorCount;
     }
-    c->wl[1].cfg = cgks_launch{1536, 0, 0, 0, 0};  // fewer workgroups stage the constants
-    c->wl[2].cfg = cgks_launch{kFluxTile, 0, 0, 0, 0};
-    c->wl[3].cfg = cgks_launch{kUpdateTile, 0, 0, 0, 0};
+    // reconstruction: bricks staged in LDS (FP64 and FP32x3), else runs of 1536 cells (fewer
+    // workgroups stage the constants)
+    c->wl[1].cfg = (p->recon_prec != 2 && p->recon_impl == 0)
+                       ? cgks_launch{kStgTile[0], 0, 0, kStgTile[1], kStgTile[2], 1}
+                       : cgks_launch{1536, 0, 0, 0, 0, 0};
+    c->wl[2].cfg = cgks_launch{kFluxTile, 0, 0, 0, 0, 0};
+    c->wl[3].cfg = cgks_launch{kUpdateTile, 0, 0, 0, 0, 0};
     int rc = CGKS_OK;
     do {
         hipError_t e = hipMemcpyAsync(c->K, &dk, sizeof dk, hipMemcpyHostToDevice, s);
@@ -545,10 +565,10 @@ int cgks_ctx_create(cgks_ctx **out, int nblocks, const int *dims, const double *
             double *dn = nullptr;
             e = hipMalloc((void **)&dn, nn * sizeof(double));
             if (e != hipSuccess) { rc = hip_fail(e, "node buffer"); break; }
+            c->dnodes.push_back(dn);  // kept: the diagnostics integrate over each cell's trilinear map
             e = hipMemcpyAsync(dn, nodes[b], nn * sizeof(double), hipMemcpyHostToDevice, s);
             if (e == hipSuccess) e = launch_metrics(bv, dn, c->M, Ntot, c->flag, s);
             if (e == hipSuccess) e = hipStreamSynchronize(s);
-            (void)hipFree(dn);
             if (e != hipSuccess) rc = hip_fail(e, "metrics");
         }
         if (rc) break;
@@ -614,6 +634,30 @@ int cgks_diagnostics(cgks_ctx *ctx, const double *Q, const double *G, double *ou
     return CGKS_OK;
 }
 
+int cgks_diagnostics_hq(cgks_ctx *ctx, const double *Q, const double *G, const double *L, double *out,
+                        void *stream) {
+    if (!ctx || !Q || !G || !L || !out) return fail(CGKS_EINVAL, "cgks_diagnostics_hq: NULL argument");
+    if (ctx->walls) return fail(CGKS_EUNSUPPORTED, "cgks_diagnostics_hq: periodic blocks only");
+    const int nb = (int)ctx->blocks.size();
+    if (nb > kMaxDtParts) return fail(CGKS_EUNSUPPORTED, "cgks_diagnostics_hq: at most 1024 blocks");
+    hipStream_t s = (hipStream_t)stream;
+    ctx->last = s;
+    // each block's cells in a fixed number of parts: deterministic sums; the coefficients go
+    // to the Gauss-point buffer (a stage rebuilds it; stage 2 reads only the stash)
+    const int per = kMaxDtParts / nb;
+    int at = 0;
+    for (int b = 0; b < nb; ++b) {
+        const BlockView &bv = ctx->blocks[b];
+        const int np = (int)std::max<long>(1, std::min<long>(per, (bv.N + 255) / 256));
+        HIP_TRY(launch_diagnostics_hq(bv, ctx->Ntot, Q, G, L, ctx->dnodes[b], ctx->M, ctx->K, ctx->P, ctx->gp,
+                                      ctx->diag_part + 7L * at, np, s),
+                "diagnostics (Gauss points)");
+        at += np;
+    }
+    HIP_TRY(launch_diagnostics_final(ctx->diag_part, at, out, s), "diagnostics final");
+    return CGKS_OK;
+}
+
 int cgks_qcriterion(cgks_ctx *ctx, const double *Q, const double *G, double *out, void *stream) {
     if (!ctx || !Q || !G || !out) return fail(CGKS_EINVAL, "cgks_qcriterion: NULL argument");
     hipStream_t s = (hipStream_t)stream;
@@ -638,7 +682,7 @@ int cgks_stage(cgks_ctx *ctx, int stage, const double *dt_dev, double *Q, double
         }
         {
             Timed t(ctx, s, stage == 1 ? 2 : 4);
-            HIP_TRY(run_flux(ctx, b, dt_dev, s, stage == 1), "flux");
+            HIP_TRY(run_flux(ctx, b, dt_dev, Q, s, stage == 1), "flux");
         }
         {
             Timed t(ctx, s, stage == 1 ? 3 : 5);
@@ -743,6 +787,13 @@ static int check_launch(const cgks_ctx *ctx, int kind, const cgks_launch &c) {
     if (c.brick_y < 0 || c.brick_z < 0 || (c.brick_y > 0) != (c.brick_z > 0) || c.brick_y > 4096 || c.brick_z > 4096)
         return fail(CGKS_EINVAL, "brick_y and brick_z must both be 0 (runs) or both in [1, 4096]");
     if (kind != 1 && c.brick_y != 0) return fail(CGKS_EINVAL, "bricks are for the reconstruction only");
+    if (c.stage != 0 && c.stage != 1) return fail(CGKS_EINVAL, "stage must be 0 or 1");
+    if (c.stage && (kind != 1 || c.tile_cells != 16 || c.brick_y < 1 ||
+                    kStgRow * (c.brick_y + 2) * (c.brick_z + 2) > kStgCells))
+        return fail(CGKS_EINVAL, "staged reconstruction: bricks of 16 x brick_y x brick_z cells with "
+                                 "(brick_y + 2)(brick_z + 2) <= 120");
+    if (c.stage && (ctx->user.recon_prec == 2 || ctx->user.recon_impl != 0))
+        return fail(CGKS_EUNSUPPORTED, "staged reconstruction: FP64 or FP32x3 matrix-core reconstruction only");
     if (kind == 2 && (c.tile_cells != kFluxTile || c.ngroups != 0))
         return fail(CGKS_EINVAL, "flux: tiles of 128 cells, one workgroup per unit (ngroups 0)");
     if (kind == 3 && c.tile_cells != kUpdateTile) return fail(CGKS_EINVAL, "update tiles are 256 cells");
@@ -842,12 +893,12 @@ int cgks_autotune(cgks_ctx *ctx, const double *Q, const double *G, const double 
                         e = timeit([&] { return launch_recon_mfma(ctx->user.recon_prec, gp32(ctx), w, ctx->Ntot, Q, G, L,
                                                                   ctx->M, ctx->Kmf, ctx->P, ctx->gp, base.ngroups,
                                                                   BlendIO{ctx->jump, ctx->mlp_packed, nullptr, nullptr},
-                                                                  false, ctx->walls, s); },
+                                                                  false, false, s); },
                                    ms);
                         ms_sum += ms;
                     }
                     if (e != hipSuccess) break;
-                    note(1, cgks_launch{cand[ci][0], base.ngroups, base.xcd, cand[ci][1], cand[ci][2]}, ms_sum);
+                    note(1, cgks_launch{cand[ci][0], base.ngroups, base.xcd, cand[ci][1], cand[ci][2], 0}, ms_sum);
                     if (ms_sum < bestms) {
                         bestms = ms_sum;
                         best_c[k] = ci;
@@ -866,6 +917,7 @@ int cgks_autotune(cgks_ctx *ctx, const double *Q, const double *G, const double 
             l.cfg.tile_cells = l.tile_cells[0];
             l.cfg.brick_y = l.by[0];
             l.cfg.brick_z = l.bz[0];
+            l.cfg.stage = 0;  // these candidates gather from memory; the staged form is timed below
             // 2) grid and XCD order over the whole list
             const int grids[4] = {ctx->ncu, 2 * ctx->ncu, 4 * ctx->ncu, 0};
             double best = 1e300;
@@ -880,7 +932,7 @@ int cgks_autotune(cgks_ctx *ctx, const double *Q, const double *G, const double 
                     e = timeit([&] { return launch_recon_mfma(ctx->user.recon_prec, gp32(ctx), w, ctx->Ntot, Q, G, L,
                                                               ctx->M, ctx->Kmf, ctx->P, ctx->gp, grids[gi],
                                                               BlendIO{ctx->jump, ctx->mlp_packed, nullptr, nullptr},
-                                                              false, ctx->walls, s); },
+                                                              false, false, s); },
                                ms);
                     note(1, l.cfg, ms);
                     if (ms < best) {
@@ -891,6 +943,33 @@ int cgks_autotune(cgks_ctx *ctx, const double *Q, const double *G, const double 
             l.cfg.ngroups = pick.ngroups;
             l.cfg.xcd = pick.xcd;
             if (e != hipSuccess) break;
+            // 2b) the bricks staged in LDS (one form for the whole list), against the pick
+            if (ctx->user.recon_prec != 2) {
+                const std::vector<int> tc = l.tile_cells, by = l.by, bz = l.bz;
+                l.tile_cells.assign(nb, kStgTile[0]);
+                l.by.assign(nb, kStgTile[1]);
+                l.bz.assign(nb, kStgTile[2]);
+                e = build_list(ctx, 1);
+                if (e != hipSuccess) break;
+                const WorkList w = work_list(ctx, 1, -1);
+                double ms = 0.0;
+                e = timeit([&] { return launch_recon_mfma(ctx->user.recon_prec, gp32(ctx), w, ctx->Ntot, Q, G, L,
+                                                          ctx->M, ctx->Kmf, ctx->P, ctx->gp, 0,
+                                                          BlendIO{ctx->jump, ctx->mlp_packed, nullptr, nullptr},
+                                                          false, true, s); },
+                           ms);
+                const cgks_launch stg{kStgTile[0], 0, 0, kStgTile[1], kStgTile[2], 1};
+                note(1, stg, ms);
+                if (ms < best) {
+                    l.cfg = stg;
+                } else {
+                    l.tile_cells = tc;
+                    l.by = by;
+                    l.bz = bz;
+                    e = build_list(ctx, 1);
+                }
+                if (e != hipSuccess) break;
+            }
         }
         // 3) flux: XCD order (its inputs are the Gauss-point values of the reconstruction run
         //    just before)
@@ -903,7 +982,7 @@ int cgks_autotune(cgks_ctx *ctx, const double *Q, const double *G, const double 
                 l.cfg.ngroups = 0;
                 l.cfg.xcd = x;
                 double ms = 0.0;
-                e = timeit([&] { return run_flux(ctx, -1, dt_dev, s); }, ms);
+                e = timeit([&] { return run_flux(ctx, -1, dt_dev, Q, s); }, ms);
                 note(2, l.cfg, ms);
                 if (ms < best) {
                     best = ms;
@@ -1088,7 +1167,7 @@ int cgks_weights(cgks_ctx *ctx, const double *Q, const double *G, const double *
     ctx->jexamined += ctx->Ntot;
     BlendIO io{ctx->jump, ctx->mlp_packed, Wt, X};
     HIP_TRY(launch_recon_mfma(0, false, work_list(ctx, 1, -1), ctx->Ntot, Q, G, L, ctx->M, ctx->Kmf, ctx->P, ctx->gp,
-                              ctx->wl[1].cfg.ngroups, io, true, false, s),
+                              ctx->wl[1].cfg.ngroups, io, true, ctx->wl[1].cfg.stage != 0, s),
             "recon export");
     if (jump) HIP_TRY(hipMemcpyAsync(jump, ctx->jump, ctx->Ntot, hipMemcpyDeviceToDevice, s), "copy jump flags");
     return CGKS_OK;

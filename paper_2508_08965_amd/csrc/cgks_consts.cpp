@@ -262,6 +262,26 @@ void build_constants(HostConsts &K) {
             }
         }
 
+    // ---- basis at the 3^3 Gauss points of the cell (volume integrals of the diagnostics) --
+    for (int gv = 0; gv < 27; ++gv) {
+        const int ix[3] = {gv % 3, (gv / 3) % 3, gv / 9};
+        double x[3];
+        K.wv[gv] = 1.0;
+        for (int j = 0; j < 3; ++j) {
+            x[j] = kG3x[ix[j]];
+            K.xv[gv][j] = x[j];
+            K.wv[gv] *= kG3w[ix[j]];
+        }
+        for (int i = 0; i < kNB; ++i) {
+            K.V[gv][0][i] = point_val(B.d[i], zero, x) - B.mean[i];
+            for (int j = 0; j < 3; ++j) {
+                int l[3] = {0, 0, 0};
+                l[j] = 1;
+                K.V[gv][1 + j][i] = point_val(B.d[i], l, x);
+            }
+        }
+    }
+
     // ---- Gram matrices of the smoothness indicators -------------------------------------
     std::memset(K.GL, 0, sizeof K.GL);
     std::memset(K.GT, 0, sizeof K.GT);

@@ -93,12 +93,16 @@ struct Metrics {
     double *dtm;  // [3 axis][4][Ntot] mean unit normal (3) and 1/h of the axis
 };
 
+constexpr int kVolGP = 27;  // 3^3 Gauss points of the volume integrals of the diagnostics
 struct DevConsts {
     double R[kNB][kNR];
     double E[kNGP][4][kNB];
     double GL[kNB][kNB];
     double GT[kNB][kNB];
     double xg[kNGP][3];
+    double V[kVolGP][4][kNB];  // basis value and reference gradient at the volume Gauss points
+    double xv[kVolGP][3];      // the volume Gauss points (centred standard cell), x fastest
+    double wv[kVolGP];         // their weights (sum 1)
 };
 
 // ------------------------------------------------------------------------------------------
@@ -254,6 +258,49 @@ __host__ __device__ inline void time_integrals(T Tw, T tau, T e, bool tau_zero, 
     C[3] = tau * ome;
     C[4] = T(2.0) * tau * tau * ome - tau * Tw * e;
     C[5] = tau * tau * ome;
+}
+
+// Interface-state limiter (an addition to the paper, for flows whose local Mach number reaches
+// ~3 and whose internal energy is then a small part of the total): a cell's reconstructed
+// state at a face Gauss point, value q and gradient g, becomes qb + theta (q - qb) and
+// theta g, theta the largest value in [0, 1] keeping density and pressure at or above eps
+// times those of the cell average qb.  The density bound is linear in theta; along the
+// segment rho p / (gamma - 1) = rho E - |m|^2 / 2 is a quadratic a t^2 + b t + c, positive
+// at t = 0, whose root in (0, 1) is 2c / (-b + sqrt(b^2 - 4ac)).  Evaluated in FP64 whatever
+// the flux precision.  States at or above the floor and cells whose average is not physical
+// are left as they are.
+template <class T>
+__host__ __device__ inline void positivity_state(const DevParams &P, const double qb[5], T q[5], T g[5][3]) {
+    const double gm1 = P.gamma - 1.0;
+    const double rb = qb[0];
+    const double mb2 = qb[1] * qb[1] + qb[2] * qb[2] + qb[3] * qb[3];
+    const double pb = gm1 * (qb[4] - 0.5 * mb2 / rb);
+    if (!(rb > 0.0) || !(pb > 0.0)) return;
+    const double er = P.pos_eps * rb, ep = P.pos_eps * pb;
+    double th = 1.0;
+    if ((double)q[0] < er) th = (rb - er) / (rb - (double)q[0]);
+    double d[5], z[5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+        d[v] = th * ((double)q[v] - qb[v]);
+        z[v] = qb[v] + d[v];
+    }
+    const double pz = gm1 * (z[4] - 0.5 * (z[1] * z[1] + z[2] * z[2] + z[3] * z[3]) / z[0]);
+    if (pz < ep) {
+        const double e1 = ep / gm1;
+        const double a = d[0] * d[4] - 0.5 * (d[1] * d[1] + d[2] * d[2] + d[3] * d[3]);
+        const double b = rb * d[4] + qb[4] * d[0] - (qb[1] * d[1] + qb[2] * d[2] + qb[3] * d[3]) - e1 * d[0];
+        const double c = rb * qb[4] - 0.5 * mb2 - e1 * rb;
+        th *= 2.0 * c / (-b + sqrt(b * b - 4.0 * a * c));
+    }
+    if (th < 1.0) {
+#pragma unroll
+        for (int v = 0; v < 5; ++v) {
+            q[v] = (T)(qb[v] + th * ((double)q[v] - qb[v]));
+#pragma unroll
+            for (int r = 0; r < 3; ++r) g[v][r] = (T)(th * (double)g[v][r]);
+        }
+    }
 }
 
 // Gas-kinetic flux of one Gauss point evaluated by a lane pair (see cgks_flux in cgks.h for
@@ -524,6 +571,13 @@ hipError_t launch_dt_final(const double *part, int n, double *dt, hipStream_t s)
 hipError_t launch_diagnostics(long Ntot, const double *Q, const double *G, const double *vol, const DevParams &P,
                               double *part, int nparts, double *out, hipStream_t s);
 hipError_t launch_qcriterion(long Ntot, const double *Q, const double *G, double *out, hipStream_t s);
+// Diagnostics from the compact reconstruction, one periodic block: coefficients into coef
+// (38 doubles per cell and variable, stride Ntot), partial sums into part[nparts][7]; the
+// parts of all blocks are then reduced by launch_diagnostics_final into out[6].
+hipError_t launch_diagnostics_hq(const BlockView &b, long Ntot, const double *Q, const double *G, const double *L,
+                                 const double *nodes, const Metrics &M, const DevConsts *K, const DevParams &P,
+                                 double *coef, double *part, int nparts, hipStream_t s);
+hipError_t launch_diagnostics_final(const double *part, int nparts, double *out, hipStream_t s);
 hipError_t launch_recon(const BlockView &b, long Ntot, const double *Q, const double *G, const double *L,
                         const Metrics &M, const DevConsts *K, const DevParams &P, double *gp, hipStream_t s);
 // Per-cell stored matrices (cgks_percell.hip): Rc (34 x 84) and Ec (96 x 34) per cell, tiled by
@@ -543,9 +597,15 @@ struct BlendIO {
     double *wexp;               // export: weights used, [Ntot][5][7] (chi, omega_1..6)
     float *xexp;                // export: learned-weight input features, [Ntot][5][18]
 };
+// Bricks of the staged reconstruction (stg): at most 16 cells in x; the brick with its one-cell
+// halo, in rows of kStgRow cells, holds at most kStgCells cells, whose average and gradient of
+// one variable (four FP64 planes, 69 KB) sit in LDS beside the 84 KB of constants.
+constexpr int kStgRow = 18, kStgCells = 2160;
+// the default staged brick: 16 x 8 x 10 cells (80 rows of 16 cells per variable pass)
+constexpr int kStgTile[3] = {16, 8, 10};
 hipError_t launch_recon_mfma(int prec, bool gp32, const WorkList &W, long Ntot, const double *Q, const double *G,
                              const double *L, const Metrics &M, const double *Kblk, const DevParams &P, void *gp,
-                             int ngroups, const BlendIO &io, bool exp, bool walls, hipStream_t s);
+                             int ngroups, const BlendIO &io, bool exp, bool stg, hipStream_t s);
 hipError_t launch_jump(const WorkList &W, long Ntot, const double *Q, const DevParams &P, unsigned char *flag,
                        unsigned long long *count, hipStream_t s);
 hipError_t launch_mlp_infer(const float *X, long n, const unsigned char *packed, double *Y, hipStream_t s);
@@ -562,8 +622,10 @@ hipError_t launch_gp_export(bool gp32, const BlockView &b, long Ntot, const void
 constexpr int kFluxTile = 128, kUpdateTile = 256;
 // full = false (second stage) skips the flux and one-sided states, which the second update
 // does not read.
+// Q: the stage's cell averages (read only with the interface-state limiter, P.positivity).
 hipError_t launch_flux(int flux_prec, bool gp32, const WorkList &W, long Ntot, const void *gp, const Metrics &M,
-                       const double *dt, const DevParams &P, void *fo, int *flag, bool full, hipStream_t s);
+                       const double *dt, const DevParams &P, void *fo, int *flag, bool full, const double *Q,
+                       hipStream_t s);
 hipError_t launch_flux_points(int flux_prec, long n, const double *ql, const double *gl, const double *qr,
                               const double *gr, const double *nrm, const double *dt, const DevParams &P, double *F,
                               double *Ft, double *S, int *flag, hipStream_t s);

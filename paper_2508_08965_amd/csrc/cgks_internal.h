@@ -46,6 +46,9 @@ struct HostConsts {
     double GL[kNB][kNB];        // first derivatives                    (IS^L)
     double GT[kNB][kNB];        // derivatives 2..4                     (IS^tau)
     double xg[kNGP][3];         // reference Gauss points (centred standard cell)
+    double V[27][4][kNB];       // basis value and reference gradient at the 3^3 volume Gauss points
+    double xv[27][3];           // those points (centred standard cell, x fastest)
+    double wv[27];              // their weights (product of 5/18, 8/18, 5/18; sum 1)
 };
 
 void build_constants(HostConsts &K);
@@ -74,6 +77,8 @@ struct DevParams {
     int weights;                 // 0 GENO weights, 1 learned weights with GENO fallback
     double far[5];               // far-field state (conserved variables) of far-field sides
     double inv_K3, inv_Tref;     // 1 / (K + 3), 1 / T_ref
+    int positivity;              // 1: interface-state limiter (an addition to the paper)
+    double pos_eps;              // its floor, a fraction of the cell average's density, pressure
 };
 
 }  // namespace cgks

@@ -332,13 +332,13 @@ __global__ void __launch_bounds__(256) k_diag_final(const double *__restrict__ p
 // ------------------------------------------------------------------------------------------
 // reconstruction + GENO blend: one thread per (cell, conserved variable)
 // ------------------------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_recon(BlockView b, long Ntot, const double *__restrict__ Q,
-                                               const double *__restrict__ G, const double *__restrict__ L,
-                                               Metrics M, const DevConsts *__restrict__ K, DevParams P,
-                                               double *__restrict__ gp) {
-    long cl = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (cl >= b.N) return;
-    const int v = blockIdx.y;
+// Coefficients of one cell and variable on the vector ALU (periodic blocks): the quartic's
+// a = R b from the stencil data (eq. compact-big-ref), the path function chi and the weighted
+// gradient bbar of the linear sub-polynomials (eq. weno-new, compact-sub-2).
+__device__ inline void valu_coeffs(const BlockView &b, long Ntot, const double *__restrict__ Q,
+                                   const double *__restrict__ G, const double *__restrict__ L, const Metrics &M,
+                                   const DevConsts *__restrict__ K, const DevParams &P, long cl, int v, double &q0_out,
+                                   double a[kNB], double &chi_out, double bbar[3]) {
     Idx3 id = unflatten(b, cl);
     const long c = b.off + cl;
     const double *Qv = Q + v * Ntot;
@@ -386,7 +386,7 @@ __global__ void __launch_bounds__(256) k_recon(BlockView b, long Ntot, const dou
     }
 
     // low-order blend: linear polynomials of the six sub-stencils and their weights
-    double bbar[3] = {0.0, 0.0, 0.0};
+    bbar[0] = bbar[1] = bbar[2] = 0.0;
     if (!P.linear) {
         double lm[3];
 #pragma unroll
@@ -410,7 +410,6 @@ __global__ void __launch_bounds__(256) k_recon(BlockView b, long Ntot, const dou
     }
 
     // a = R b
-    double a[kNB];
 #pragma unroll
     for (int r = 0; r < kNB; ++r) {
         double s = 0.0;
@@ -446,6 +445,21 @@ __global__ void __launch_bounds__(256) k_recon(BlockView b, long Ntot, const dou
         double alpha = 2.0 * ah / (ah + al);
         chi = tanh(P.geno_C * alpha) * P.inv_tanhC;
     }
+    q0_out = q0;
+    chi_out = chi;
+}
+
+__global__ void __launch_bounds__(256) k_recon(BlockView b, long Ntot, const double *__restrict__ Q,
+                                               const double *__restrict__ G, const double *__restrict__ L,
+                                               Metrics M, const DevConsts *__restrict__ K, DevParams P,
+                                               double *__restrict__ gp) {
+    long cl = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (cl >= b.N) return;
+    const int v = blockIdx.y;
+    Idx3 id = unflatten(b, cl);
+    const long c = b.off + cl;
+    double q0, a[kNB], chi, bbar[3];
+    valu_coeffs(b, Ntot, Q, G, L, M, K, P, cl, v, q0, a, chi, bbar);
 
     double JiT[3][3];
     for (int r = 0; r < 3; ++r)
@@ -520,10 +534,12 @@ __global__ void __launch_bounds__(256) k_gp_export(BlockView b, long Ntot, const
 // ------------------------------------------------------------------------------------------
 // Two lanes per Gauss point.  A unit is (tile, owned-face Gauss point qk = 4q + kk); thread t of
 // the workgroup serves cell t / 2 of the tile (the face record of its plus face), side t & 1.
-template <class TC, class TG, class TF, bool FULL>
+// POS: each side's state is first limited toward its own cell's average (positivity_state);
+// the cell of the right side is the +q neighbour of the record's cell, periodic in its block.
+template <class TC, class TG, class TF, bool FULL, bool POS = false>
 __global__ void __launch_bounds__(256, 2) k_flux(WorkList W, long Ntot, const TG *__restrict__ gp, Metrics M,
                                               const double *__restrict__ dtp, DevParams P,
-                                              TF *__restrict__ fo, int *__restrict__ flag) {
+                                              TF *__restrict__ fo, int *__restrict__ flag, const double *__restrict__ Q) {
     const long u = unit_once((long)W.ntiles * 12, W.xcd);
     if (u < 0) return;
     const Tile tile = W.tiles[u / 12];
@@ -538,6 +554,22 @@ __global__ void __launch_bounds__(256, 2) k_flux(WorkList W, long Ntot, const TG
         qv[v] = (TC)src[(4 * v) * Ntot];
 #pragma unroll
         for (int j = 0; j < 3; ++j) gv[v][j] = (TC)src[(4 * v + 1 + j) * Ntot];
+    }
+    if constexpr (POS) {
+        long own = f;
+        if (sd) {
+            const BlockView &b = W.blocks[tile.blk];
+            const long l = tile.start + i, nxy = (long)b.nx * b.ny;
+            int ci = (int)(l % b.nx), cj = (int)((l / b.nx) % b.ny), ck = (int)(l / nxy);
+            if (q == 0) ci = (ci + 1 == b.nx) ? 0 : ci + 1;
+            else if (q == 1) cj = (cj + 1 == b.ny) ? 0 : cj + 1;
+            else ck = (ck + 1 == b.nz) ? 0 : ck + 1;
+            own = b.off + ci + (long)b.nx * cj + nxy * ck;
+        }
+        double qb[5];
+#pragma unroll
+        for (int v = 0; v < 5; ++v) qb[v] = Q[v * Ntot + own];
+        positivity_state<TC>(P, qb, qv, gv);
     }
 #pragma unroll
     for (int r = 0; r < 3; ++r) n[r] = (TC)M.fn[((q * 4 + kk) * 3 + r) * Ntot + f];
@@ -795,6 +827,158 @@ hipError_t launch_dt_final(const double *part, int n, double *dt, hipStream_t s)
     return hipGetLastError();
 }
 
+// ------------------------------------------------------------------------------------------
+// flow diagnostics from the compact reconstruction (3^3 Gauss points per cell)
+// ------------------------------------------------------------------------------------------
+// Coefficients of every cell and variable of a periodic block into coef [v][kDiagCoef][Ntot]:
+// a (34), chi, bbar (3).
+constexpr int kDiagCoef = kNB + 4;
+__global__ void __launch_bounds__(256) k_diag_coeffs(BlockView b, long Ntot, const double *__restrict__ Q,
+                                                     const double *__restrict__ G, const double *__restrict__ L,
+                                                     Metrics M, const DevConsts *__restrict__ K, DevParams P,
+                                                     double *__restrict__ coef) {
+    const long cl = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (cl >= b.N) return;
+    const int v = blockIdx.y;
+    const long c = b.off + cl;
+    double q0, a[kNB], chi, bbar[3];
+    valu_coeffs(b, Ntot, Q, G, L, M, K, P, cl, v, q0, a, chi, bbar);
+    double *dst = coef + (long)v * kDiagCoef * Ntot + c;
+#pragma unroll
+    for (int r = 0; r < kNB; ++r) dst[r * Ntot] = a[r];
+    dst[kNB * Ntot] = chi;
+#pragma unroll
+    for (int t = 0; t < 3; ++t) dst[(kNB + 1 + t) * Ntot] = bbar[t];
+}
+
+// Partial sums of a periodic block's cells over the 27 Gauss points of each cell (the sums of
+// k_diag_partial), at the points' reconstructed states: values chi P^4 + (1 - chi)(Q_0 +
+// bbar . xi), reference gradients likewise, physical gradients by (J0^T)^-1, volume element
+// |det J| of the cell's trilinear map at the point.  One workgroup per part, the cells of the
+// block in a fixed order.
+__global__ void __launch_bounds__(256) k_diag_hq_partial(BlockView b, long Ntot, const double *__restrict__ Q,
+                                                         const double *__restrict__ coef,
+                                                         const double *__restrict__ nodes, Metrics M,
+                                                         const DevConsts *__restrict__ K, DevParams P,
+                                                         double *__restrict__ part) {
+    __shared__ double red[kDiagVals][256];
+    double acc[kDiagVals] = {0.0, 0.0, 0.0, 0.0, 0.0, INFINITY, INFINITY};
+    for (long cl = (long)blockIdx.x * blockDim.x + threadIdx.x; cl < b.N; cl += (long)gridDim.x * blockDim.x) {
+        const Idx3 id = unflatten(b, cl);
+        const long c = b.off + cl;
+        const double *Pn[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) Pn[t] = node_ptr(nodes, b, id.i + (t & 1), id.j + ((t >> 1) & 1), id.k + (t >> 2));
+        double JiT[3][3], q0[5], chi[5], bb[5][3];
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+            for (int q = 0; q < 3; ++q) JiT[r][q] = M.JiT[(3 * r + q) * Ntot + c];
+#pragma unroll
+        for (int v = 0; v < 5; ++v) {
+            const double *cv = coef + (long)v * kDiagCoef * Ntot + c;
+            q0[v] = Q[v * Ntot + c];
+            chi[v] = cv[kNB * Ntot];
+#pragma unroll
+            for (int t = 0; t < 3; ++t) bb[v][t] = cv[(kNB + 1 + t) * Ntot];
+        }
+#pragma unroll 1
+        for (int g = 0; g < kVolGP; ++g) {
+            const double *xi = K->xv[g];
+            // trilinear map on the centred cell [-1/2, 1/2]^3: Jacobian at xi
+            double Jm[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                const int ci = t & 1, cj = (t >> 1) & 1, ck = t >> 2;
+                const double f0 = ci ? 0.5 + xi[0] : 0.5 - xi[0], f1 = cj ? 0.5 + xi[1] : 0.5 - xi[1],
+                             f2 = ck ? 0.5 + xi[2] : 0.5 - xi[2];
+                const double d0 = ci ? 1.0 : -1.0, d1 = cj ? 1.0 : -1.0, d2 = ck ? 1.0 : -1.0;
+#pragma unroll
+                for (int r = 0; r < 3; ++r) {
+                    Jm[r][0] += Pn[t][r] * d0 * f1 * f2;
+                    Jm[r][1] += Pn[t][r] * f0 * d1 * f2;
+                    Jm[r][2] += Pn[t][r] * f0 * f1 * d2;
+                }
+            }
+            const double det = Jm[0][0] * (Jm[1][1] * Jm[2][2] - Jm[1][2] * Jm[2][1]) -
+                               Jm[0][1] * (Jm[1][0] * Jm[2][2] - Jm[1][2] * Jm[2][0]) +
+                               Jm[0][2] * (Jm[1][0] * Jm[2][1] - Jm[1][1] * Jm[2][0]);
+            const double dV = K->wv[g] * fabs(det);
+            double qv[5], gr[5][3];
+#pragma unroll
+            for (int v = 0; v < 5; ++v) {
+                const double *cv = coef + (long)v * kDiagCoef * Ntot + c;
+                double pv = 0.0, p1 = 0.0, p2 = 0.0, p3 = 0.0;
+#pragma unroll 2
+                for (int r = 0; r < kNB; ++r) {
+                    const double a = cv[r * Ntot];
+                    pv = fma(K->V[g][0][r], a, pv);
+                    p1 = fma(K->V[g][1][r], a, p1);
+                    p2 = fma(K->V[g][2][r], a, p2);
+                    p3 = fma(K->V[g][3][r], a, p3);
+                }
+                const double om = 1.0 - chi[v];
+                qv[v] = q0[v] + chi[v] * pv + om * (bb[v][0] * xi[0] + bb[v][1] * xi[1] + bb[v][2] * xi[2]);
+                const double r0 = chi[v] * p1 + om * bb[v][0], r1 = chi[v] * p2 + om * bb[v][1],
+                             r2 = chi[v] * p3 + om * bb[v][2];
+#pragma unroll
+                for (int r = 0; r < 3; ++r) gr[v][r] = JiT[r][0] * r0 + JiT[r][1] * r1 + JiT[r][2] * r2;
+            }
+            const double rho = qv[0];
+            double U[3], uu = 0.0;
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                U[d] = qv[1 + d] / rho;
+                uu += U[d] * U[d];
+            }
+            const double kin = 0.5 * rho * uu;
+            const double p = (P.gamma - 1.0) * (qv[4] - kin);
+            const double mu = viscosity_dt(P, p / rho);
+            double dU[3][3];
+#pragma unroll
+            for (int d = 0; d < 3; ++d)
+#pragma unroll
+                for (int e = 0; e < 3; ++e) dU[d][e] = (gr[1 + d][e] - U[d] * gr[0][e]) / rho;
+            const double w0 = dU[2][1] - dU[1][2], w1 = dU[0][2] - dU[2][0], w2 = dU[1][0] - dU[0][1];
+            acc[0] += dV;
+            acc[1] += rho * dV;
+            acc[2] += kin * dV;
+            acc[3] += mu * (w0 * w0 + w1 * w1 + w2 * w2) * dV;
+            acc[4] += qv[4] * dV;
+            acc[5] = fmin(acc[5], rho);
+            acc[6] = fmin(acc[6], p);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < kDiagVals; ++i) red[i][threadIdx.x] = acc[i];
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) {
+#pragma unroll
+            for (int i = 0; i < 5; ++i) red[i][threadIdx.x] += red[i][threadIdx.x + h];
+#pragma unroll
+            for (int i = 5; i < kDiagVals; ++i) red[i][threadIdx.x] = fmin(red[i][threadIdx.x], red[i][threadIdx.x + h]);
+        }
+        __syncthreads();
+    }
+    if ((int)threadIdx.x < kDiagVals) part[(long)blockIdx.x * kDiagVals + threadIdx.x] = red[threadIdx.x][0];
+}
+
+hipError_t launch_diagnostics_hq(const BlockView &b, long Ntot, const double *Q, const double *G, const double *L,
+                                 const double *nodes, const Metrics &M, const DevConsts *K, const DevParams &P,
+                                 double *coef, double *part, int nparts, hipStream_t s) {
+    hipLaunchKernelGGL(k_diag_coeffs, dim3((unsigned)((b.N + 255) / 256), 5), dim3(256), 0, s, b, Ntot, Q, G, L, M, K,
+                       P, coef);
+    hipLaunchKernelGGL(k_diag_hq_partial, dim3((unsigned)nparts), dim3(256), 0, s, b, Ntot, Q, coef, nodes, M, K, P,
+                       part);
+    return hipGetLastError();
+}
+
+hipError_t launch_diagnostics_final(const double *part, int nparts, double *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(256), 0, s, part, nparts, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_recon(const BlockView &b, long Ntot, const double *Q, const double *G, const double *L,
                         const Metrics &M, const DevConsts *K, const DevParams &P, double *gp, hipStream_t s) {
     dim3 grid((unsigned)((b.N + 255) / 256), 5);
@@ -816,18 +1000,21 @@ static dim3 work_grid(long units, int ngroups) {
 }
 
 hipError_t launch_flux(int flux_prec, bool gp32, const WorkList &W, long Ntot, const void *gp, const Metrics &M,
-                       const double *dt, const DevParams &P, void *fo, int *flag, bool full, hipStream_t s) {
+                       const double *dt, const DevParams &P, void *fo, int *flag, bool full, const double *Q,
+                       hipStream_t s) {
     if (W.ntiles <= 0) return hipSuccess;
     const long units = (long)W.ntiles * 12;
     const dim3 grid((unsigned)(W.xcd ? 8 * ((units + 7) / 8) : units));
+    const bool pos = P.positivity != 0;
+#define CGKS_FLUX_ONE(TC, TG, TF, FULL, POS)                                                               \
+    hipLaunchKernelGGL((k_flux<TC, TG, TF, FULL, POS>), grid, dim3(2 * kFluxTile), 0, s, W, Ntot,        \
+                       (const TG *)gp, M, dt, P, (TF *)fo, flag, Q)
 #define CGKS_FLUX(TC, TG, TF)                                                                              \
     do {                                                                                                   \
-        if (full)                                                                                          \
-            hipLaunchKernelGGL((k_flux<TC, TG, TF, true>), grid, dim3(2 * kFluxTile), 0, s, W, Ntot,       \
-                               (const TG *)gp, M, dt, P, (TF *)fo, flag);                                  \
-        else                                                                                               \
-            hipLaunchKernelGGL((k_flux<TC, TG, TF, false>), grid, dim3(2 * kFluxTile), 0, s, W, Ntot,      \
-                               (const TG *)gp, M, dt, P, (TF *)fo, flag);                                  \
+        if (full && !pos) CGKS_FLUX_ONE(TC, TG, TF, true, false);                                          \
+        else if (full) CGKS_FLUX_ONE(TC, TG, TF, true, true);                                              \
+        else if (!pos) CGKS_FLUX_ONE(TC, TG, TF, false, false);                                            \
+        else CGKS_FLUX_ONE(TC, TG, TF, false, true);                                                       \
     } while (0)
     if (flux_prec == 0 && !gp32)
         CGKS_FLUX(double, double, double);
@@ -836,6 +1023,7 @@ hipError_t launch_flux(int flux_prec, bool gp32, const WorkList &W, long Ntot, c
     else
         CGKS_FLUX(float, float, float);
 #undef CGKS_FLUX
+#undef CGKS_FLUX_ONE
     return hipGetLastError();
 }
 

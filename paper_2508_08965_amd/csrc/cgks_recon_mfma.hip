@@ -187,14 +187,19 @@ __device__ inline typename PR::V mac_coef(const typename PR::T *Ablk, int blk, t
 // where the pressure-jump flag of the cell is set.  EXP: also write the weights used
 // (wexp [N][5][7]: chi, omega_1..6) and the MLP input features (xexp [N][5][18]).
 
-template <class PR, class TG, int WM, bool EXP>
-__global__ void __launch_bounds__(512) k_recon_mfma(WorkList W, long Ntot, const double *__restrict__ Q,
-                                                    const double *__restrict__ G, const double *__restrict__ L,
-                                                    Metrics M, const double *__restrict__ Kblk, DevParams P,
-                                                    TG *__restrict__ gp, BlendIO io) {
+// STG: the work list holds bricks of at most 16 cells in x (kStgCells bounds the brick with its
+// one-cell halo); for each variable in turn the workgroup first copies the brick's averages and
+// gradients with the halo into LDS (walls and far-field sides applied there), then every wave
+// takes rows of 16 cells and gathers its neighbours from LDS instead of from memory.
+template <class PR, class TG, int WM, bool EXP, bool STG = false, int NT = 512>
+__global__ void __launch_bounds__(NT) k_recon_mfma(WorkList W, long Ntot, const double *__restrict__ Q,
+                                                   const double *__restrict__ G, const double *__restrict__ L,
+                                                   Metrics M, const double *__restrict__ Kblk, DevParams P,
+                                                   TG *__restrict__ gp, BlendIO io) {
     using T = typename PR::T;
     using V = typename PR::V;
     __shared__ T lds[PR::kSplit * kMfmaBlocks * 64];
+    __shared__ double halo[STG ? 4 * kStgCells : 1];  // planes: average, gradient x, y, z
     __shared__ v8bf_t mlp_w[WM ? 3 * 64 : 1];
     __shared__ float mlp_b[WM ? kMlpHidden + 8 : 1];
     for (int i = threadIdx.x; i < kMfmaBlocks * 64; i += blockDim.x) {
@@ -233,9 +238,44 @@ __global__ void __launch_bounds__(512) k_recon_mfma(WorkList W, long Ntot, const
             bz0 = (int)(t0 / b.ny);
         }
         const int nit = cpr * (tile.ty > 0 ? tile.ty * tile.tz : 1) * kNV;
-        for (int it = __builtin_amdgcn_readfirstlane(wave); it < nit; it += nwaves) {
-            const int v = it % kNV;
-            const int chunk = it / kNV;
+        // halo box of a staged brick: x stride kStgRow, rows of HY cells, HY * HZ rows
+        const int HY = tile.ty + 2, HZ = tile.tz + 2;
+        for (int vp = 0; vp < (STG ? kNV : 1); ++vp) {
+        if constexpr (STG) {
+            __syncthreads();  // the previous pass has finished reading the halo
+            const int nh = kStgRow * HY * HZ;
+            const double farv = (vp == 0)   ? P.far[0]
+                                : (vp == 1) ? P.far[1]
+                                : (vp == 2) ? P.far[2]
+                                : (vp == 3) ? P.far[3]
+                                            : P.far[4];
+            for (int h = threadIdx.x; h < nh; h += blockDim.x) {
+                const int hx = h % kStgRow, hr = h / kStgRow;
+                if (hx > tile.count + 1) continue;
+                int gi = bx0 - 1 + hx, gj = by0 - 1 + hr % HY, gk = bz0 - 1 + hr / HY;
+                int crossed = 0;
+                // outside the block: periodic image, or the mirror cell inside a wall side
+                if (gi < 0) { if (b.wall & 1) { gi = 0; crossed |= 1; } else gi += b.nx; }
+                if (gi >= b.nx) { if (b.wall & 2) { gi = b.nx - 1; crossed |= 2; } else gi -= b.nx; }
+                if (gj < 0) { if (b.wall & 4) { gj = 0; crossed |= 4; } else gj += b.ny; }
+                if (gj >= b.ny) { if (b.wall & 8) { gj = b.ny - 1; crossed |= 8; } else gj -= b.ny; }
+                if (gk < 0) { if (b.wall & 16) { gk = 0; crossed |= 16; } else gk += b.nz; }
+                if (gk >= b.nz) { if (b.wall & 32) { gk = b.nz - 1; crossed |= 32; } else gk -= b.nz; }
+                const int nb = (int)b.off + gi + b.nx * (gj + b.ny * gk);
+                double q = ld32(Q + vp * Ntot, nb), gg[3];
+    #pragma unroll
+                for (int r = 0; r < 3; ++r) gg[r] = ld32(G + (3 * vp + r) * Ntot, nb);
+                if (crossed) ghost_mirror(b.wall, crossed, vp, farv, q, gg);
+                halo[h] = q;
+    #pragma unroll
+                for (int r = 0; r < 3; ++r) halo[(1 + r) * kStgCells + h] = gg[r];
+            }
+            __syncthreads();
+        }
+        const int nit_pass = STG ? nit / kNV : nit;
+        for (int it = __builtin_amdgcn_readfirstlane(wave); it < nit_pass; it += nwaves) {
+            const int v = STG ? vp : it % kNV;
+            const int chunk = STG ? it : it / kNV;
             bool valid;
             int ci, cj, ck;
             lane_cell(tile, b, cpr, chunk, col, bx0, by0, bz0, ci, cj, ck, valid);
@@ -285,24 +325,46 @@ __global__ void __launch_bounds__(512) k_recon_mfma(WorkList W, long Ntot, const
                                 : (v == 3) ? P.far[3]
                                            : P.far[4];
             double nq[9], ng[9][3];
+            if constexpr (STG) {
+                // this lane's cell in the halo box, and the box strides of x, y, z
+                const int hb = (ci - bx0 + 1) + kStgRow * ((cj - by0 + 1) + HY * (ck - bz0 + 1));
+                const int hs[3] = {1, kStgRow, kStgRow * HY};
     #pragma unroll
-            for (int st = 0; st < 9; ++st) {
-                int nb;
-                if (st < 6) {
-                    nb = c + ((st & 1) ? gn.dp[st >> 1] : gn.dm[st >> 1]);
-                } else {
-                    const int p = st - 6, pa = (p < 2) ? 0 : 1, pb = (p == 0) ? 1 : 2;
-                    nb = c + (sa > 0 ? gn.dp[pa] : gn.dm[pa]) + (sb > 0 ? gn.dp[pb] : gn.dm[pb]);
+                for (int st = 0; st < 9; ++st) {
+                    int h;
+                    if (st < 6) {
+                        h = hb + ((st & 1) ? hs[st >> 1] : -hs[st >> 1]);
+                    } else {
+                        const int p = st - 6, pa = (p < 2) ? 0 : 1, pb = (p == 0) ? 1 : 2;
+                        h = hb + sa * hs[pa] + sb * hs[pb];
+                    }
+                    nq[st] = halo[h];
+                    ng[st][0] = halo[kStgCells + h];
+                    ng[st][1] = halo[2 * kStgCells + h];
+                    ng[st][2] = halo[3 * kStgCells + h];
                 }
-                nq[st] = ld32(Qv, nb);
-                ng[st][0] = ld32(Gv, nb);
-                ng[st][1] = ld32(Gv + Ntot, nb);
-                ng[st][2] = ld32(Gv + 2 * Ntot, nb);
-            }
+                (void)touch;
+                (void)farv;
+            } else {
     #pragma unroll
-            for (int st = 0; st < 9; ++st) {
-                const int crossed = step_crossed(touch, st, sa, sb);
-                if (crossed) ghost_mirror(b.wall, crossed, v, farv, nq[st], ng[st]);
+                for (int st = 0; st < 9; ++st) {
+                    int nb;
+                    if (st < 6) {
+                        nb = c + ((st & 1) ? gn.dp[st >> 1] : gn.dm[st >> 1]);
+                    } else {
+                        const int p = st - 6, pa = (p < 2) ? 0 : 1, pb = (p == 0) ? 1 : 2;
+                        nb = c + (sa > 0 ? gn.dp[pa] : gn.dm[pa]) + (sb > 0 ? gn.dp[pb] : gn.dm[pb]);
+                    }
+                    nq[st] = ld32(Qv, nb);
+                    ng[st][0] = ld32(Gv, nb);
+                    ng[st][1] = ld32(Gv + Ntot, nb);
+                    ng[st][2] = ld32(Gv + 2 * Ntot, nb);
+                }
+    #pragma unroll
+                for (int st = 0; st < 9; ++st) {
+                    const int crossed = step_crossed(touch, st, sa, sb);
+                    if (crossed) ghost_mirror(b.wall, crossed, v, farv, nq[st], ng[st]);
+                }
             }
     #pragma unroll
             for (int st = 0; st < 9; ++st) {
@@ -534,6 +596,7 @@ __global__ void __launch_bounds__(512) k_recon_mfma(WorkList W, long Ntot, const
                 }
             }
         }
+        }  // variable passes of a staged brick
     }
 }
 
@@ -834,18 +897,28 @@ __global__ void __launch_bounds__(512) k_recon_bf16(WorkList W, long Ntot, const
 
 hipError_t launch_recon_mfma(int prec, bool gp32, const WorkList &W, long Ntot, const double *Q, const double *G,
                              const double *L, const Metrics &M, const double *Kblk, const DevParams &P, void *gp,
-                             int ngroups, const BlendIO &io, bool exp, bool walls, hipStream_t s) {
+                             int ngroups, const BlendIO &io, bool exp, bool stg, hipStream_t s) {
     // prec: 0 FP64, 1 FP32x3, 2 BF16x3 (Kblk holds the blocks packed for that instruction).
     // A workgroup takes whole tiles; ngroups <= 0 launches one workgroup per tile.  Learned
-    // weights (P.weights = 1) and the export exist for the FP64 reconstruction only.
+    // weights (P.weights = 1) and the export exist for the FP64 reconstruction only.  stg: the
+    // tiles are bricks that fit kStgCells with their halo (checked by the caller), gathered
+    // through LDS (FP64 and FP32x3 only).  One kernel form serves periodic blocks and blocks
+    // with wall sides.
     if (W.ntiles <= 0) return hipSuccess;
     if ((P.weights == 1 || exp) && prec != 0) return hipErrorInvalidValue;
     if (exp && gp32) return hipErrorInvalidValue;
-    (void)walls;  // one kernel form serves periodic blocks and blocks with wall sides
+    if (stg && prec == 2) return hipErrorInvalidValue;
     const int grid = (ngroups <= 0 || ngroups > W.ntiles) ? W.ntiles : ngroups;
     const dim3 gr((unsigned)grid), bl(512);
-#define CGKS_RECON(PRC, TGT, WMV, EXV) \
-    hipLaunchKernelGGL((k_recon_mfma<PRC, TGT, WMV, EXV>), gr, bl, 0, s, W, Ntot, Q, G, L, M, Kblk, P, (TGT *)gp, io)
+#define CGKS_RECON(PRC, TGT, WMV, EXV)                                                                     \
+    do {                                                                                                   \
+        if (stg)                                                                                           \
+            hipLaunchKernelGGL((k_recon_mfma<PRC, TGT, WMV, EXV, true>), gr, bl, 0, s, W, Ntot, Q, G, L, M,  \
+                               Kblk, P, (TGT *)gp, io);                                                    \
+        else                                                                                               \
+            hipLaunchKernelGGL((k_recon_mfma<PRC, TGT, WMV, EXV, false>), gr, bl, 0, s, W, Ntot, Q, G, L, M, \
+                               Kblk, P, (TGT *)gp, io);                                                    \
+    } while (0)
     if (prec == 0 && !gp32) {
         if (P.weights == 1) {
             if (exp) CGKS_RECON(PrecF64, double, 1, true);

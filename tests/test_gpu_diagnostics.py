@@ -123,3 +123,62 @@ def test_qcriterion_parity_with_oracle():
     ctx.close()
     got = out.cpu().numpy()
     assert np.max(np.abs(got - ref)) <= 1e-13 * np.max(np.abs(ref)), np.max(np.abs(got - ref))
+
+
+def gpu_diag_hq(ctx, Q, G, L):
+    out = torch.zeros(6, dtype=torch.float64, device=dev())
+    K().cgks_diagnostics_hq(ctx, Q, G, L, out)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+@pytest.mark.parametrize("Ma,linear", [(0.1, 1), (1.25, 0)])
+def test_gauss_point_diagnostics_match_oracle_curvilinear(Ma, linear):
+    """cgks_diagnostics_hq (3^3 Gauss points per cell on the compact reconstruction) against the
+    oracle's, on a perturbed mesh with several tiles and ragged tails, after two steps."""
+    n = (21, 12, 10)
+    nodes = W.perturbed_nodes(n, amp=0.05)
+    Q, G, L = (t.to(dev()) for t in W.initial_state(nodes, W.taylor_green(Ma=Ma), GAM))
+    kw = dict(tgv_kw(Ma), linear=linear)
+    ctx = K().Context([n], [nodes], K().default_params(**kw))
+    dt = torch.zeros(1, dtype=torch.float64, device=dev())
+    for _ in range(2):
+        K().cgks_step(ctx, Q, G, L, dt, use_cfl=True)
+    g = gpu_diag_hq(ctx, Q, G, L)
+    o = O.diagnostics_hq(n, nodes.numpy(), O.params(**kw), Q.cpu().numpy(), G.cpu().numpy(), L.cpu().numpy())
+    ref = np.array([o[k] for k in K().DIAG_NAMES])
+    assert np.all(np.abs(g - ref) <= 1e-12 * np.abs(ref)), (g, ref)
+    assert np.array_equal(g, gpu_diag_hq(ctx, Q, G, L))  # a fixed summation tree
+    # the state is untouched and a step after the call runs as before
+    assert K().cgks_check(ctx) == (0, 0)
+    ctx.close()
+
+
+def test_gauss_point_diagnostics_multiblock_and_walls_refused():
+    dims = [(9, 8, 7), (12, 6, 5)]
+    nodes = [W.perturbed_nodes(d, amp=0.05) for d in dims]
+    states = [W.initial_state(nd, W.isotropic_turbulence(16, k0=4.0, Mt=0.5, seed=8965 + b), GAM)
+              for b, nd in enumerate(nodes)]
+    Q, G, L = (torch.cat([s[i] for s in states], dim=-1).contiguous().to(dev()) for i in range(3))
+    kw = dict(viscous=1, visc_law=0, mu0=2.0e-3, Pr=0.72, prandtl_fix=1)
+    ctx = K().Context(dims, nodes, K().default_params(**kw))
+    g = gpu_diag_hq(ctx, Q, G, L)
+    ctx.close()
+    V = mass = ke = ens = en = 0.0
+    rmin = pmin = math.inf
+    for d, nd, s in zip(dims, nodes, states):
+        o = O.diagnostics_hq(d, nd.numpy(), O.params(**kw), s[0].numpy(), s[1].numpy(), s[2].numpy())
+        v = O.metrics(d, nd.numpy())["vol"].sum()  # 3^3 Gauss points integrate |det J| exactly
+        m = o["rho_mean"] * v
+        V, mass, ke, ens, en = V + v, mass + m, ke + o["Ek"] * m, ens + o["epsS"] * m, en + o["rhoE_mean"] * v
+        rmin, pmin = min(rmin, o["rho_min"]), min(pmin, o["p_min"])
+    ref = np.array([ke / mass, ens / mass, mass / V, en / V, rmin, pmin])
+    assert np.all(np.abs(g - ref) <= 1e-12 * np.abs(ref)), (g, ref)
+
+    n = (8, 8, 8)
+    nodes = W.cartesian_nodes(n)
+    Q, G, L = (t.to(dev()) for t in W.initial_state(nodes, W.taylor_green(Ma=0.1), GAM))
+    ctx = K().Context([n], [nodes], K().default_params(**dict(tgv_kw(0.1), bc=(1,) * 6)))
+    with pytest.raises(RuntimeError, match="cgks_diagnostics_hq"):
+        gpu_diag_hq(ctx, Q, G, L)
+    ctx.close()

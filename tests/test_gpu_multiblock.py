@@ -110,6 +110,13 @@ def test_batched_equals_per_block_launches_bitwise():
     assert a[4] == b[4]
 
 
+def memory_gather(ctx):
+    """The reconstruction form that gathers neighbours from memory (runs of 1536 cells): the
+    configurations below are compared with it, bitwise (the staged form is another kernel
+    instantiation, compared in tests/test_gpu_staged.py)."""
+    K().cgks_set_launch(ctx, 1, 1536, 0, 0)
+
+
 @pytest.mark.parametrize("rtile,rgroups,rxcd,fgroups,fxcd,ugroups,by,bz", [
     (16, 0, 0, 0, 0, 0, 0, 0),
     (48, 8, 1, 0, 1, 8, 0, 0),
@@ -121,14 +128,14 @@ def test_batched_equals_per_block_launches_bitwise():
 ])
 def test_launch_configurations_bitwise(rtile, rgroups, rxcd, fgroups, fxcd, ugroups, by, bz):
     nodes, states = blocks_state()
-    ref = run_gpu(K().default_params(**hit_kw()), nodes, states, 2)
+    ref = run_gpu(K().default_params(**hit_kw()), nodes, states, 2, configure=memory_gather)
 
     def configure(ctx):
         K().cgks_set_launch(ctx, 1, rtile, rgroups, rxcd, by, bz)
         K().cgks_set_launch(ctx, 2, 128, fgroups, fxcd)
         K().cgks_set_launch(ctx, 3, 256, ugroups, 0)
         assert K().cgks_get_launch(ctx, 1) == {"tile_cells": rtile, "ngroups": rgroups, "xcd": rxcd,
-                                              "brick_y": by, "brick_z": bz}
+                                              "brick_y": by, "brick_z": bz, "stage": 0}
 
     got = run_gpu(K().default_params(**hit_kw()), nodes, states, 2, configure=configure)
     assert got[0] == (0, 0)
@@ -150,19 +157,22 @@ def test_invalid_launch_configurations_rejected():
 
 def test_autotune_keeps_results_bitwise():
     nodes, states = blocks_state()
-    ref = run_gpu(K().default_params(**hit_kw()), nodes, states, 2)
     rep = {}
 
     def configure(ctx):
         Q, G, L = (t.to(dev()) for t in concat(states))
         dt = torch.full((1,), 1e-3, dtype=torch.float64, device=dev())
         rep["r"] = K().cgks_autotune(ctx, Q, G, L, dt, reps=2)
+        rep["stage"] = K().cgks_get_launch(ctx, 1)["stage"]
         # the tuner only reads the state
         for x, y in zip((Q, G, L), concat(states)):
             assert torch.equal(x.cpu(), y)
 
     got = run_gpu(K().default_params(**hit_kw()), nodes, states, 2, configure=configure)
     assert got[0] == (0, 0)
+    # against the default of the form the tuner picked (staged bricks, or memory gather)
+    ref = run_gpu(K().default_params(**hit_kw()), nodes, states, 2,
+                  configure=None if rep["stage"] else memory_gather)
     kinds = {r["kind"] for r in rep["r"]}
     assert kinds == {"reconstruction", "flux"}
     assert all(r["ms"] > 0 and math.isfinite(r["ms"]) for r in rep["r"])
@@ -208,8 +218,9 @@ def test_reduced_precision_batched_equals_per_block_and_bricks(recon_prec, flux_
     and brick launches agree bitwise, and stay close to the FP64 path."""
     nodes, states = blocks_state()
     kw = dict(recon_prec=recon_prec, flux_prec=flux_prec, **hit_kw())
-    a = run_gpu(K().default_params(**kw), nodes, states, 2)
-    b = run_gpu(K().default_params(per_block=1, **kw), nodes, states, 2)
+    # the memory-gathering form throughout (the staged FP32x3 form: tests/test_gpu_staged.py)
+    a = run_gpu(K().default_params(**kw), nodes, states, 2, configure=memory_gather)
+    b = run_gpu(K().default_params(per_block=1, **kw), nodes, states, 2, configure=memory_gather)
     c = run_gpu(K().default_params(**kw), nodes, states, 2,
                 configure=lambda ctx: K().cgks_set_launch(ctx, 1, 32, 0, 1, 3, 5))
     ref = run_gpu(K().default_params(**hit_kw()), nodes, states, 2)

@@ -133,3 +133,49 @@ def test_qcriterion_of_the_taylor_green_field_converges():
         z, y, x = np.meshgrid(c, c, c, indexing="ij")
         errs.append(np.max(np.abs(q - exact(x, y, z).reshape(-1))))
     assert errs[1] < 0.3 * errs[0] and errs[1] < 5e-3, errs
+
+
+def tgv_diag_hq(n, Ma, curved=False):
+    dims = (n, n, n)
+    nodes = W.perturbed_nodes(dims, amp=0.05) if curved else W.cartesian_nodes(dims, hi=(2 * math.pi,) * 3)
+    Q, G, L = W.initial_state(nodes, W.taylor_green(Ma=Ma), GAM)
+    p0 = 1.0 / (GAM * Ma * Ma)
+    prm = O.params(viscous=1, visc_law=1, mu0=1.0 / 1600, T_ref=p0, S_suth=p0 * 110.4 / 288.15, Pr=0.7)
+    return O.diagnostics_hq(dims, nodes.numpy(), prm, Q.numpy(), G.numpy(), L.numpy())
+
+
+@pytest.mark.parametrize("Ma", [0.1, 1.25])
+def test_diagnostics_from_the_reconstruction_converge_at_high_order(Ma):
+    """E_k and eps_S by 3^3 Gauss points per cell on the compact reconstruction (reading D24,
+    high-order form) converge to the closed forms at fourth order or better (the midpoint rule
+    on cell averages: second), on the Cartesian and on the perturbed curvilinear mesh."""
+    mu0 = 1.0 / 1600
+    for curved in (False, True):
+        d = {n: tgv_diag_hq(n, Ma, curved) for n in (12, 24)}
+        ek = [abs(d[n]["Ek"] - 0.125) for n in (12, 24)]
+        es = [abs(d[n]["epsS"] - 0.75 * mu0) / mu0 for n in (12, 24)]
+        assert math.log2(ek[0] / ek[1]) > 4.5, ek
+        assert math.log2(es[0] / es[1]) > 3.5, es
+        assert ek[1] < 2e-6 and es[1] < 1e-3
+        # an order of magnitude below the midpoint rule on the same mesh
+        m = tgv_diag(24, Ma) if not curved else None
+        if m is not None:
+            assert ek[1] < 0.01 * abs(m["Ek"] - 0.125) and es[1] < 0.1 * abs(m["epsS"] - 0.75 * mu0) / mu0
+        # the quadrature holds the reconstruction's cell mean exactly where the map is affine (the
+        # standard cell's polynomial integrated against a constant Jacobian); on the curved
+        # cells the Jacobian varies inside the cell, an O(h^2) effect of reading D13
+        assert d[24]["rho_mean"] == pytest.approx(1.0, abs=1e-12 if not curved else 1e-5)
+
+
+def test_diagnostics_hq_uniform_flow_exact_and_walls_refused():
+    dims = (6, 5, 4)
+    nodes = W.perturbed_nodes(dims, amp=0.05)
+    rho, u, v, w, p = 1.3, 0.4, -0.2, 0.7, 2.5
+    Q, G, L = W.initial_state(nodes, W.uniform(rho, u, v, w, p), GAM)
+    prm = O.params(viscous=1, mu0=1e-3, Pr=0.72)
+    d = O.diagnostics_hq(dims, nodes.numpy(), prm, Q.numpy(), G.numpy(), L.numpy())
+    assert d["Ek"] == pytest.approx(0.5 * (u * u + v * v + w * w), rel=1e-13)
+    assert abs(d["epsS"]) < 1e-20 and d["rho_min"] == pytest.approx(rho, rel=1e-13)
+    with pytest.raises(ValueError):
+        O.diagnostics_hq(dims, W.wall_perturbed_nodes(dims).numpy(), O.params(bc=(1,) * 6), Q.numpy(), G.numpy(),
+                         L.numpy())

@@ -213,3 +213,34 @@ def test_recon_with_chi_zero_is_exact_for_linear_fields():
                 x[tb] += (2 * (kk >> 1) - 1) * g * h
                 assert abs(gp[t, 4 * m + kk, 0, 0] - (2.0 + a @ x)) < 1e-13
                 np.testing.assert_allclose(gp[t, 4 * m + kk, 0, 1:], a, atol=1e-12)
+
+
+def test_stage_with_given_weights():
+    """A stage with weights given per cell (the learned-weight path of the oracle): GENO's own
+    weights reproduce the plain stage bitwise, and chi = 1 everywhere the linear scheme's."""
+    n = (9, 8, 7)
+    nodes = W.perturbed_nodes(n, amp=0.05)
+    Q, G, L = W.initial_state(nodes, W.isotropic_turbulence(16, k0=4.0, Mt=0.6, seed=3), 1.4)
+    prm = O.params(viscous=1, mu0=2e-3, Pr=0.72, prandtl_fix=1)
+    N = Q.shape[1]
+    dt = 0.5 * O.cfl_dt(n, nodes.numpy(), prm, Q.numpy())
+    _, wg = O.recon_weights(n, nodes.numpy(), prm, Q.numpy(), G.numpy(), L.numpy(), np.arange(N))
+    assert (wg[:, :, 0] < 0.999).any()  # the blend is active somewhere
+
+    def one(stage_fn):
+        q, g, l = (np.array(a.numpy()) for a in (Q, G, L))
+        stash = np.zeros((90, N))
+        assert stage_fn(q, g, l, stash) == 0
+        return q, g, l
+
+    plain = one(lambda q, g, l, s: O.stage(n, nodes.numpy(), prm, 1, dt, q, g, l, s))
+    given = one(lambda q, g, l, s: O.stage_weights(n, nodes.numpy(), prm, 1, dt, q, g, l, s, wg))
+    for a, b in zip(plain, given):
+        np.testing.assert_array_equal(a, b)
+    ones = wg.copy()
+    ones[:, :, 0] = 1.0
+    lin = one(lambda q, g, l, s: O.stage(n, nodes.numpy(), O.params(linear=1, viscous=1, mu0=2e-3, Pr=0.72,
+                                                                     prandtl_fix=1), 1, dt, q, g, l, s))
+    chi1 = one(lambda q, g, l, s: O.stage_weights(n, nodes.numpy(), prm, 1, dt, q, g, l, s, ones))
+    for a, b in zip(lin, chi1):
+        np.testing.assert_allclose(b, a, rtol=0, atol=1e-13 * np.abs(a).max())
