@@ -29,14 +29,23 @@ PEAK = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}  # TFLOP/s, MI355X dense (F
 #         twice (left and right), the work both lanes of a pair repeat (frame, pair sums,
 #         equilibrium state and slopes, collision time, time integrals) once; one stage
 #         evaluates 12 Gauss points per cell (3 owned faces x 4 points)
-#   reconstruction: the products the method needs per cell and stage, 5 variables x 2 flops x
-#         (34 x 72 for a = R b, 96 x 34 for the Gauss-point values and gradients E a, and the two
-#         smoothness forms through their triangular factors, 34 x 35 / 2 + 31 x 32 / 2)
+#   reconstruction: the products as the method writes them, per cell and stage, 5 variables x
+#         2 flops x (34 x 72 for a = R b, 96 x 34 for the Gauss-point values and gradients E a,
+#         and the two smoothness forms through their triangular factors, 34 x 35 / 2 +
+#         31 x 32 / 2); also reported with the cell's reflection symmetry taken out (below)
 FLUX_FLOP_PER_GP = 7733        # first stage: flux, its time derivative, one-sided values and rates
 FLUX_FLOP_PER_GP_DERIV = 7498  # second stage: time derivatives only (the update reads nothing else)
 # what the lane pairs issue (the shared work twice): the hardware's view, for context only
 FLUX_ISSUED_PER_GP, FLUX_ISSUED_PER_GP_DERIV = 8240, 7950
 RECON_FLOP_PER_CELL = 2 * 5 * (34 * 72 + 96 * 34 + 34 * 35 // 2 + 31 * 32 // 2)
+# the same products with the reflection symmetry of the centred standard cell taken out (the
+# FP64 kernel's formulation): each face pair's values and gradients from one even and one odd
+# product (48 x 34 instead of 96 x 34, then 96 additions), smoothness forms block diagonal by
+# parity class (106 + 94 instead of 595 + 496 terms)
+RECON_FLOP_PER_CELL_SYMMETRIC = 2 * 5 * (34 * 72 + 48 * 34 + 106 + 94) + 5 * 96
+# what the FP64 kernel issues per cell: 86 matrix instructions (2048 flops) per 16 columns of
+# (cell, variable), and coefficients 32-33 of a = R b on the vector ALU
+RECON_MFMA_FLOP_PER_CELL = 5 * 86 * 2048 // 16 + 2 * 5 * 2 * 72
 # algorithmic HBM bytes per cell of the update (state, stash, metrics, face records) and per
 # Gauss point of the flux (344 in; 240 out in stage 1, 120 in stage 2)
 UPDATE_BYTES = {1: 4592, 2: 3112}
@@ -144,7 +153,10 @@ def kernel_table(prof, N, ms_per_step=None):
         stage = 2 if k.endswith("_s2") else 1
         if k == "reconstruction":
             w = RECON_FLOP_PER_CELL * N
+            ws = RECON_FLOP_PER_CELL_SYMMETRIC * N
             out[k] = {"avg_ms": avg, "bound": "mfma", "tflops": w / avg / 1e9, "frac": w / avg / 1e9 / PEAK["fp64"],
+                      "tflops_symmetric": ws / avg / 1e9, "frac_symmetric": ws / avg / 1e9 / PEAK["fp64"],
+                      "issued_frac": RECON_MFMA_FLOP_PER_CELL * N / avg / 1e9 / PEAK["fp64"],
                       "algorithmic_gbps": (98 + 480) * 8 * N / avg / 1e6}
         elif k.startswith("flux"):
             w = (FLUX_FLOP_PER_GP if stage == 1 else FLUX_FLOP_PER_GP_DERIV) * 12 * N

@@ -288,12 +288,21 @@ static hipError_t build_list(cgks_ctx *c, int k) {
         const long T = l.tile_cells[b];
         const int by = l.by.empty() ? 0 : l.by[b], bz = l.bz.empty() ? 0 : l.bz[b];
         if (by > 0) {
-            for (int z0 = 0; z0 < bv.nz; z0 += bz)
-                for (int y0 = 0; y0 < bv.ny; y0 += by)
+            // the fewest bricks of at most by x bz rows that cover the block, with extents in y
+            // and z that differ by at most one (no thin remainder brick whose rows would leave
+            // most waves of the workgroup idle)
+            const int ny_b = (bv.ny + by - 1) / by, nz_b = (bv.nz + bz - 1) / bz;
+            for (int kz = 0, z0 = 0; kz < nz_b; ++kz) {
+                const int ez = bv.nz / nz_b + (kz < bv.nz % nz_b ? 1 : 0);
+                for (int ky = 0, y0 = 0; ky < ny_b; ++ky) {
+                    const int ey = bv.ny / ny_b + (ky < bv.ny % ny_b ? 1 : 0);
                     for (int x0 = 0; x0 < bv.nx; x0 += (int)T)
                         t.push_back(Tile{b, (int)std::min<long>(T, bv.nx - x0),
-                                         x0 + (long)bv.nx * (y0 + (long)bv.ny * z0), std::min(by, bv.ny - y0),
-                                         std::min(bz, bv.nz - z0), 0, 0});
+                                         x0 + (long)bv.nx * (y0 + (long)bv.ny * z0), ey, ez, 0, 0});
+                    y0 += ey;
+                }
+                z0 += ez;
+            }
         } else {
             for (long st = 0; st < bv.N; st += T) t.push_back(Tile{b, (int)std::min(T, bv.N - st), st, 0, 0, 0, 0});
         }

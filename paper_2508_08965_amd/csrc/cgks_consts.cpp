@@ -356,7 +356,136 @@ int mfma_arow(int sp, int g, bool f64) {
 
 }  // namespace
 
+namespace {
+
+// FP64 layout: the coefficients ordered by parity class (odd or even in x, y, z), the
+// classes in the order of kParityClass; within a class the basis order.  The first members of
+// OEE, EOE and EEO are x, y and z (the degree-1 monomials).
+constexpr int kParityClass[8] = {1, 2, 4, 3, 5, 6, 0, 7};  // bit q set: odd in axis q
+bool parity_order(int perm[kNB]) {
+    Basis B;
+    make_basis(B);
+    int n = 0;
+    for (int c : kParityClass)
+        for (int i = 0; i < kNB; ++i) {
+            const int cls = (B.d[i][0] & 1) | ((B.d[i][1] & 1) << 1) | ((B.d[i][2] & 1) << 2);
+            if (cls == c) perm[n++] = i;
+        }
+    // the k-step lists the FP64 kernel compiles in (groups of 4 coefficients, one class per
+    // group but for the last, which holds the ninth even-even-even coefficient and the
+    // odd-odd-odd one)
+    static const int kClassOfStep[8] = {1, 2, 4, 3, 5, 6, 0, 0};
+    for (int k = 0; k < 32; ++k) {
+        const int *d = B.d[perm[k]];
+        if (((d[0] & 1) | ((d[1] & 1) << 1) | ((d[2] & 1) << 2)) != kClassOfStep[k / 4]) return false;
+    }
+    const int *d32 = B.d[perm[32]], *d33 = B.d[perm[33]];
+    return n == kNB && (d32[0] | d32[1] | d32[2]) % 2 == 0 && (d33[0] & d33[1] & d33[2] & 1) &&
+           perm[0] == 0 && perm[4] == 1 && perm[8] == 2;
+}
+
+// Cholesky factor of the Gram matrix G restricted to the index list idx (in that order), with
+// the entries between different parity classes, zero on the centred cell up to the rounding
+// of the quadrature sums, set to zero
+bool cholesky_sub(const Basis &B, const double G[kNB][kNB], const std::vector<int> &idx, std::vector<double> &Lo) {
+    const int n = (int)idx.size();
+    std::vector<double> A((size_t)n * n);
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+            const int *di = B.d[idx[i]], *dj = B.d[idx[j]];
+            const bool same = (((di[0] ^ dj[0]) | (di[1] ^ dj[1]) | (di[2] ^ dj[2])) & 1) == 0;
+            if (!same && std::fabs(G[idx[i]][idx[j]]) > 1e-13) return false;
+            A[(size_t)i * n + j] = same ? G[idx[i]][idx[j]] : 0.0;
+        }
+    Lo.assign((size_t)n * n, 0.0);
+    return cholesky(n, A.data(), Lo.data());
+}
+
+// FP64 packing in the parity order (see the kernel): R rows permuted; L_L^T and L_T^T of the
+// permuted Gram matrices (block diagonal: products of different classes integrate to zero on
+// the centred cell); per face pair q the even and odd parts of the + face's E rows, from which
+// both faces follow (the - face's rows are the + face's times (-1)^(exponent of axis q), the
+// normal derivative with the opposite sign), checked here against the - face's own rows.
+bool pack_mfma_parity(const HostConsts &K, double *blk) {
+    int perm[kNB];
+    if (!parity_order(perm)) return false;
+    Basis B;
+    make_basis(B);
+    std::vector<int> all(kNB), nonlin;
+    for (int n = 0; n < kNB; ++n) {
+        all[n] = perm[n];
+        if (n != 0 && n != 4 && n != 8) nonlin.push_back(perm[n]);
+    }
+    std::vector<double> ll, lt;
+    if (!cholesky_sub(B, K.GL, all, ll) || !cholesky_sub(B, K.GT, nonlin, lt)) return false;
+    // coefficient position (new index) of row r of L_T^T: the non-linear coefficients in order
+    int tpos[31];
+    for (int r = 0, n = 0; n < kNB; ++n)
+        if (n != 0 && n != 4 && n != 8) tpos[r++] = n;
+    for (int i = 0; i < kMfmaBlocks * 64; ++i) blk[i] = 0.0;
+    for (int l = 0; l < 64; ++l) {
+        const int row = l % 16, g = l / 16;
+        for (int t = 0; t < 3; ++t)
+            for (int s = 0; s < 18; ++s) {
+                const int i = 16 * t + row;
+                blk[(kMfmaOffA1 + t * 18 + s) * 64 + l] = (i < kNB) ? K.R[perm[i]][mfma_item(4 * s + g)] : 0.0;
+            }
+        for (int s = 0; s < 9; ++s) {
+            const int ar = 4 * s + g;  // coefficient (new index) of k-step s, lane group g
+            for (int u = 0; u < 3; ++u) {
+                const int i = 16 * u + row;  // row of L_L^T
+                blk[(kMfmaOffAL + u * 10 + s) * 64 + l] = (i < kNB && ar < kNB) ? ll[(size_t)ar * kNB + i] : 0.0;
+            }
+            for (int u = 0; u < 2; ++u) {
+                const int r = 16 * u + row;  // row of L_T^T (non-linear coefficient r)
+                double v = 0.0;
+                if (r < 31 && ar < kNB)
+                    for (int c = 0; c < 31; ++c)
+                        if (tpos[c] == ar) v = lt[(size_t)c * 31 + r];
+                blk[(kMfmaOffAT + u * 10 + s) * 64 + l] = v;
+            }
+        }
+        // E: pair q, even steps (6) then odd steps (4) of kParityEven / kParityOdd
+        static const int kEven[3][6] = {{1, 2, 5, 6, 7, 8}, {0, 2, 4, 6, 7, 8}, {0, 1, 3, 6, 7, 8}};
+        static const int kOdd[3][4] = {{0, 3, 4, 8}, {1, 3, 5, 8}, {2, 4, 5, 8}};
+        const int gpl = row % 4, comp = row / 4;
+        for (int q = 0; q < 3; ++q)
+            for (int j = 0; j < 10; ++j) {
+                const int s = (j < 6) ? kEven[q][j] : kOdd[q][j - 6];
+                const int ar = 4 * s + g;
+                double v = 0.0;
+                if (ar < kNB) {
+                    const bool odd = (B.d[perm[ar]][q] & 1) != 0;
+                    if (odd == (j >= 6)) v = K.E[4 * (2 * q + 1) + gpl][comp][perm[ar]];
+                }
+                blk[(kMfmaOffA2 + q * 10 + j) * 64 + l] = v;
+            }
+    }
+    // the smoothness-form tiles read only k-steps [kISFrom, kISTo): every other block is zero
+    static const int kISFrom[5] = {0, 4, 8, 0, 4}, kISTo[5] = {4, 9, 9, 5, 9};
+    for (int u = 0; u < 5; ++u)
+        for (int st = 0; st < 10; ++st)
+            if (st < kISFrom[u] || st >= kISTo[u]) {
+                const int base = (u < 3) ? kMfmaOffAL + u * 10 : kMfmaOffAT + (u - 3) * 10;
+                for (int l = 0; l < 64; ++l)
+                    if (blk[(base + st) * 64 + l] != 0.0) return false;
+            }
+    // the - face of each pair from the + face's rows
+    for (int q = 0; q < 3; ++q)
+        for (int gp = 0; gp < 4; ++gp)
+            for (int comp = 0; comp < 4; ++comp)
+                for (int i = 0; i < kNB; ++i) {
+                    const double sgn = ((B.d[i][q] & 1) ? -1.0 : 1.0) * ((comp == 1 + q) ? -1.0 : 1.0);
+                    const double want = K.E[4 * (2 * q) + gp][comp][i], have = sgn * K.E[4 * (2 * q + 1) + gp][comp][i];
+                    if (std::fabs(want - have) > 1e-13 * (1.0 + std::fabs(want))) return false;
+                }
+    return true;
+}
+
+}  // namespace
+
 bool pack_mfma(const HostConsts &K, double *blk, bool f64) {
+    if (f64) return pack_mfma_parity(K, blk);
     // Cholesky factors of the Gram matrices: IS^L = |L_L^T a|^2 over all 34 coefficients,
     // IS^tau = |L_T^T a_s|^2 over the 31 coefficients of degree >= 2 (indices 3..33)
     std::vector<double> gl(kNB * kNB), ll(kNB * kNB), gt(31 * 31), lt(31 * 31);

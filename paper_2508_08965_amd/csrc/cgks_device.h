@@ -603,6 +603,9 @@ struct BlendIO {
 constexpr int kStgRow = 18, kStgCells = 2160;
 // the default staged brick: 16 x 8 x 10 cells (80 rows of 16 cells per variable pass)
 constexpr int kStgTile[3] = {16, 8, 10};
+// workgroup size of the staged reconstruction: 12 waves, 3 per SIMD (one workgroup per CU,
+// bound by the LDS; the kernel then fits 168 VGPRs)
+constexpr int kStgThreads = 768;
 hipError_t launch_recon_mfma(int prec, bool gp32, const WorkList &W, long Ntot, const double *Q, const double *G,
                              const double *L, const Metrics &M, const double *Kblk, const DevParams &P, void *gp,
                              int ngroups, const BlendIO &io, bool exp, bool stg, hipStream_t s);

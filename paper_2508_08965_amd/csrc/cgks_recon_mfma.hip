@@ -50,6 +50,9 @@ struct PrecF64 {
     // coefficients 32 and 33 (the only real rows of the third GEMM1 tile) are accumulated on the
     // vector ALU instead of with 18 mostly-padding matrix instructions
     static constexpr bool kTailOnValu = true;
+    // coefficients in parity order (below): block-diagonal smoothness forms, face pairs from
+    // one even and one odd product
+    static constexpr bool kParity = true;
     using Blend = double;  // type of the blend and Gauss-point output arithmetic
     __device__ static V mma(T a, T b, V c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
 };
@@ -58,10 +61,28 @@ struct PrecF32x3 {
     using V = v4f;
     static constexpr int kCoefSteps = 10;
     static constexpr bool kTailOnValu = false;
+    static constexpr bool kParity = false;
     using Blend = float;
     static constexpr int kSplit = 2;
     __device__ static V mma(T a, T b, V c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
 };
+
+// Parity order of the FP64 coefficients.  On the centred standard cell a monomial
+// xi^a eta^b zeta^c is even or odd in each axis; the 34 coefficients are ordered by class
+// (odd axes) x | y | z | xy | xz | yz | none (9) | xyz (1), so k-step s of the coefficient
+// contractions (coefficients 4s..4s+3) holds one class: s = 0..5 the six classes of four, 6
+// and 7 eight of the nine even ones, 8 the ninth even one and the odd-odd-odd one.
+//   * Products of two basis functions' derivatives of different classes integrate to zero,
+//     so the Gram matrices of IS^L and IS^tau are block diagonal and the rows of tile u of their
+//     Cholesky-factor products need only k-steps [kISFrom[u], kISTo[u]) (tiles 0..2: L_L^T,
+//     3..4: L_T^T over the 31 coefficients of degree >= 2 in the same order).
+//   * The Gauss points of the - face of axis q mirror those of the + face, so the - face's
+//     values and tangential derivatives are Y_even - Y_odd and its normal derivative
+//     Y_odd - Y_even, where Y_even + Y_odd is the + face's and Y_even (Y_odd) takes the
+//     coefficients even (odd) in axis q: 10 instead of 18 products per face pair.
+constexpr int kISFrom[5] = {0, 4, 8, 0, 4}, kISTo[5] = {4, 9, 9, 5, 9};
+constexpr int kParEven[3][6] = {{1, 2, 5, 6, 7, 8}, {0, 2, 4, 6, 7, 8}, {0, 1, 3, 6, 7, 8}};
+constexpr int kParOdd[3][4] = {{0, 3, 4, 8}, {1, 3, 5, 8}, {2, 4, 5, 8}};
 
 namespace {
 
@@ -325,24 +346,17 @@ __global__ void __launch_bounds__(NT) k_recon_mfma(WorkList W, long Ntot, const 
                                 : (v == 3) ? P.far[3]
                                            : P.far[4];
             double nq[9], ng[9][3];
-            if constexpr (STG) {
-                // this lane's cell in the halo box, and the box strides of x, y, z
-                const int hb = (ci - bx0 + 1) + kStgRow * ((cj - by0 + 1) + HY * (ck - bz0 + 1));
+            // staged: this lane's cell in the halo box and the box offset of each gather step;
+            // the steps read LDS one at a time below (short latency: no registers held for all
+            // nine neighbours)
+            const int hb = STG ? (ci - bx0 + 1) + kStgRow * ((cj - by0 + 1) + HY * (ck - bz0 + 1)) : 0;
+            auto halo_at = [&](int st) {
                 const int hs[3] = {1, kStgRow, kStgRow * HY};
-    #pragma unroll
-                for (int st = 0; st < 9; ++st) {
-                    int h;
-                    if (st < 6) {
-                        h = hb + ((st & 1) ? hs[st >> 1] : -hs[st >> 1]);
-                    } else {
-                        const int p = st - 6, pa = (p < 2) ? 0 : 1, pb = (p == 0) ? 1 : 2;
-                        h = hb + sa * hs[pa] + sb * hs[pb];
-                    }
-                    nq[st] = halo[h];
-                    ng[st][0] = halo[kStgCells + h];
-                    ng[st][1] = halo[2 * kStgCells + h];
-                    ng[st][2] = halo[3 * kStgCells + h];
-                }
+                if (st < 6) return hb + ((st & 1) ? hs[st >> 1] : -hs[st >> 1]);
+                const int p = st - 6, pa = (p < 2) ? 0 : 1, pb = (p == 0) ? 1 : 2;
+                return hb + sa * hs[pa] + sb * hs[pb];
+            };
+            if constexpr (STG) {
                 (void)touch;
                 (void)farv;
             } else {
@@ -368,6 +382,13 @@ __global__ void __launch_bounds__(NT) k_recon_mfma(WorkList W, long Ntot, const 
             }
     #pragma unroll
             for (int st = 0; st < 9; ++st) {
+                if constexpr (STG) {
+                    const int h = halo_at(st);
+                    nq[st] = halo[h];
+                    ng[st][0] = halo[kStgCells + h];
+                    ng[st][1] = halo[2 * kStgCells + h];
+                    ng[st][2] = halo[3 * kStgCells + h];
+                }
                 const double d = nq[st] - q0;
                 double rg[3];
     #pragma unroll
@@ -423,7 +444,7 @@ __global__ void __launch_bounds__(NT) k_recon_mfma(WorkList W, long Ntot, const 
                 const RW lm[3] = {RW(0.25 * lsum[0]), RW(0.25 * lsum[1]), RW(0.25 * lsum[2])};
                 RW fdiff[6];  // face-neighbour differences: the averages gathered in steps 0..5
     #pragma unroll
-                for (int m = 0; m < 6; ++m) fdiff[m] = RW(nq[m] - q0);
+                for (int m = 0; m < 6; ++m) fdiff[m] = RW((STG ? halo[halo_at(m)] : nq[m]) - q0);
                 // learned-weight inputs: differences and line derivatives over their largest magnitude
                 double fscale = 1.0;
                 if constexpr (WM == 1 || EXP) {
@@ -457,12 +478,14 @@ __global__ void __launch_bounds__(NT) k_recon_mfma(WorkList W, long Ntot, const 
                     for (int u = 0; u < 5; ++u) {  // tiles 0..2: L_L^T rows, tiles 3..4: L_T^T rows
                         const int base = (u < 3) ? kMfmaOffAL + u * 10 : kMfmaOffAT + (u - 3) * 10;
                         // the Cholesky factors are triangular: rows 16w.. of tile w = u (mod 3) vanish on
-                        // the coefficients of k-steps below 4w, which are skipped (their products are zero)
-                        const int s0 = 4 * ((u < 3) ? u : u - 3);
+                        // the coefficients of k-steps below 4w, which are skipped (their products are
+                        // zero); in parity order they are also block diagonal
+                        const int s0 = PR::kParity ? kISFrom[u] : 4 * ((u < 3) ? u : u - 3);
+                        const int s1 = PR::kParity ? kISTo[u] : PR::kCoefSteps;
                         V z = {0, 0, 0, 0};
     #pragma unroll
                         for (int s = 0; s < PR::kCoefSteps; ++s)
-                            if (s >= s0) z = mac_coef<PR>(lds + lane, base + s, acc[s >> 2][s & 3], z);
+                            if (s >= s0 && s < s1) z = mac_coef<PR>(lds + lane, base + s, acc[s >> 2][s & 3], z);
                         const RW zz = (RW)z[0] * z[0] + (RW)z[1] * z[1] + (RW)z[2] * z[2] + (RW)z[3] * z[3];
                         if (u < 3) isl += zz;
                         else ist += zz;
@@ -566,12 +589,7 @@ __global__ void __launch_bounds__(NT) k_recon_mfma(WorkList W, long Ntot, const 
             const RW om = RW(1) - chi;
 
             // ---- Gauss-point values: face m = tile u, Gauss point k = g ----------------------------
-    #pragma unroll 2
-            for (int u = 0; u < 6; ++u) {
-                V y = {0, 0, 0, 0};
-    #pragma unroll
-                for (int s = 0; s < PR::kCoefSteps; ++s)
-                    y = mac_coef<PR>(lds + lane, kMfmaOffA2 + u * 10 + s, acc[s >> 2][s & 3], y);
+            auto emit = [&](int u, const V y) __attribute__((always_inline)) {
                 const int q = u >> 1;
                 const RW xq = (u & 1) ? RW(0.5) : RW(-0.5);
                 const RW x0 = (q == 0) ? xq : RW(ta);
@@ -593,6 +611,39 @@ __global__ void __launch_bounds__(NT) k_recon_mfma(WorkList W, long Ntot, const 
                     __builtin_nontemporal_store((TG)(JiT[0][0] * r0 + JiT[0][1] * r1 + JiT[0][2] * r2), dst + Ntot);
                     __builtin_nontemporal_store((TG)(JiT[1][0] * r0 + JiT[1][1] * r1 + JiT[1][2] * r2), dst + 2 * Ntot);
                     __builtin_nontemporal_store((TG)(JiT[2][0] * r0 + JiT[2][1] * r1 + JiT[2][2] * r2), dst + 3 * Ntot);
+                }
+            };
+            if constexpr (PR::kParity) {
+    #pragma unroll
+                for (int q = 0; q < 3; ++q) {
+                    V ye = {0, 0, 0, 0}, yo = {0, 0, 0, 0};
+    #pragma unroll
+                    for (int j = 0; j < 6; ++j) {
+                        const int st = kParEven[q][j];
+                        ye = mac_coef<PR>(lds + lane, kMfmaOffA2 + q * 10 + j, acc[st >> 2][st & 3], ye);
+                    }
+    #pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const int st = kParOdd[q][j];
+                        yo = mac_coef<PR>(lds + lane, kMfmaOffA2 + q * 10 + 6 + j, acc[st >> 2][st & 3], yo);
+                    }
+                    V yp, ym;
+    #pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        yp[r] = ye[r] + yo[r];
+                        ym[r] = (r == 1 + q) ? yo[r] - ye[r] : ye[r] - yo[r];
+                    }
+                    emit(2 * q, ym);
+                    emit(2 * q + 1, yp);
+                }
+            } else {
+    #pragma unroll
+                for (int u = 0; u < 6; ++u) {
+                    V y = {0, 0, 0, 0};
+    #pragma unroll
+                    for (int s = 0; s < PR::kCoefSteps; ++s)
+                        y = mac_coef<PR>(lds + lane, kMfmaOffA2 + u * 10 + s, acc[s >> 2][s & 3], y);
+                    emit(u, y);
                 }
             }
         }
@@ -913,8 +964,8 @@ hipError_t launch_recon_mfma(int prec, bool gp32, const WorkList &W, long Ntot, 
 #define CGKS_RECON(PRC, TGT, WMV, EXV)                                                                     \
     do {                                                                                                   \
         if (stg)                                                                                           \
-            hipLaunchKernelGGL((k_recon_mfma<PRC, TGT, WMV, EXV, true>), gr, bl, 0, s, W, Ntot, Q, G, L, M,  \
-                               Kblk, P, (TGT *)gp, io);                                                    \
+            hipLaunchKernelGGL((k_recon_mfma<PRC, TGT, WMV, EXV, true, kStgThreads>), gr, dim3(kStgThreads), \
+                               0, s, W, Ntot, Q, G, L, M, Kblk, P, (TGT *)gp, io);                         \
         else                                                                                               \
             hipLaunchKernelGGL((k_recon_mfma<PRC, TGT, WMV, EXV, false>), gr, bl, 0, s, W, Ntot, Q, G, L, M, \
                                Kblk, P, (TGT *)gp, io);                                                    \
