@@ -76,7 +76,7 @@ typedef struct {
     int prandtl_fix;         /* 1: heat-flux correction to Pr (viscous only) */
     int bc[6];               /* sides x-, x+, y-, y+, z-, z+: 0 periodic, 1 symmetry plane
                                 (slip, adiabatic), 2 no-slip adiabatic wall (reading D26),
-                                3 far field (reading D27) */
+                                3 far field (reading D27), 4 non-reflecting (reading D29) */
     double far[5];           /* far-field state (conserved variables) */
     int positivity;          /* 1: interface states kept physical (reading D28, not in the paper) */
     double pos_eps;          /* floor of that limiter, a fraction of the cell average's rho, p */
@@ -351,6 +351,7 @@ static long nb_cell(const or_mesh *M, const int idx[3], int side[3]) {
 /* Sign of conserved variable v in the mirror image across wall side s: the momentum normal to a
    symmetry plane, and every momentum component at a no-slip wall, change sign (reading D26). */
 static double mirror_sign(const or_mesh *M, int s, int v) {
+    if (M->bc[s] == 4) return 1.0; /* non-reflecting side: every variable extended evenly (D29) */
     if (v >= 1 && v <= 3 && (M->bc[s] == 2 || v - 1 == s / 2)) return -1.0;
     return 1.0;
 }
@@ -413,11 +414,57 @@ static void mirror_state(const or_mesh *M, int s, const double q[5], const doubl
     }
 }
 
+/* Boundary state of a non-reflecting side (reading D29): locally one-dimensional characteristics
+   along the outward unit normal n.  The Riemann invariants u_n +- 2c/(gamma - 1) are carried
+   out of the domain from the interior state q and into it from the far-field state; with
+   the normal velocity and sound speed they fix, the entropy p/rho^gamma and the tangential
+   velocity come from the interior at an outflow and from the far field at an inflow.  A
+   supersonic outflow takes q, a supersonic inflow the far-field state. */
+static void nonreflecting_state(const or_params *P, const double q[5], const double n[3], double qb[5]) {
+    const double gam = P->gamma, gm1 = gam - 1.0;
+    const double *f = P->far;
+    double ui[3], ue[3];
+    for (int r = 0; r < 3; ++r) { ui[r] = q[1 + r] / q[0]; ue[r] = f[1 + r] / f[0]; }
+    const double pi = gm1 * (q[4] - 0.5 * q[0] * (ui[0] * ui[0] + ui[1] * ui[1] + ui[2] * ui[2]));
+    const double pe = gm1 * (f[4] - 0.5 * f[0] * (ue[0] * ue[0] + ue[1] * ue[1] + ue[2] * ue[2]));
+    const double ci = sqrt(gam * pi / q[0]), ce = sqrt(gam * pe / f[0]);
+    const double uni = ui[0] * n[0] + ui[1] * n[1] + ui[2] * n[2];
+    const double une = ue[0] * n[0] + ue[1] * n[1] + ue[2] * n[2];
+    if (uni >= ci) { for (int v = 0; v < 5; ++v) qb[v] = q[v]; return; }
+    if (uni <= -ci) { for (int v = 0; v < 5; ++v) qb[v] = f[v]; return; }
+    const double rout = uni + 2.0 * ci / gm1, rin = une - 2.0 * ce / gm1;
+    const double unb = 0.5 * (rout + rin), cb = 0.25 * gm1 * (rout - rin);
+    const int out = unb > 0.0;
+    const double rho_s = out ? q[0] : f[0], p_s = out ? pi : pe, un_s = out ? uni : une;
+    const double *u_s = out ? ui : ue;
+    /* rho_b from the entropy of the source state: c_b^2 / c_s^2 = (rho_b / rho_s)^(gamma - 1) */
+    const double cs2 = gam * p_s / rho_s;
+    const double rhob = rho_s * pow(cb * cb / cs2, 1.0 / gm1);
+    const double pb = rhob * cb * cb / gam;
+    double ub[3], k = 0.0;
+    for (int r = 0; r < 3; ++r) { ub[r] = u_s[r] + (unb - un_s) * n[r]; k += ub[r] * ub[r]; }
+    qb[0] = rhob;
+    for (int r = 0; r < 3; ++r) qb[1 + r] = rhob * ub[r];
+    qb[4] = pb / gm1 + 0.5 * rhob * k;
+}
+
+int oracle_nonreflecting_state(const or_params *P, const double q[5], const double n[3], double qb[5]) {
+    if (!P || !q || !n || !qb) return OR_EINVAL;
+    nonreflecting_state(P, q, n, qb);
+    return OR_OK;
+}
+
 /* Ghost state across side s: the mirror image at a symmetry plane or no-slip wall; at a far-field
-   side the prescribed far-field state, uniform (zero gradient), reading D27. */
+   side the prescribed far-field state, uniform (zero gradient), reading D27; at a non-reflecting
+   side the state of nonreflecting_state with the interior gradient (reading D29).  nout: the
+   outward unit normal of the side at the point. */
 static void ghost_state(const or_mesh *M, const or_params *P, int s, const double q[5], const double g[5][3],
-                        double qm[5], double gm[5][3]) {
-    if (M->bc[s] == 3) {
+                        const double nout[3], double qm[5], double gm[5][3]) {
+    if (M->bc[s] == 4) {
+        nonreflecting_state(P, q, nout, qm);
+        for (int v = 0; v < 5; ++v)
+            for (int r = 0; r < 3; ++r) gm[v][r] = g[v][r];
+    } else if (M->bc[s] == 3) {
         for (int v = 0; v < 5; ++v) {
             qm[v] = P->far[v];
             gm[v][0] = gm[v][1] = gm[v][2] = 0.0;
@@ -514,13 +561,13 @@ static int mesh_build(or_mesh *M, const int dims[3], const double *nodes, const 
     M->bfn = M->bfw = NULL;
     for (int s = 0; s < 6; ++s) M->bc[s] = P ? P->bc[s] : 0;
     for (int q = 0; q < 3; ++q) {
-        if (M->bc[2 * q] < 0 || M->bc[2 * q] > 3 || M->bc[2 * q + 1] < 0 || M->bc[2 * q + 1] > 3) return OR_EINVAL;
+        if (M->bc[2 * q] < 0 || M->bc[2 * q] > 4 || M->bc[2 * q + 1] < 0 || M->bc[2 * q + 1] > 4) return OR_EINVAL;
         if ((M->bc[2 * q] == 0) != (M->bc[2 * q + 1] == 0)) return OR_EINVAL; /* periodic pairs */
     }
     for (int s = 0; s < 6 && P; ++s)
         if (P->positivity && M->bc[s]) return OR_EINVAL; /* the limiter is for periodic blocks */
     for (int s = 0; s < 6 && P; ++s)
-        if (M->bc[s] == 3) { /* the far-field state needs positive density and pressure */
+        if (M->bc[s] >= 3) { /* the far-field state needs positive density and pressure */
             const double *f = P->far;
             if (!(f[0] > 0.0)) return OR_EINVAL;
             if (!((P->gamma - 1.0) * (f[4] - 0.5 * (f[1] * f[1] + f[2] * f[2] + f[3] * f[3]) / f[0]) > 0.0))
@@ -643,17 +690,28 @@ static void cell_coeffs(const or_mesh *M, const or_params *P, const double *Q, c
     for (int t = 0; t < 18; ++t) {
         const long nb = (t < 6) ? S->fnb[t] : S->enb[t - 6];
         const int *sd = (t < 6) ? S->fside[t] : S->eside[t - 6];
-        double sv = 1.0, sr[3] = {1.0, 1.0, 1.0};
-        int far = 0;
+        double sv = 1.0, sr[3] = {1.0, 1.0, 1.0}, dl[3] = {0.0, 0.0, 0.0};
+        int far = 0, nr = 0;
         for (int q = 0; q < 3; ++q)
             if (sd[q] >= 0) {
                 far |= M->bc[sd[q]] == 3;
+                if (M->bc[sd[q]] == 4) { /* non-reflecting: extrapolated, not mirrored (D29) */
+                    nr = 1;
+                    dl[q] = (sd[q] & 1) ? 1.0 : -1.0;
+                    continue;
+                }
                 double m = mirror_sign(M, sd[q], v);
                 sv *= m;
                 for (int r = 0; r < 3; ++r) sr[r] *= (r == q) ? -m : m;
             }
         nq[t] = sv * Q[v * N + nb];
         for (int r = 0; r < 3; ++r) ngr[t][r] = sr[r] * G[(v * 3 + r) * N + nb];
+        if (nr) { /* behind a non-reflecting side: the linear continuation of the cell beside it,
+                     one cell on in reference coordinates along each such side's axis */
+            const double *Jn = &M->J0[9 * nb];
+            for (int q = 0; q < 3; ++q)
+                if (dl[q] != 0.0) nq[t] += dl[q] * (Jn[q] * ngr[t][0] + Jn[3 + q] * ngr[t][1] + Jn[6 + q] * ngr[t][2]);
+        }
         if (far) { /* behind a far-field side: the uniform far-field state */
             nq[t] = P->far[v];
             ngr[t][0] = ngr[t][1] = ngr[t][2] = 0.0;
@@ -1188,7 +1246,7 @@ static int run_stage(const or_mesh *M, const or_params *P, int stage, double dt,
                 positivity_state(P, qbr, qr, gr);
             }
             /* plus-side wall: the right state is the mirror image of the left one */
-            if (at_wall) ghost_state(M, P, 2 * q + 1, ql, (const double (*)[3])gl, qr, gr);
+            if (at_wall) ghost_state(M, P, 2 * q + 1, ql, (const double (*)[3])gl, &M->fn[(4 * f + g) * 3], qr, gr);
             if (gks_flux(P, ql, gl, qr, gr, &M->fn[(4 * f + g) * 3], dt, fr[f].F[g], fr[f].Ft[g], fr[f].side[g]))
                 bad = 1;
             if (at_wall && M->bc[2 * q + 1] == 2) noslip_flux(fr[f].F[g], fr[f].Ft[g]);
@@ -1198,7 +1256,9 @@ static int run_stage(const or_mesh *M, const or_params *P, int stage, double dt,
                     qr[v] = rec[cr][gpr][v][0];
                     for (int r = 0; r < 3; ++r) gr[v][r] = rec[cr][gpr][v][1 + r];
                 }
-                ghost_state(M, P, 2 * q, qr, (const double (*)[3])gr, ql, gl);
+                const double *bn = &M->bfn[((3 * cr + q) * 4 + g) * 3];
+                const double nout[3] = {-bn[0], -bn[1], -bn[2]};
+                ghost_state(M, P, 2 * q, qr, (const double (*)[3])gr, nout, ql, gl);
                 if (gks_flux(P, ql, gl, qr, gr, &M->bfn[((3 * cr + q) * 4 + g) * 3], dt, frb[f].F[g], frb[f].Ft[g],
                              frb[f].side[g]))
                     bad = 1;
@@ -1475,13 +1535,14 @@ int oracle_stage1_cells(const int dims[3], const double *nodes, const or_params 
                             ql[v] = rec[0][gpl][v][0];
                             for (int r = 0; r < 3; ++r) gl[v][r] = rec[0][gpl][v][1 + r];
                         }
-                        ghost_state(&M, P, m, ql, (const double (*)[3])gl, qr, gr);
+                        ghost_state(&M, P, m, ql, (const double (*)[3])gl, &fn[m][3 * g], qr, gr);
                     } else {
                         for (int v = 0; v < 5; ++v) {
                             qr[v] = rec[0][gpr][v][0];
                             for (int r = 0; r < 3; ++r) gr[v][r] = rec[0][gpr][v][1 + r];
                         }
-                        ghost_state(&M, P, m, qr, (const double (*)[3])gr, ql, gl);
+                        const double nout[3] = {-fn[m][3 * g], -fn[m][3 * g + 1], -fn[m][3 * g + 2]};
+                        ghost_state(&M, P, m, qr, (const double (*)[3])gr, nout, ql, gl);
                     }
                 } else {
                     for (int v = 0; v < 5; ++v) {

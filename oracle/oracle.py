@@ -97,6 +97,7 @@ def lib(variant: str = "ieee"):
         L.oracle_recon.argtypes = [ip, dp, pp, dp, dp, dp, lp, C.c_long, dp]
         L.oracle_flux.argtypes = [pp, C.c_long, dp, dp, dp, dp, dp, C.c_double, dp, dp, dp]
         L.oracle_positivity.argtypes = [pp, C.c_long, dp, dp, dp]
+        L.oracle_nonreflecting_state.argtypes = [pp, dp, dp, dp]
         L.oracle_dt.argtypes = [ip, dp, pp, dp, dp]
         L.oracle_stage.argtypes = [ip, dp, pp, C.c_int, C.c_double, dp, dp, dp, dp, C.c_int]
         L.oracle_stage_weights.argtypes = [ip, dp, pp, C.c_int, C.c_double, dp, dp, dp, dp, dp]
@@ -187,6 +188,17 @@ def positivity(prm, qbar, q, g):
     if st:
         raise ValueError(f"oracle_positivity status {st}")
     return q, g
+
+
+def nonreflecting_state(prm, q, n):
+    """Boundary state of a non-reflecting side (reading D29) for the interior state q [5] and
+    the outward unit normal n [3]."""
+    q, n = _arr(q), _arr(n)
+    out = np.zeros(5)
+    st = lib().oracle_nonreflecting_state(C.byref(prm), _d(q), _d(n), _d(out))
+    if st:
+        raise ValueError(f"oracle_nonreflecting_state status {st}")
+    return out
 
 
 def cfl_dt(dims, nodes, prm, Q):
