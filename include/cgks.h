@@ -96,7 +96,14 @@ typedef struct {
                             2 no-slip adiabatic wall, 3 far field (the ghost data are the
                             uniform state farfield, and a far-field face takes the
                             gas-kinetic flux between the interior Gauss-point state and
-                            it).  The two sides of an axis are both periodic or both not.  Sec. 5 names walls but gives no
+                            it), 4 non-reflecting (Sec. 5, jet outflow sides: the ghost data
+                            continue the cell beside the side linearly, its average plus its
+                            reference gradient times the one-cell offset, its gradient
+                            unchanged; a face on the side takes the gas-kinetic flux between
+                            the interior Gauss-point state and the boundary state of locally
+                            one-dimensional characteristics, the outgoing Riemann invariant
+                            from the interior and the incoming one from farfield; EUNSUPPORTED
+                            with learned weights).  The two sides of an axis are both periodic or both not.  Sec. 5 names walls but gives no
                             treatment for the compact stencil; here a neighbour behind a
                             wall is the mirror image of its mirror cell inside (average and
                             cell-averaged gradient reflected across the wall plane, with the
@@ -110,7 +117,7 @@ typedef struct {
                             Walls need recon_impl 0 (EUNSUPPORTED).  With learned weights
                             the jump indicator takes a neighbour behind a wall as the cell's
                             mirror image and one behind a far-field side as the far field */
-    double farfield[5];  /* far-field state (rho, rho U, rho V, rho W, rho E) of bc 3 sides;
+    double farfield[5];  /* far-field state (rho, rho U, rho V, rho W, rho E) of bc 3 and 4 sides;
                             positive density and pressure (EINVAL otherwise)             */
     int positivity;      /* 1: interface-state limiter (not in the paper; for flows whose
                             local Mach number reaches ~3, where internal energy is a small

@@ -210,7 +210,7 @@ static int check_params(const cgks_params *p) {
     bool walls = false;
     for (int q = 0; q < 3; ++q) {
         const int a = p->bc[2 * q], b = p->bc[2 * q + 1];
-        if (a < 0 || a > 3 || b < 0 || b > 3) return fail(CGKS_EINVAL, "bc entries must be 0, 1, 2 or 3");
+        if (a < 0 || a > 4 || b < 0 || b > 4) return fail(CGKS_EINVAL, "bc entries must be 0, 1, 2, 3 or 4");
         if ((a == 0) != (b == 0)) return fail(CGKS_EINVAL, "the two sides of an axis are both periodic or both walls");
         walls = walls || a != 0;
     }
@@ -219,7 +219,10 @@ static int check_params(const cgks_params *p) {
     if (walls && p->positivity)
         return fail(CGKS_EUNSUPPORTED, "the interface-state limiter is for periodic blocks");
     for (int sd = 0; sd < 6; ++sd)
-        if (p->bc[sd] == 3) {
+        if (p->bc[sd] == 4 && p->weights == 1)
+            return fail(CGKS_EUNSUPPORTED, "learned weights are not available with non-reflecting sides");
+    for (int sd = 0; sd < 6; ++sd)
+        if (p->bc[sd] >= 3) {
             const double *f = p->farfield;
             const double ke = 0.5 * (f[1] * f[1] + f[2] * f[2] + f[3] * f[3]) / f[0];
             if (!(f[0] > 0.0) || !((p->gamma - 1.0) * (f[4] - ke) > 0.0))
@@ -476,6 +479,7 @@ int cgks_ctx_create(cgks_ctx **out, int nblocks, const int *dims, const double *
                 bv.wall |= 1 << (2 * q + sd);
                 if (p->bc[2 * q + sd] == 2) bv.wall |= 1 << (8 + 2 * q + sd);
                 if (p->bc[2 * q + sd] == 3) bv.wall |= 1 << (16 + 2 * q + sd);
+                if (p->bc[2 * q + sd] == 4) bv.wall |= 1 << (24 + 2 * q + sd);
             }
             bv.wbase[q] = Wtot;
             Wtot += bv.N / ((q == 0) ? bv.nx : (q == 1) ? bv.ny : bv.nz);

@@ -27,7 +27,55 @@ struct BlockView {
 // Sign of conserved variable v in the mirror image across wall side s: the momentum normal to
 // a symmetry plane, and every momentum component at a no-slip wall, change sign.
 __host__ __device__ inline double mirror_sign(int wall, int s, int v) {
+    if ((wall >> (24 + s)) & 1) return 1.0;  // non-reflecting side: no mirror image
     return (v >= 1 && v <= 3 && (((wall >> (8 + s)) & 1) || v - 1 == (s >> 1))) ? -1.0 : 1.0;
+}
+
+// Boundary state of a non-reflecting side: locally one-dimensional characteristics along the
+// outward unit normal n.  The Riemann invariant u_n + 2c/(gamma - 1) leaves the domain with
+// the interior state q, u_n - 2c/(gamma - 1) enters with the far-field state f; with the
+// normal velocity and sound speed these fix, entropy p/rho^gamma and tangential velocity come
+// from q at an outflow and from f at an inflow.  Supersonic outflow: q; supersonic inflow: f.
+template <class T>
+__device__ inline void nonreflecting_state(T gam, const double *f, const T q[5], const T n[3], T qb[5]) {
+    const T gm1 = gam - T(1);
+    T ui[3], ue[3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        ui[r] = q[1 + r] / q[0];
+        ue[r] = (T)f[1 + r] / (T)f[0];
+    }
+    const T pi = gm1 * (q[4] - T(0.5) * q[0] * (ui[0] * ui[0] + ui[1] * ui[1] + ui[2] * ui[2]));
+    const T pe = gm1 * ((T)f[4] - T(0.5) * (T)f[0] * (ue[0] * ue[0] + ue[1] * ue[1] + ue[2] * ue[2]));
+    const T ci = sqrt(gam * pi / q[0]), ce = sqrt(gam * pe / (T)f[0]);
+    const T uni = ui[0] * n[0] + ui[1] * n[1] + ui[2] * n[2];
+    const T une = ue[0] * n[0] + ue[1] * n[1] + ue[2] * n[2];
+    if (uni >= ci) {
+#pragma unroll
+        for (int v = 0; v < 5; ++v) qb[v] = q[v];
+        return;
+    }
+    if (uni <= -ci) {
+#pragma unroll
+        for (int v = 0; v < 5; ++v) qb[v] = (T)f[v];
+        return;
+    }
+    const T rout = uni + T(2) * ci / gm1, rin = une - T(2) * ce / gm1;
+    const T unb = T(0.5) * (rout + rin), cb = T(0.25) * gm1 * (rout - rin);
+    const bool out = unb > T(0);
+    const T rho_s = out ? q[0] : (T)f[0], p_s = out ? pi : pe, un_s = out ? uni : une;
+    const T cs2 = gam * p_s / rho_s;
+    const T rhob = rho_s * pow(cb * cb / cs2, T(1) / gm1);
+    const T pb = rhob * cb * cb / gam;
+    T k = T(0);
+    qb[0] = rhob;
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        const T ub = (out ? ui[r] : ue[r]) + (unb - un_s) * n[r];
+        qb[1 + r] = rhob * ub;
+        k += ub * ub;
+    }
+    qb[4] = pb / gm1 + T(0.5) * rhob * k;
 }
 
 // Index of a wall face of axis q within its side: i_a + n_a i_b over the tangential axes.

@@ -627,18 +627,28 @@ __global__ void __launch_bounds__(256) k_flux_wall(BlockView b, int q, long Ntot
 #pragma unroll
         for (int r = 0; r < 3; ++r) gv[v][r] = (TC)src[(4 * v + 1 + r) * Ntot];
     }
-    if (sd == w) {
-        const bool far = (b.wall >> (16 + side)) & 1;  // far field: the uniform far-field state
-#pragma unroll
-        for (int v = 0; v < 5; ++v) {
-            const TC m = (TC)mirror_sign(b.wall, side, v);
-            qv[v] = far ? (TC)P.far[v] : qv[v] * m;
-#pragma unroll
-            for (int r = 0; r < 3; ++r) gv[v][r] = far ? (TC)0 : ((r == q) ? -m : m) * gv[v][r];
-        }
-    }
 #pragma unroll
     for (int r = 0; r < 3; ++r) n[r] = (TC)M.fn[((q * 4 + kk) * 3 + r) * Ntot + f];
+    if (sd == w) {
+        if ((b.wall >> (24 + side)) & 1) {
+            // non-reflecting: the characteristic boundary state of the interior one (outward
+            // normal: n at the plus wall, -n at the minus wall), with the interior gradient
+            const TC no[3] = {w ? n[0] : -n[0], w ? n[1] : -n[1], w ? n[2] : -n[2]};
+            TC qb[5];
+            nonreflecting_state<TC>((TC)P.gamma, P.far, qv, no, qb);
+#pragma unroll
+            for (int v = 0; v < 5; ++v) qv[v] = qb[v];
+        } else {
+            const bool far = (b.wall >> (16 + side)) & 1;  // far field: the uniform far-field state
+#pragma unroll
+            for (int v = 0; v < 5; ++v) {
+                const TC m = (TC)mirror_sign(b.wall, side, v);
+                qv[v] = far ? (TC)P.far[v] : qv[v] * m;
+#pragma unroll
+                for (int r = 0; r < 3; ++r) gv[v][r] = far ? (TC)0 : ((r == q) ? -m : m) * gv[v][r];
+            }
+        }
+    }
     TC F[5], Ft[5], Qs[5], dQs[5];
     const int bad = gks_flux_pair<DevMath, TC, FULL>(P, sd, qv, gv, n, (TC)*dtp, F, Ft, Qs, dQs);
     if (bad && sd == 0) atomicOr(flag, bad);

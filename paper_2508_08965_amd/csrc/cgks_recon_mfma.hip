@@ -121,17 +121,30 @@ __device__ inline int wall_touch(const BlockView &b, int ci, int cj, int ck, Cel
 }
 // Ghost neighbour behind the sides in `crossed`: behind a far-field side the uniform far-field
 // state (zero gradient); otherwise the mirror image of its mirror cell's average and physical
-// gradient of variable v: the average changes sign with the variable (mirror_sign), the
-// gradient also in its component normal to each wall.
-__device__ inline void ghost_mirror(int wall, int crossed, int v, double farv, double &q, double g[3]) {
+// gradient of variable v across the walls (the average changes sign with the variable,
+// mirror_sign, the gradient also in its component normal to each wall), continued linearly
+// across the non-reflecting sides: the average plus the reference gradient J0^T g of the mirror
+// cell nb times the one-cell offset along each such side's axis.
+__device__ inline void ghost_mirror(int wall, int crossed, int v, double farv, const double *__restrict__ J0, long Ntot,
+                                    int nb, double &q, double g[3]) {
+    const int nr = (wall >> 24) & crossed;
 #pragma unroll
     for (int s = 0; s < 6; ++s)
-        if ((crossed >> s) & 1) {
+        if (((crossed & ~nr) >> s) & 1) {
             const double m = mirror_sign(wall, s, v);
             q *= m;
 #pragma unroll
             for (int r = 0; r < 3; ++r) g[r] *= (r == (s >> 1)) ? -m : m;
         }
+    if (nr) {
+#pragma unroll
+        for (int s = 0; s < 6; ++s)
+            if ((nr >> s) & 1) {
+                const long a = s >> 1;
+                const double d = (s & 1) ? 1.0 : -1.0;
+                q += d * (J0[a * Ntot + nb] * g[0] + J0[(3 + a) * Ntot + nb] * g[1] + J0[(6 + a) * Ntot + nb] * g[2]);
+            }
+    }
     const bool far = ((wall >> 16) & crossed) != 0;
     q = far ? farv : q;
 #pragma unroll
@@ -142,6 +155,13 @@ __device__ inline int step_crossed(int touch, int st, int sa, int sb) {
     if (st < 6) return touch & (1 << st);
     const int p = st - 6, pa = (p < 2) ? 0 : 1, pb = (p == 0) ? 1 : 2;
     return touch & ((1 << (2 * pa + (sa > 0))) | (1 << (2 * pb + (sb > 0))));
+}
+// Cell read by gather step st (face neighbour st < 6, else edge neighbour of plane st - 6 with
+// the lane's edge signs): with the offsets toward wall sides zeroed, the mirror cell.
+__device__ inline int step_cell(int c, const CellNb &gn, int st, int sa, int sb) {
+    if (st < 6) return c + ((st & 1) ? gn.dp[st >> 1] : gn.dm[st >> 1]);
+    const int p = st - 6, pa = (p < 2) ? 0 : 1, pb = (p == 0) ? 1 : 2;
+    return c + (sa > 0 ? gn.dp[pa] : gn.dm[pa]) + (sb > 0 ? gn.dp[pb] : gn.dm[pb]);
 }
 
 // Cell coordinates of this lane: tile of runs (ty = 0; the wave's first cell is decoded once,
@@ -286,7 +306,7 @@ __global__ void __launch_bounds__(NT) k_recon_mfma(WorkList W, long Ntot, const 
                 double q = ld32(Q + vp * Ntot, nb), gg[3];
     #pragma unroll
                 for (int r = 0; r < 3; ++r) gg[r] = ld32(G + (3 * vp + r) * Ntot, nb);
-                if (crossed) ghost_mirror(b.wall, crossed, vp, farv, q, gg);
+                if (crossed) ghost_mirror(b.wall, crossed, vp, farv, M.J0, Ntot, nb, q, gg);
                 halo[h] = q;
     #pragma unroll
                 for (int r = 0; r < 3; ++r) halo[(1 + r) * kStgCells + h] = gg[r];
@@ -377,7 +397,8 @@ __global__ void __launch_bounds__(NT) k_recon_mfma(WorkList W, long Ntot, const 
     #pragma unroll
                 for (int st = 0; st < 9; ++st) {
                     const int crossed = step_crossed(touch, st, sa, sb);
-                    if (crossed) ghost_mirror(b.wall, crossed, v, farv, nq[st], ng[st]);
+                    if (crossed) ghost_mirror(b.wall, crossed, v, farv, M.J0, Ntot, step_cell(c, gn, st, sa, sb), nq[st],
+                                              ng[st]);
                 }
             }
     #pragma unroll
@@ -776,7 +797,7 @@ __global__ void __launch_bounds__(512) k_recon_bf16(WorkList W, long Ntot, const
     #pragma unroll
             for (int st = 0; st < 9; ++st) {
                 const int crossed = step_crossed(touch, st, sa, sb);
-                if (crossed) ghost_mirror(b.wall, crossed, v, farv, nq[st], ng[st]);
+                if (crossed) ghost_mirror(b.wall, crossed, v, farv, M.J0, Ntot, step_cell(c, gn, st, sa, sb), nq[st], ng[st]);
             }
             double lvd[3];
     #pragma unroll
