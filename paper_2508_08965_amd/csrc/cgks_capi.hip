@@ -73,7 +73,7 @@ struct cgks_ctx {
     Metrics M{};
     double *metric_mem = nullptr;
     DevConsts *K = nullptr;
-    double *gp = nullptr;     // [3][2][4][20][Ntot]
+    double *gp = nullptr;     // [3][2][4][20][Gtot] (padded rows: BlockView::gp_at)
     double *fo = nullptr;     // [3][4][30][Ntot]
     double *stash = nullptr;  // [80][Ntot]
     double *Kmf = nullptr;    // constant blocks of the matrix-core reconstruction
@@ -307,7 +307,12 @@ static hipError_t build_list(cgks_ctx *c, int k) {
                 z0 += ez;
             }
         } else {
-            for (long st = 0; st < bv.N; st += T) t.push_back(Tile{b, (int)std::min(T, bv.N - st), st, 0, 0, 0, 0});
+            // a short first run up to the next multiple of 16 cells of the whole mesh, so that
+            // every later chunk of 16 cells, a wave's row, starts on a 128-byte boundary of the
+            // component arrays (a chunk across two cache lines costs its stores a second line)
+            const long a = std::min<long>((16 - bv.off % 16) % 16, bv.N);
+            if (a > 0) t.push_back(Tile{b, (int)a, 0, 0, 0, 0, 0});
+            for (long st = a; st < bv.N; st += T) t.push_back(Tile{b, (int)std::min(T, bv.N - st), st, 0, 0, 0, 0});
         }
     }
     l.first[nb] = (int)t.size();
@@ -464,6 +469,16 @@ int cgks_ctx_create(cgks_ctx **out, int nblocks, const int *dims, const double *
         Ntot += blocks[b].N;
         if (Ntot >= kMaxCells) return fail(CGKS_EINVAL, "total number of cells must be below 2^27");
     }
+    // Gauss-point buffer: rows padded to a multiple of 16 cells where that costs at most a
+    // quarter more (a block a few cells wide keeps its rows), block starts on 16 cells
+    long Gtot = 0;
+    for (BlockView &bv : blocks) {
+        const int nxp = 16 * ((bv.nx + 15) / 16);
+        bv.nxp = (4 * nxp <= 5 * bv.nx) ? nxp : bv.nx;
+        bv.goff = Gtot;
+        Gtot += 16 * (((long)bv.nxp * bv.ny * bv.nz + 15) / 16);
+    }
+    for (BlockView &bv : blocks) bv.gstride = Gtot;
     // wall sides (the same for every block): geometry check on the host nodes, wall-face offsets
     long Wtot = 0;
     for (int b = 0; b < nblocks; ++b) {
@@ -505,7 +520,7 @@ int cgks_ctx_create(cgks_ctx **out, int nblocks, const int *dims, const double *
     const size_t nmet = 1 + 9 + 9 + 36 + 12 + 12;
     bool ok = alloc((void **)&c->metric_mem, sizeof(double) * nmet * Ntot) && alloc((void **)&c->K, sizeof(DevConsts)) &&
               alloc((void **)&c->Kmf, sizeof(double) * std::max(kMfmaBlocks * 64, kBfBlocks * 512)) &&
-              alloc((void **)&c->gp, sizeof(double) * 480 * Ntot) && alloc((void **)&c->fo, sizeof(double) * 360 * Ntot) &&
+              alloc((void **)&c->gp, sizeof(double) * 480 * Gtot) && alloc((void **)&c->fo, sizeof(double) * 360 * Ntot) &&
               alloc((void **)&c->stash, sizeof(double) * 80 * Ntot) &&
               alloc((void **)&c->dt_part, sizeof(double) * kMaxDtParts) && alloc((void **)&c->flag, sizeof(int)) &&
               alloc((void **)&c->diag_part, sizeof(double) * 7 * kMaxDtParts) &&

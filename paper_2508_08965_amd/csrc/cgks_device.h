@@ -16,13 +16,32 @@ struct BlockView {
     long N;    // cells of the block
     long off;  // offset of the block's first cell in the concatenated state
     // Sides s = 2q + (0 minus, 1 plus) of axis q: bit s marks a non-periodic side (symmetry
-    // plane, no-slip wall or far field), bit 8 + s a no-slip wall, bit 16 + s a far-field side;
-    // 0 for a periodic block.  Non-periodic sides come in pairs per axis.
+    // plane, no-slip wall, far field or non-reflecting), bit 8 + s a no-slip wall, bit 16 + s a
+    // far-field side, bit 24 + s a non-reflecting side; 0 for a periodic block.  Non-periodic
+    // sides come in pairs per axis.
     int wall;
     // Per axis with walls: offset of the block's minus-side wall faces in the wall-face buffer
     // (one entry per face of that side, index i_a + n_a i_b over the tangential axes a < b).
     long wbase[3];
+    // Gauss-point buffer: cell (i, j, k) of the block at goff + i + nxp (j + ny k), rows padded
+    // to nxp = nx rounded up to 16 cells and goff a multiple of 16, so that every row of 16
+    // cells the reconstruction writes starts on a 128-byte boundary; gstride: the buffer's
+    // stride between components (the same for every block).
+    long goff, gstride;
+    int nxp;
 };
+
+// Index in the Gauss-point buffer of cell (i, j, k) of block b, periodic in the block.
+__host__ __device__ inline long gp_at(const BlockView &b, int i, int j, int k) {
+    i = (i < 0) ? i + b.nx : (i >= b.nx ? i - b.nx : i);
+    j = (j < 0) ? j + b.ny : (j >= b.ny ? j - b.ny : j);
+    k = (k < 0) ? k + b.nz : (k >= b.nz ? k - b.nz : k);
+    return b.goff + (long)i + (long)b.nxp * ((long)j + (long)b.ny * k);
+}
+// Index in the Gauss-point buffer of the block-local linear cell index l.
+__host__ __device__ inline long gp_local(const BlockView &b, long l) {
+    return (b.nxp == b.nx) ? b.goff + l : b.goff + l % b.nx + (long)b.nxp * (l / b.nx);
+}
 
 // Sign of conserved variable v in the mirror image across wall side s: the momentum normal to
 // a symmetry plane, and every momentum component at a no-slip wall, change sign.

@@ -8,10 +8,11 @@
 //   k_update    : face -> cell accumulation and S2O4 stage update (Sec. 3.1, temporal section)
 //
 // Data layout (SoA, stride Ntot = cells of all blocks, x fastest inside a block):
-//   gp  [q][side][k][v*4 + c][Ntot]   reconstructed value (c = 0) and physical gradient
+//   gp  [q][side][k][v*4 + c][Gtot]   reconstructed value (c = 0) and physical gradient
 //                                     (c = 1..3) at Gauss point k of face q of the face
 //                                     record owned by the minus-side cell; side 0 = values
-//                                     of the minus-side (left) cell, side 1 = plus-side cell.
+//                                     of the minus-side (left) cell, side 1 = plus-side cell;
+//                                     cells at gp_at(), rows padded to 16 cells.
 //   fo  [q][k][30][Ntot]              F^n (5), F_t^n (5), Q^l, dQ^l/dt, Q^r, dQ^r/dt (20)
 #include <hip/hip_runtime.h>
 
@@ -485,20 +486,12 @@ __global__ void __launch_bounds__(256) k_recon(BlockView b, long Ntot, const dou
 #pragma unroll
         for (int r = 0; r < 3; ++r) out[1 + r] = JiT[r][0] * r0 + JiT[r][1] * r1 + JiT[r][2] * r2;
         const int m = g >> 2, kk = g & 3, q = m >> 1;
-        long f;
-        int side;
-        if (m & 1) {
-            f = c;
-            side = 0;
-        } else {
-            int o[3] = {0, 0, 0};
-            o[q] = -1;
-            f = cell_at(b, id.i + o[0], id.j + o[1], id.k + o[2]);
-            side = 1;
-        }
-        double *dst = gp + ((long)(((q * 2 + side) * 4 + kk) * 20 + v * 4)) * Ntot + f;
+        // the face record of the minus-side cell: this cell's plus face, the minus neighbour's
+        const int side = (m & 1) ? 0 : 1;
+        const long f = gp_at(b, id.i - (side && q == 0), id.j - (side && q == 1), id.k - (side && q == 2));
+        double *dst = gp + ((long)(((q * 2 + side) * 4 + kk) * 20 + v * 4)) * b.gstride + f;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) dst[r * Ntot] = out[r];
+        for (int r = 0; r < 4; ++r) dst[r * b.gstride] = out[r];
     }
 }
 
@@ -511,21 +504,13 @@ __global__ void __launch_bounds__(256) k_gp_export(BlockView b, long Ntot, const
     Idx3 id = unflatten(b, cl);
     long c = b.off + cl;
     for (int g = 0; g < kNGP; ++g) {
-        int m = g >> 2, kk = g & 3, q = m >> 1;
-        long f;
-        int side;
-        if (m & 1) {
-            f = c;
-            side = 0;
-        } else {
-            int o[3] = {0, 0, 0};
-            o[q] = -1;
-            f = cell_at(b, id.i + o[0], id.j + o[1], id.k + o[2]);
-            side = 1;
-        }
+        const int m = g >> 2, kk = g & 3, q = m >> 1;
+        const int side = (m & 1) ? 0 : 1;
+        const long f = gp_at(b, id.i - (side && q == 0), id.j - (side && q == 1), id.k - (side && q == 2));
         for (int v = 0; v < 5; ++v)
             for (int r = 0; r < 4; ++r)
-                out[((c * kNGP + g) * 5 + v) * 4 + r] = (double)gp[((long)(((q * 2 + side) * 4 + kk) * 20 + v * 4 + r)) * Ntot + f];
+                out[((c * kNGP + g) * 5 + v) * 4 + r] =
+                    (double)gp[((long)(((q * 2 + side) * 4 + kk) * 20 + v * 4 + r)) * b.gstride + f];
     }
 }
 
@@ -546,14 +531,16 @@ __global__ void __launch_bounds__(256, 2) k_flux(WorkList W, long Ntot, const TG
     const int qk = (int)(u % 12), q = qk >> 2, kk = qk & 3;
     const int i = (int)(threadIdx.x >> 1), sd = (int)(threadIdx.x & 1);
     if (i >= tile.count) return;  // both lanes of a pair leave together
-    const long f = W.blocks[tile.blk].off + tile.start + i;
+    const BlockView &bk = W.blocks[tile.blk];
+    const long f = bk.off + tile.start + i;
     TC qv[5], gv[5][3], n[3];
-    const TG *src = gp + (long)(((q * 2 + sd) * 4 + kk) * 20) * Ntot + f;
+    const long gs = bk.gstride;
+    const TG *src = gp + (long)(((q * 2 + sd) * 4 + kk) * 20) * gs + gp_local(bk, tile.start + i);
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
-        qv[v] = (TC)src[(4 * v) * Ntot];
+        qv[v] = (TC)src[(4 * v) * gs];
 #pragma unroll
-        for (int j = 0; j < 3; ++j) gv[v][j] = (TC)src[(4 * v + 1 + j) * Ntot];
+        for (int j = 0; j < 3; ++j) gv[v][j] = (TC)src[(4 * v + 1 + j) * gs];
     }
     if constexpr (POS) {
         long own = f;
@@ -620,12 +607,12 @@ __global__ void __launch_bounds__(256) k_flux_wall(BlockView b, int q, long Ntot
     const long f = b.off + i + (long)b.nx * (j + (long)b.ny * k);
     const int side = 2 * q + w;
     TC qv[5], gv[5][3], n[3];
-    const TG *src = gp + (long)(((q * 2 + (1 - w)) * 4 + kk) * 20) * Ntot + f;
+    const TG *src = gp + (long)(((q * 2 + (1 - w)) * 4 + kk) * 20) * b.gstride + gp_at(b, i, j, k);
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
-        qv[v] = (TC)src[(4 * v) * Ntot];
+        qv[v] = (TC)src[(4 * v) * b.gstride];
 #pragma unroll
-        for (int r = 0; r < 3; ++r) gv[v][r] = (TC)src[(4 * v + 1 + r) * Ntot];
+        for (int r = 0; r < 3; ++r) gv[v][r] = (TC)src[(4 * v + 1 + r) * b.gstride];
     }
 #pragma unroll
     for (int r = 0; r < 3; ++r) n[r] = (TC)M.fn[((q * 4 + kk) * 3 + r) * Ntot + f];

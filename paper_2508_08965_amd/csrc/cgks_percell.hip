@@ -226,21 +226,13 @@ __global__ void __launch_bounds__(64) k_recon_percell(BlockView b, long Ntot, co
         const double *xg = K->xg[g];
         const double low = bbar[0] * xg[0] + bbar[1] * xg[1] + bbar[2] * xg[2];
         const int m = g >> 2, kk = g & 3, q = m >> 1;
-        long f;
-        int side;
-        if (m & 1) {
-            f = c;
-            side = 0;
-        } else {
-            int o[3] = {0, 0, 0};
-            o[q] = -1;
-            f = pc_cell(b, ci + o[0], cj + o[1], ck + o[2]);
-            side = 1;
-        }
-        double *dst = gp + ((long)(((q * 2 + side) * 4 + kk) * 20 + v * 4)) * Ntot + f;
+        // the face record of the minus-side cell: this cell's plus face, the minus neighbour's
+        const int side = (m & 1) ? 0 : 1;
+        const long f = gp_at(b, ci - (side && q == 0), cj - (side && q == 1), ck - (side && q == 2));
+        double *dst = gp + ((long)(((q * 2 + side) * 4 + kk) * 20 + v * 4)) * b.gstride + f;
         dst[0] = q0 + chi * p[0] + om * low;
 #pragma unroll
-        for (int r = 0; r < 3; ++r) dst[(1 + r) * Ntot] = chi * p[1 + r] + om * jb[r];
+        for (int r = 0; r < 3; ++r) dst[(1 + r) * b.gstride] = chi * p[1 + r] + om * jb[r];
     }
 }
 

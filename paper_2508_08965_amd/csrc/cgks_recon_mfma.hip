@@ -610,6 +610,9 @@ __global__ void __launch_bounds__(NT) k_recon_mfma(WorkList W, long Ntot, const 
             const RW om = RW(1) - chi;
 
             // ---- Gauss-point values: face m = tile u, Gauss point k = g ----------------------------
+            // the cell in the Gauss-point buffer (rows padded to nxp cells)
+            const int gl = c - (int)b.off;
+            const int gc = (int)b.goff + gl + ((b.nxp == b.nx) ? 0 : (b.nxp - b.nx) * (gl / b.nx));
             auto emit = [&](int u, const V y) __attribute__((always_inline)) {
                 const int q = u >> 1;
                 const RW xq = (u & 1) ? RW(0.5) : RW(-0.5);
@@ -625,13 +628,19 @@ __global__ void __launch_bounds__(NT) k_recon_mfma(WorkList W, long Ntot, const 
                          r2 = chi * (RW)y[3] + om * bbar[2];
                 // face u is the + face of this cell (side 0) or the + face of the - neighbour (side 1)
                 const int side = (u & 1) ? 0 : 1;
-                const int f = (u & 1) ? c : c + ((q == 0) ? cn.dm[0] : (q == 1) ? cn.dm[1] : cn.dm[2]);
+                // face record in the Gauss-point buffer: this cell's (+ face) or the minus
+                // neighbour's, periodic in the block (its offset from the cell's sign of cn.dm)
+                const int f = (u & 1) ? gc
+                                      : gc + ((q == 0)   ? cn.dm[0]
+                                              : (q == 1) ? ((cn.dm[1] < 0) ? -b.nxp : (b.ny - 1) * b.nxp)
+                                                         : ((cn.dm[2] < 0) ? -b.ny * b.nxp : (b.nz - 1) * b.ny * b.nxp));
                 if (valid) {
-                    TG *dst = gp + ((long)(((q * 2 + side) * 4 + g) * 20 + v * 4)) * Ntot + f;
+                    const long gs = b.gstride;
+                    TG *dst = gp + ((long)(((q * 2 + side) * 4 + g) * 20 + v * 4)) * gs + f;
                     __builtin_nontemporal_store((TG)val, dst);
-                    __builtin_nontemporal_store((TG)(JiT[0][0] * r0 + JiT[0][1] * r1 + JiT[0][2] * r2), dst + Ntot);
-                    __builtin_nontemporal_store((TG)(JiT[1][0] * r0 + JiT[1][1] * r1 + JiT[1][2] * r2), dst + 2 * Ntot);
-                    __builtin_nontemporal_store((TG)(JiT[2][0] * r0 + JiT[2][1] * r1 + JiT[2][2] * r2), dst + 3 * Ntot);
+                    __builtin_nontemporal_store((TG)(JiT[0][0] * r0 + JiT[0][1] * r1 + JiT[0][2] * r2), dst + gs);
+                    __builtin_nontemporal_store((TG)(JiT[1][0] * r0 + JiT[1][1] * r1 + JiT[1][2] * r2), dst + 2 * gs);
+                    __builtin_nontemporal_store((TG)(JiT[2][0] * r0 + JiT[2][1] * r1 + JiT[2][2] * r2), dst + 3 * gs);
                 }
             };
             if constexpr (PR::kParity) {
@@ -656,6 +665,7 @@ __global__ void __launch_bounds__(NT) k_recon_mfma(WorkList W, long Ntot, const 
                     }
                     emit(2 * q, ym);
                     emit(2 * q + 1, yp);
+                    __builtin_amdgcn_sched_barrier(0);  // one face pair at a time (register pressure)
                 }
             } else {
     #pragma unroll
@@ -938,6 +948,9 @@ __global__ void __launch_bounds__(512) k_recon_bf16(WorkList W, long Ntot, const
                 for (int s = 0; s < 3; ++s) JiT[r][s] = (float)JiTd[r][s];
             const float om = 1.0f - chi;
             const float taf = (float)ta, tbf = (float)tb;
+            // the cell in the Gauss-point buffer (rows padded to nxp cells)
+            const int gl = c - (int)b.off;
+            const int gc = (int)b.goff + gl + ((b.nxp == b.nx) ? 0 : (b.nxp - b.nx) * (gl / b.nx));
     #pragma unroll 2
             for (int u = 0; u < 6; ++u) {
                 v4f y = {0, 0, 0, 0};
@@ -954,13 +967,19 @@ __global__ void __launch_bounds__(512) k_recon_bf16(WorkList W, long Ntot, const
                             r2 = chi * y[3] + om * bbar[2];
                 // face u is the + face of this cell (side 0) or the + face of the - neighbour (side 1)
                 const int side = (u & 1) ? 0 : 1;
-                const int f = (u & 1) ? c : c + ((q == 0) ? cn.dm[0] : (q == 1) ? cn.dm[1] : cn.dm[2]);
+                // face record in the Gauss-point buffer: this cell's (+ face) or the minus
+                // neighbour's, periodic in the block (its offset from the cell's sign of cn.dm)
+                const int f = (u & 1) ? gc
+                                      : gc + ((q == 0)   ? cn.dm[0]
+                                              : (q == 1) ? ((cn.dm[1] < 0) ? -b.nxp : (b.ny - 1) * b.nxp)
+                                                         : ((cn.dm[2] < 0) ? -b.ny * b.nxp : (b.nz - 1) * b.ny * b.nxp));
                 if (valid) {
-                    TG *dst = gp + ((long)(((q * 2 + side) * 4 + g) * 20 + v * 4)) * Ntot + f;
+                    const long gs = b.gstride;
+                    TG *dst = gp + ((long)(((q * 2 + side) * 4 + g) * 20 + v * 4)) * gs + f;
                     __builtin_nontemporal_store((TG)(q0 + (double)dv), dst);
-                    __builtin_nontemporal_store((TG)(JiT[0][0] * r0 + JiT[0][1] * r1 + JiT[0][2] * r2), dst + Ntot);
-                    __builtin_nontemporal_store((TG)(JiT[1][0] * r0 + JiT[1][1] * r1 + JiT[1][2] * r2), dst + 2 * Ntot);
-                    __builtin_nontemporal_store((TG)(JiT[2][0] * r0 + JiT[2][1] * r1 + JiT[2][2] * r2), dst + 3 * Ntot);
+                    __builtin_nontemporal_store((TG)(JiT[0][0] * r0 + JiT[0][1] * r1 + JiT[0][2] * r2), dst + gs);
+                    __builtin_nontemporal_store((TG)(JiT[1][0] * r0 + JiT[1][1] * r1 + JiT[1][2] * r2), dst + 2 * gs);
+                    __builtin_nontemporal_store((TG)(JiT[2][0] * r0 + JiT[2][1] * r1 + JiT[2][2] * r2), dst + 3 * gs);
                 }
             }
         }
