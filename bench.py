@@ -196,10 +196,11 @@ def oracle_rate(O, dims, nodes, prm, Q, G, L, steps, nthreads=0):
 
 def cpu_baseline(W, kw):
     """The oracle as it is (C, OpenMP), timed on this host: a bounded sample of the headline
-    workload on every thread, the same on one thread, and the 2D density wave in full."""
+    workload on every thread (one step on the 128^3 mesh of the 20-step parity configuration),
+    the same workload on one thread, and the 2D density wave in full."""
     from oracle import oracle as O
     cores = O.num_threads()
-    m, ksteps = 96, 3
+    m, ksteps = 128, 1
     ns = (m, m, m)
     nd = W.perturbed_nodes(ns, amp=0.05)
     Qs, Gs, Ls = W.initial_state(nd, W.taylor_green(Ma=0.1), GAM)
