@@ -141,8 +141,10 @@ void cgks_default_params(cgks_params *p);
  *   stream       hipStream_t used for the set-up work (may be NULL: the null stream)
  * Metrics are computed on the device.  Cells must have positive volume and positive
  * det J0.  The total number of cells must be below 2^27 (the kernels index one component
- * array with 32-bit offsets; one MI355X holds about 33M cells of state and buffers).
- * On failure *out is NULL. */
+ * array with 32-bit offsets; one MI355X holds about 33M cells of state and buffers).  The
+ * internal Gauss-point buffer pads a block's rows to a multiple of 16 cells where that costs
+ * at most a quarter more (aligned stores), so its size grows by up to 25 % for blocks whose x
+ * extent is not a multiple of 16.  On failure *out is NULL. */
 int cgks_ctx_create(cgks_ctx **out, int nblocks, const int *dims, const double *const *nodes,
                     const cgks_params *p, void *stream);
 
