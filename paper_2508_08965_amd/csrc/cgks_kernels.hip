@@ -1039,7 +1039,7 @@ hipError_t launch_update(int stage, bool fo32, const WorkList &W, long Ntot, con
                          const double *dt, double *Q, double *G, double *L, double *stash, int ngroups,
                          const void *wf, long Wtot, hipStream_t s) {
     // wf: the wall-face buffer, or NULL for work lists of periodic blocks only.  The stage-1
-    // FP64 update runs in its wall-capable form for every block: with the per-face redirect
+    // update runs in its wall-capable form for every block: with the per-face redirect
     // (not taken without walls) it measured faster than the periodic form, 14.4 against 16.2
     // ms at 256^3 (the periodic form unrolled over the four Gauss points of a face; without
     // the unroll it was slower still), with bitwise equal results.
@@ -1049,13 +1049,10 @@ hipError_t launch_update(int stage, bool fo32, const WorkList &W, long Ntot, con
     hipLaunchKernelGGL((k_update<ST, TF, WL>), grid, bl, 0, s, W, Ntot, (const TF *)fo, M, dt, Q, G, L, stash, \
                        (const TF *)wf, Wtot)
     if (fo32) {
-        if (wf) {
-            if (stage == 1) CGKS_UPDATE(1, float, true);
-            else CGKS_UPDATE(2, float, true);
-        } else {
-            if (stage == 1) CGKS_UPDATE(1, float, false);
-            else CGKS_UPDATE(2, float, false);
-        }
+        // stage 1 in the wall-capable form here too (its code measured faster, as for FP64)
+        if (stage == 1) CGKS_UPDATE(1, float, true);
+        else if (wf) CGKS_UPDATE(2, float, true);
+        else CGKS_UPDATE(2, float, false);
     } else {
         if (stage == 1) CGKS_UPDATE(1, double, true);
         else if (wf) CGKS_UPDATE(2, double, true);
