@@ -629,7 +629,7 @@ __host__ __device__ inline int gks_flux_pair(const DevParams &P, const int sd, c
     return err;
 }
 
-// launch wrappers (cgks_kernels.hip)
+// launch wrappers (cgks_kernels.hip; the flux ones in cgks_flux.hip)
 hipError_t launch_metrics(const BlockView &b, const double *nodes, const Metrics &M, long Ntot, int *bad, hipStream_t s);
 hipError_t launch_dt(long off, long N, long Ntot, const double *Q, const double *dtm, const DevParams &P,
                      double *part, int nparts, int *flag, hipStream_t s);
